@@ -1,0 +1,247 @@
+"""Python handle on the FP64 CPU oracle (``snake_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  The tests, the smoke check and the CPU-baseline
+leg of the benchmark use it; the GPU library never imports, links or runs
+anything in this folder, and this folder imports nothing from the GPU
+library.  Inputs come from the shared seeded generator in ``workloads``.
+
+State arrays here are array-of-structures per body, float64:
+``x[N,3]``, ``q[N,4]`` (w,x,y,z), ``v[N,3]``, ``w[N,3]``, ``p[Mtot,2]``,
+``cmd[Mtot]``, ``lam_j[Jtot,6]`` (stretch xyz, twist, bend_y, bend_z) and
+``lam_c[N,3]`` (normal, tangential x, tangential y).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "snake_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+FLAG_FIXED_ROOT = 1
+FLAG_NO_GROUND = 2
+FLAG_LINEARISED = 8
+WARM_ZERO, WARM_PREV, WARM_GIVEN = 0, 1, 2
+STATUS_NONFINITE, STATUS_NOT_CONVERGED = 1, 2
+
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+                build(force=True)
+            _lib = C.CDLL(LIB)
+            _declare(_lib)
+    return _lib
+
+
+_P = C.c_void_p
+
+
+class Batch(C.Structure):
+    _fields_ = [
+        ("n_snakes", C.c_int32),
+        ("n_modules", _P), ("segs", _P),
+        ("alpha_s", _P), ("alpha_b", _P), ("alpha_t", _P), ("mu", _P),
+        ("freq", _P), ("phase0", _P),
+        ("sched_off", _P), ("sched_steps", _P), ("sched_val", _P),
+        ("mass", C.c_double), ("length", C.c_double), ("radius", C.c_double),
+        ("gravity", C.c_double),
+        ("dt", C.c_double),
+        ("substeps", C.c_int32), ("iters", C.c_int32),
+        ("tol", C.c_double), ("relax", C.c_double),
+        ("law", C.c_int32),
+        ("tau_inf", C.c_double), ("tau_def", C.c_double), ("kappa_max", C.c_double),
+        ("k_i", C.c_double), ("k_d", C.c_double), ("T_p", C.c_double), ("p_s", C.c_double),
+        ("amp_psi", C.c_double),
+        ("flags", C.c_int32), ("controller", C.c_int32), ("warm", C.c_int32),
+        ("ctrl_alpha", C.c_double), ("ctrl_offset", C.c_double),
+    ]
+
+
+class State(C.Structure):
+    _fields_ = [(n, _P) for n in ("x", "q", "v", "w", "p", "cmd", "lam_j", "lam_c",
+                                  "residual", "iters", "status", "iters_total", "step")]
+
+
+def _declare(L):
+    bp, sp = C.POINTER(Batch), C.POINTER(State)
+    L.orc_offsets.argtypes = [bp, _P, _P, _P, _P]
+    L.orc_init_state.argtypes = [bp, sp]
+    L.orc_commands.argtypes = [bp, sp, C.c_int32, C.c_int32]
+    L.orc_run.argtypes = [bp, sp, C.c_int32, C.c_int32, C.c_int32]
+    L.orc_run.restype = C.c_int
+    L.orc_assemble.argtypes = [bp, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.orc_assemble.restype = C.c_int
+    L.orc_predict_snake.argtypes = [bp, C.c_int32, _P, _P, _P, _P, C.c_double]
+    L.orc_index.argtypes = [bp] + [_P] * 7
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Oracle:
+    """An FP64 batch built from a ``workloads.Workload`` (or any object with
+    the same fields).  Keyword overrides replace workload settings."""
+
+    def __init__(self, wl, **over):
+        self.L = lib()
+        g = lambda k: over.get(k, getattr(wl, k))  # noqa: E731
+        self._keep = {}
+
+        def arr(name, a, dt):
+            a = np.ascontiguousarray(np.asarray(a, dtype=dt))
+            self._keep[name] = a
+            return _ptr(a)
+
+        n = int(len(wl.n_modules))
+        b = Batch()
+        b.n_snakes = n
+        b.n_modules = arr("nm", g("n_modules"), np.int32)
+        b.segs = arr("sg", g("segs_per_module"), np.int32)
+        b.alpha_s = arr("as", g("alpha_stretch"), np.float64)
+        b.alpha_b = arr("ab", g("alpha_bend"), np.float64)
+        b.alpha_t = arr("at", g("alpha_twist"), np.float64)
+        b.mu = arr("mu", g("mu"), np.float64)
+        b.freq = arr("fr", g("ctrl_freq"), np.float64)
+        b.phase0 = arr("ph", g("ctrl_phase0"), np.float64)
+        so = g("sched_off")
+        if so is not None:
+            b.sched_off = arr("so", so, np.int32)
+            b.sched_steps = arr("ss", g("sched_steps"), np.int32)
+            b.sched_val = arr("sv", g("sched_val"), np.float64)
+        for f, k in (("mass", "seg_mass"), ("length", "seg_length"), ("radius", "seg_radius"),
+                     ("gravity", "gravity"), ("dt", "dt"), ("tol", "tol"), ("relax", "relax"),
+                     ("tau_inf", "tau_inflate"), ("tau_def", "tau_deflate"),
+                     ("kappa_max", "kappa_max"), ("k_i", "k_inflate"), ("k_d", "k_deflate"),
+                     ("T_p", "T_p"), ("p_s", "p_source"), ("amp_psi", "amplitude_psi"),
+                     ("ctrl_alpha", "ctrl_alpha"), ("ctrl_offset", "ctrl_offset")):
+            setattr(b, f, float(g(k)))
+        b.substeps = int(g("substeps"))
+        b.iters = int(g("iters"))
+        b.law = int(g("pressure_law"))
+        b.flags = int(g("flags"))
+        b.controller = int(g("controller"))
+        b.warm = int(over.get("warm", WARM_ZERO))
+        self.batch = b
+        self.n = n
+        self.B = (np.asarray(g("n_modules"), np.int64) * np.asarray(g("segs_per_module"), np.int64))
+        self.M = np.asarray(g("n_modules"), np.int64)
+        self.body_off = np.zeros(n + 1, np.int64)
+        self.joint_off = np.zeros(n + 1, np.int64)
+        self.module_off = np.zeros(n + 1, np.int64)
+        self.block_off = np.zeros(n + 1, np.int64)
+        self.L.orc_offsets(C.byref(b), _ptr(self.body_off), _ptr(self.joint_off),
+                           _ptr(self.module_off), _ptr(self.block_off))
+        N, J, Mt = int(self.body_off[-1]), int(self.joint_off[-1]), int(self.module_off[-1])
+        self.x = np.zeros((N, 3))
+        self.q = np.zeros((N, 4))
+        self.v = np.zeros((N, 3))
+        self.w = np.zeros((N, 3))
+        self.p = np.zeros((Mt, 2))
+        self.cmd = np.zeros(Mt)
+        self.lam_j = np.zeros((max(J, 0), 6))
+        self.lam_c = np.zeros((N, 3))
+        self.residual = np.zeros(n)
+        self.iters = np.zeros(n, np.int32)
+        self.status = np.zeros(n, np.int32)
+        self.iters_total = np.zeros(n, np.int64)
+        self.step = np.zeros(n, np.int64)
+        self._state()
+        self.L.orc_init_state(C.byref(self.batch), C.byref(self.st))
+
+    def _state(self):
+        s = State()
+        for f in ("x", "q", "v", "w", "p", "cmd", "lam_j", "lam_c", "residual", "iters",
+                  "status", "iters_total", "step"):
+            setattr(s, f, _ptr(getattr(self, f)))
+        self.st = s
+
+    # -- stepping ---------------------------------------------------------
+    def commands(self):
+        self.L.orc_commands(C.byref(self.batch), C.byref(self.st), 0, self.n)
+        return self.cmd
+
+    def run(self, n_steps: int, threads: int = 1, snakes=None):
+        """Advance snakes (default all) by ``n_steps`` steps.  With threads > 1
+        contiguous snake ranges run concurrently (ctypes releases the GIL)."""
+        s0, s1 = (0, self.n) if snakes is None else snakes
+        if threads <= 1 or s1 - s0 <= 1:
+            self.L.orc_run(C.byref(self.batch), C.byref(self.st), s0, s1, int(n_steps))
+            return self
+        cost = self.B[s0:s1].astype(np.float64)
+        cuts = np.searchsorted(np.cumsum(cost), np.linspace(0, cost.sum(), threads + 1)[1:-1])
+        bounds = [s0] + [s0 + int(c) + 1 for c in cuts] + [s1]
+        bounds = sorted(set(min(max(b, s0), s1) for b in bounds))
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            futs = [ex.submit(self.L.orc_run, C.byref(self.batch), C.byref(self.st), a, b, int(n_steps))
+                    for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+            for f in futs:
+                f.result()
+        return self
+
+    # -- per-snake views ----------------------------------------------------
+    def snake(self, s: int) -> dict:
+        b0, b1 = self.body_off[s], self.body_off[s + 1]
+        j0, j1 = self.joint_off[s], self.joint_off[s + 1]
+        m0, m1 = self.module_off[s], self.module_off[s + 1]
+        return dict(x=self.x[b0:b1], q=self.q[b0:b1], v=self.v[b0:b1], w=self.w[b0:b1],
+                    p=self.p[m0:m1], cmd=self.cmd[m0:m1], lam_j=self.lam_j[j0:j1],
+                    lam_c=self.lam_c[b0:b1])
+
+    def assemble(self, s, x, q, xp, p):
+        """Dense C, J, W, comp of snake s at configuration (x, q)."""
+        B = int(self.B[s])
+        ground = 0 if (self.batch.flags & FLAG_NO_GROUND) else 1
+        rows = 6 * (B - 1) + (3 * B if ground else 0)
+        Cv = np.zeros(rows)
+        J = np.zeros((rows, 6 * B))
+        W = np.zeros((6 * B, 6 * B))
+        comp = np.zeros(rows)
+        x, q, xp, p = (np.ascontiguousarray(a, np.float64) for a in (x, q, xp, p))
+        self.L.orc_assemble(C.byref(self.batch), int(s), _ptr(x), _ptr(q), _ptr(xp), _ptr(p),
+                            _ptr(Cv), _ptr(J), _ptr(W), _ptr(comp))
+        return Cv, J, W, comp
+
+    def predict(self, s, h):
+        """Apply the prediction stage to snake s in place (returns its views)."""
+        d = self.snake(s)
+        arrs = [np.ascontiguousarray(d[k]) for k in ("x", "q", "v", "w")]
+        self.L.orc_predict_snake(C.byref(self.batch), int(s), *[_ptr(a) for a in arrs], float(h))
+        for k, a in zip(("x", "q", "v", "w"), arrs):
+            d[k][...] = a
+        return d
+
+    def index(self):
+        """Offsets, block list, degrees, greedy colours, buckets, work order."""
+        nb = int(self.block_off[-1])
+        N = int(self.body_off[-1])
+        out = dict(blk_type=np.zeros(nb, np.int32), blk_a=np.zeros(nb, np.int32),
+                   blk_b=np.zeros(nb, np.int32), blk_color=np.zeros(nb, np.int32),
+                   body_degree=np.zeros(N, np.int32), bucket=np.zeros(self.n, np.int32),
+                   order=np.zeros(self.n, np.int32))
+        self.L.orc_index(C.byref(self.batch), *[_ptr(out[k]) for k in (
+            "blk_type", "blk_a", "blk_b", "blk_color", "body_degree", "bucket", "order")])
+        out.update(body_off=self.body_off.copy(), joint_off=self.joint_off.copy(),
+                   module_off=self.module_off.copy(), block_off=self.block_off.copy())
+        return out

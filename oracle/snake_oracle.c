@@ -1,0 +1,1011 @@
+/*
+ * FP64 CPU oracle of the compliant-constraint snake solve.
+ *
+ * TEST INFRASTRUCTURE ONLY: called by the tests, the smoke check and the CPU
+ * baseline leg of the benchmark.  Shares no code with the GPU library.
+ * Plain scalar loops, double precision, no reordering beyond what each
+ * formula states, so each step can be read against the paper:
+ *
+ *   step      paper passage
+ *   --------  -----------------------------------------------------------
+ *   command   eq. snake_control (clamped sine per module)
+ *   pressure  first-order lag, or eq. delta_p_i + eq. deflation
+ *   rest      eq. expansion: strain linear in pressure -> rest curvature
+ *             linear in the chamber pressure difference
+ *   predict   section "Time-Stepping" (first-order implicit), rigid bodies
+ *             as centre + quaternion (section "Rigid Bodies")
+ *   blocks    compliant constraints c + E lambda = 0 (section "Simulator");
+ *             stretch in the form of eq. rigid_to_particle; contact
+ *             c_n >= 0 with a Coulomb cone (sections "Simulator" and
+ *             "Rigid Body Joints and Contact")
+ *   solve     block Jacobi on the system of eq. schur_system, each block
+ *             increment scaled by relax / (number of blocks on its busiest
+ *             body), applied to both lambda and the bodies
+ *   finalize  velocities from the implicit step's displacement
+ */
+#include "snake_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* small fp64 algebra                                                   */
+/* ------------------------------------------------------------------ */
+
+static void cross3(const double* a, const double* b, double* o)
+{
+    double t0 = a[1] * b[2] - a[2] * b[1];
+    double t1 = a[2] * b[0] - a[0] * b[2];
+    double t2 = a[0] * b[1] - a[1] * b[0];
+    o[0] = t0;
+    o[1] = t1;
+    o[2] = t2;
+}
+
+/* row-major 3x3 */
+static void m3_mul(const double* A, const double* B, double* O)
+{
+    double T[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += A[3 * i + k] * B[3 * k + j];
+            T[3 * i + j] = s;
+        }
+    memcpy(O, T, sizeof T);
+}
+
+static void m3_transpose(const double* A, double* O)
+{
+    double T[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) T[3 * j + i] = A[3 * i + j];
+    memcpy(O, T, sizeof T);
+}
+
+static void m3_vec(const double* A, const double* v, double* o)
+{
+    double t[3];
+    for (int i = 0; i < 3; ++i) t[i] = A[3 * i] * v[0] + A[3 * i + 1] * v[1] + A[3 * i + 2] * v[2];
+    memcpy(o, t, sizeof t);
+}
+
+/* S such that S u = v x u */
+static void skew3(const double* v, double* S)
+{
+    S[0] = 0.0;   S[1] = -v[2]; S[2] = v[1];
+    S[3] = v[2];  S[4] = 0.0;   S[5] = -v[0];
+    S[6] = -v[1]; S[7] = v[0];  S[8] = 0.0;
+}
+
+/* Hamilton product, q = (w, x, y, z) */
+static void q_mul(const double* a, const double* b, double* o)
+{
+    double w = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    double x = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    double y = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    double z = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+    o[0] = w;
+    o[1] = x;
+    o[2] = y;
+    o[3] = z;
+}
+
+static void q_conj(const double* a, double* o)
+{
+    o[0] = a[0];
+    o[1] = -a[1];
+    o[2] = -a[2];
+    o[3] = -a[3];
+}
+
+static void q_normalize(double* q)
+{
+    double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int k = 0; k < 4; ++k) q[k] /= n;
+}
+
+/* rotation matrix of a unit quaternion (body -> world) */
+static void q_to_matrix(const double* q, double* R)
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+/* q <- normalize(q + 1/2 [0, dtheta] (x) q): a world-frame rotation vector
+ * applied to a quaternion to first order, then renormalised */
+static void q_apply_rotvec(double* q, const double* dth)
+{
+    double p[4] = {0.0, dth[0], dth[1], dth[2]};
+    double t[4];
+    q_mul(p, q, t);
+    for (int k = 0; k < 4; ++k) q[k] += 0.5 * t[k];
+    q_normalize(q);
+}
+
+/* solve A x = b for a 3x3 system, Gaussian elimination, partial pivoting */
+static void solve3(const double* Ain, const double* bin, double* x)
+{
+    double A[9], b[3];
+    memcpy(A, Ain, sizeof A);
+    memcpy(b, bin, sizeof b);
+    for (int c = 0; c < 3; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(A[3 * r + c]) > fabs(A[3 * piv + c])) piv = r;
+        if (piv != c) {
+            for (int k = 0; k < 3; ++k) {
+                double t = A[3 * c + k];
+                A[3 * c + k] = A[3 * piv + k];
+                A[3 * piv + k] = t;
+            }
+            double t = b[c];
+            b[c] = b[piv];
+            b[piv] = t;
+        }
+        for (int r = c + 1; r < 3; ++r) {
+            double f = A[3 * r + c] / A[3 * c + c];
+            for (int k = c; k < 3; ++k) A[3 * r + k] -= f * A[3 * c + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = 2; r >= 0; --r) {
+        double s = b[r];
+        for (int k = r + 1; k < 3; ++k) s -= A[3 * r + k] * x[k];
+        x[r] = s / A[3 * r + r];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* per-snake context                                                    */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int B, M, S, nj, ground, fixed_root, linear;
+    double m, L, R, g, h;
+    double Ib[3];               /* principal inertia in the body frame */
+    double a_s, a_b, a_t;       /* joint compliance = per-length value * L */
+    double mu, relax;
+} snake_ctx;
+
+static void make_ctx(const orc_batch* b, int s, snake_ctx* c)
+{
+    c->M = b->n_modules[s];
+    c->S = b->segs[s];
+    c->B = c->M * c->S;
+    c->nj = c->B - 1;
+    c->ground = (b->flags & ORC_FLAG_NO_GROUND) ? 0 : 1;
+    c->fixed_root = (b->flags & ORC_FLAG_FIXED_ROOT) ? 1 : 0;
+    c->linear = (b->flags & ORC_FLAG_LINEARISED) ? 1 : 0;
+    c->m = b->mass;
+    c->L = b->length;
+    c->R = b->radius;
+    c->g = b->gravity;
+    c->h = b->dt / b->substeps;
+    /* solid cylinder of radius R and length L, axis along body e_x */
+    c->Ib[0] = 0.5 * c->m * c->R * c->R;
+    c->Ib[1] = c->m * (3.0 * c->R * c->R + c->L * c->L) / 12.0;
+    c->Ib[2] = c->Ib[1];
+    c->a_s = b->alpha_s[s] * c->L;
+    c->a_b = b->alpha_b[s] * c->L;
+    c->a_t = b->alpha_t[s] * c->L;
+    c->mu = b->mu[s];
+    c->relax = b->relax;
+}
+
+static int is_fixed(const snake_ctx* c, int i) { return c->fixed_root && i == 0; }
+
+static double inv_mass(const snake_ctx* c, int i) { return is_fixed(c, i) ? 0.0 : 1.0 / c->m; }
+
+/* world inverse inertia R diag(1/I) R^T (zero for a fixed body) */
+static void inv_inertia_world(const snake_ctx* c, int i, const double* q, double* Iinv)
+{
+    if (is_fixed(c, i)) {
+        memset(Iinv, 0, 9 * sizeof(double));
+        return;
+    }
+    double R[9], RT[9], D[9] = {0}, T[9];
+    q_to_matrix(q, R);
+    m3_transpose(R, RT);
+    for (int k = 0; k < 3; ++k) D[4 * k] = 1.0 / c->Ib[k];
+    m3_mul(R, D, T);
+    m3_mul(T, RT, Iinv);
+}
+
+static void inertia_world(const snake_ctx* c, const double* q, double* Iw)
+{
+    double R[9], RT[9], D[9] = {0}, T[9];
+    q_to_matrix(q, R);
+    m3_transpose(R, RT);
+    for (int k = 0; k < 3; ++k) D[4 * k] = c->Ib[k];
+    m3_mul(R, D, T);
+    m3_mul(T, RT, Iw);
+}
+
+/* number of blocks touching body i: two per joint on each side, one contact */
+static int body_degree(int i, int B, int ground)
+{
+    int d = ground ? 1 : 0;
+    if (i > 0) d += 2;
+    if (i < B - 1) d += 2;
+    return d;
+}
+
+/* ------------------------------------------------------------------ */
+/* constraint blocks                                                    */
+/* ------------------------------------------------------------------ */
+
+enum { BLK_STRETCH = 0, BLK_BEND = 1, BLK_CONTACT = 2 };
+
+typedef struct {
+    int type, a, b;         /* b < 0 for a contact */
+    double C[3];            /* constraint value at the current iterate */
+    double Ja[18];          /* 3x6 row-major: d C / d (x_a, theta_a) */
+    double Jb[18];          /* 3x6: d C / d (x_b, theta_b) */
+    double comp[3];         /* alpha~ = compliance / h^2 per row */
+    double scale;           /* relax / block degree */
+} block_t;
+
+/* Stretch: the end point of body a must coincide with the start point of
+ * body b.  Same form as the rigid attachment c = x + R(q) r - x_p, here with
+ * both points carried by rigid bodies: r_a = +L/2 e_x, r_b = -L/2 e_x. */
+static void eval_stretch(const snake_ctx* c, const double* xa, const double* qa, const double* xb,
+                         const double* qb, block_t* k)
+{
+    double ex[3] = {1.0, 0.0, 0.0}, Ra[9], Rb[9], ra[3], rb[3], Sa[9], Sb[9];
+    q_to_matrix(qa, Ra);
+    q_to_matrix(qb, Rb);
+    m3_vec(Ra, ex, ra);
+    m3_vec(Rb, ex, rb);
+    for (int d = 0; d < 3; ++d) {
+        ra[d] *= 0.5 * c->L;
+        rb[d] *= -0.5 * c->L;
+    }
+    for (int d = 0; d < 3; ++d) k->C[d] = (xa[d] + ra[d]) - (xb[d] + rb[d]);
+    /* a world rotation dtheta moves an attached offset r by dtheta x r = -[r]x dtheta */
+    skew3(ra, Sa);
+    skew3(rb, Sb);
+    for (int r = 0; r < 3; ++r)
+        for (int col = 0; col < 3; ++col) {
+            double id = (r == col) ? 1.0 : 0.0;
+            k->Ja[6 * r + col] = id;
+            k->Ja[6 * r + 3 + col] = -Sa[3 * r + col];
+            k->Jb[6 * r + col] = -id;
+            k->Jb[6 * r + 3 + col] = Sb[3 * r + col];
+        }
+    double a = c->a_s / (c->h * c->h);
+    k->comp[0] = k->comp[1] = k->comp[2] = a;
+}
+
+/* Bend-twist: relative rotation of body b in the frame of body a, measured
+ * against the rest rotation q0 = rotation by theta0 about the body z axis.
+ * e = conj(q0) conj(qa) qb (sign chosen so e_w >= 0), C = 2 e_xyz: rows are
+ * twist (about x), bend about y, bend about z. */
+static void eval_bend(const snake_ctx* c, const double* qa, const double* qb, double theta0,
+                      block_t* k)
+{
+    double q0[4] = {cos(0.5 * theta0), 0.0, 0.0, sin(0.5 * theta0)};
+    double q0c[4], qac[4], t[4], e[4];
+    q_conj(q0, q0c);
+    q_conj(qa, qac);
+    q_mul(q0c, qac, t);
+    q_mul(t, qb, e);
+    if (e[0] < 0.0)
+        for (int d = 0; d < 4; ++d) e[d] = -e[d];
+    for (int d = 0; d < 3; ++d) k->C[d] = 2.0 * e[1 + d];
+    /* d C = G F^T (dtheta_b - dtheta_a), G = e_w I - [e_xyz]x, F = R(qa q0) */
+    double G[9], Se[9], F[9], FT[9], A[9], qaq0[4];
+    skew3(e + 1, Se);
+    for (int d = 0; d < 9; ++d) G[d] = -Se[d];
+    G[0] += e[0];
+    G[4] += e[0];
+    G[8] += e[0];
+    q_mul(qa, q0, qaq0);
+    q_to_matrix(qaq0, F);
+    m3_transpose(F, FT);
+    m3_mul(G, FT, A);
+    for (int r = 0; r < 3; ++r)
+        for (int col = 0; col < 3; ++col) {
+            k->Ja[6 * r + col] = 0.0;
+            k->Jb[6 * r + col] = 0.0;
+            k->Ja[6 * r + 3 + col] = -A[3 * r + col];
+            k->Jb[6 * r + 3 + col] = A[3 * r + col];
+        }
+    double hh = c->h * c->h;
+    k->comp[0] = c->a_t / hh;
+    k->comp[1] = c->a_b / hh;
+    k->comp[2] = c->a_b / hh;
+}
+
+/* Contact with the ground plane z = 0 of a sphere of radius R at the body
+ * centre: C_n = z - R >= 0.  Friction rows measure the tangential slip of the
+ * centre since the start of the substep (static friction keeps it at 0). */
+static void eval_contact(const snake_ctx* c, const double* x, const double* xp, block_t* k)
+{
+    k->C[0] = x[2] - c->R;
+    k->C[1] = x[0] - xp[0];
+    k->C[2] = x[1] - xp[1];
+    memset(k->Ja, 0, sizeof k->Ja);
+    memset(k->Jb, 0, sizeof k->Jb);
+    k->Ja[0 * 6 + 2] = 1.0;
+    k->Ja[1 * 6 + 0] = 1.0;
+    k->Ja[2 * 6 + 1] = 1.0;
+    k->comp[0] = k->comp[1] = k->comp[2] = 0.0;
+}
+
+/* rest angle of joint j: intra-module joints follow their module's
+ * pressure difference, joints between modules are straight */
+static double rest_angle(const orc_batch* b, const snake_ctx* c, const double* p, int j)
+{
+    if ((j + 1) % c->S == 0) return 0.0;
+    int m = j / c->S;
+    return b->kappa_max * (p[2 * m] - p[2 * m + 1]) * c->L;
+}
+
+/* K += J W J^T for one body (J is 3x6, W = diag(w I, Iinv)) */
+static void add_jwjt(const double* J, double w, const double* Iinv, double* K)
+{
+    for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s) {
+            double acc = 0.0;
+            for (int d = 0; d < 3; ++d) acc += J[6 * r + d] * w * J[6 * s + d];
+            for (int d = 0; d < 3; ++d)
+                for (int e = 0; e < 3; ++e) acc += J[6 * r + 3 + d] * Iinv[3 * d + e] * J[6 * s + 3 + e];
+            K[3 * r + s] += acc;
+        }
+}
+
+/* (dx, dth) += (w J_x^T l, Iinv J_th^T l) */
+static void add_jt(const double* J, double w, const double* Iinv, const double* l, double* dx,
+                   double* dth)
+{
+    double jx[3], jt[3], it[3];
+    for (int d = 0; d < 3; ++d) {
+        jx[d] = J[d] * l[0] + J[6 + d] * l[1] + J[12 + d] * l[2];
+        jt[d] = J[3 + d] * l[0] + J[9 + d] * l[1] + J[15 + d] * l[2];
+    }
+    m3_vec(Iinv, jt, it);
+    for (int d = 0; d < 3; ++d) {
+        dx[d] += w * jx[d];
+        dth[d] += it[d];
+    }
+}
+
+/* Evaluate every block of the snake at configuration (x, q).
+ * Block order: (stretch_j, bend_j) for j = 0..B-2, then contact_i. */
+static void eval_blocks(const orc_batch* b, const snake_ctx* c, const double* x, const double* q,
+                        const double* xp, const double* theta0, block_t* blk)
+{
+    int n = 0;
+    for (int j = 0; j < c->nj; ++j) {
+        block_t* ks = &blk[n++];
+        block_t* kb = &blk[n++];
+        ks->type = BLK_STRETCH;
+        kb->type = BLK_BEND;
+        ks->a = kb->a = j;
+        ks->b = kb->b = j + 1;
+        eval_stretch(c, x + 3 * j, q + 4 * j, x + 3 * (j + 1), q + 4 * (j + 1), ks);
+        eval_bend(c, q + 4 * j, q + 4 * (j + 1), theta0[j], kb);
+        int d = body_degree(j, c->B, c->ground);
+        int d1 = body_degree(j + 1, c->B, c->ground);
+        ks->scale = kb->scale = c->relax / (double)(d > d1 ? d : d1);
+    }
+    if (c->ground)
+        for (int i = 0; i < c->B; ++i) {
+            block_t* k = &blk[n++];
+            k->type = BLK_CONTACT;
+            k->a = i;
+            k->b = -1;
+            eval_contact(c, x + 3 * i, xp + 3 * i, k);
+            k->scale = c->relax / (double)body_degree(i, c->B, c->ground);
+        }
+    (void)b;
+}
+
+static int n_blocks(const snake_ctx* c) { return 2 * c->nj + (c->ground ? c->B : 0); }
+
+/* lambda of block k inside the state arrays */
+static double* block_lambda(const snake_ctx* c, double* lam_j, double* lam_c, const block_t* k, int idx)
+{
+    if (k->type == BLK_CONTACT) return lam_c + 3 * k->a;
+    (void)c;
+    return lam_j + 6 * (idx / 2) + 3 * (idx % 2);
+}
+
+/* Gather the increments dl[block] onto body i in the fixed order
+ * stretch_{i-1}, bend_{i-1}, stretch_i, bend_i, contact_i. */
+static void gather_body(const snake_ctx* c, int i, const block_t* blk, const double* dl, double w,
+                        const double* Iinv, double* dx, double* dth)
+{
+    dx[0] = dx[1] = dx[2] = 0.0;
+    dth[0] = dth[1] = dth[2] = 0.0;
+    if (i > 0) {
+        int k = 2 * (i - 1);
+        add_jt(blk[k].Jb, w, Iinv, dl + 3 * k, dx, dth);
+        add_jt(blk[k + 1].Jb, w, Iinv, dl + 3 * (k + 1), dx, dth);
+    }
+    if (i < c->B - 1) {
+        int k = 2 * i;
+        add_jt(blk[k].Ja, w, Iinv, dl + 3 * k, dx, dth);
+        add_jt(blk[k + 1].Ja, w, Iinv, dl + 3 * (k + 1), dx, dth);
+    }
+    if (c->ground) {
+        int k = 2 * c->nj + i;
+        add_jt(blk[k].Ja, w, Iinv, dl + 3 * k, dx, dth);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* one substep of one snake                                             */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    block_t* blk;       /* [n_blocks] */
+    block_t* blk0;      /* [n_blocks] frozen copy (linearised mode) */
+    double* dl;         /* [n_blocks*3] applied increments */
+    double* xp;         /* [B*3] positions at the start of the substep */
+    double* qp;         /* [B*4] */
+    double* xt;         /* [B*3] predicted (after warm start) */
+    double* qt;         /* [B*4] */
+    double* acc;        /* [B*6] linearised accumulated displacement */
+    double* Iinv;       /* [B*9] */
+    double* theta0;     /* [B] */
+} scratch_t;
+
+static void scratch_alloc(scratch_t* w, const snake_ctx* c)
+{
+    int nb = n_blocks(c) + 1;
+    int B = c->B;
+    w->blk = (block_t*)calloc((size_t)nb, sizeof(block_t));
+    w->blk0 = (block_t*)calloc((size_t)nb, sizeof(block_t));
+    w->dl = (double*)calloc((size_t)nb * 3, sizeof(double));
+    w->xp = (double*)calloc((size_t)B * 3, sizeof(double));
+    w->qp = (double*)calloc((size_t)B * 4, sizeof(double));
+    w->xt = (double*)calloc((size_t)B * 3, sizeof(double));
+    w->qt = (double*)calloc((size_t)B * 4, sizeof(double));
+    w->acc = (double*)calloc((size_t)B * 6, sizeof(double));
+    w->Iinv = (double*)calloc((size_t)B * 9, sizeof(double));
+    w->theta0 = (double*)calloc((size_t)B, sizeof(double));
+}
+
+static void scratch_free(scratch_t* w)
+{
+    free(w->blk);
+    free(w->blk0);
+    free(w->dl);
+    free(w->xp);
+    free(w->qp);
+    free(w->xt);
+    free(w->qt);
+    free(w->acc);
+    free(w->Iinv);
+    free(w->theta0);
+}
+
+/* Predicted positions of a first-order implicit step: gravity on the linear
+ * velocity, gyroscopic torque -w x (I w) on the angular velocity, then a
+ * position-level step of length h. */
+static void predict(const snake_ctx* c, double* x, double* q, double* v, double* w)
+{
+    for (int i = 0; i < c->B; ++i) {
+        if (is_fixed(c, i)) {
+            v[3 * i] = v[3 * i + 1] = v[3 * i + 2] = 0.0;
+            w[3 * i] = w[3 * i + 1] = w[3 * i + 2] = 0.0;
+            continue;
+        }
+        v[3 * i + 2] -= c->h * c->g;
+        for (int d = 0; d < 3; ++d) x[3 * i + d] += c->h * v[3 * i + d];
+        double Iw[9], Iinv[9], Lw[3], tq[3], dw[3];
+        inertia_world(c, q + 4 * i, Iw);
+        inv_inertia_world(c, i, q + 4 * i, Iinv);
+        m3_vec(Iw, w + 3 * i, Lw);
+        cross3(w + 3 * i, Lw, tq);
+        for (int d = 0; d < 3; ++d) tq[d] = -tq[d];
+        m3_vec(Iinv, tq, dw);
+        for (int d = 0; d < 3; ++d) w[3 * i + d] += c->h * dw[d];
+        double dth[3] = {c->h * w[3 * i], c->h * w[3 * i + 1], c->h * w[3 * i + 2]};
+        q_apply_rotvec(q + 4 * i, dth);
+    }
+}
+
+/* Block-Jacobi solve of one substep.  Returns the number of applied
+ * iterations; *res is the residual of the final iterate. */
+static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* x, double* q,
+                         double* lam_j, double* lam_c, int warm, int kmax, double tol, double* res,
+                         int* status)
+{
+    int nb = n_blocks(c);
+    int B = c->B;
+
+    /* warm start: x <- x~ + W J(x~)^T lambda0 with lambda0 = current lambda */
+    if (warm != ORC_WARM_ZERO) {
+        eval_blocks(b, c, x, q, W->xp, W->theta0, W->blk);
+        for (int k = 0; k < nb; ++k) {
+            double* l = block_lambda(c, lam_j, lam_c, &W->blk[k], k);
+            for (int d = 0; d < 3; ++d) W->dl[3 * k + d] = l[d];
+        }
+        for (int i = 0; i < B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
+        for (int i = 0; i < B; ++i) {
+            double dx[3], dth[3];
+            gather_body(c, i, W->blk, W->dl, inv_mass(c, i), W->Iinv + 9 * i, dx, dth);
+            for (int d = 0; d < 3; ++d) x[3 * i + d] += dx[d];
+            if (!is_fixed(c, i)) q_apply_rotvec(q + 4 * i, dth);
+        }
+    } else {
+        memset(lam_j, 0, sizeof(double) * 6 * (size_t)c->nj);
+        memset(lam_c, 0, sizeof(double) * 3 * (size_t)B);
+    }
+
+    if (c->linear) {
+        memcpy(W->xt, x, sizeof(double) * 3 * (size_t)B);
+        memcpy(W->qt, q, sizeof(double) * 4 * (size_t)B);
+        memset(W->acc, 0, sizeof(double) * 6 * (size_t)B);
+        eval_blocks(b, c, x, q, W->xp, W->theta0, W->blk0);
+        for (int i = 0; i < B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
+    }
+
+    int k = 0;
+    double r = 0.0;
+    for (;; ++k) {
+        /* evaluate every block at the current iterate */
+        if (c->linear) {
+            memcpy(W->blk, W->blk0, sizeof(block_t) * (size_t)nb);
+            for (int n = 0; n < nb; ++n) {
+                block_t* kb = &W->blk[n];
+                const double* da = W->acc + 6 * kb->a;
+                for (int row = 0; row < 3; ++row) {
+                    double s = 0.0;
+                    for (int d = 0; d < 6; ++d) s += kb->Ja[6 * row + d] * da[d];
+                    if (kb->b >= 0) {
+                        const double* db = W->acc + 6 * kb->b;
+                        for (int d = 0; d < 6; ++d) s += kb->Jb[6 * row + d] * db[d];
+                    }
+                    kb->C[row] += s;
+                }
+            }
+        } else {
+            eval_blocks(b, c, x, q, W->xp, W->theta0, W->blk);
+            for (int i = 0; i < B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
+        }
+
+        /* local solves and the residual of this iterate */
+        r = 0.0;
+        for (int n = 0; n < nb; ++n) {
+            block_t* kb = &W->blk[n];
+            double* l = block_lambda(c, lam_j, lam_c, kb, n);
+            double* dl = W->dl + 3 * n;
+            if (kb->type == BLK_CONTACT) {
+                int i = kb->a;
+                double cn = kb->C[0];
+                double rc = (l[0] > 0.0) ? fabs(cn) : (cn < 0.0 ? -cn : 0.0);
+                rc /= c->L;
+                if (rc > r || rc != rc) r = rc;
+                double wi = inv_mass(c, i);
+                if (wi == 0.0) {
+                    dl[0] = dl[1] = dl[2] = 0.0;
+                    continue;
+                }
+                /* normal: projected increment; tangential: trial increment
+                 * projected onto the Coulomb disc of radius mu * lambda_n */
+                double ln = l[0] + kb->scale * (-cn / wi);
+                if (ln < 0.0) ln = 0.0;
+                double lt0 = l[1] + kb->scale * (-kb->C[1] / wi);
+                double lt1 = l[2] + kb->scale * (-kb->C[2] / wi);
+                double cap = c->mu * ln;
+                double nt = sqrt(lt0 * lt0 + lt1 * lt1);
+                if (ln <= 0.0) {
+                    lt0 = lt1 = 0.0;
+                } else if (nt > cap) {
+                    lt0 *= cap / nt;
+                    lt1 *= cap / nt;
+                }
+                dl[0] = ln - l[0];
+                dl[1] = lt0 - l[1];
+                dl[2] = lt1 - l[2];
+            } else {
+                double rhs[3], K[9] = {0}, Iinva[9], Iinvb[9], dlam[3];
+                for (int d = 0; d < 3; ++d) rhs[d] = kb->C[d] + kb->comp[d] * l[d];
+                double rb = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    double t = fabs(rhs[d]);
+                    if (t > rb || t != t) rb = t;
+                }
+                if (kb->type == BLK_STRETCH) rb /= c->L;
+                if (rb > r || rb != rb) r = rb;
+                memcpy(Iinva, W->Iinv + 9 * kb->a, sizeof Iinva);
+                memcpy(Iinvb, W->Iinv + 9 * kb->b, sizeof Iinvb);
+                add_jwjt(kb->Ja, inv_mass(c, kb->a), Iinva, K);
+                add_jwjt(kb->Jb, inv_mass(c, kb->b), Iinvb, K);
+                for (int d = 0; d < 3; ++d) K[4 * d] += kb->comp[d];
+                solve3(K, rhs, dlam);
+                for (int d = 0; d < 3; ++d) dl[d] = -kb->scale * dlam[d];
+            }
+        }
+        if (!isfinite(r)) {
+            *status |= ORC_STATUS_NONFINITE;
+            break;
+        }
+        int stop = (tol > 0.0) ? (r <= tol || k >= kmax) : (k >= kmax);
+        if (stop) {
+            if (tol > 0.0 && r > tol) *status |= ORC_STATUS_NOT_CONVERGED;
+            break;
+        }
+
+        /* apply: lambda += dl, bodies += W J^T dl in the fixed gather order */
+        for (int n = 0; n < nb; ++n) {
+            double* l = block_lambda(c, lam_j, lam_c, &W->blk[n], n);
+            for (int d = 0; d < 3; ++d) l[d] += W->dl[3 * n + d];
+        }
+        for (int i = 0; i < B; ++i) {
+            double dx[3], dth[3];
+            gather_body(c, i, W->blk, W->dl, inv_mass(c, i), W->Iinv + 9 * i, dx, dth);
+            if (c->linear) {
+                for (int d = 0; d < 3; ++d) {
+                    W->acc[6 * i + d] += dx[d];
+                    W->acc[6 * i + 3 + d] += dth[d];
+                }
+            } else {
+                for (int d = 0; d < 3; ++d) x[3 * i + d] += dx[d];
+                if (!is_fixed(c, i)) q_apply_rotvec(q + 4 * i, dth);
+            }
+        }
+    }
+
+    if (c->linear) {
+        for (int i = 0; i < B; ++i) {
+            for (int d = 0; d < 3; ++d) x[3 * i + d] = W->xt[3 * i + d] + W->acc[6 * i + d];
+            memcpy(q + 4 * i, W->qt + 4 * i, 4 * sizeof(double));
+            if (!is_fixed(c, i)) q_apply_rotvec(q + 4 * i, W->acc + 6 * i + 3);
+        }
+    }
+    *res = r;
+    return k;
+}
+
+/* velocities of the implicit step from the substep displacement */
+static void finalize(const snake_ctx* c, const double* xp, const double* qp, const double* x,
+                     const double* q, double* v, double* w)
+{
+    for (int i = 0; i < c->B; ++i) {
+        for (int d = 0; d < 3; ++d) v[3 * i + d] = (x[3 * i + d] - xp[3 * i + d]) / c->h;
+        double qpc[4], dq[4];
+        q_conj(qp + 4 * i, qpc);
+        q_mul(q + 4 * i, qpc, dq);
+        double sg = dq[0] >= 0.0 ? 1.0 : -1.0;
+        for (int d = 0; d < 3; ++d) w[3 * i + d] = 2.0 / c->h * sg * dq[1 + d];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* chamber pressure and command                                         */
+/* ------------------------------------------------------------------ */
+
+/* first-order lag toward the target over h, exact for a held target */
+static double lag_update(double p, double u, double h, double tau_inf, double tau_def)
+{
+    double tau = (u > p) ? tau_inf : tau_def;
+    return u + (p - u) * exp(-h / tau);
+}
+
+/* the paper's latency law, one application per step, pressures in psi:
+ * inflating (target above pressure): p += p_s k_i ((u - p)/p_s)^2;
+ * deflating: p -= min(k_d p, T_p), not going below the target */
+static double paper_update(const orc_batch* b, double p_frac, double u_frac)
+{
+    double p = p_frac * b->amp_psi;
+    double u = u_frac * b->amp_psi;
+    if (u > p) {
+        double dp = (u - p) / b->p_s;
+        p = p + b->p_s * dp * dp * b->k_i;
+    } else if (u < p) {
+        double cut = p * b->k_d;
+        if (cut > b->T_p) cut = b->T_p;
+        p = p - cut;
+        if (p < u) p = u;
+    }
+    return p / b->amp_psi;
+}
+
+void orc_offsets(const orc_batch* b, int64_t* body_off, int64_t* joint_off, int64_t* module_off,
+                 int64_t* block_off)
+{
+    int ground = (b->flags & ORC_FLAG_NO_GROUND) ? 0 : 1;
+    body_off[0] = joint_off[0] = module_off[0] = block_off[0] = 0;
+    for (int s = 0; s < b->n_snakes; ++s) {
+        int64_t B = (int64_t)b->n_modules[s] * b->segs[s];
+        body_off[s + 1] = body_off[s] + B;
+        joint_off[s + 1] = joint_off[s] + (B - 1);
+        module_off[s + 1] = module_off[s] + b->n_modules[s];
+        block_off[s + 1] = block_off[s] + 2 * (B - 1) + (ground ? B : 0);
+    }
+}
+
+/* serpenoid command of module m at time t:
+ * clamp(sin(2 pi f t + alpha m + phase0) + offset, -1, 1) */
+static double serpenoid(const orc_batch* b, int s, int m, double t)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    double a = sin(two_pi * b->freq[s] * t + b->ctrl_alpha * m + b->phase0[s]) + b->ctrl_offset;
+    if (a > 1.0) a = 1.0;
+    if (a < -1.0) a = -1.0;
+    return a;
+}
+
+/* piecewise-constant schedule: value of the piece that holds step n */
+static double schedule(const orc_batch* b, int64_t gm, int64_t n)
+{
+    int32_t a = b->sched_off[gm], e = b->sched_off[gm + 1];
+    int64_t start = 0;
+    for (int32_t k = a; k < e; ++k) {
+        if (n < start + b->sched_steps[k]) return b->sched_val[k];
+        start += b->sched_steps[k];
+    }
+    return e > a ? b->sched_val[e - 1] : 0.0;
+}
+
+static void offsets_of(const orc_batch* b, int s, int64_t* bo, int64_t* jo, int64_t* mo)
+{
+    int64_t B = 0, J = 0, M = 0;
+    for (int k = 0; k < s; ++k) {
+        int64_t nb = (int64_t)b->n_modules[k] * b->segs[k];
+        B += nb;
+        J += nb - 1;
+        M += b->n_modules[k];
+    }
+    *bo = B;
+    *jo = J;
+    *mo = M;
+}
+
+/* commands of the M modules of snake s (first module index mo) for its
+ * current step n: the value for the end of the step, t = (n+1) dt */
+static void snake_commands(const orc_batch* b, int s, int64_t mo, int64_t n, double* cmd)
+{
+    double t = (double)(n + 1) * b->dt;
+    for (int m = 0; m < b->n_modules[s]; ++m) {
+        if (b->controller == ORC_CTRL_SERPENOID)
+            cmd[m] = serpenoid(b, s, m, t);
+        else if (b->controller == ORC_CTRL_SCHEDULE)
+            cmd[m] = schedule(b, mo + m, n);
+    }
+}
+
+void orc_commands(const orc_batch* b, orc_state* st, int32_t s0, int32_t s1)
+{
+    int64_t bo, jo, mo;
+    offsets_of(b, s0, &bo, &jo, &mo);
+    for (int s = s0; s < s1; ++s) {
+        snake_commands(b, s, mo, st->step[s], st->cmd + mo);
+        mo += b->n_modules[s];
+    }
+}
+
+void orc_init_state(const orc_batch* b, orc_state* st)
+{
+    int64_t bo = 0, jo = 0, mo = 0;
+    for (int s = 0; s < b->n_snakes; ++s) {
+        snake_ctx c;
+        make_ctx(b, s, &c);
+        for (int i = 0; i < c.B; ++i) {
+            double* x = st->x + 3 * (bo + i);
+            double* q = st->q + 4 * (bo + i);
+            x[0] = (i + 0.5) * c.L;
+            x[1] = 0.0;
+            x[2] = c.R;
+            q[0] = 1.0;
+            q[1] = q[2] = q[3] = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                st->v[3 * (bo + i) + d] = 0.0;
+                st->w[3 * (bo + i) + d] = 0.0;
+                st->lam_c[3 * (bo + i) + d] = 0.0;
+            }
+        }
+        for (int j = 0; j < 6 * (c.B - 1); ++j) st->lam_j[6 * jo + j] = 0.0;
+        for (int m = 0; m < c.M; ++m) {
+            st->p[2 * (mo + m)] = st->p[2 * (mo + m) + 1] = 0.0;
+            st->cmd[mo + m] = 0.0;
+        }
+        st->residual[s] = 0.0;
+        st->iters[s] = 0;
+        st->status[s] = 0;
+        st->iters_total[s] = 0;
+        st->step[s] = 0;
+        bo += c.B;
+        jo += c.B - 1;
+        mo += c.M;
+    }
+}
+
+int orc_run(const orc_batch* b, orc_state* st, int32_t s0, int32_t s1, int32_t n_steps)
+{
+    int64_t bo, jo, mo;
+    offsets_of(b, s0, &bo, &jo, &mo);
+    for (int s = s0; s < s1; ++s) {
+        snake_ctx c;
+        make_ctx(b, s, &c);
+        scratch_t W;
+        scratch_alloc(&W, &c);
+        double* x = st->x + 3 * bo;
+        double* q = st->q + 4 * bo;
+        double* v = st->v + 3 * bo;
+        double* w = st->w + 3 * bo;
+        double* p = st->p + 2 * mo;
+        double* cmd = st->cmd + mo;
+        double* lj = st->lam_j + 6 * jo;
+        double* lc = st->lam_c + 3 * bo;
+        for (int n = 0; n < n_steps; ++n) {
+            snake_commands(b, s, mo, st->step[s], cmd);
+            double rmax = 0.0;
+            int it = 0, status = 0;
+            if (b->law == ORC_LAW_PAPER)
+                for (int m = 0; m < c.M; ++m) {
+                    double a = cmd[m];
+                    p[2 * m] = paper_update(b, p[2 * m], a > 0.0 ? a : 0.0);
+                    p[2 * m + 1] = paper_update(b, p[2 * m + 1], a < 0.0 ? -a : 0.0);
+                }
+            for (int sub = 0; sub < b->substeps; ++sub) {
+                if (b->law == ORC_LAW_LAG)
+                    for (int m = 0; m < c.M; ++m) {
+                        double a = cmd[m];
+                        p[2 * m] = lag_update(p[2 * m], a > 0.0 ? a : 0.0, c.h, b->tau_inf, b->tau_def);
+                        p[2 * m + 1] =
+                            lag_update(p[2 * m + 1], a < 0.0 ? -a : 0.0, c.h, b->tau_inf, b->tau_def);
+                    }
+                for (int j = 0; j < c.nj; ++j) W.theta0[j] = rest_angle(b, &c, p, j);
+                memcpy(W.xp, x, sizeof(double) * 3 * (size_t)c.B);
+                memcpy(W.qp, q, sizeof(double) * 4 * (size_t)c.B);
+                predict(&c, x, q, v, w);
+                double r;
+                it += solve_substep(b, &c, &W, x, q, lj, lc, b->warm, b->iters, b->tol, &r, &status);
+                if (r > rmax || r != r) rmax = r;
+                finalize(&c, W.xp, W.qp, x, q, v, w);
+            }
+            st->residual[s] = rmax;
+            st->iters[s] = it;
+            st->status[s] = status;
+            st->iters_total[s] += it;
+            st->step[s] += 1;
+        }
+        scratch_free(&W);
+        bo += c.B;
+        jo += c.B - 1;
+        mo += c.M;
+    }
+    return 0;
+}
+
+void orc_predict_snake(const orc_batch* b, int32_t snake, double* x, double* q, double* v, double* w,
+                       double h)
+{
+    snake_ctx c;
+    make_ctx(b, snake, &c);
+    c.h = h;
+    predict(&c, x, q, v, w);
+}
+
+int orc_assemble(const orc_batch* b, int32_t snake, const double* x, const double* q,
+                 const double* xp, const double* p, double* C, double* J, double* W, double* comp)
+{
+    snake_ctx c;
+    make_ctx(b, snake, &c);
+    int nb = n_blocks(&c);
+    int B = c.B;
+    int ncol = 6 * B;
+    block_t* blk = (block_t*)calloc((size_t)nb + 1, sizeof(block_t));
+    double* th = (double*)calloc((size_t)B, sizeof(double));
+    for (int j = 0; j < c.nj; ++j) th[j] = rest_angle(b, &c, p, j);
+    eval_blocks(b, &c, x, q, xp, th, blk);
+    int rows = 3 * nb;
+    memset(J, 0, sizeof(double) * (size_t)rows * (size_t)ncol);
+    memset(W, 0, sizeof(double) * (size_t)ncol * (size_t)ncol);
+    for (int n = 0; n < nb; ++n)
+        for (int r = 0; r < 3; ++r) {
+            int row = 3 * n + r;
+            C[row] = blk[n].C[r];
+            comp[row] = blk[n].comp[r];
+            for (int d = 0; d < 6; ++d) {
+                J[(size_t)row * ncol + 6 * blk[n].a + d] = blk[n].Ja[6 * r + d];
+                if (blk[n].b >= 0) J[(size_t)row * ncol + 6 * blk[n].b + d] = blk[n].Jb[6 * r + d];
+            }
+        }
+    for (int i = 0; i < B; ++i) {
+        double Iinv[9];
+        inv_inertia_world(&c, i, q + 4 * i, Iinv);
+        double wi = inv_mass(&c, i);
+        for (int d = 0; d < 3; ++d) {
+            W[(size_t)(6 * i + d) * ncol + 6 * i + d] = wi;
+            for (int e = 0; e < 3; ++e) W[(size_t)(6 * i + 3 + d) * ncol + 6 * i + 3 + e] = Iinv[3 * d + e];
+        }
+    }
+    free(blk);
+    free(th);
+    return rows;
+}
+
+/* ------------------------------------------------------------------ */
+/* index work                                                           */
+/* ------------------------------------------------------------------ */
+
+static const int32_t* g_sort_B;
+
+static int cmp_work(const void* pa, const void* pb)
+{
+    int32_t a = *(const int32_t*)pa, b = *(const int32_t*)pb;
+    if (g_sort_B[a] != g_sort_B[b]) return g_sort_B[a] > g_sort_B[b] ? -1 : 1;
+    return (a > b) - (a < b);
+}
+
+void orc_index(const orc_batch* b, int32_t* blk_type, int32_t* blk_a, int32_t* blk_b,
+               int32_t* blk_color, int32_t* body_degree_out, int32_t* bucket, int32_t* order)
+{
+    int ground = (b->flags & ORC_FLAG_NO_GROUND) ? 0 : 1;
+    int64_t n = 0, bo = 0;
+    int64_t nbody = 0;
+    for (int s = 0; s < b->n_snakes; ++s) nbody += (int64_t)b->n_modules[s] * b->segs[s];
+    /* colours already taken by coloured blocks on each body (at most 5) */
+    int32_t* used = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nbody * 5 + 1));
+    int32_t* nused = (int32_t*)calloc((size_t)nbody + 1, sizeof(int32_t));
+    int32_t* Bs = (int32_t*)malloc(sizeof(int32_t) * (size_t)(b->n_snakes + 1));
+    for (int s = 0; s < b->n_snakes; ++s) {
+        int B = b->n_modules[s] * b->segs[s];
+        Bs[s] = B;
+        for (int j = 0; j < B - 1; ++j)
+            for (int t = 0; t < 2; ++t) {
+                blk_type[n] = t;
+                blk_a[n] = (int32_t)(bo + j);
+                blk_b[n] = (int32_t)(bo + j + 1);
+                ++n;
+            }
+        if (ground)
+            for (int i = 0; i < B; ++i) {
+                blk_type[n] = 2;
+                blk_a[n] = (int32_t)(bo + i);
+                blk_b[n] = -1;
+                ++n;
+            }
+        for (int i = 0; i < B; ++i) body_degree_out[bo + i] = body_degree(i, B, ground);
+        int bk = 0;
+        while ((1 << bk) < B) ++bk;
+        bucket[s] = bk;
+        bo += B;
+    }
+    /* sequential greedy colouring in block-list order: the smallest colour
+     * not already taken by an earlier block that shares a body */
+    for (int64_t k = 0; k < n; ++k) {
+        int32_t bodies[2] = {blk_a[k], blk_b[k]};
+        int col = 0;
+        for (;;) {
+            int clash = 0;
+            for (int e = 0; e < 2 && !clash; ++e) {
+                if (bodies[e] < 0) continue;
+                for (int u = 0; u < nused[bodies[e]]; ++u)
+                    if (used[5 * bodies[e] + u] == col) {
+                        clash = 1;
+                        break;
+                    }
+            }
+            if (!clash) break;
+            ++col;
+        }
+        blk_color[k] = col;
+        for (int e = 0; e < 2; ++e)
+            if (bodies[e] >= 0) used[5 * bodies[e] + nused[bodies[e]]++] = col;
+    }
+    /* work order: cost (bodies) descending, snake id ascending */
+    for (int s = 0; s < b->n_snakes; ++s) order[s] = s;
+    g_sort_B = Bs;
+    qsort(order, (size_t)b->n_snakes, sizeof(int32_t), cmp_work);
+    g_sort_B = NULL;
+    free(used);
+    free(nused);
+    free(Bs);
+}
