@@ -1,0 +1,149 @@
+"""Throughput of the batched snake solver on one MI355X.
+
+One step = one dt of every snake in the batch: on-device command
+evaluation, chamber pressures, rest shape, prediction, the block-Jacobi
+solve of every substep (to residual <= 1e-4, at most 200 iterations, by
+default) and the velocity update.  The state lives in HBM between steps.
+
+Prints one JSON line: snake-steps/s (value), constraint-iterations/s, the
+dominant kernel's roofline position (measured with HIP events on the
+solver's stream) and the FP64 CPU oracle timed on a bounded sample of the
+same workload on this machine's host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "snake-steps/s & constraint-iters/s at residual≤1e-4, plain vs NN warm-start"
+# FP32 operations per body per iteration (evaluation of its joint's stretch
+# and bend-twist blocks, its contact, the increments and the gathered
+# update; a fused multiply-add counts 2), per final evaluation-only pass, and
+# per body per substep outside the iterations.  Counted from the kernel.
+FLOP_ITER = 542
+FLOP_EVAL = 336
+FLOP_SUBSTEP = 100
+PEAK_FP32 = 157.3e12       # MI355X FP32 vector, packed; 78.6e12 without packed FP32
+PEAK_HBM = 8.0e12
+STATE_BYTES = 4 * (13 + 13 + 9 + 9)   # per body: state in/out, multipliers in/out
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="uniform")
+    ap.add_argument("--snakes", type=int, default=None)
+    ap.add_argument("--fixed", action="store_true", help="fixed 20 iterations per substep")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-snakes", type=int, default=256)
+    ap.add_argument("--cpu-steps", type=int, default=6)
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, n_snakes, n_steps):
+    import oracle
+
+    sub = wl.take(np.arange(min(n_snakes, wl.n_snakes)))
+    threads = max(1, min(16, os.cpu_count() or 1))
+    o = oracle.Oracle(sub)
+    t0 = time.perf_counter()
+    o.run(n_steps, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": sub.n_snakes * n_steps / dt, "unit": "snake-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n_steps} steps of {sub.n_snakes} of the {wl.n_snakes} snakes, "
+                      f"FP64 C oracle, {dt:.1f} s wall",
+            "constraint_iters_per_s": float(np.sum((9 * sub.bodies - 6) * o.iters_total) / dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 "
+                          "(snakes are independent, see DESIGN.md for the multi-GPU split)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1904_02833_amd as snk
+    import workloads as W
+
+    wl = W.make(args.workload, n_snakes=args.snakes)
+    if args.fixed:
+        wl.tol, wl.iters = 0.0, 20
+    else:
+        wl.tol, wl.iters = 1e-4, 200
+    sim = snk.Sim(wl, use_graph=1)
+    stream = sim.stream
+    for _ in range(args.warmup):
+        sim.step(1)
+    torch.cuda.synchronize()
+    before = sim.read("iters_total")["iters_total"].copy()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    res_hist = []
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        sim.step(1)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    r = sim.read("iters_total", "residual", "status")
+    its = (r["iters_total"] - before).astype(np.float64)
+    B = wl.bodies.astype(np.float64)
+    rows = 9 * B - 6
+    secs = ms / 1e3
+    snake_steps = wl.n_snakes * args.steps / secs
+    citers = float(np.sum(rows * its)) / secs
+    flops = float(np.sum(B * (its * FLOP_ITER + args.steps * wl.substeps * (FLOP_EVAL + FLOP_SUBSTEP))))
+    per_launch_ms = ms / args.steps
+    achieved = flops / args.steps / (per_launch_ms / 1e3)
+    hbm_bytes = float(B.sum()) * STATE_BYTES
+    out = {
+        "metric": METRIC,
+        "value": snake_steps,
+        "unit": "snake-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": per_launch_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.n_snakes} snakes, {int(B.sum())} bodies, "
+                               f"{wl.substeps} substeps, "
+                               + ("20 iterations" if args.fixed else "residual<=1e-4, max 200 iterations")
+                               + ", plain (zero warm start)",
+                   "snakes": wl.n_snakes, "bodies": int(B.sum()), "substeps": wl.substeps,
+                   "tol": wl.tol, "max_iters": wl.iters},
+        "constraint_iters_per_s": citers,
+        "mean_iters_per_substep": float(its.sum() / (wl.n_snakes * args.steps * wl.substeps)),
+        "not_converged_snakes_last_step": int(np.sum(r["status"] & 2 != 0)),
+        "residual_last_step": {"median": float(np.median(r["residual"])),
+                               "p99": float(np.percentile(r["residual"], 99)),
+                               "max": float(np.max(r["residual"]))},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "kernel": "k_step<64>", "flop_per_body_iter": FLOP_ITER,
+                     "hbm_frac_algorithmic": hbm_bytes / (per_launch_ms / 1e3) / PEAK_HBM},
+    }
+    sim.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_snakes, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

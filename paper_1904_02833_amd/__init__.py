@@ -1,0 +1,255 @@
+"""Python binding of the MI355X snake solver (``libsnake.so``).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  PyTorch provides the device workspace and the stream.  The
+library must have been built (``paper_1904_02833_amd.build.build()``);
+loading fails loudly otherwise, there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsnake.so")
+
+SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE = 0, -1, -2, -3, -4
+MEM_HOST, MEM_DEVICE = 0, 1
+LAW_LAG, LAW_PAPER = 0, 1
+CTRL_EXTERNAL, CTRL_SERPENOID, CTRL_SCHEDULE = 0, 1, 2
+WARM_ZERO, WARM_PREV = 0, 1
+FLAG_FIXED_ROOT, FLAG_NO_GROUND = 1, 2
+STATUS_NONFINITE, STATUS_NOT_CONVERGED = 1, 2
+
+# state fields: bit -> (name, dtype, rows, length key)
+FIELDS = [
+    ("pos", np.float32, 3, "N"),
+    ("quat", np.float32, 4, "N"),
+    ("vel", np.float32, 3, "N"),
+    ("angvel", np.float32, 3, "N"),
+    ("pressure", np.float32, 2, "Mt"),
+    ("lambda_joint", np.float32, 6, "J"),
+    ("lambda_contact", np.float32, 3, "N"),
+    ("cmd", np.float32, 1, "Mt"),
+    ("residual", np.float32, 1, "n"),
+    ("iters", np.int32, 1, "n"),
+    ("status", np.int32, 1, "n"),
+    ("step", np.int64, 1, "n"),
+    ("iters_total", np.int64, 1, "n"),
+]
+FIELD_BIT = {f[0]: 1 << k for k, f in enumerate(FIELDS)}
+INDEX = ["body_off", "joint_off", "module_off", "block_off", "blk_type", "blk_a", "blk_b",
+         "blk_color", "degree", "bucket", "order"]
+EXPORTS = ["sim_workspace_bytes", "sim_create", "sim_set_pressures", "sim_step",
+           "sim_read_state", "sim_write_state", "sim_read_index", "sim_sizes", "sim_destroy",
+           "sim_last_error"]
+
+_P = C.c_void_p
+
+
+class Desc(C.Structure):
+    _fields_ = [
+        ("n_snakes", C.c_int32),
+        ("n_modules", _P), ("segs_per_module", _P),
+        ("alpha_stretch", _P), ("alpha_bend", _P), ("alpha_twist", _P), ("mu", _P),
+        ("seg_mass", C.c_double), ("seg_length", C.c_double), ("seg_radius", C.c_double),
+        ("gravity", C.c_double),
+        ("dt", C.c_double), ("substeps", C.c_int32), ("iters", C.c_int32),
+        ("tol", C.c_double), ("relax", C.c_double),
+        ("pressure_law", C.c_int32),
+        ("tau_inflate", C.c_double), ("tau_deflate", C.c_double), ("kappa_max", C.c_double),
+        ("k_inflate", C.c_double), ("k_deflate", C.c_double), ("T_p", C.c_double),
+        ("p_source", C.c_double), ("amplitude_psi", C.c_double),
+        ("controller", C.c_int32),
+        ("ctrl_freq", _P), ("ctrl_phase0", _P),
+        ("ctrl_alpha", C.c_double), ("ctrl_offset", C.c_double),
+        ("sched_off", _P), ("sched_steps", _P), ("sched_val", _P),
+        ("warm_start", C.c_int32), ("flags", C.c_uint32), ("use_graph", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsnake.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1904_02833_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        L.sim_workspace_bytes.argtypes = [C.POINTER(Desc), C.POINTER(C.c_size_t)]
+        L.sim_create.argtypes = [C.POINTER(Desc), _P, C.c_size_t, _P, C.POINTER(_P)]
+        L.sim_set_pressures.argtypes = [_P, _P, C.c_int64, C.c_int]
+        L.sim_step.argtypes = [_P, C.c_int32]
+        L.sim_read_state.argtypes = [_P, C.c_uint32, C.POINTER(_P), C.c_int]
+        L.sim_write_state.argtypes = [_P, C.c_uint32, C.POINTER(_P), C.c_int]
+        L.sim_read_index.argtypes = [_P, C.c_int32, _P, C.c_int64]
+        L.sim_sizes.argtypes = [_P, C.POINTER(C.c_int64)]
+        L.sim_destroy.argtypes = [_P]
+        L.sim_destroy.restype = None
+        L.sim_last_error.argtypes = []
+        L.sim_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+class SimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != SIM_OK:
+        raise SimError(rc, lib().sim_last_error().decode())
+
+
+def _arr(keep, a, dt):
+    a = np.ascontiguousarray(np.asarray(a, dtype=dt))
+    keep.append(a)
+    return a.ctypes.data_as(_P)
+
+
+def make_desc(wl, **over):
+    """sim_desc_t from a workload (any object with the workload fields);
+    keyword overrides replace fields.  Returns (desc, keep-alive list)."""
+    g = lambda k: over.get(k, getattr(wl, k))  # noqa: E731
+    keep = []
+    d = Desc()
+    d.n_snakes = int(len(g("n_modules")))
+    d.n_modules = _arr(keep, g("n_modules"), np.int32)
+    d.segs_per_module = _arr(keep, g("segs_per_module"), np.int32)
+    d.alpha_stretch = _arr(keep, g("alpha_stretch"), np.float64)
+    d.alpha_bend = _arr(keep, g("alpha_bend"), np.float64)
+    d.alpha_twist = _arr(keep, g("alpha_twist"), np.float64)
+    d.mu = _arr(keep, g("mu"), np.float64)
+    for f in ("seg_mass", "seg_length", "seg_radius", "gravity", "dt", "tol", "relax",
+              "tau_inflate", "tau_deflate", "kappa_max", "k_inflate", "k_deflate", "T_p",
+              "p_source", "amplitude_psi", "ctrl_alpha", "ctrl_offset"):
+        setattr(d, f, float(g(f)))
+    d.substeps = int(g("substeps"))
+    d.iters = int(g("iters"))
+    d.pressure_law = int(g("pressure_law"))
+    d.controller = int(g("controller"))
+    d.ctrl_freq = _arr(keep, g("ctrl_freq"), np.float64)
+    d.ctrl_phase0 = _arr(keep, g("ctrl_phase0"), np.float64)
+    if g("sched_off") is not None:
+        d.sched_off = _arr(keep, g("sched_off"), np.int32)
+        d.sched_steps = _arr(keep, g("sched_steps"), np.int32)
+        d.sched_val = _arr(keep, g("sched_val"), np.float64)
+    d.warm_start = int(over.get("warm_start", WARM_ZERO))
+    d.flags = int(g("flags"))
+    d.use_graph = int(over.get("use_graph", 1))
+    return d, keep
+
+
+def workspace_bytes(wl, **over) -> int:
+    d, _keep = make_desc(wl, **over)
+    n = C.c_size_t(0)
+    _check(lib().sim_workspace_bytes(C.byref(d), C.byref(n)))
+    return int(n.value)
+
+
+class Sim:
+    """One batched solver on a GPU.  ``wl`` is a workload; keyword
+    overrides replace its fields (``warm_start``, ``use_graph`` too)."""
+
+    def __init__(self, wl, device="cuda", stream=None, **over):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the snake solver needs a ROCm GPU; none is visible")
+        self.L = lib()
+        self.torch = torch
+        self.device = torch.device(device)
+        d, keep = make_desc(wl, **over)
+        n = C.c_size_t(0)
+        _check(self.L.sim_workspace_bytes(C.byref(d), C.byref(n)))
+        self.ws_bytes = int(n.value)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = (self.ws.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _P()
+        _check(self.L.sim_create(C.byref(d), _P(base), self.ws_bytes, _P(self.stream.cuda_stream),
+                                 C.byref(h)))
+        self.h = h
+        sz = (C.c_int64 * 5)()
+        _check(self.L.sim_sizes(self.h, sz))
+        self.n, self.N, self.J, self.Mt, self.n_blocks = (int(v) for v in sz)
+        self._len = dict(n=self.n, N=self.N, J=self.J, Mt=self.Mt)
+        del keep
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.L.sim_destroy(h)
+            self.h = None
+
+    # -- calls -------------------------------------------------------------
+    def step(self, n_steps: int = 1):
+        _check(self.L.sim_step(self.h, int(n_steps)))
+
+    def set_pressures(self, cmd):
+        """Commands, one per module: numpy (host) or a device tensor."""
+        if hasattr(cmd, "is_cuda") and cmd.is_cuda:
+            t = cmd.to(self.torch.float32).contiguous()
+            _check(self.L.sim_set_pressures(self.h, _P(t.data_ptr()), t.numel(), MEM_DEVICE))
+            self._cmd_keep = t
+        else:
+            a = np.ascontiguousarray(np.asarray(cmd, np.float32))
+            _check(self.L.sim_set_pressures(self.h, a.ctypes.data_as(_P), a.size, MEM_HOST))
+
+    def _shape(self, k):
+        name, dt, rows, key = FIELDS[k]
+        ln = self._len[key]
+        return (rows, ln) if rows > 1 else (ln,)
+
+    def read(self, *names) -> dict:
+        """Host copies of the named fields (all if none), SoA as stored."""
+        names = names or tuple(f[0] for f in FIELDS)
+        ptrs = (_P * len(FIELDS))()
+        out, mask = {}, 0
+        for name in names:
+            k = [f[0] for f in FIELDS].index(name)
+            a = np.empty(self._shape(k), FIELDS[k][1])
+            out[name] = a
+            ptrs[k] = a.ctypes.data_as(_P)
+            mask |= 1 << k
+        _check(self.L.sim_read_state(self.h, mask, ptrs, MEM_HOST))
+        return out
+
+    def write(self, **fields):
+        ptrs = (_P * len(FIELDS))()
+        keep, mask = [], 0
+        for name, val in fields.items():
+            k = [f[0] for f in FIELDS].index(name)
+            a = np.ascontiguousarray(np.asarray(val, FIELDS[k][1]).reshape(self._shape(k)))
+            keep.append(a)
+            ptrs[k] = a.ctypes.data_as(_P)
+            mask |= 1 << k
+        _check(self.L.sim_write_state(self.h, mask, ptrs, MEM_HOST))
+
+    def read_device(self, names, tensors):
+        """Device-to-device copies into torch tensors (same layouts)."""
+        ptrs = (_P * len(FIELDS))()
+        mask = 0
+        for name, t in zip(names, tensors):
+            k = [f[0] for f in FIELDS].index(name)
+            ptrs[k] = _P(t.data_ptr())
+            mask |= 1 << k
+        _check(self.L.sim_read_state(self.h, mask, ptrs, MEM_DEVICE))
+
+    def index(self, name) -> np.ndarray:
+        k = INDEX.index(name)
+        ln = {"body_off": self.n + 1, "joint_off": self.n + 1, "module_off": self.n + 1,
+              "block_off": self.n + 1, "degree": self.N, "bucket": self.n,
+              "order": self.n}.get(name, self.n_blocks)
+        a = np.empty(ln, np.int32)
+        _check(self.L.sim_read_index(self.h, k, a.ctypes.data_as(_P), ln))
+        return a

@@ -1,0 +1,530 @@
+// Host runtime behind the C ABI in include/snake.h: descriptor validation,
+// workspace layout, parameter upload, tile packing, graph capture and the
+// state/index copies.  All device work is in step.hip and index.hip.
+#include "snake.h"
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace snake;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(SIM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct Sizes {
+    int64_t n = 0, N = 0, J = 0, Mt = 0, blocks = 0, pieces = 0;
+    int max_B = 0;
+};
+
+// Carves 256-byte aligned sub-arrays out of the workspace (base == nullptr
+// only measures).
+struct Carver {
+    char* base;
+    size_t pos = 0;
+    template <class T>
+    T* take(int64_t count)
+    {
+        pos = (pos + 255) & ~(size_t)255;
+        T* p = base ? reinterpret_cast<T*>(base + pos) : nullptr;
+        pos += (size_t)(count > 0 ? count : 1) * sizeof(T);
+        return p;
+    }
+};
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int validate(const sim_desc_t* d, Sizes* z)
+{
+    if (!d) return fail(SIM_EINVAL, "descriptor is NULL");
+    if (d->n_snakes < 1) return fail(SIM_EINVAL, "n_snakes must be >= 1");
+    if (!d->n_modules || !d->segs_per_module || !d->alpha_stretch || !d->alpha_bend ||
+        !d->alpha_twist || !d->mu)
+        return fail(SIM_EINVAL, "per-snake array is NULL");
+    if (!finite_pos(d->seg_mass) || !finite_pos(d->seg_length) || !finite_pos(d->seg_radius))
+        return fail(SIM_EINVAL, "segment mass, length and radius must be finite and > 0");
+    if (!std::isfinite(d->gravity)) return fail(SIM_EINVAL, "gravity must be finite");
+    if (!finite_pos(d->dt)) return fail(SIM_EINVAL, "dt must be finite and > 0");
+    if (d->substeps < 1) return fail(SIM_EINVAL, "substeps must be >= 1");
+    if (d->iters < 0 || d->iters > 1000000) return fail(SIM_EINVAL, "iters must be in [0, 1e6]");
+    if (!std::isfinite(d->tol)) return fail(SIM_EINVAL, "tol must be finite");
+    if (!(d->relax > 0.0 && d->relax <= 1.0)) return fail(SIM_EINVAL, "relax must be in (0, 1]");
+    if (d->pressure_law != SIM_LAW_LAG && d->pressure_law != SIM_LAW_PAPER)
+        return fail(SIM_EINVAL, "unknown pressure law");
+    if (d->pressure_law == SIM_LAW_LAG && (!finite_pos(d->tau_inflate) || !finite_pos(d->tau_deflate)))
+        return fail(SIM_EINVAL, "tau_inflate and tau_deflate must be > 0");
+    if (d->pressure_law == SIM_LAW_PAPER &&
+        (!finite_pos(d->p_source) || !finite_pos(d->amplitude_psi) || !(d->k_inflate > 0.0) ||
+         !(d->k_deflate > 0.0) || !(d->T_p >= 0.0)))
+        return fail(SIM_EINVAL, "paper pressure-law constants out of range");
+    if (!std::isfinite(d->kappa_max)) return fail(SIM_EINVAL, "kappa_max must be finite");
+    if (d->warm_start != SIM_WARM_ZERO && d->warm_start != SIM_WARM_PREV)
+        return fail(SIM_EINVAL, "unknown warm start");
+    if (d->flags & ~(SIM_FLAG_FIXED_ROOT | SIM_FLAG_NO_GROUND)) return fail(SIM_EINVAL, "unknown flag bits");
+    if (d->controller < SIM_CTRL_EXTERNAL || d->controller > SIM_CTRL_SCHEDULE)
+        return fail(SIM_EINVAL, "unknown controller");
+    const bool ground = !(d->flags & SIM_FLAG_NO_GROUND);
+    z->n = d->n_snakes;
+    for (int s = 0; s < d->n_snakes; ++s) {
+        const int M = d->n_modules[s], S = d->segs_per_module[s];
+        if (M < 1 || S < 1) return fail(SIM_EINVAL, "n_modules and segs_per_module must be >= 1");
+        const int64_t B = (int64_t)M * S;
+        if (B > 64) return fail(SIM_EINVAL, "snakes longer than 64 bodies are not supported yet");
+        const double a[4] = {d->alpha_stretch[s], d->alpha_bend[s], d->alpha_twist[s], d->mu[s]};
+        for (double v : a)
+            if (!std::isfinite(v) || v < 0.0) return fail(SIM_EINVAL, "compliance and mu must be finite and >= 0");
+        z->N += B;
+        z->J += B - 1;
+        z->Mt += M;
+        z->blocks += 2 * (B - 1) + (ground ? B : 0);
+        if (B > z->max_B) z->max_B = (int)B;
+    }
+    if (z->N > (int64_t)1 << 28) return fail(SIM_EINVAL, "too many bodies (limit 2^28)");
+    if (d->controller == SIM_CTRL_SERPENOID && (!d->ctrl_freq || !d->ctrl_phase0))
+        return fail(SIM_EINVAL, "serpenoid controller needs ctrl_freq and ctrl_phase0");
+    if (d->controller == SIM_CTRL_SCHEDULE) {
+        if (!d->sched_off || !d->sched_steps || !d->sched_val)
+            return fail(SIM_EINVAL, "schedule controller needs sched_off, sched_steps, sched_val");
+        if (d->sched_off[0] != 0) return fail(SIM_EINVAL, "sched_off[0] must be 0");
+        for (int64_t m = 0; m < z->Mt; ++m) {
+            if (d->sched_off[m + 1] <= d->sched_off[m]) return fail(SIM_EINVAL, "every module needs >= 1 piece");
+            int64_t len = 0;
+            for (int k = d->sched_off[m]; k < d->sched_off[m + 1]; ++k) {
+                if (d->sched_steps[k] < 1) return fail(SIM_EINVAL, "piece lengths must be >= 1");
+                if (!std::isfinite(d->sched_val[k])) return fail(SIM_EINVAL, "piece value not finite");
+                len += d->sched_steps[k];
+            }
+            if (len > INT32_MAX) return fail(SIM_EINVAL, "schedule too long");
+        }
+        z->pieces = d->sched_off[z->Mt];
+    }
+    return SIM_OK;
+}
+
+struct Views {
+    KParams kp;
+    IParams ip;
+    int* tiles;
+    int* Bn;
+    int* Mn;
+    int* Sn;
+    float* comp;
+    float* mu;
+    double* freq;
+    double* phase0;
+    int* sched_off;
+    int* sched_start;
+    float* sched_val;
+};
+
+size_t carve(const Sizes& z, char* base, Views* v)
+{
+    Carver c{base};
+    const int64_t n = z.n, N = z.N, J = z.J, Mt = z.Mt;
+    KParams& k = v->kp;
+    IParams& ip = v->ip;
+    k.x = c.take<float>(3 * N);
+    k.q = c.take<float>(4 * N);
+    k.v = c.take<float>(3 * N);
+    k.w = c.take<float>(3 * N);
+    k.p = c.take<float>(2 * Mt);
+    k.cmd = c.take<float>(Mt);
+    k.lam_j = c.take<float>(6 * J);
+    k.lam_c = c.take<float>(3 * N);
+    k.residual = c.take<float>(n);
+    k.iters_out = c.take<int>(n);
+    k.status = c.take<int>(n);
+    k.step = c.take<long long>(n);
+    k.iters_total = c.take<long long>(n);
+    v->Bn = c.take<int>(n);
+    v->Mn = c.take<int>(n);
+    v->Sn = c.take<int>(n);
+    v->comp = c.take<float>(3 * n);
+    v->mu = c.take<float>(n);
+    v->freq = c.take<double>(n);
+    v->phase0 = c.take<double>(n);
+    v->sched_off = c.take<int>(Mt + 1);
+    v->sched_start = c.take<int>(z.pieces);
+    v->sched_val = c.take<float>(z.pieces);
+    ip.body_off = c.take<int>(n + 1);
+    ip.joint_off = c.take<int>(n + 1);
+    ip.module_off = c.take<int>(n + 1);
+    ip.block_off = c.take<int>(n + 1);
+    ip.blk_type = c.take<int>(z.blocks);
+    ip.blk_a = c.take<int>(z.blocks);
+    ip.blk_b = c.take<int>(z.blocks);
+    ip.blk_color = c.take<int>(z.blocks);
+    ip.degree = c.take<int>(N);
+    ip.bucket = c.take<int>(n);
+    ip.order = c.take<int>(n);
+    ip.color_scratch = c.take<int>(N);
+    v->tiles = c.take<int>(n * 4 + 64);
+    return c.pos + 256;
+}
+
+int seg_class(int B) { return B <= 16 ? 16 : (B <= 32 ? 32 : 64); }
+
+}  // namespace
+
+struct sim {
+    Sizes z;
+    Views v;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    struct Group {
+        int seg;
+        const int* tiles;
+        int n_tiles;
+    };
+    std::vector<Group> groups;
+    bool use_graph = false;
+    std::map<int, hipGraphExec_t> graphs;
+    std::vector<int> order_host;
+};
+
+extern "C" {
+
+const char* sim_last_error(void) { return g_err.c_str(); }
+
+int sim_workspace_bytes(const sim_desc_t* d, size_t* bytes)
+{
+    if (!bytes) return fail(SIM_EINVAL, "bytes is NULL");
+    Sizes z;
+    int rc = validate(d, &z);
+    if (rc) return rc;
+    Views v;
+    *bytes = carve(z, nullptr, &v);
+    return SIM_OK;
+}
+
+int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_stream, sim_t** out)
+{
+    if (!out) return fail(SIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    Sizes z;
+    int rc = validate(d, &z);
+    if (rc) return rc;
+    if (!workspace) return fail(SIM_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(SIM_EINVAL, "workspace must be 256-byte aligned");
+    Views v;
+    const size_t need = carve(z, nullptr, &v);
+    if (bytes < need)
+        return fail(SIM_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes, got " +
+                                    std::to_string(bytes));
+    sim* s = new sim();
+    s->z = z;
+    s->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    carve(z, reinterpret_cast<char*>(workspace), &s->v);
+    Views& w = s->v;
+    const int n = (int)z.n;
+    const bool ground = !(d->flags & SIM_FLAG_NO_GROUND);
+    const double h = d->dt / d->substeps;
+
+    // host copies of the per-snake parameters
+    std::vector<int> Bn(n), Mn(n), Sn(n);
+    std::vector<float> comp(3 * (size_t)n), mu(n);
+    std::vector<double> freq(n, 0.0), ph(n, 0.0);
+    for (int k = 0; k < n; ++k) {
+        Mn[k] = d->n_modules[k];
+        Sn[k] = d->segs_per_module[k];
+        Bn[k] = Mn[k] * Sn[k];
+        comp[k] = (float)(d->alpha_stretch[k] * d->seg_length / (h * h));
+        comp[n + k] = (float)(d->alpha_bend[k] * d->seg_length / (h * h));
+        comp[2 * (size_t)n + k] = (float)(d->alpha_twist[k] * d->seg_length / (h * h));
+        mu[k] = (float)d->mu[k];
+        if (d->controller == SIM_CTRL_SERPENOID) {
+            freq[k] = d->ctrl_freq[k];
+            ph[k] = d->ctrl_phase0[k];
+        }
+    }
+    std::vector<int> soff(z.Mt + 1, 0), sstart(z.pieces > 0 ? z.pieces : 1, 0);
+    std::vector<float> sval(z.pieces > 0 ? z.pieces : 1, 0.f);
+    if (d->controller == SIM_CTRL_SCHEDULE) {
+        for (int64_t m = 0; m <= z.Mt; ++m) soff[m] = d->sched_off[m];
+        for (int64_t m = 0; m < z.Mt; ++m) {
+            int start = 0;
+            for (int k = soff[m]; k < soff[m + 1]; ++k) {
+                sstart[k] = start;
+                sval[k] = (float)d->sched_val[k];
+                start += d->sched_steps[k];
+            }
+        }
+    }
+
+    KParams& k = w.kp;
+    k.n_snakes = n;
+    k.N = (int)z.N;
+    k.J = (int)z.J;
+    k.Mt = (int)z.Mt;
+    k.Bn = w.Bn;
+    k.Mn = w.Mn;
+    k.Sn = w.Sn;
+    k.body_off = w.ip.body_off;
+    k.module_off = w.ip.module_off;
+    k.comp = w.comp;
+    k.mu = w.mu;
+    k.freq = w.freq;
+    k.phase0 = w.phase0;
+    k.sched_off = w.sched_off;
+    k.sched_start = w.sched_start;
+    k.sched_val = w.sched_val;
+    const double m = d->seg_mass, L = d->seg_length, R = d->seg_radius;
+    const double I_ax = 0.5 * m * R * R, I_pe = m * (3.0 * R * R + L * L) / 12.0;
+    k.h = (float)h;
+    k.inv_h = (float)(1.0 / h);
+    k.inv_m = (float)(1.0 / m);
+    k.L = (float)L;
+    k.half_L = (float)(0.5 * L);
+    k.inv_L = (float)(1.0 / L);
+    k.R = (float)R;
+    k.g = (float)d->gravity;
+    k.c1 = (float)(1.0 / I_pe);
+    k.c2 = (float)(1.0 / I_ax - 1.0 / I_pe);
+    k.I_ax = (float)I_ax;
+    k.I_pe = (float)I_pe;
+    k.tol = (float)d->tol;
+    k.relax = (float)d->relax;
+    k.iters = d->iters;
+    k.substeps = d->substeps;
+    k.lag_in = d->pressure_law == SIM_LAW_LAG ? (float)std::exp(-h / d->tau_inflate) : 0.f;
+    k.lag_de = d->pressure_law == SIM_LAW_LAG ? (float)std::exp(-h / d->tau_deflate) : 0.f;
+    k.law = d->pressure_law;
+    k.k_i = (float)d->k_inflate;
+    k.k_d = (float)d->k_deflate;
+    k.T_p = (float)d->T_p;
+    k.p_s = (float)d->p_source;
+    k.amp = (float)(d->pressure_law == SIM_LAW_PAPER ? d->amplitude_psi : 1.0);
+    k.kappa_max = (float)d->kappa_max;
+    k.controller = d->controller;
+    k.dt = d->dt;
+    k.ctrl_alpha = d->ctrl_alpha;
+    k.ctrl_offset = d->ctrl_offset;
+    k.flags = (int)d->flags;
+    k.warm = d->warm_start;
+
+    IParams& ip = w.ip;
+    ip.n_snakes = n;
+    ip.N = (int)z.N;
+    ip.n_blocks = (int)z.blocks;
+    ip.ground = ground ? 1 : 0;
+    ip.Bn = w.Bn;
+    ip.Mn = w.Mn;
+
+    hipError_t e;
+    hipStream_t st = s->stream;
+#define CK(expr, what)                      \
+    do {                                    \
+        e = (expr);                         \
+        if (e != hipSuccess) {              \
+            rc = hip_fail(e, what);         \
+            goto error;                     \
+        }                                   \
+    } while (0)
+    CK(hipMemcpyAsync(w.Bn, Bn.data(), n * sizeof(int), hipMemcpyHostToDevice, st), "upload B");
+    CK(hipMemcpyAsync(w.Mn, Mn.data(), n * sizeof(int), hipMemcpyHostToDevice, st), "upload M");
+    CK(hipMemcpyAsync(w.Sn, Sn.data(), n * sizeof(int), hipMemcpyHostToDevice, st), "upload S");
+    CK(hipMemcpyAsync(w.comp, comp.data(), comp.size() * sizeof(float), hipMemcpyHostToDevice, st), "upload compliance");
+    CK(hipMemcpyAsync(w.mu, mu.data(), n * sizeof(float), hipMemcpyHostToDevice, st), "upload mu");
+    CK(hipMemcpyAsync(w.freq, freq.data(), n * sizeof(double), hipMemcpyHostToDevice, st), "upload freq");
+    CK(hipMemcpyAsync(w.phase0, ph.data(), n * sizeof(double), hipMemcpyHostToDevice, st), "upload phase");
+    CK(hipMemcpyAsync(w.sched_off, soff.data(), soff.size() * sizeof(int), hipMemcpyHostToDevice, st), "upload schedule");
+    CK(hipMemcpyAsync(w.sched_start, sstart.data(), sstart.size() * sizeof(int), hipMemcpyHostToDevice, st), "upload schedule");
+    CK(hipMemcpyAsync(w.sched_val, sval.data(), sval.size() * sizeof(float), hipMemcpyHostToDevice, st), "upload schedule");
+    CK(launch_index(ip, st), "index kernels");
+    CK(hipStreamSynchronize(st), "index work");
+    {
+        // tiles: snakes in work order, packed 64/seg per wave per size class
+        std::vector<int> order(n);
+        CK(hipMemcpy(order.data(), ip.order, n * sizeof(int), hipMemcpyDeviceToHost), "read order");
+        s->order_host = order;
+        std::vector<int> tiles;
+        for (int seg : {64, 32, 16}) {
+            const int per = 64 / seg;
+            std::vector<int> cls;
+            for (int o : order)
+                if (seg_class(Bn[o]) == seg) cls.push_back(o);
+            if (cls.empty()) continue;
+            const int nt = (int)((cls.size() + per - 1) / per);
+            const size_t first = tiles.size();
+            for (int t = 0; t < nt * per; ++t) tiles.push_back(t < (int)cls.size() ? cls[t] : -1);
+            s->groups.push_back({seg, w.tiles + first, nt});
+        }
+        CK(hipMemcpy(w.tiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice), "upload tiles");
+    }
+    CK(launch_init_state(k, st), "init state");
+    CK(hipStreamSynchronize(st), "create");
+    s->use_graph = d->use_graph != 0;
+    if (s->use_graph) CK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking), "capture stream");
+#undef CK
+    *out = s;
+    return SIM_OK;
+error:
+    delete s;
+    return rc;
+}
+
+static int launch_steps(sim* s, hipStream_t st, int n_steps)
+{
+    for (const auto& g : s->groups) {
+        hipError_t e = launch_step(g.seg, s->v.kp, g.tiles, g.n_tiles, n_steps, st);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+    }
+    return SIM_OK;
+}
+
+int sim_step(sim_t* s, int32_t n_steps)
+{
+    if (!s) return fail(SIM_EINVAL, "sim is NULL");
+    if (n_steps < 0) return fail(SIM_EINVAL, "n_steps must be >= 0");
+    if (n_steps == 0) return SIM_OK;
+    if (!s->use_graph) {
+        for (int k = 0; k < n_steps; ++k) {
+            int rc = launch_steps(s, s->stream, 1);
+            if (rc) return rc;
+        }
+        return SIM_OK;
+    }
+    auto it = s->graphs.find(n_steps);
+    if (it == s->graphs.end()) {
+        hipGraph_t graph;
+        hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "begin capture");
+        int rc = SIM_OK;
+        for (int k = 0; k < n_steps && rc == SIM_OK; ++k) rc = launch_steps(s, s->cap_stream, 1);
+        e = hipStreamEndCapture(s->cap_stream, &graph);
+        if (rc) return rc;
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        hipGraphExec_t exec;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "instantiate graph");
+        it = s->graphs.emplace(n_steps, exec).first;
+    }
+    hipError_t e = hipGraphLaunch(it->second, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return SIM_OK;
+}
+
+int sim_set_pressures(sim_t* s, const float* cmd, int64_t n, int mem)
+{
+    if (!s || !cmd) return fail(SIM_EINVAL, "sim or cmd is NULL");
+    if (n != s->z.Mt) return fail(SIM_EINVAL, "expected one command per module (" + std::to_string(s->z.Mt) + ")");
+    hipError_t e;
+    if (mem == SIM_MEM_HOST) {
+        std::vector<float> c(cmd, cmd + n);
+        for (auto& a : c) {
+            if (std::isnan(a)) return fail(SIM_EINVAL, "command is NaN");
+            a = std::fmin(1.f, std::fmax(-1.f, a));
+        }
+        e = hipMemcpyAsync(s->v.kp.cmd, c.data(), n * sizeof(float), hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    } else if (mem == SIM_MEM_DEVICE) {
+        e = launch_set_cmd(s->v.kp.cmd, cmd, (int)n, s->stream);
+    } else {
+        return fail(SIM_EINVAL, "unknown memory kind");
+    }
+    if (e != hipSuccess) return hip_fail(e, "set pressures");
+    return SIM_OK;
+}
+
+static void field_table(sim* s, void* ptr[SIM_F_COUNT], size_t bytes[SIM_F_COUNT])
+{
+    const KParams& k = s->v.kp;
+    const size_t N = s->z.N, J = s->z.J, Mt = s->z.Mt, n = s->z.n;
+    void* p[SIM_F_COUNT] = {k.x, k.q, k.v, k.w, k.p, k.lam_j, k.lam_c, k.cmd, k.residual,
+                            k.iters_out, k.status, k.step, k.iters_total};
+    size_t b[SIM_F_COUNT] = {3 * N * 4, 4 * N * 4, 3 * N * 4, 3 * N * 4, 2 * Mt * 4, 6 * J * 4,
+                             3 * N * 4, Mt * 4, n * 4, n * 4, n * 4, n * 8, n * 8};
+    for (int f = 0; f < SIM_F_COUNT; ++f) {
+        ptr[f] = p[f];
+        bytes[f] = b[f];
+    }
+}
+
+static int copy_fields(sim_t* s, uint32_t fields, void* const* user, int mem, bool to_user)
+{
+    if (!s || !user) return fail(SIM_EINVAL, "sim or pointer array is NULL");
+    if (fields & ~((1u << SIM_F_COUNT) - 1)) return fail(SIM_EINVAL, "unknown field bits");
+    if (mem != SIM_MEM_HOST && mem != SIM_MEM_DEVICE) return fail(SIM_EINVAL, "unknown memory kind");
+    void* ptr[SIM_F_COUNT];
+    size_t bytes[SIM_F_COUNT];
+    field_table(s, ptr, bytes);
+    for (int f = 0; f < SIM_F_COUNT; ++f) {
+        if (!(fields & (1u << f))) continue;
+        if (!user[f]) return fail(SIM_EINVAL, "pointer for a selected field is NULL");
+        hipMemcpyKind kind = mem == SIM_MEM_HOST ? (to_user ? hipMemcpyDeviceToHost : hipMemcpyHostToDevice)
+                                                 : hipMemcpyDeviceToDevice;
+        hipError_t e = to_user ? hipMemcpyAsync(user[f], ptr[f], bytes[f], kind, s->stream)
+                               : hipMemcpyAsync(ptr[f], user[f], bytes[f], kind, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "state copy");
+    }
+    if (mem == SIM_MEM_HOST) {
+        hipError_t e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return hip_fail(e, "state copy");
+    }
+    return SIM_OK;
+}
+
+int sim_read_state(sim_t* s, uint32_t fields, void* const* dst, int mem)
+{
+    return copy_fields(s, fields, dst, mem, true);
+}
+
+int sim_write_state(sim_t* s, uint32_t fields, const void* const* src, int mem)
+{
+    return copy_fields(s, fields, const_cast<void* const*>(src), mem, false);
+}
+
+int sim_read_index(sim_t* s, int32_t which, int32_t* dst, int64_t count)
+{
+    if (!s || !dst) return fail(SIM_EINVAL, "sim or dst is NULL");
+    const IParams& ip = s->v.ip;
+    const int64_t n = s->z.n, nb = s->z.blocks, N = s->z.N;
+    const int* src[SIM_IDX_COUNT] = {ip.body_off, ip.joint_off, ip.module_off, ip.block_off, ip.blk_type,
+                                     ip.blk_a, ip.blk_b, ip.blk_color, ip.degree, ip.bucket, ip.order};
+    const int64_t len[SIM_IDX_COUNT] = {n + 1, n + 1, n + 1, n + 1, nb, nb, nb, nb, N, n, n};
+    if (which < 0 || which >= SIM_IDX_COUNT) return fail(SIM_EINVAL, "unknown index array");
+    if (count != len[which]) return fail(SIM_EINVAL, "count does not match the index array's length");
+    hipError_t e = hipMemcpyAsync(dst, src[which], count * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "read index");
+    return SIM_OK;
+}
+
+int sim_sizes(const sim_t* s, int64_t* out5)
+{
+    if (!s || !out5) return fail(SIM_EINVAL, "sim or out is NULL");
+    out5[0] = s->z.n;
+    out5[1] = s->z.N;
+    out5[2] = s->z.J;
+    out5[3] = s->z.Mt;
+    out5[4] = s->z.blocks;
+    return SIM_OK;
+}
+
+void sim_destroy(sim_t* s)
+{
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Kernel parameter block and launch wrappers shared by the HIP translation
+// units of the snake solver.  Host-visible; no torch types.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace snake {
+
+enum : int { kFixedRoot = 1, kNoGround = 2 };
+enum : int { kLawLag = 0, kLawPaper = 1 };
+enum : int { kCtrlExternal = 0, kCtrlSerpenoid = 1, kCtrlSchedule = 2 };
+enum : int { kWarmZero = 0, kWarmPrev = 1 };
+enum : int { kStatusNonfinite = 1, kStatusNotConverged = 2 };
+
+// Everything one step kernel needs.  Device pointers into the workspace,
+// structure-of-arrays (component k of body i at [k * N + i]).
+struct KParams {
+    int n_snakes, N, J, Mt;
+    // per snake
+    const int* Bn;
+    const int* Mn;
+    const int* Sn;
+    const int* body_off;
+    const int* module_off;
+    const float* comp;      // [3][n]: stretch, bend, twist compliance / h^2
+    const float* mu;        // [n]
+    const double* freq;     // [n]
+    const double* phase0;   // [n]
+    const int* sched_off;   // [Mt+1]
+    const int* sched_start; // [pieces] first step of each piece
+    const float* sched_val; // [pieces]
+    // state
+    float* x;
+    float* q;
+    float* v;
+    float* w;
+    float* p;               // [2][Mt]
+    float* cmd;             // [Mt]
+    float* lam_j;           // [6][J]
+    float* lam_c;           // [3][N]
+    float* residual;        // [n]
+    int* iters_out;         // [n]
+    int* status;            // [n]
+    long long* step;        // [n]
+    long long* iters_total; // [n]
+    // constants
+    float h, inv_h, inv_m, L, half_L, inv_L, R, g;
+    float c1, c2;           // 1/I_perp and 1/I_axis - 1/I_perp
+    float I_ax, I_pe;
+    float tol, relax;
+    int iters, substeps;
+    float lag_in, lag_de;   // exp(-h / tau)
+    int law;
+    float k_i, k_d, T_p, p_s, amp, kappa_max;
+    int controller;
+    double dt, ctrl_alpha, ctrl_offset;
+    int flags, warm;
+};
+
+// Index-work parameters.
+struct IParams {
+    int n_snakes, N, n_blocks, ground;
+    const int* Bn;
+    const int* Mn;
+    int* body_off;
+    int* joint_off;
+    int* module_off;
+    int* block_off;
+    int* blk_type;
+    int* blk_a;
+    int* blk_b;
+    int* blk_color;
+    int* degree;
+    int* bucket;
+    int* order;
+    int* color_scratch;     // [N]
+};
+
+// Solver launch: snakes of at most `seg` bodies, 64/seg snakes per tile.
+hipError_t launch_step(int seg, const KParams& P, const int* tiles, int n_tiles, int n_steps,
+                       hipStream_t stream);
+hipError_t launch_index(const IParams& P, hipStream_t stream);
+hipError_t launch_init_state(const KParams& P, hipStream_t stream);
+hipError_t launch_set_cmd(float* dst, const float* src, int n, hipStream_t stream);
+
+}  // namespace snake

@@ -1,0 +1,100 @@
+"""Shared helpers of the GPU-vs-oracle parity tests (the per-substep
+protocol): run the FP64 oracle to a realistic state, round that state to
+FP32, hand the same rounded state to both sides, advance both by one
+substep (or one step) with the same command, and compare.
+
+Errors reported per snake:
+  pos     max |x_gpu - x_orc| / max(max |x_orc|, L)
+  lam_*   max |l_gpu - l_orc| / max |l_orc|, per block type
+Contacts whose active set or stick/slip branch differs between the two
+precisions are counted separately and left out of the contact errors."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+import workloads as W
+
+POS_TOL = 1e-5
+LAM_TOL = 1e-4
+
+
+def f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def rounded_state(o: oracle.Oracle):
+    return dict(x=f32(o.x), q=f32(o.q), v=f32(o.v), w=f32(o.w), p=f32(o.p), cmd=f32(o.cmd),
+                lam_j=f32(o.lam_j), lam_c=f32(o.lam_c))
+
+
+def load_oracle(o: oracle.Oracle, st):
+    for k in ("x", "q", "v", "w", "p", "cmd", "lam_j", "lam_c"):
+        getattr(o, k)[...] = st[k]
+
+
+def load_gpu(sim, st):
+    sim.write(pos=st["x"].T, quat=st["q"].T, vel=st["v"].T, angvel=st["w"].T,
+              pressure=st["p"].T, lambda_joint=st["lam_j"].T, lambda_contact=st["lam_c"].T)
+    sim.set_pressures(st["cmd"])
+
+
+def gpu_state(sim):
+    r = sim.read("pos", "quat", "vel", "angvel", "pressure", "lambda_joint", "lambda_contact",
+                 "residual", "iters", "status")
+    return dict(x=r["pos"].T.astype(np.float64), q=r["quat"].T.astype(np.float64),
+                v=r["vel"].T.astype(np.float64), w=r["angvel"].T.astype(np.float64),
+                p=r["pressure"].T.astype(np.float64), lam_j=r["lambda_joint"].T.astype(np.float64),
+                lam_c=r["lambda_contact"].T.astype(np.float64), residual=r["residual"],
+                iters=r["iters"], status=r["status"])
+
+
+def compare(o: oracle.Oracle, g: dict, mu):
+    """Per-snake error table (dict of arrays) between oracle o and GPU state g."""
+    n = o.n
+    out = {k: np.zeros(n) for k in ("pos", "lam_s", "lam_b", "lam_n", "lam_t")}
+    out["branch"] = np.zeros(n, np.int64)
+    L = o.batch.length
+    for s in range(n):
+        b0, b1 = o.body_off[s], o.body_off[s + 1]
+        j0, j1 = o.joint_off[s], o.joint_off[s + 1]
+        xo, xg = o.x[b0:b1], g["x"][b0:b1]
+        out["pos"][s] = np.abs(xg - xo).max() / max(np.abs(xo).max(), L)
+        for key, sl in (("lam_s", slice(0, 3)), ("lam_b", slice(3, 6))):
+            lo, lg = o.lam_j[j0:j1, sl], g["lam_j"][j0:j1, sl]
+            if lo.size:
+                sc = np.abs(lo).max()
+                out[key][s] = np.abs(lg - lo).max() / sc if sc > 0 else np.abs(lg).max()
+        lco, lcg = o.lam_c[b0:b1], g["lam_c"][b0:b1]
+        act_o, act_g = lco[:, 0] > 0, lcg[:, 0] > 0
+        cap_o = np.linalg.norm(lco[:, 1:], axis=1) >= mu[s] * lco[:, 0] * (1 - 1e-4)
+        cap_g = np.linalg.norm(lcg[:, 1:], axis=1) >= mu[s] * lcg[:, 0] * (1 - 1e-4)
+        same = (act_o == act_g) & ((cap_o == cap_g) | ~act_o)
+        out["branch"][s] = int((~same).sum())
+        if same.any():
+            sc = np.abs(lco[:, 0]).max()
+            if sc > 0:
+                out["lam_n"][s] = np.abs(lcg[same, 0] - lco[same, 0]).max() / sc
+                out["lam_t"][s] = np.abs(lcg[same, 1:] - lco[same, 1:]).max() / sc
+    return out
+
+
+def advance_both(wl, st, one_substep=True, threads=8, **over):
+    """Build an oracle and a GPU sim for `wl` (external commands), load the
+    rounded state st into both, advance one substep (or one step)."""
+    import paper_1904_02833_amd as snk
+
+    kw = dict(controller=W.CTRL_EXTERNAL)
+    if one_substep:
+        kw.update(dt=wl.dt / wl.substeps, substeps=1)
+    kw.update(over)
+    o = oracle.Oracle(wl, **{k: v for k, v in kw.items() if k not in ("warm_start", "use_graph")},
+                      warm=kw.get("warm_start", 0))
+    load_oracle(o, st)
+    o.run(1, threads=threads)
+    sim = snk.Sim(wl, **kw)
+    load_gpu(sim, st)
+    sim.step(1)
+    g = gpu_state(sim)
+    sim.close()
+    return o, g

@@ -1,0 +1,141 @@
+"""C ABI checks that need no GPU: the library loads and exports every entry
+point include/snake.h declares, the ctypes descriptor matches the C layout,
+and descriptor validation rejects bad input before touching the device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1904_02833_amd as snk
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "snake.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(snk.LIB_PATH):
+        from paper_1904_02833_amd import build
+        build.build()
+    return snk.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(sim_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert set(names) == set(snk.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", snk.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (sim_\w+)$", out, re.M))
+    for n in names:
+        assert n in exported, n
+        assert hasattr(L, n)
+
+
+def test_descriptor_layout_matches_c(tmp_path):
+    """Compile a probe against the header with gcc and compare sizeof and
+    every field offset with the ctypes mirror."""
+    fields = [f[0] for f in snk.Desc._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "snake.h"', 'int main(void){',
+           'printf("%zu\\n", sizeof(sim_desc_t));']
+    src += [f'printf("%zu\\n", offsetof(sim_desc_t, {f}));' for f in fields]
+    src += ["return 0;}"]
+    c = tmp_path / "probe.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == C.sizeof(snk.Desc)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(snk.Desc, f).offset == off, f
+
+
+def test_oracle_batch_layout_matches_c(tmp_path):
+    import oracle
+    fields = [f[0] for f in oracle.Batch._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "snake_oracle.h"',
+           'int main(void){', 'printf("%zu\\n", sizeof(orc_batch));']
+    src += [f'printf("%zu\\n", offsetof(orc_batch, {f}));' for f in fields]
+    src += ["return 0;}"]
+    c = tmp_path / "probe.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "oracle"), str(c), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == C.sizeof(oracle.Batch)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(oracle.Batch, f).offset == off, f
+
+
+def ws_bytes(L, wl, **over):
+    d, keep = snk.make_desc(wl, **over)
+    n = C.c_size_t(0)
+    rc = L.sim_workspace_bytes(C.byref(d), C.byref(n))
+    return rc, n.value, L.sim_last_error().decode()
+
+
+def test_workspace_bytes_valid_and_monotone(L):
+    rc1, b1, _ = ws_bytes(L, W.make("uniform", n_snakes=16))
+    rc2, b2, _ = ws_bytes(L, W.make("uniform", n_snakes=64))
+    assert rc1 == rc2 == 0
+    assert 0 < b1 < b2
+    rc, b, _ = ws_bytes(L, W.make("uneven", n_snakes=50).take(
+        np.nonzero((W.make("uneven", n_snakes=50).bodies) <= 64)[0]))
+    assert rc == 0 and b > 0
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("n_modules", np.zeros(2, np.int32), "n_modules"),
+    ("alpha_bend", np.array([1e-5, np.nan]), "compliance"),
+    ("mu", np.array([0.5, -1.0]), "mu"),
+    ("dt", 0.0, "dt"),
+    ("substeps", 0, "substeps"),
+    ("iters", -1, "iters"),
+    ("relax", 1.5, "relax"),
+    ("tau_inflate", 0.0, "tau"),
+    ("controller", 7, "controller"),
+    ("flags", 64, "flag"),
+])
+def test_descriptor_validation(L, field, value, msg):
+    wl = W.custom([2, 2], 8)
+    rc, _, err = ws_bytes(L, wl, **{field: value})
+    assert rc == snk.SIM_EINVAL
+    assert msg in err
+
+
+def test_schedule_validation(L):
+    wl = W.custom([1, 1], 8, controller=W.CTRL_SCHEDULE)
+    wl.sched_off = np.array([0, 1, 1], np.int32)     # second module has no piece
+    wl.sched_steps = np.array([5], np.int32)
+    wl.sched_val = np.array([0.5])
+    rc, _, err = ws_bytes(L, wl)
+    assert rc == snk.SIM_EINVAL and "piece" in err
+
+
+def test_create_rejects_bad_workspace_without_device(L):
+    wl = W.custom([2], 8)
+    d, keep = snk.make_desc(wl)
+    h = C.c_void_p()
+    assert L.sim_create(C.byref(d), None, 1 << 20, None, C.byref(h)) == snk.SIM_EINVAL
+    assert L.sim_create(C.byref(d), C.c_void_p(4096 + 8), 1 << 20, None, C.byref(h)) == snk.SIM_EINVAL
+    assert L.sim_create(C.byref(d), C.c_void_p(4096), 16, None, C.byref(h)) == snk.SIM_ENOMEM
+    assert "workspace too small" in L.sim_last_error().decode()
+    assert not h.value
+
+
+def test_null_handles(L):
+    L.sim_destroy(None)
+    assert L.sim_step(None, 1) == snk.SIM_EINVAL
+    assert L.sim_set_pressures(None, None, 0, 0) == snk.SIM_EINVAL
+    assert L.sim_read_state(None, 1, None, 0) == snk.SIM_EINVAL
+    assert L.sim_read_index(None, 0, None, 0) == snk.SIM_EINVAL

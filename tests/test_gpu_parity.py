@@ -1,0 +1,265 @@
+"""GPU (FP32 HIP kernels through the C ABI) against the FP64 oracle.
+
+Index work is compared bit for bit.  Physics follows the per-substep
+protocol (tests/parity.py): the same FP32-rounded state goes into both, both
+take one substep or one step with a fixed iteration count, positions must
+agree to 1e-5 relative and multipliers to 1e-4 relative per block type.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from parity import LAM_TOL, POS_TOL, advance_both, compare, gpu_state, load_gpu, rounded_state
+
+pytestmark = pytest.mark.gpu
+
+snk = pytest.importorskip("paper_1904_02833_amd")
+
+
+def short_uneven(n, seed=None, max_B=64):
+    wl = W.make("uneven", n_snakes=4 * n, seed=seed)
+    keep = np.nonzero(wl.bodies <= max_B)[0][:n]
+    return wl.take(keep)
+
+
+def report(tag, err):
+    worst = {k: float(np.max(v)) for k, v in err.items()}
+    print(f"\n[{tag}] " + " ".join(f"{k}={v:.3g}" for k, v in worst.items()), flush=True)
+    return worst
+
+
+def assert_parity(tag, err, max_branch_frac=0.02, n_bodies=None):
+    worst = report(tag, err)
+    assert worst["pos"] <= POS_TOL
+    for k in ("lam_s", "lam_b", "lam_n", "lam_t"):
+        assert worst[k] <= LAM_TOL, (k, worst[k])
+    if n_bodies:
+        assert err["branch"].sum() <= max_branch_frac * n_bodies
+
+
+# ---------------------------------------------------------------- index work
+
+@pytest.mark.parametrize("case", ["custom", "uniform", "uneven", "noground"])
+def test_index_bit_exact(case):
+    if case == "custom":
+        wl = W.custom([1, 1, 1, 2, 3, 1, 4, 2, 1], [1, 2, 3, 5, 7, 64, 16, 32, 13])
+    elif case == "uniform":
+        wl = W.make("uniform", n_snakes=300)
+    elif case == "uneven":
+        wl = short_uneven(700, max_B=64)
+    else:
+        wl = W.custom([3, 1, 2], [4, 9, 1], flags=oracle.FLAG_NO_GROUND)
+    o = oracle.Oracle(wl)
+    ix = o.index()
+    sim = snk.Sim(wl)
+    for name in snk.INDEX:
+        got = sim.index(name)
+        want = ix[name]
+        assert got.dtype == np.int32
+        assert np.array_equal(got.astype(np.int64), np.asarray(want, np.int64)), name
+    sim.close()
+
+
+# ---------------------------------------------------------------- commands
+
+def test_serpenoid_commands_match():
+    wl = W.make("uniform", n_snakes=64)
+    sim = snk.Sim(wl)
+    o = oracle.Oracle(wl)
+    for n in range(5):
+        sim.step(1)
+        o.commands()
+        got = sim.read("cmd")["cmd"]
+        assert np.abs(got - o.cmd).max() <= 1e-6
+        o.step[:] += 1
+    sim.close()
+
+
+def test_schedule_commands_match():
+    wl = short_uneven(120)
+    sim = snk.Sim(wl)
+    o = oracle.Oracle(wl)
+    for n in range(80):
+        sim.step(1)
+        o.commands()
+        assert np.array_equal(sim.read("cmd")["cmd"], o.cmd.astype(np.float32)), n
+        o.step[:] += 1
+    sim.close()
+
+
+# ---------------------------------------------------------------- physics
+
+@pytest.mark.parametrize("warm_steps", [1, 40, 200])
+def test_substep_parity_single(warm_steps):
+    wl = W.make("single")
+    o = oracle.Oracle(wl)
+    o.run(warm_steps)
+    o.commands()
+    st = rounded_state(o)
+    oo, g = advance_both(wl, st)
+    assert_parity(f"single@{warm_steps}", compare(oo, g, wl.mu), n_bodies=64)
+
+
+def test_step_parity_single():
+    wl = W.make("single")
+    o = oracle.Oracle(wl)
+    o.run(120)
+    o.commands()
+    oo, g = advance_both(wl, rounded_state(o), one_substep=False)
+    assert_parity("single-step", compare(oo, g, wl.mu), n_bodies=64)
+
+
+def test_substep_parity_uniform_slice():
+    wl = W.make("uniform", n_snakes=48)
+    o = oracle.Oracle(wl)
+    o.run(30, threads=8)
+    o.commands()
+    oo, g = advance_both(wl, rounded_state(o))
+    assert_parity("uniform", compare(oo, g, wl.mu), n_bodies=wl.total_bodies)
+
+
+def test_substep_parity_uneven_tiles():
+    """Snakes of 16..64 bodies: 4, 2 and 1 snakes per wave, ragged tails."""
+    wl = short_uneven(150)
+    o = oracle.Oracle(wl)
+    o.run(25, threads=8)
+    o.commands()
+    oo, g = advance_both(wl, rounded_state(o))
+    assert_parity("uneven", compare(oo, g, wl.mu), n_bodies=wl.total_bodies)
+
+
+def test_parity_tiny_and_odd_sizes():
+    wl = W.custom([1, 1, 1, 1, 3, 1], [1, 2, 3, 17, 5, 63], mu=0.4,
+                  controller=W.CTRL_EXTERNAL)
+    o = oracle.Oracle(wl)
+    o.cmd[:] = np.linspace(-1, 1, o.cmd.size)
+    o.run(20)
+    oo, g = advance_both(wl, rounded_state(o))
+    assert_parity("tiny", compare(oo, g, wl.mu), n_bodies=wl.total_bodies)
+
+
+def test_parity_warm_start_prev():
+    wl = W.make("single")
+    o = oracle.Oracle(wl, warm=oracle.WARM_PREV)
+    o.run(60)
+    o.commands()
+    oo, g = advance_both(wl, rounded_state(o), warm_start=snk.WARM_PREV)
+    assert_parity("warm-prev", compare(oo, g, wl.mu), n_bodies=64)
+
+
+def test_parity_paper_pressure_law():
+    wl = W.make("uniform", n_snakes=8)
+    wl.pressure_law = W.LAW_PAPER
+    o = oracle.Oracle(wl)
+    o.run(30, threads=8)
+    o.commands()
+    oo, g = advance_both(wl, rounded_state(o), one_substep=False)
+    assert np.abs(g["p"] - oo.p).max() <= 1e-6
+    assert_parity("paper-law", compare(oo, g, wl.mu), n_bodies=wl.total_bodies)
+
+
+def test_parity_cantilever_fixed_root():
+    wl = W.custom([1], [12], alpha=(1e-3, 2.0, 2.0), controller=W.CTRL_EXTERNAL,
+                  flags=oracle.FLAG_FIXED_ROOT | oracle.FLAG_NO_GROUND)
+    o = oracle.Oracle(wl)
+    o.run(10)
+    oo, g = advance_both(wl, rounded_state(o))
+    err = compare(oo, g, wl.mu)
+    report("cantilever", err)
+    assert err["pos"].max() <= POS_TOL
+    assert err["lam_s"].max() <= LAM_TOL and err["lam_b"].max() <= LAM_TOL
+
+
+def test_trajectory_report_single():
+    """Full rollouts drift apart (chaotic contact); reported, not gated,
+    beyond staying finite and close for the first steps."""
+    wl = W.make("single")
+    o = oracle.Oracle(wl)
+    sim = snk.Sim(wl)
+    errs = []
+    for n in range(60):
+        o.run(1)
+        sim.step(1)
+        x = sim.read("pos")["pos"].T
+        errs.append(np.abs(x - o.x).max() / np.abs(o.x).max())
+    print(f"\n[rollout] pos rel err after 1/10/60 steps: {errs[0]:.2e} {errs[9]:.2e} {errs[-1]:.2e}")
+    assert np.all(np.isfinite(errs))
+    assert errs[0] <= POS_TOL
+    sim.close()
+
+
+# ---------------------------------------------------------------- runtime
+
+def test_deterministic_and_graph_equals_direct():
+    wl = short_uneven(200)
+    a = snk.Sim(wl, use_graph=1)
+    b = snk.Sim(wl, use_graph=0)
+    a.step(7)
+    for _ in range(7):
+        b.step(1)
+    ra, rb = a.read(), b.read()
+    for k in ra:
+        assert np.array_equal(ra[k], rb[k]), k
+    c = snk.Sim(wl, use_graph=1)
+    c.step(3)
+    c.step(4)
+    rc = c.read()
+    for k in ra:
+        assert np.array_equal(ra[k], rc[k]), k
+    for s in (a, b, c):
+        s.close()
+
+
+def test_checkpoint_roundtrip_bitwise():
+    wl = W.make("uniform", n_snakes=32)
+    a = snk.Sim(wl)
+    a.step(10)
+    snap = a.read()
+    a.step(10)
+    end_a = a.read()
+    b = snk.Sim(wl)
+    b.write(**{k: v for k, v in snap.items()})
+    assert all(np.array_equal(b.read()[k], snap[k]) for k in snap)
+    b.step(10)
+    end_b = b.read()
+    for k in end_a:
+        assert np.array_equal(end_a[k], end_b[k]), k
+    a.close()
+    b.close()
+
+
+def test_nonfinite_snake_is_isolated():
+    wl = W.make("uniform", n_snakes=16)
+    a = snk.Sim(wl)
+    b = snk.Sim(wl)
+    a.step(3)
+    b.step(3)
+    pos = b.read("pos")["pos"]
+    pos[0, 64 * 5 + 7] = np.nan          # snake 5, body 7
+    b.write(pos=pos)
+    a.step(2)
+    b.step(2)
+    ra, rb = a.read(), b.read()
+    assert rb["status"][5] & snk.STATUS_NONFINITE
+    others = np.ones(16, bool)
+    others[5] = False
+    assert np.all(rb["status"][others] == ra["status"][others])
+    keep = np.repeat(others, 64)
+    assert np.array_equal(ra["pos"][:, keep], rb["pos"][:, keep])
+    a.close()
+    b.close()
+
+
+def test_set_pressures_errors_and_device_path():
+    import torch
+    wl = W.custom([2, 3], 8)
+    sim = snk.Sim(wl)
+    with pytest.raises(snk.SimError):
+        sim.set_pressures(np.array([0.1, np.nan, 0, 0, 0], np.float32))
+    with pytest.raises(snk.SimError):
+        sim.set_pressures(np.zeros(4, np.float32))
+    sim.set_pressures(torch.tensor([2.0, -0.5, float("nan"), 0.25, -3.0], device="cuda"))
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.read("cmd")["cmd"], np.array([1, -0.5, 0, 0.25, -1], np.float32))
+    sim.close()
