@@ -5,9 +5,14 @@ substep (or one step) with the same command, and compare.
 
 Errors reported per snake:
   pos     max |x_gpu - x_orc| / max(max |x_orc|, L)
-  lam_*   max |l_gpu - l_orc| / max |l_orc|, per block type
-Contacts whose active set or stick/slip branch differs between the two
-precisions are counted separately and left out of the contact errors."""
+  lam_*   max |l_gpu - l_orc| / max(max |l_orc|, l_ref), per block type
+The floor l_ref is the multiplier scale of one segment's weight over one
+substep: m g h^2 (stretch, contact; g = 9.81) and m g h^2 L (bend-twist).
+It only matters for snakes whose joints carry almost no load, where the
+multipliers are ~1e-9 of that scale and the relative error would divide
+rounding noise by ~0.  Contacts whose active set or stick/slip branch differs
+between the two precisions are counted separately and left out of the
+contact errors."""
 from __future__ import annotations
 
 import numpy as np
@@ -55,6 +60,9 @@ def compare(o: oracle.Oracle, g: dict, mu):
     out = {k: np.zeros(n) for k in ("pos", "lam_s", "lam_b", "lam_n", "lam_t")}
     out["branch"] = np.zeros(n, np.int64)
     L = o.batch.length
+    h = o.batch.dt / o.batch.substeps
+    ref = o.batch.mass * 9.81 * h * h
+    floor = {"lam_s": ref, "lam_b": ref * L}
     for s in range(n):
         b0, b1 = o.body_off[s], o.body_off[s + 1]
         j0, j1 = o.joint_off[s], o.joint_off[s + 1]
@@ -63,8 +71,7 @@ def compare(o: oracle.Oracle, g: dict, mu):
         for key, sl in (("lam_s", slice(0, 3)), ("lam_b", slice(3, 6))):
             lo, lg = o.lam_j[j0:j1, sl], g["lam_j"][j0:j1, sl]
             if lo.size:
-                sc = np.abs(lo).max()
-                out[key][s] = np.abs(lg - lo).max() / sc if sc > 0 else np.abs(lg).max()
+                out[key][s] = np.abs(lg - lo).max() / max(np.abs(lo).max(), floor[key])
         lco, lcg = o.lam_c[b0:b1], g["lam_c"][b0:b1]
         act_o, act_g = lco[:, 0] > 0, lcg[:, 0] > 0
         cap_o = np.linalg.norm(lco[:, 1:], axis=1) >= mu[s] * lco[:, 0] * (1 - 1e-4)
@@ -72,10 +79,9 @@ def compare(o: oracle.Oracle, g: dict, mu):
         same = (act_o == act_g) & ((cap_o == cap_g) | ~act_o)
         out["branch"][s] = int((~same).sum())
         if same.any():
-            sc = np.abs(lco[:, 0]).max()
-            if sc > 0:
-                out["lam_n"][s] = np.abs(lcg[same, 0] - lco[same, 0]).max() / sc
-                out["lam_t"][s] = np.abs(lcg[same, 1:] - lco[same, 1:]).max() / sc
+            sc = max(np.abs(lco[:, 0]).max(), ref)
+            out["lam_n"][s] = np.abs(lcg[same, 0] - lco[same, 0]).max() / sc
+            out["lam_t"][s] = np.abs(lcg[same, 1:] - lco[same, 1:]).max() / sc
     return out
 
 
