@@ -45,8 +45,8 @@ def parse():
     ap.add_argument("--snakes", type=int, default=None)
     ap.add_argument("--fixed", action="store_true", help="fixed 20 iterations per substep")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-snakes", type=int, default=256)
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-snakes", type=int, default=1024)
+    ap.add_argument("--cpu-steps", type=int, default=12)
     return ap.parse_args()
 
 
