@@ -154,6 +154,18 @@ typedef struct sim_desc {
     int32_t warm_start;        /* SIM_WARM_*                                */
     uint32_t flags;            /* SIM_FLAG_*                                */
     int32_t use_graph;         /* 1: replay sim_step launches from a graph  */
+    /* Mapping of snakes to lanes.  A workgroup of map_waves wavefronts takes
+     * tiles of snakes; each snake owns an aligned power-of-two lane segment
+     * of at least map_min_seg lanes (16, 32 or 64); map_grid workgroups loop
+     * over the tiles (0: one workgroup per tile).  0 selects the default.
+     * autotune = 1 times the candidate mappings on the real batch inside
+     * sim_create (the state is restored afterwards) and keeps the fastest;
+     * explicit map_* values are then ignored.  Every mapping gives
+     * bit-identical results. */
+    int32_t autotune;
+    int32_t map_waves;         /* 1, 2, 4, 8 or 16; 64 * map_waves >= every segment */
+    int32_t map_min_seg;
+    int32_t map_grid;
 } sim_desc_t;
 
 typedef struct sim sim_t;
@@ -198,6 +210,10 @@ int sim_read_index(sim_t* s, int32_t which, int32_t* dst, int64_t count);
 
 /* Sizes: n_snakes, N, Jtot, Mtot, n_blocks (host int64 out[5]). */
 int sim_sizes(const sim_t* s, int64_t* out5);
+
+/* Mapping in use: waves per workgroup, minimum segment, grid, tiles
+ * (host int32 out[4]). */
+int sim_mapping(const sim_t* s, int32_t* out4);
 
 /* Release host resources (the caller frees the workspace).  NULL is a
  * no-op.  Waits for the stream. */

@@ -43,8 +43,8 @@ FIELD_BIT = {f[0]: 1 << k for k, f in enumerate(FIELDS)}
 INDEX = ["body_off", "joint_off", "module_off", "block_off", "blk_type", "blk_a", "blk_b",
          "blk_color", "degree", "bucket", "order"]
 EXPORTS = ["sim_workspace_bytes", "sim_create", "sim_set_pressures", "sim_step",
-           "sim_read_state", "sim_write_state", "sim_read_index", "sim_sizes", "sim_destroy",
-           "sim_last_error"]
+           "sim_read_state", "sim_write_state", "sim_read_index", "sim_sizes", "sim_mapping",
+           "sim_destroy", "sim_last_error"]
 
 _P = C.c_void_p
 
@@ -67,6 +67,8 @@ class Desc(C.Structure):
         ("ctrl_alpha", C.c_double), ("ctrl_offset", C.c_double),
         ("sched_off", _P), ("sched_steps", _P), ("sched_val", _P),
         ("warm_start", C.c_int32), ("flags", C.c_uint32), ("use_graph", C.c_int32),
+        ("autotune", C.c_int32), ("map_waves", C.c_int32), ("map_min_seg", C.c_int32),
+        ("map_grid", C.c_int32),
     ]
 
 
@@ -88,6 +90,7 @@ def lib():
         L.sim_write_state.argtypes = [_P, C.c_uint32, C.POINTER(_P), C.c_int]
         L.sim_read_index.argtypes = [_P, C.c_int32, _P, C.c_int64]
         L.sim_sizes.argtypes = [_P, C.POINTER(C.c_int64)]
+        L.sim_mapping.argtypes = [_P, C.POINTER(C.c_int32)]
         L.sim_destroy.argtypes = [_P]
         L.sim_destroy.restype = None
         L.sim_last_error.argtypes = []
@@ -143,6 +146,10 @@ def make_desc(wl, **over):
     d.warm_start = int(over.get("warm_start", WARM_ZERO))
     d.flags = int(g("flags"))
     d.use_graph = int(over.get("use_graph", 1))
+    d.autotune = int(over.get("autotune", 0))
+    d.map_waves = int(over.get("map_waves", 0))
+    d.map_min_seg = int(over.get("map_min_seg", 0))
+    d.map_grid = int(over.get("map_grid", 0))
     return d, keep
 
 
@@ -179,6 +186,9 @@ class Sim:
         sz = (C.c_int64 * 5)()
         _check(self.L.sim_sizes(self.h, sz))
         self.n, self.N, self.J, self.Mt, self.n_blocks = (int(v) for v in sz)
+        mp = (C.c_int32 * 4)()
+        _check(self.L.sim_mapping(self.h, mp))
+        self.mapping = dict(waves=mp[0], min_seg=mp[1], grid=mp[2], tiles=mp[3])
         self._len = dict(n=self.n, N=self.N, J=self.J, Mt=self.Mt)
         del keep
 

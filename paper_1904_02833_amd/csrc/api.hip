@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -31,6 +32,7 @@ int hip_fail(hipError_t e, const char* what)
 struct Sizes {
     int64_t n = 0, N = 0, J = 0, Mt = 0, blocks = 0, pieces = 0;
     int max_B = 0;
+    bool autotune = false;
 };
 
 // Carves 256-byte aligned sub-arrays out of the workspace (base == nullptr
@@ -85,7 +87,7 @@ int validate(const sim_desc_t* d, Sizes* z)
         const int M = d->n_modules[s], S = d->segs_per_module[s];
         if (M < 1 || S < 1) return fail(SIM_EINVAL, "n_modules and segs_per_module must be >= 1");
         const int64_t B = (int64_t)M * S;
-        if (B > 64) return fail(SIM_EINVAL, "snakes longer than 64 bodies are not supported yet");
+        if (B > 1024) return fail(SIM_EINVAL, "snakes longer than 1024 bodies are not supported");
         const double a[4] = {d->alpha_stretch[s], d->alpha_bend[s], d->alpha_twist[s], d->mu[s]};
         for (double v : a)
             if (!std::isfinite(v) || v < 0.0) return fail(SIM_EINVAL, "compliance and mu must be finite and >= 0");
@@ -96,6 +98,18 @@ int validate(const sim_desc_t* d, Sizes* z)
         if (B > z->max_B) z->max_B = (int)B;
     }
     if (z->N > (int64_t)1 << 28) return fail(SIM_EINVAL, "too many bodies (limit 2^28)");
+    const int mw = d->map_waves;
+    if (mw != 0 && mw != 1 && mw != 2 && mw != 4 && mw != 8 && mw != 16)
+        return fail(SIM_EINVAL, "map_waves must be 0, 1, 2, 4, 8 or 16");
+    if (d->map_min_seg != 0 && d->map_min_seg != 16 && d->map_min_seg != 32 && d->map_min_seg != 64)
+        return fail(SIM_EINVAL, "map_min_seg must be 0, 16, 32 or 64");
+    if (d->map_grid < 0) return fail(SIM_EINVAL, "map_grid must be >= 0");
+    if (mw != 0 && !d->autotune) {
+        int seg = 16;
+        while (seg < z->max_B) seg <<= 1;
+        if (seg > 64 * mw) return fail(SIM_EINVAL, "map_waves too small for the longest snake");
+    }
+    z->autotune = d->autotune != 0;
     if (d->controller == SIM_CTRL_SERPENOID && (!d->ctrl_freq || !d->ctrl_phase0))
         return fail(SIM_EINVAL, "serpenoid controller needs ctrl_freq and ctrl_phase0");
     if (d->controller == SIM_CTRL_SCHEDULE) {
@@ -120,7 +134,11 @@ int validate(const sim_desc_t* d, Sizes* z)
 struct Views {
     KParams kp;
     IParams ip;
-    int* tiles;
+    int4* hdr;
+    int2* slots;
+    char* state_begin;      // the mutable state is one contiguous range
+    size_t state_bytes;
+    char* backup;           // copy of the state while autotuning
     int* Bn;
     int* Mn;
     int* Sn;
@@ -152,6 +170,8 @@ size_t carve(const Sizes& z, char* base, Views* v)
     k.status = c.take<int>(n);
     k.step = c.take<long long>(n);
     k.iters_total = c.take<long long>(n);
+    v->state_begin = reinterpret_cast<char*>(k.x);
+    v->state_bytes = c.pos;
     v->Bn = c.take<int>(n);
     v->Mn = c.take<int>(n);
     v->Sn = c.take<int>(n);
@@ -174,11 +194,52 @@ size_t carve(const Sizes& z, char* base, Views* v)
     ip.bucket = c.take<int>(n);
     ip.order = c.take<int>(n);
     ip.color_scratch = c.take<int>(N);
-    v->tiles = c.take<int>(n * 4 + 64);
+    v->hdr = c.take<int4>(n + 1);
+    v->slots = c.take<int2>(n + 1);
+    v->backup = z.autotune ? c.take<char>((int64_t)v->state_bytes) : nullptr;
     return c.pos + 256;
 }
 
-int seg_class(int B) { return B <= 16 ? 16 : (B <= 32 ? 32 : 64); }
+int pow2_at_least(int b, int lo)
+{
+    int p = lo;
+    while (p < b) p <<= 1;
+    return p;
+}
+
+struct Mapping {
+    int nw = 1, min_seg = 16, grid = 0;
+};
+
+// Pack snakes, in work order (longest first), into tiles of 64*nw lanes.
+// Each snake gets max(min_seg, 2^ceil(log2 B)) lanes; segments arrive in
+// non-increasing size, so placing them one after another keeps every
+// segment aligned to its own size.
+void build_tiles(const std::vector<int>& order, const std::vector<int>& Bn, const Mapping& mp,
+                 std::vector<int4>& hdr, std::vector<int2>& slots)
+{
+    hdr.clear();
+    slots.clear();
+    const int cap = 64 * mp.nw;
+    int pos = cap;
+    for (int sidx : order) {
+        const int seg = pow2_at_least(Bn[sidx], mp.min_seg);
+        if (pos + seg > cap) {
+            hdr.push_back(make_int4((int)slots.size(), 0, 0, 0));
+            pos = 0;
+        }
+        int lg = 0;
+        while ((1 << lg) < seg) ++lg;
+        slots.push_back(make_int2(sidx, (pos << 8) | lg));
+        int4& h = hdr.back();
+        h.y += 1;
+        if (seg > 64) h.z = 1;
+        pos += seg;
+    }
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, Mapping> g_tune_cache;
 
 }  // namespace
 
@@ -187,16 +248,126 @@ struct sim {
     Views v;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
-    struct Group {
-        int seg;
-        const int* tiles;
-        int n_tiles;
-    };
-    std::vector<Group> groups;
+    Mapping map;
+    int n_tiles = 0;
     bool use_graph = false;
     std::map<int, hipGraphExec_t> graphs;
     std::vector<int> order_host;
+    std::vector<int> B_host;
 };
+
+namespace {
+
+int upload_tiles(sim* s, const Mapping& mp)
+{
+    std::vector<int4> hdr;
+    std::vector<int2> slots;
+    build_tiles(s->order_host, s->B_host, mp, hdr, slots);
+    hipError_t e = hipMemcpy(s->v.hdr, hdr.data(), hdr.size() * sizeof(int4), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(s->v.slots, slots.data(), slots.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload tiles");
+    s->map = mp;
+    s->n_tiles = (int)hdr.size();
+    return SIM_OK;
+}
+
+int launch_steps(sim* s, hipStream_t st, int n_steps)
+{
+    hipError_t e = launch_tiles(s->map.nw, s->v.kp, s->v.hdr, s->v.slots, s->n_tiles, s->map.grid,
+                                n_steps, st);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    return SIM_OK;
+}
+
+// Time every candidate mapping for a few steps on the real batch and keep
+// the fastest.  The state is saved first and restored after each trial.
+int autotune(sim* s)
+{
+    const int max_seg = pow2_at_least(s->z.max_B, 16);
+    const int nw_min = max_seg > 64 ? max_seg / 64 : 1;
+    int cus = 256;
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            cus = prop.multiProcessorCount;
+        }
+    }
+    std::string key = std::to_string(cus) + ":" + std::to_string(s->z.n) + ":" +
+                      std::to_string(s->z.N) + ":" + std::to_string(s->z.max_B) + ":" +
+                      std::to_string(s->v.kp.iters) + ":" + std::to_string(s->v.kp.tol > 0.f);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) return upload_tiles(s, it->second);
+    }
+    int min_pow2 = 1 << 30;
+    for (int b : s->B_host) min_pow2 = std::min(min_pow2, pow2_at_least(b, 16));
+    std::vector<Mapping> cand;
+    for (int nw = nw_min; nw <= 16 && nw <= 4 * nw_min; nw <<= 1)
+        for (int ms : {16, 32, 64}) {
+            if (ms != 16 && ms <= min_pow2) continue;   // same packing as 16
+            Mapping m;
+            m.nw = nw;
+            m.min_seg = ms;
+            cand.push_back(m);
+            // persistent variant: one resident wave set per SIMD slot
+            Mapping p = m;
+            p.grid = cus * (16 / nw > 0 ? 16 / nw : 1);
+            cand.push_back(p);
+        }
+    hipError_t e = hipMemcpyAsync(s->v.backup, s->v.state_begin, s->v.state_bytes,
+                                  hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "autotune backup");
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+        return hip_fail(e, "autotune events");
+    Mapping best;
+    float best_ms = 1e30f;
+    int rc = SIM_OK;
+    for (const Mapping& m : cand) {
+        rc = upload_tiles(s, m);
+        if (rc) break;
+        if (m.grid >= s->n_tiles && m.grid != 0) continue;
+        rc = launch_steps(s, s->stream, 1);   // warm-up
+        if (rc) break;
+        (void)hipEventRecord(e0, s->stream);
+        rc = launch_steps(s, s->stream, 1);
+        if (rc == SIM_OK) rc = launch_steps(s, s->stream, 1);
+        (void)hipEventRecord(e1, s->stream);
+        if (rc) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+            rc = hip_fail(e, "autotune timing");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = m;
+        }
+        e = hipMemcpyAsync(s->v.state_begin, s->v.backup, s->v.state_bytes, hipMemcpyDeviceToDevice,
+                           s->stream);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune restore");
+            break;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    e = hipMemcpyAsync(s->v.state_begin, s->v.backup, s->v.state_bytes, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "autotune restore");
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    return upload_tiles(s, best);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -349,25 +520,26 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     CK(launch_index(ip, st), "index kernels");
     CK(hipStreamSynchronize(st), "index work");
     {
-        // tiles: snakes in work order, packed 64/seg per wave per size class
+        // tiles: snakes in work order (longest first), packed into segments
         std::vector<int> order(n);
         CK(hipMemcpy(order.data(), ip.order, n * sizeof(int), hipMemcpyDeviceToHost), "read order");
         s->order_host = order;
-        std::vector<int> tiles;
-        for (int seg : {64, 32, 16}) {
-            const int per = 64 / seg;
-            std::vector<int> cls;
-            for (int o : order)
-                if (seg_class(Bn[o]) == seg) cls.push_back(o);
-            if (cls.empty()) continue;
-            const int nt = (int)((cls.size() + per - 1) / per);
-            const size_t first = tiles.size();
-            for (int t = 0; t < nt * per; ++t) tiles.push_back(t < (int)cls.size() ? cls[t] : -1);
-            s->groups.push_back({seg, w.tiles + first, nt});
-        }
-        CK(hipMemcpy(w.tiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice), "upload tiles");
+        s->B_host = Bn;
     }
     CK(launch_init_state(k, st), "init state");
+    CK(hipStreamSynchronize(st), "init state");
+    if (z.autotune) {
+        rc = autotune(s);
+        if (rc) goto error;
+    } else {
+        Mapping mp;
+        const int max_seg = pow2_at_least(z.max_B, 16);
+        mp.nw = d->map_waves ? d->map_waves : (max_seg > 64 ? max_seg / 64 : 1);
+        mp.min_seg = d->map_min_seg ? d->map_min_seg : 16;
+        mp.grid = d->map_grid;
+        rc = upload_tiles(s, mp);
+        if (rc) goto error;
+    }
     CK(hipStreamSynchronize(st), "create");
     s->use_graph = d->use_graph != 0;
     if (s->use_graph) CK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking), "capture stream");
@@ -377,15 +549,6 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
 error:
     delete s;
     return rc;
-}
-
-static int launch_steps(sim* s, hipStream_t st, int n_steps)
-{
-    for (const auto& g : s->groups) {
-        hipError_t e = launch_step(g.seg, s->v.kp, g.tiles, g.n_tiles, n_steps, st);
-        if (e != hipSuccess) return hip_fail(e, "step launch");
-    }
-    return SIM_OK;
 }
 
 int sim_step(sim_t* s, int32_t n_steps)
@@ -515,6 +678,16 @@ int sim_sizes(const sim_t* s, int64_t* out5)
     out5[2] = s->z.J;
     out5[3] = s->z.Mt;
     out5[4] = s->z.blocks;
+    return SIM_OK;
+}
+
+int sim_mapping(const sim_t* s, int32_t* out4)
+{
+    if (!s || !out4) return fail(SIM_EINVAL, "sim or out is NULL");
+    out4[0] = s->map.nw;
+    out4[1] = s->map.min_seg;
+    out4[2] = s->map.grid;
+    out4[3] = s->n_tiles;
     return SIM_OK;
 }
 

@@ -77,9 +77,11 @@ struct IParams {
     int* color_scratch;     // [N]
 };
 
-// Solver launch: snakes of at most `seg` bodies, 64/seg snakes per tile.
-hipError_t launch_step(int seg, const KParams& P, const int* tiles, int n_tiles, int n_steps,
-                       hipStream_t stream);
+// Solver launch: workgroups of nw waves over n_tiles tiles (grid-stride
+// when grid < n_tiles).  hdr[t] = {first slot, slots, spans waves, 0};
+// slot = {snake, lane offset << 8 | log2 segment}.
+hipError_t launch_tiles(int nw, const KParams& P, const int4* hdr, const int2* slots, int n_tiles,
+                        int grid, int n_steps, hipStream_t stream);
 hipError_t launch_index(const IParams& P, hipStream_t stream);
 hipError_t launch_init_state(const KParams& P, hipStream_t stream);
 hipError_t launch_set_cmd(float* dst, const float* src, int n, hipStream_t stream);

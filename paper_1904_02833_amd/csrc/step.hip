@@ -1,13 +1,15 @@
-// Solver kernels: one fused launch advances a tile of snakes by whole steps.
+// Solver kernel: one launch advances every snake by whole steps.
 //
-// Mapping (wave64, gfx950): a snake of B <= SEG bodies owns an aligned group
-// of SEG lanes; lane i holds body i (its state stays in VGPRs for the whole
+// Mapping (wave64, gfx950): a snake of B bodies owns an aligned segment of
+// 2^k >= B lanes; lane i holds body i (its state stays in VGPRs for the whole
 // launch), joint i (bodies i, i+1) and the ground contact of body i.  Each
-// iteration a lane fetches the displacement and orientation of body i+1 from
-// lane i+1, evaluates its three blocks, sends the increments of joint i that
-// land on body i+1 to lane i+1, and gathers in a fixed order.  The snake's
-// residual is an xor-butterfly max over its SEG lanes, so a snake stops at
-// its own tolerance while its wave continues for the others.
+// iteration a lane fetches the displacement, orientation and axis of body
+// i+1 from lane i+1, evaluates its three blocks, sends the increments of
+// joint i that land on body i+1 to lane i+1, and gathers in a fixed order.
+// Lane shifts use ds_bpermute (the LDS pipe), leaving the VALU, which bounds
+// the kernel, to the arithmetic.  The snake's residual is an xor-butterfly
+// max over its segment, so a snake stops at its own tolerance while its wave
+// continues for the others.
 //
 // Every substep: chamber pressure -> rest rotation of intra-module joints ->
 // predicted positions (first-order implicit step, section "Time-Stepping")
@@ -28,7 +30,7 @@ namespace {
 
 // geometry of joint i needed again by the increment application
 struct Geo {
-    V3 rA, rB, aA, aB;
+    V3 aA, aB;   // body axes; the attachment offsets are +-L/2 along them
     Q4 e, qA;
     float ct, st;
 };
@@ -50,22 +52,22 @@ __device__ __forceinline__ float paper_update(const KParams& P, float pf, float 
 // Stretch and bend-twist blocks of joint (A = i, B = i+1) at the current
 // iterate.  Returns the unscaled local solutions -(K + alpha~)^-1 (C + alpha~ l)
 // and the block residuals.
-__device__ __forceinline__ void joint_eval(V3 dxp, V3 dA, V3 dB, Q4 qA, Q4 qB, float c0h, float s0h,
-                                           float ct, float st, float wA, float c1A, float c2A,
-                                           float wB, float c1B, float c2B, float hl, float inv_L,
-                                           float comp_s, float comp_b, float comp_t, V3 ls, V3 lb,
-                                           Geo& g, V3& Dls, V3& Dlb, float& rs, float& rb)
+__device__ __forceinline__ void joint_eval(V3 dxp, V3 dA, V3 dB, Q4 qA, Q4 qB, V3 aA, V3 aB,
+                                           float c0h, float s0h, float ct, float st, float wA,
+                                           float c1A, float c2A, float wB, float c1B, float c2B,
+                                           float hl, float inv_L, float comp_s, float comp_b,
+                                           float comp_t, V3 ls, V3 lb, Geo& g, V3& Dls, V3& Dlb,
+                                           float& rs, float& rb)
 {
-    g.aA = qaxis(qA);
-    g.aB = qaxis(qB);
-    g.rA = hl * g.aA;
-    g.rB = (-hl) * g.aB;
+    g.aA = aA;   // body x axes R(q) e_x of A and B
+    g.aB = aB;
+    const V3 rA = hl * aA, rB = (-hl) * aB;
     g.qA = qA;
     g.ct = ct;
     g.st = st;
 
     // stretch: end point of A minus start point of B (eq. rigid_to_particle form)
-    const V3 C = (dxp + (dA - dB)) + (g.rA - g.rB);
+    const V3 C = (dxp + (dA - dB)) + (rA - rB);
     const V3 rhs = C + comp_s * ls;
     // K = (wA + wB) I + c1A hl^2 (I - aA aA^T) + c1B hl^2 (I - aB aB^T)
     const float kA = c1A * (hl * hl), kB = c1B * (hl * hl);
@@ -103,13 +105,15 @@ __device__ __forceinline__ void joint_eval(V3 dxp, V3 dA, V3 dB, Q4 qA, Q4 qB, f
 
 // W J^T of joint increments (dls, dlb) on bodies A and B
 __device__ __forceinline__ void joint_corr(const Geo& g, V3 dls, V3 dlb, float wA, float c1A,
-                                           float c2A, float wB, float c1B, float c2B, V3& dxA,
-                                           V3& dthA, V3& dxB, V3& dthB)
+                                           float c2A, float wB, float c1B, float c2B, float hl,
+                                           V3& dxA, V3& dthA, V3& dxB, V3& dthB)
 {
     dxA = wA * dls;
     dxB = (-wB) * dls;
-    const V3 thsA = c1A * cross(g.rA, dls);
-    const V3 thsB = (-c1B) * cross(g.rB, dls);
+    // Ia^-1 (rA x dl) with rA = hl aA, and -Ib^-1 (rB x dl) with rB = -hl aB
+    // (the axis component of r x dl vanishes)
+    const V3 thsA = (c1A * hl) * cross(g.aA, dls);
+    const V3 thsB = (c1B * hl) * cross(g.aB, dls);
     const V3 ev{g.e.x, g.e.y, g.e.z};
     const V3 y = g.e.w * dlb + cross(ev, dlb);
     const V3 y0{g.ct * y.x - g.st * y.y, g.st * y.x + g.ct * y.y, y.z};
@@ -139,267 +143,372 @@ __device__ __forceinline__ V3 contact_incr(V3 lc, float cn, V3 d, float sc, floa
     return V3{ln - lc.x, t0 - lc.y, t1 - lc.z};
 }
 
-template <int SEG>
-__global__ void __launch_bounds__(64) k_step(KParams P, const int* __restrict__ tiles, int n_steps)
+// Tile kernel.  A workgroup of NW waves takes tiles from the cost-ordered
+// tile list (grid-stride, so a grid smaller than the list is persistent).
+// A tile holds snakes in power-of-two lane segments placed largest first, so
+// each segment is aligned to its size: segments of <= 64 lanes stay inside a
+// wave, larger ones span whole waves and exchange the boundary body and the
+// residual through LDS (two workgroup barriers per iteration, only in tiles
+// that have such a snake).
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4)))
+k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, int n_tiles,
+       int n_steps)
 {
-    constexpr int PER = 64 / SEG;
-    const int lane = threadIdx.x;
-    const int i = lane & (SEG - 1);
-    const int s = tiles[blockIdx.x * PER + lane / SEG];
-    const bool live = s >= 0;
-    int B = 0, S = 1, bo = 0, mo = 0;
-    float comp_s = 0.f, comp_b = 0.f, comp_t = 0.f, mu = 0.f;
-    double freq = 0.0, ph0 = 0.0;
-    if (live) {
-        B = P.Bn[s];
-        S = P.Sn[s];
-        bo = P.body_off[s];
-        mo = P.module_off[s];
-        comp_s = P.comp[s];
-        comp_b = P.comp[P.n_snakes + s];
-        comp_t = P.comp[2 * P.n_snakes + s];
-        mu = P.mu[s];
-        freq = P.freq[s];
-        ph0 = P.phase0[s];
-    }
-    const bool hasb = i < B;
-    const bool hasj = i + 1 < B;
-    const int gnd = (P.flags & kNoGround) ? 0 : 1;
-    const bool fixed = (P.flags & kFixedRoot) && i == 0;
-    const int N = P.N, J = P.J, Mt = P.Mt;
-    const int gb = bo + i;
-    const int gj = bo - s + i;
-    const int m = i / S;
-    const int gm = mo + m;
-    const bool intra = hasj && ((i + 1) % S != 0);
-    // blocks on body i and body i+1; scale of a joint block uses the larger
-    const int dA = gnd + (i > 0 ? 2 : 0) + (i + 1 < B ? 2 : 0);
-    const int dB = gnd + 2 + (i + 2 < B ? 2 : 0);
-    const float sj = P.relax / (float)max(dA, dB);
-    const float sc = P.relax / (float)max(dA, 1);
-    const float wA = fixed ? 0.f : P.inv_m, c1A = fixed ? 0.f : P.c1, c2A = fixed ? 0.f : P.c2;
-    const float wB = P.inv_m, c1B = P.c1, c2B = P.c2;
-    const float hl = P.half_L, h = P.h, mass = 1.f / P.inv_m;
+    __shared__ float xnext[NW][12];  // lane 0 of each wave: u(3), q(4), axis(3), wave done
+    __shared__ float xprev[NW][6];   // lane 63 of each wave: increments on the next body
+    __shared__ float xred[NW];       // per-wave residual maximum
+    const int L = threadIdx.x;
+    const int lane = L & 63;
+    const int wv = L >> 6;
 
-    V3 x{0.f, 0.f, 0.f}, v{0.f, 0.f, 0.f}, w{0.f, 0.f, 0.f};
-    Q4 q{1.f, 0.f, 0.f, 0.f};
-    V3 ls{0.f, 0.f, 0.f}, lb{0.f, 0.f, 0.f}, lc{0.f, 0.f, 0.f};
-    float p0 = 0.f, p1 = 0.f, cmdv = 0.f;
-    if (hasb) {
-        x = mk(P.x[gb], P.x[N + gb], P.x[2 * N + gb]);
-        q = Q4{P.q[gb], P.q[N + gb], P.q[2 * N + gb], P.q[3 * N + gb]};
-        v = mk(P.v[gb], P.v[N + gb], P.v[2 * N + gb]);
-        w = mk(P.w[gb], P.w[N + gb], P.w[2 * N + gb]);
-        lc = mk(P.lam_c[gb], P.lam_c[N + gb], P.lam_c[2 * N + gb]);
-        p0 = P.p[gm];
-        p1 = P.p[Mt + gm];
-        cmdv = P.cmd[gm];
-    }
-    if (hasj) {
-        ls = mk(P.lam_j[gj], P.lam_j[J + gj], P.lam_j[2 * J + gj]);
-        lb = mk(P.lam_j[3 * J + gj], P.lam_j[4 * J + gj], P.lam_j[5 * J + gj]);
-    }
-    long long stepc = live ? P.step[s] : 0;
-    long long itot = live ? P.iters_total[s] : 0;
-    float rstep = 0.f;
-    int itstep = 0, status = 0;
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int4 H = hdr[tile];
+        const bool xw = (NW > 1) && H.z != 0;
+        if (NW > 1) __syncthreads();
 
-    for (int st = 0; st < n_steps; ++st) {
-        // command for the end of this step (eq. snake_control or a schedule)
-        if (hasb && P.controller == kCtrlSerpenoid) {
-            const double t = (double)(stepc + 1) * P.dt;
-            double a = sin(6.283185307179586476925286766559 * freq * t + P.ctrl_alpha * m + ph0) +
-                       P.ctrl_offset;
-            a = fmin(1.0, fmax(-1.0, a));
-            cmdv = (float)a;
-        } else if (hasb && P.controller == kCtrlSchedule) {
-            int lo = P.sched_off[gm], hi = P.sched_off[gm + 1] - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if ((long long)P.sched_start[mid] <= stepc)
-                    lo = mid;
-                else
-                    hi = mid - 1;
+        int s = -1, i = 0, lg = 6, off = 0;
+        for (int k = 0; k < H.y; ++k) {
+            const int2 sl = slots[H.x + k];
+            const int o = sl.y >> 8, l2 = sl.y & 0xff;
+            if (L >= o && L < o + (1 << l2)) {
+                s = sl.x;
+                i = L - o;
+                lg = l2;
+                off = o;
             }
-            cmdv = P.sched_val[lo];
         }
-        const float u0 = fmaxf(cmdv, 0.f), u1 = fmaxf(-cmdv, 0.f);
-        if (P.law == kLawPaper) {
-            p0 = paper_update(P, p0, u0);
-            p1 = paper_update(P, p1, u1);
+        const int seg = 1 << lg;
+        const int w0 = off >> 6;            // first wave of a multi-wave segment
+        const bool live = s >= 0;
+
+        // neighbour exchange: body i+1 of the same snake lives in lane+1, or
+        // for lane 63 of a spanning segment in lane 0 of the next wave
+        auto fetch_next = [&](V3 u, Q4 qq, V3 a, bool wave_done, V3& un, Q4& qn, V3& an) -> bool {
+            un = lane_next(u);
+            qn = lane_next(qq);
+            an = lane_next(a);
+            if (!xw) return false;
+            if (lane == 0) {
+                float* e = xnext[wv];
+                e[0] = u.x; e[1] = u.y; e[2] = u.z;
+                e[3] = qq.w; e[4] = qq.x; e[5] = qq.y; e[6] = qq.z;
+                e[7] = a.x; e[8] = a.y; e[9] = a.z;
+                e[10] = wave_done ? 1.f : 0.f;
+            }
+            __syncthreads();
+            bool all = true;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) all = all && (xnext[w][10] != 0.f);
+            if (lane == 63 && wv + 1 < NW) {
+                const float* e = xnext[wv + 1];
+                un = mk(e[0], e[1], e[2]);
+                qn = Q4{e[3], e[4], e[5], e[6]};
+                an = mk(e[7], e[8], e[9]);
+            }
+            return all;
+        };
+        // increments of joint i-1 arriving at body i, and the segment maximum
+        auto fetch_prev = [&](V3 dxB, V3 dthB, float rw, V3& inx, V3& inth) -> float {
+            inx = lane_prev(dxB);
+            inth = lane_prev(dthB);
+            if (!xw) return rw;
+            if (lane == 63) {
+                float* e = xprev[wv];
+                e[0] = dxB.x; e[1] = dxB.y; e[2] = dxB.z;
+                e[3] = dthB.x; e[4] = dthB.y; e[5] = dthB.z;
+            }
+            if (lane == 0) xred[wv] = rw;
+            __syncthreads();
+            if (lane == 0 && wv > 0) {
+                const float* e = xprev[wv - 1];
+                inx = mk(e[0], e[1], e[2]);
+                inth = mk(e[3], e[4], e[5]);
+            }
+            float r = rw;
+            if (seg > 64)
+                for (int w = 0; w < (seg >> 6); ++w) r = fmaxf(r, xred[w0 + w]);
+            return r;
+        };
+        auto seg_reduce = [&](float v) -> float {
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const float t = __shfl_xor(v, o, 64);
+                if (o < seg) v = fmaxf(v, t);
+            }
+            return v;
+        };
+
+        int B = 0, S = 1, bo = 0, mo = 0;
+        float comp_s = 0.f, comp_b = 0.f, comp_t = 0.f, mu = 0.f;
+        if (live) {
+            B = P.Bn[s];
+            S = P.Sn[s];
+            bo = P.body_off[s];
+            mo = P.module_off[s];
+            comp_s = P.comp[s];
+            comp_b = P.comp[P.n_snakes + s];
+            comp_t = P.comp[2 * P.n_snakes + s];
+            mu = P.mu[s];
         }
-        rstep = 0.f;
-        itstep = 0;
-        status = 0;
-        for (int sub = 0; sub < P.substeps; ++sub) {
-            if (P.law == kLawLag) {
-                p0 = u0 + (p0 - u0) * (u0 > p0 ? P.lag_in : P.lag_de);
-                p1 = u1 + (p1 - u1) * (u1 > p1 ? P.lag_in : P.lag_de);
-            }
-            // rest rotation of joint i about body z, angle kappa_max (p0 - p1) L
-            const float th0 = intra ? P.kappa_max * (p0 - p1) * P.L : 0.f;
-            float s0h, c0h;
-            sincosf(0.5f * th0, &s0h, &c0h);
-            const float ct = c0h * c0h - s0h * s0h, stt = 2.f * s0h * c0h;
+        const bool hasb = i < B;
+        const bool hasj = i + 1 < B;
+        const int gnd = (P.flags & kNoGround) ? 0 : 1;
+        const bool fixed = (P.flags & kFixedRoot) && i == 0;
+        const int N = P.N, J = P.J, Mt = P.Mt;
+        const int gb = bo + i;
+        const int gj = bo - s + i;
+        const int m = i / S;
+        const int gm = mo + m;
+        const bool intra = hasj && ((i + 1) % S != 0);
+        // blocks on body i and body i+1; a joint block is scaled by the larger
+        const int dA = gnd + (i > 0 ? 2 : 0) + (i + 1 < B ? 2 : 0);
+        const int dB = gnd + 2 + (i + 2 < B ? 2 : 0);
+        const float sj = P.relax / (float)max(dA, dB);
+        const float sc = P.relax / (float)max(dA, 1);
+        const float wA = fixed ? 0.f : P.inv_m, c1A = fixed ? 0.f : P.c1, c2A = fixed ? 0.f : P.c2;
+        const float wB = P.inv_m, c1B = P.c1, c2B = P.c2;
+        const float hl = P.half_L, h = P.h, mass = 1.f / P.inv_m;
+        const V3 zero{0.f, 0.f, 0.f};
 
-            // predicted positions
-            const V3 xp = x;
-            const Q4 qp = q;
-            V3 d{0.f, 0.f, 0.f};
-            if (hasb && !fixed) {
-                v.z -= h * P.g;
-                d = h * v;
-                const V3 ax = qaxis(q);
-                const V3 Iw = P.I_pe * w + ((P.I_ax - P.I_pe) * dot(ax, w)) * ax;
-                const V3 tq = -cross(w, Iw);
-                const V3 dw = P.c1 * tq + (P.c2 * dot(ax, tq)) * ax;
-                w = w + h * dw;
-                q = qturn(q, h * w);
-            } else if (fixed) {
-                v = V3{0.f, 0.f, 0.f};
-                w = V3{0.f, 0.f, 0.f};
-            }
-            const float zp = xp.z - P.R;
-            const V3 dxp = xp - lane_next(xp);
+        V3 x = zero, v = zero, w = zero;
+        Q4 q{1.f, 0.f, 0.f, 0.f};
+        V3 ls = zero, lb = zero, lc = zero;
+        float p0 = 0.f, p1 = 0.f, cmdv = 0.f;
+        if (hasb) {
+            x = mk(P.x[gb], P.x[N + gb], P.x[2 * N + gb]);
+            q = Q4{P.q[gb], P.q[N + gb], P.q[2 * N + gb], P.q[3 * N + gb]};
+            v = mk(P.v[gb], P.v[N + gb], P.v[2 * N + gb]);
+            w = mk(P.w[gb], P.w[N + gb], P.w[2 * N + gb]);
+            lc = mk(P.lam_c[gb], P.lam_c[N + gb], P.lam_c[2 * N + gb]);
+            p0 = P.p[gm];
+            p1 = P.p[Mt + gm];
+            cmdv = P.cmd[gm];
+        }
+        if (hasj) {
+            ls = mk(P.lam_j[gj], P.lam_j[J + gj], P.lam_j[2 * J + gj]);
+            lb = mk(P.lam_j[3 * J + gj], P.lam_j[4 * J + gj], P.lam_j[5 * J + gj]);
+        }
+        float rstep = 0.f;
+        int itstep = 0, status = 0, itsum = 0;
 
-            // multiplier initialisation
-            if (P.warm == kWarmPrev) {
-                // x <- x~ + W J(x~)^T lambda0 with lambda0 = previous multipliers
-                const V3 dn = lane_next(d);
-                const Q4 qn = lane_next(q);
-                Geo g;
-                V3 Dls, Dlb;
-                float rs, rb;
-                joint_eval(dxp, d, dn, q, qn, c0h, s0h, ct, stt, wA, c1A, c2A, wB, c1B, c2B, hl,
-                           P.inv_L, comp_s, comp_b, comp_t, ls, lb, g, Dls, Dlb, rs, rb);
-                V3 dxA, dthA, dxB, dthB;
-                joint_corr(g, ls, lb, wA, c1A, c2A, wB, c1B, c2B, dxA, dthA, dxB, dthB);
-                V3 inx = lane_prev(dxB), inth = lane_prev(dthB);
-                const bool recv = hasb && i > 0;
-                inx = sel(recv, inx, V3{0.f, 0.f, 0.f});
-                inth = sel(recv, inth, V3{0.f, 0.f, 0.f});
-                const V3 ownx = sel(hasj, dxA, V3{0.f, 0.f, 0.f});
-                const V3 ownth = sel(hasj, dthA, V3{0.f, 0.f, 0.f});
-                const V3 dxc = (gnd && !fixed) ? P.inv_m * mk(lc.y, lc.z, lc.x) : V3{0.f, 0.f, 0.f};
+        for (int st = 0; st < n_steps; ++st) {
+            const long long stepc = (live ? P.step[s] : 0) + st;
+            // command for the end of this step (eq. snake_control or a schedule)
+            if (hasb && P.controller == kCtrlSerpenoid) {
+                const double freq = P.freq[s], ph0 = P.phase0[s];
+                const double t = (double)(stepc + 1) * P.dt;
+                double a = sin(6.283185307179586476925286766559 * freq * t + P.ctrl_alpha * m + ph0) +
+                           P.ctrl_offset;
+                a = fmin(1.0, fmax(-1.0, a));
+                cmdv = (float)a;
+            } else if (hasb && P.controller == kCtrlSchedule) {
+                int lo = P.sched_off[gm], hi = P.sched_off[gm + 1] - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if ((long long)P.sched_start[mid] <= stepc)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                cmdv = P.sched_val[lo];
+            }
+            const float u0 = fmaxf(cmdv, 0.f), u1 = fmaxf(-cmdv, 0.f);
+            if (P.law == kLawPaper) {
+                p0 = paper_update(P, p0, u0);
+                p1 = paper_update(P, p1, u1);
+            }
+            rstep = 0.f;
+            itstep = 0;
+            status = 0;
+            for (int sub = 0; sub < P.substeps; ++sub) {
+                if (P.law == kLawLag) {
+                    p0 = u0 + (p0 - u0) * (u0 > p0 ? P.lag_in : P.lag_de);
+                    p1 = u1 + (p1 - u1) * (u1 > p1 ? P.lag_in : P.lag_de);
+                }
+                // rest rotation of joint i about body z, angle kappa_max (p0 - p1) L
+                const float th0 = intra ? P.kappa_max * (p0 - p1) * P.L : 0.f;
+                float s0h, c0h;
+                sincosf(0.5f * th0, &s0h, &c0h);
+                const float ct = c0h * c0h - s0h * s0h, stt = 2.f * s0h * c0h;
+
+                // predicted positions
+                const V3 xp = x;
+                const Q4 qp = q;
+                V3 d = zero;
                 if (hasb && !fixed) {
-                    d = d + ((inx + ownx) + dxc);
-                    q = qturn(q, inth + ownth);
+                    v.z -= h * P.g;
+                    d = h * v;
+                    const V3 ax = qaxis(q);
+                    const V3 Iw = P.I_pe * w + ((P.I_ax - P.I_pe) * dot(ax, w)) * ax;
+                    const V3 tq = -cross(w, Iw);
+                    const V3 dw = P.c1 * tq + (P.c2 * dot(ax, tq)) * ax;
+                    w = w + h * dw;
+                    q = qturn(q, h * w);
+                } else if (fixed) {
+                    v = zero;
+                    w = zero;
                 }
-            } else {
-                ls = V3{0.f, 0.f, 0.f};
-                lb = V3{0.f, 0.f, 0.f};
-                lc = V3{0.f, 0.f, 0.f};
-            }
-
-            bool done = !live;
-            int kdone = 0;
-            float rdone = 0.f;
-            for (int k = 0;; ++k) {
-                const V3 dn = lane_next(d);
-                const Q4 qn = lane_next(q);
-                Geo g;
-                V3 Dls, Dlb;
-                float rs, rb;
-                joint_eval(dxp, d, dn, q, qn, c0h, s0h, ct, stt, wA, c1A, c2A, wB, c1B, c2B, hl,
-                           P.inv_L, comp_s, comp_b, comp_t, ls, lb, g, Dls, Dlb, rs, rb);
-                const float cn = zp + d.z;
-                const float rc = (lc.x > 0.f ? fabsf(cn) : fmaxf(-cn, 0.f)) * P.inv_L;
-                float rl = fmaxf(hasj ? fmaxf(rs, rb) : 0.f, (hasb && gnd) ? rc : 0.f);
-                rl = (rl == rl) ? rl : INFINITY;
-                const float r = seg_max<SEG>(rl);
-                if (!done) {
-                    const bool bad = !(r < INFINITY);
-                    const bool stop = bad || (P.tol > 0.f ? (r <= P.tol || k >= P.iters) : (k >= P.iters));
-                    if (stop) {
-                        done = true;
-                        kdone = k;
-                        rdone = r;
-                        if (bad)
-                            status |= kStatusNonfinite;
-                        else if (P.tol > 0.f && r > P.tol)
-                            status |= kStatusNotConverged;
-                    }
+                const float zp = xp.z - P.R;
+                V3 dxp;
+                {
+                    V3 xpn, an;
+                    Q4 qn;
+                    fetch_next(xp, q, zero, false, xpn, qn, an);
+                    dxp = xp - xpn;
                 }
-                if (__all(done)) break;
 
-                const V3 dls = sj * Dls, dlb = sj * Dlb;
-                V3 dxA, dthA, dxB, dthB;
-                joint_corr(g, dls, dlb, wA, c1A, c2A, wB, c1B, c2B, dxA, dthA, dxB, dthB);
-                V3 dlc{0.f, 0.f, 0.f};
-                if (gnd && !fixed) dlc = contact_incr(lc, cn, d, sc, mass, mu);
-                const V3 dxc = P.inv_m * mk(dlc.y, dlc.z, dlc.x);
-                // gather in the fixed order: joint i-1 (from lane i-1), joint i, contact
-                V3 inx = lane_prev(dxB), inth = lane_prev(dthB);
-                const bool recv = hasb && i > 0;
-                inx = sel(recv, inx, V3{0.f, 0.f, 0.f});
-                inth = sel(recv, inth, V3{0.f, 0.f, 0.f});
-                const V3 ownx = sel(hasj, dxA, V3{0.f, 0.f, 0.f});
-                const V3 ownth = sel(hasj, dthA, V3{0.f, 0.f, 0.f});
-                if (!done) {
-                    if (hasj) {
-                        ls = ls + dls;
-                        lb = lb + dlb;
-                    }
-                    if (hasb && gnd) lc = lc + dlc;
+                // multiplier initialisation
+                if (P.warm == kWarmPrev) {
+                    // x <- x~ + W J(x~)^T lambda0 with lambda0 = previous multipliers
+                    const V3 aA = qaxis(q);
+                    V3 dn, an;
+                    Q4 qn;
+                    fetch_next(d, q, aA, false, dn, qn, an);
+                    Geo g;
+                    V3 Dls, Dlb;
+                    float rs, rb;
+                    joint_eval(dxp, d, dn, q, qn, aA, an, c0h, s0h, ct, stt, wA, c1A, c2A, wB, c1B,
+                               c2B, hl, P.inv_L, comp_s, comp_b, comp_t, ls, lb, g, Dls, Dlb, rs, rb);
+                    V3 dxA, dthA, dxB, dthB;
+                    joint_corr(g, ls, lb, wA, c1A, c2A, wB, c1B, c2B, hl, dxA, dthA, dxB, dthB);
+                    dxB = sel(hasj, dxB, zero);
+                    dthB = sel(hasj, dthB, zero);
+                    V3 inx, inth;
+                    fetch_prev(dxB, dthB, 0.f, inx, inth);
+                    const bool recv = hasb && i > 0;
+                    inx = sel(recv, inx, zero);
+                    inth = sel(recv, inth, zero);
+                    const V3 ownx = sel(hasj, dxA, zero);
+                    const V3 ownth = sel(hasj, dthA, zero);
+                    const V3 dxc = (gnd && !fixed) ? P.inv_m * mk(lc.y, lc.z, lc.x) : zero;
                     if (hasb && !fixed) {
                         d = d + ((inx + ownx) + dxc);
                         q = qturn(q, inth + ownth);
                     }
+                } else {
+                    ls = zero;
+                    lb = zero;
+                    lc = zero;
+                }
+
+                bool done = !live;
+                int kdone = 0;
+                float rdone = 0.f;
+                for (int k = 0;; ++k) {
+                    const V3 aA = qaxis(q);
+                    V3 dn, an;
+                    Q4 qn;
+                    const bool wave_done = __all(done);
+                    const bool all_done = fetch_next(d, q, aA, wave_done, dn, qn, an);
+                    if (xw ? all_done : wave_done) break;
+                    Geo g;
+                    V3 Dls, Dlb;
+                    float rs, rb;
+                    joint_eval(dxp, d, dn, q, qn, aA, an, c0h, s0h, ct, stt, wA, c1A, c2A, wB, c1B,
+                               c2B, hl, P.inv_L, comp_s, comp_b, comp_t, ls, lb, g, Dls, Dlb, rs, rb);
+                    const float cn = zp + d.z;
+                    const float rc = (lc.x > 0.f ? fabsf(cn) : fmaxf(-cn, 0.f)) * P.inv_L;
+                    float rl = fmaxf(hasj ? fmaxf(rs, rb) : 0.f, (hasb && gnd) ? rc : 0.f);
+                    rl = (rl == rl) ? rl : INFINITY;
+                    rl = seg_reduce(rl);
+
+                    const V3 dls = sj * Dls, dlb = sj * Dlb;
+                    V3 dxA, dthA, dxB, dthB;
+                    joint_corr(g, dls, dlb, wA, c1A, c2A, wB, c1B, c2B, hl, dxA, dthA, dxB, dthB);
+                    dxB = sel(hasj, dxB, zero);
+                    dthB = sel(hasj, dthB, zero);
+                    V3 inx, inth;
+                    const float r = fetch_prev(dxB, dthB, rl, inx, inth);
+
+                    if (!done) {
+                        const bool bad = !(r < INFINITY);
+                        const bool stop = bad || (P.tol > 0.f ? (r <= P.tol || k >= P.iters) : (k >= P.iters));
+                        if (stop) {
+                            done = true;
+                            kdone = k;
+                            rdone = r;
+                            if (bad)
+                                status |= kStatusNonfinite;
+                            else if (P.tol > 0.f && r > P.tol)
+                                status |= kStatusNotConverged;
+                        }
+                    }
+                    if (!done) {
+                        V3 dlc = zero;
+                        if (gnd && !fixed) dlc = contact_incr(lc, cn, d, sc, mass, mu);
+                        const V3 dxc = P.inv_m * mk(dlc.y, dlc.z, dlc.x);
+                        // gather in the fixed order: joint i-1, joint i, contact
+                        const bool recv = hasb && i > 0;
+                        inx = sel(recv, inx, zero);
+                        inth = sel(recv, inth, zero);
+                        const V3 ownx = sel(hasj, dxA, zero);
+                        const V3 ownth = sel(hasj, dthA, zero);
+                        if (hasj) {
+                            ls = ls + dls;
+                            lb = lb + dlb;
+                        }
+                        if (hasb && gnd) lc = lc + dlc;
+                        if (hasb && !fixed) {
+                            d = d + ((inx + ownx) + dxc);
+                            q = qturn(q, inth + ownth);
+                        }
+                    }
+                }
+                itstep += kdone;
+                rstep = fmaxf(rstep, rdone);
+
+                // velocities of the implicit step
+                if (hasb && !fixed) {
+                    x = xp + d;
+                    v = P.inv_h * d;
+                    const Q4 dq = qmul(q, qconj(qp));
+                    const float sg = dq.w >= 0.f ? 2.f * P.inv_h : -2.f * P.inv_h;
+                    w = mk(sg * dq.x, sg * dq.y, sg * dq.z);
                 }
             }
-            itstep += kdone;
-            rstep = fmaxf(rstep, rdone);
+            itsum += itstep;
+        }
 
-            // velocities of the implicit step
-            if (hasb && !fixed) {
-                x = xp + d;
-                v = P.inv_h * d;
-                const Q4 dq = qmul(q, qconj(qp));
-                const float sg = dq.w >= 0.f ? 2.f * P.inv_h : -2.f * P.inv_h;
-                w = mk(sg * dq.x, sg * dq.y, sg * dq.z);
+        if (hasb) {
+            P.x[gb] = x.x;
+            P.x[N + gb] = x.y;
+            P.x[2 * N + gb] = x.z;
+            P.q[gb] = q.w;
+            P.q[N + gb] = q.x;
+            P.q[2 * N + gb] = q.y;
+            P.q[3 * N + gb] = q.z;
+            P.v[gb] = v.x;
+            P.v[N + gb] = v.y;
+            P.v[2 * N + gb] = v.z;
+            P.w[gb] = w.x;
+            P.w[N + gb] = w.y;
+            P.w[2 * N + gb] = w.z;
+            P.lam_c[gb] = lc.x;
+            P.lam_c[N + gb] = lc.y;
+            P.lam_c[2 * N + gb] = lc.z;
+            if (i % S == 0) {
+                P.p[gm] = p0;
+                P.p[Mt + gm] = p1;
+                P.cmd[gm] = cmdv;
             }
         }
-        stepc += 1;
-        itot += itstep;
-    }
-
-    if (hasb) {
-        P.x[gb] = x.x;
-        P.x[N + gb] = x.y;
-        P.x[2 * N + gb] = x.z;
-        P.q[gb] = q.w;
-        P.q[N + gb] = q.x;
-        P.q[2 * N + gb] = q.y;
-        P.q[3 * N + gb] = q.z;
-        P.v[gb] = v.x;
-        P.v[N + gb] = v.y;
-        P.v[2 * N + gb] = v.z;
-        P.w[gb] = w.x;
-        P.w[N + gb] = w.y;
-        P.w[2 * N + gb] = w.z;
-        P.lam_c[gb] = lc.x;
-        P.lam_c[N + gb] = lc.y;
-        P.lam_c[2 * N + gb] = lc.z;
-        if (i % S == 0) {
-            P.p[gm] = p0;
-            P.p[Mt + gm] = p1;
-            P.cmd[gm] = cmdv;
+        if (hasj) {
+            P.lam_j[gj] = ls.x;
+            P.lam_j[J + gj] = ls.y;
+            P.lam_j[2 * J + gj] = ls.z;
+            P.lam_j[3 * J + gj] = lb.x;
+            P.lam_j[4 * J + gj] = lb.y;
+            P.lam_j[5 * J + gj] = lb.z;
         }
-    }
-    if (hasj) {
-        P.lam_j[gj] = ls.x;
-        P.lam_j[J + gj] = ls.y;
-        P.lam_j[2 * J + gj] = ls.z;
-        P.lam_j[3 * J + gj] = lb.x;
-        P.lam_j[4 * J + gj] = lb.y;
-        P.lam_j[5 * J + gj] = lb.z;
-    }
-    if (live && i == 0) {
-        P.residual[s] = rstep;
-        P.iters_out[s] = itstep;
-        P.status[s] = status;
-        P.step[s] = stepc;
-        P.iters_total[s] = itot;
+        if (NW > 1) __syncthreads();   // every lane has read step[s] before it moves
+        if (live && i == 0) {
+            P.residual[s] = rstep;
+            P.iters_out[s] = itstep;
+            P.status[s] = status;
+            P.step[s] = P.step[s] + n_steps;
+            P.iters_total[s] = P.iters_total[s] + itsum;
+        }
     }
 }
 
@@ -459,15 +568,18 @@ __global__ void k_set_cmd(float* dst, const float* src, int n)
 
 }  // namespace
 
-hipError_t launch_step(int seg, const KParams& P, const int* tiles, int n_tiles, int n_steps,
-                       hipStream_t stream)
+hipError_t launch_tiles(int nw, const KParams& P, const int4* hdr, const int2* slots, int n_tiles,
+                        int grid, int n_steps, hipStream_t stream)
 {
     if (n_tiles <= 0) return hipSuccess;
-    const dim3 grid(n_tiles), block(64);
-    switch (seg) {
-        case 16: hipLaunchKernelGGL(k_step<16>, grid, block, 0, stream, P, tiles, n_steps); break;
-        case 32: hipLaunchKernelGGL(k_step<32>, grid, block, 0, stream, P, tiles, n_steps); break;
-        case 64: hipLaunchKernelGGL(k_step<64>, grid, block, 0, stream, P, tiles, n_steps); break;
+    if (grid <= 0 || grid > n_tiles) grid = n_tiles;
+    const dim3 g(grid), b(64 * nw);
+    switch (nw) {
+        case 1: hipLaunchKernelGGL(k_tile<1>, g, b, 0, stream, P, hdr, slots, n_tiles, n_steps); break;
+        case 2: hipLaunchKernelGGL(k_tile<2>, g, b, 0, stream, P, hdr, slots, n_tiles, n_steps); break;
+        case 4: hipLaunchKernelGGL(k_tile<4>, g, b, 0, stream, P, hdr, slots, n_tiles, n_steps); break;
+        case 8: hipLaunchKernelGGL(k_tile<8>, g, b, 0, stream, P, hdr, slots, n_tiles, n_steps); break;
+        case 16: hipLaunchKernelGGL(k_tile<16>, g, b, 0, stream, P, hdr, slots, n_tiles, n_steps); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -277,3 +277,96 @@ def test_set_pressures_errors_and_device_path():
     torch.cuda.synchronize()
     assert np.array_equal(sim.read("cmd")["cmd"], np.array([1, -0.5, 0, 0.25, -1], np.float32))
     sim.close()
+
+
+# ---------------------------------------------------------------- long chains
+
+def test_substep_parity_multiwave_lengths():
+    """Snakes spanning 2..16 waves (boundary bodies and residuals through
+    LDS), mixed with short ones in the same tiles."""
+    wl = W.custom([1, 1, 1, 2, 4, 1, 8, 4, 1, 2], [65, 100, 128, 100, 64, 300, 64, 128, 17, 8],
+                  mu=0.5, controller=W.CTRL_EXTERNAL)
+    o = oracle.Oracle(wl)
+    o.cmd[:] = np.sin(np.arange(o.cmd.size))
+    o.run(15, threads=8)
+    oo, g = advance_both(wl, rounded_state(o))
+    assert_parity("multiwave", compare(oo, g, wl.mu), n_bodies=wl.total_bodies)
+
+
+def test_substep_parity_uneven_full_range():
+    wl = W.make("uneven", n_snakes=90)
+    assert wl.bodies.max() > 128
+    o = oracle.Oracle(wl)
+    o.run(20, threads=8)
+    o.commands()
+    oo, g = advance_both(wl, rounded_state(o))
+    assert_parity("uneven-full", compare(oo, g, wl.mu), n_bodies=wl.total_bodies)
+
+
+def test_substep_parity_stiff_1024():
+    wl = W.make("stiff", n_snakes=2)
+    wl.tol, wl.iters = 0.0, 20
+    o = oracle.Oracle(wl)
+    o.run(6, threads=2)
+    o.commands()
+    oo, g = advance_both(wl, rounded_state(o))
+    assert_parity("stiff", compare(oo, g, wl.mu), n_bodies=wl.total_bodies)
+
+
+def test_tolerance_mode_matches_oracle_iterations():
+    """Tolerance mode on short chains that do converge (several snakes per
+    wave stop at different iterations): the iteration counts
+    of the two precisions agree up to the substeps whose residual sits at the
+    threshold, and every converged substep reports a residual <= tol."""
+    # without friction these short chains converge in tens of iterations
+    wl = W.custom([1] * 12, [2, 3, 4, 5, 6, 7, 8, 3, 4, 5, 6, 7], controller=W.CTRL_EXTERNAL,
+                  tol=1e-4, iters=400, mu=0.0, substeps=1, dt=1 / 240)
+    o = oracle.Oracle(wl)
+    o.cmd[:] = np.linspace(-1, 1, 12)
+    o.run(10)
+    st = rounded_state(o)
+    oo, g = advance_both(wl, st)
+    print("\n[tol] oracle iters", oo.iters, "gpu iters", g["iters"])
+    assert np.all(g["residual"][g["status"] == 0] <= 1e-4)
+    assert np.abs(g["iters"] - oo.iters).max() <= 2
+    assert (g["iters"] == oo.iters).mean() >= 0.75
+
+
+# ---------------------------------------------------------------- mappings
+
+MAPPINGS = [dict(map_waves=4, map_min_seg=16), dict(map_waves=4, map_min_seg=64),
+            dict(map_waves=8, map_min_seg=32), dict(map_waves=16, map_min_seg=16),
+            dict(map_waves=4, map_min_seg=16, map_grid=64)]
+
+
+def test_all_mappings_bit_identical():
+    wl = W.make("uneven", n_snakes=300)
+    ref = None
+    for mp in MAPPINGS:
+        sim = snk.Sim(wl, **mp)
+        sim.step(4)
+        r = sim.read()
+        print(mp, sim.mapping)
+        if ref is None:
+            ref = r
+        else:
+            for k in r:
+                assert np.array_equal(r[k], ref[k]), (mp, k)
+        sim.close()
+
+
+def test_autotune_restores_state_and_matches():
+    wl = W.make("uneven", n_snakes=200)
+    a = snk.Sim(wl, autotune=1)
+    b = snk.Sim(wl)
+    print("\n[autotune] picked", a.mapping, "default", b.mapping)
+    ra0, rb0 = a.read(), b.read()
+    for k in ra0:
+        assert np.array_equal(ra0[k], rb0[k]), k
+    a.step(3)
+    b.step(3)
+    ra, rb = a.read(), b.read()
+    for k in ra:
+        assert np.array_equal(ra[k], rb[k]), k
+    a.close()
+    b.close()
