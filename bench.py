@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--workload", default="uniform")
     ap.add_argument("--snakes", type=int, default=None)
     ap.add_argument("--fixed", action="store_true", help="fixed 20 iterations per substep")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-snakes", type=int, default=1024)
     ap.add_argument("--cpu-steps", type=int, default=12)
@@ -82,7 +83,7 @@ def main():
         wl.tol, wl.iters = 0.0, 20
     else:
         wl.tol, wl.iters = 1e-4, 200
-    sim = snk.Sim(wl, use_graph=1)
+    sim = snk.Sim(wl, use_graph=1, autotune=0 if args.no_autotune else 1)
     stream = sim.stream
     for _ in range(args.warmup):
         sim.step(1)
@@ -136,12 +137,13 @@ def main():
                                "max": float(np.max(r["residual"]))},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-                     "kernel": "k_step<64>", "flop_per_body_iter": FLOP_ITER,
+                     "kernel": f"k_tile<{sim.mapping['waves']}>", "mapping": sim.mapping,
+                     "flop_per_body_iter": FLOP_ITER,
                      "hbm_frac_algorithmic": hbm_bytes / (per_launch_ms / 1e3) / PEAK_HBM},
     }
-    sim.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_snakes, args.cpu_steps)
+    sim.close()
     print(json.dumps(out), flush=True)
 
 

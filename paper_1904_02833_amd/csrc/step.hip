@@ -155,7 +155,11 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4)
 k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, int n_tiles,
        int n_steps)
 {
-    __shared__ float xnext[NW][12];  // lane 0 of each wave: u(3), q(4), axis(3), wave done
+    // lane 0 of each wave: u(3), q(4), axis(3), wave done.  Buffer 2 is used
+    // at the start of a substep, buffers 0/1 alternate between iterations (and
+    // buffer 1 serves the warm start): a buffer is written again only after a
+    // barrier that every reader of its previous contents has passed.
+    __shared__ float xnext[3][NW][12];
     __shared__ float xprev[NW][6];   // lane 63 of each wave: increments on the next body
     __shared__ float xred[NW];       // per-wave residual maximum
     const int L = threadIdx.x;
@@ -184,13 +188,14 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
 
         // neighbour exchange: body i+1 of the same snake lives in lane+1, or
         // for lane 63 of a spanning segment in lane 0 of the next wave
-        auto fetch_next = [&](V3 u, Q4 qq, V3 a, bool wave_done, V3& un, Q4& qn, V3& an) -> bool {
+        auto fetch_next = [&](int buf, V3 u, Q4 qq, V3 a, bool wave_done, V3& un, Q4& qn,
+                              V3& an) -> bool {
             un = lane_next(u);
             qn = lane_next(qq);
             an = lane_next(a);
             if (!xw) return false;
             if (lane == 0) {
-                float* e = xnext[wv];
+                float* e = xnext[buf][wv];
                 e[0] = u.x; e[1] = u.y; e[2] = u.z;
                 e[3] = qq.w; e[4] = qq.x; e[5] = qq.y; e[6] = qq.z;
                 e[7] = a.x; e[8] = a.y; e[9] = a.z;
@@ -199,9 +204,9 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
             __syncthreads();
             bool all = true;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) all = all && (xnext[w][10] != 0.f);
+            for (int w = 0; w < NW; ++w) all = all && (xnext[buf][w][10] != 0.f);
             if (lane == 63 && wv + 1 < NW) {
-                const float* e = xnext[wv + 1];
+                const float* e = xnext[buf][wv + 1];
                 un = mk(e[0], e[1], e[2]);
                 qn = Q4{e[3], e[4], e[5], e[6]};
                 an = mk(e[7], e[8], e[9]);
@@ -354,7 +359,7 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                 {
                     V3 xpn, an;
                     Q4 qn;
-                    fetch_next(xp, q, zero, false, xpn, qn, an);
+                    fetch_next(2, xp, q, zero, false, xpn, qn, an);
                     dxp = xp - xpn;
                 }
 
@@ -364,7 +369,7 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                     const V3 aA = qaxis(q);
                     V3 dn, an;
                     Q4 qn;
-                    fetch_next(d, q, aA, false, dn, qn, an);
+                    fetch_next(1, d, q, aA, false, dn, qn, an);
                     Geo g;
                     V3 Dls, Dlb;
                     float rs, rb;
@@ -400,7 +405,7 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                     V3 dn, an;
                     Q4 qn;
                     const bool wave_done = __all(done);
-                    const bool all_done = fetch_next(d, q, aA, wave_done, dn, qn, an);
+                    const bool all_done = fetch_next(k & 1, d, q, aA, wave_done, dn, qn, an);
                     if (xw ? all_done : wave_done) break;
                     Geo g;
                     V3 Dls, Dlb;

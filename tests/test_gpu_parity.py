@@ -370,3 +370,20 @@ def test_autotune_restores_state_and_matches():
         assert np.array_equal(ra[k], rb[k]), k
     a.close()
     b.close()
+
+
+def test_uneven_full_batch_residuals_stay_bounded():
+    """The full 16384-snake uneven batch for 30 steps: no snake's residual
+    may spike (a spike of |x|/L showed a stale neighbour exchange between
+    waves of a spanning snake) and every snake stays finite."""
+    wl = W.make("uneven")
+    sim = snk.Sim(wl)
+    worst = 0.0
+    for n in range(30):
+        sim.step(1)
+        r = sim.read("residual", "status")
+        assert not np.any(r["status"] & snk.STATUS_NONFINITE)
+        worst = max(worst, float(r["residual"].max()))
+        assert r["residual"].max() < 1.0, (n, int(np.argmax(r["residual"])), float(r["residual"].max()))
+    print(f"\n[uneven-full] worst residual over 30 steps {worst:.3g}")
+    sim.close()
