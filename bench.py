@@ -32,6 +32,12 @@ FLOP_ITER = 542
 FLOP_EVAL = 336
 FLOP_SUBSTEP = 100
 PEAK_FP32 = 157.3e12       # MI355X FP32 vector, packed; 78.6e12 without packed FP32
+# HBM bytes per launch of the solver kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs scaled by a device copy of known size (summaries in
+# profiles/), keyed by workload and waves per workgroup, with the digest of
+# the kernel sources they were taken on; a changed kernel reports null.
+MEASURED_TRAFFIC = {("uniform", 4): 136.3e6, ("uneven", 4): 913.9e6}
+TRAFFIC_SOURCES_DIGEST = "174bdb2cebbfaff4:46f9fd9afa94955f:fcc196db1ba34bbf"
 PEAK_HBM = 8.0e12
 STATE_BYTES = 4 * (13 + 13 + 9 + 9)   # per body: state in/out, multipliers in/out
 
@@ -49,6 +55,13 @@ def parse():
     ap.add_argument("--cpu-snakes", type=int, default=1024)
     ap.add_argument("--cpu-steps", type=int, default=12)
     return ap.parse_args()
+
+
+def kernel_digest():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1904_02833_amd", "csrc")
+    return ":".join(hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()[:16]
+                    for f in ("step.hip", "device_math.h", "kernels.h"))
 
 
 def cpu_baseline(wl, n_snakes, n_steps):
@@ -110,6 +123,9 @@ def main():
     per_launch_ms = ms / args.steps
     achieved = flops / args.steps / (per_launch_ms / 1e3)
     hbm_bytes = float(B.sum()) * STATE_BYTES
+    traffic = MEASURED_TRAFFIC.get((args.workload, sim.mapping["waves"]))
+    if traffic is not None and kernel_digest() != TRAFFIC_SOURCES_DIGEST:
+        traffic = None
     out = {
         "metric": METRIC,
         "value": snake_steps,
@@ -136,7 +152,7 @@ def main():
                                "p99": float(np.percentile(r["residual"], 99)),
                                "max": float(np.max(r["residual"]))},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic,
                      "kernel": f"k_tile<{sim.mapping['waves']}>", "mapping": sim.mapping,
                      "flop_per_body_iter": FLOP_ITER,
                      "hbm_frac_algorithmic": hbm_bytes / (per_launch_ms / 1e3) / PEAK_HBM},
