@@ -22,6 +22,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "snake_oracle.c")
+SRCS = [SRC, os.path.join(HERE, "mlp_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 FLAG_FIXED_ROOT = 1
@@ -36,18 +37,22 @@ _lib = None
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, no fast-math)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    if force or _stale():
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, *SRCS, "-lm"])
         os.replace(tmp, LIB)
     return LIB
+
+
+def _stale():
+    return not os.path.exists(LIB) or any(os.path.getmtime(LIB) < os.path.getmtime(s) for s in SRCS)
 
 
 def lib():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            if _stale():
                 build(force=True)
             _lib = C.CDLL(LIB)
             _declare(_lib)
@@ -94,6 +99,13 @@ def _declare(L):
     L.orc_assemble.restype = C.c_int
     L.orc_predict_snake.argtypes = [bp, C.c_int32, _P, _P, _P, _P, C.c_double]
     L.orc_index.argtypes = [bp] + [_P] * 7
+    L.mlo_param_count.restype = C.c_int
+    L.mlo_norm_stats.argtypes = [_P, C.c_int64, _P, _P]
+    L.mlo_forward.argtypes = [_P, _P, _P, _P, C.c_int64, _P]
+    L.mlo_loss_grad.argtypes = [_P, _P, _P, _P, _P, C.c_int64, _P]
+    L.mlo_loss_grad.restype = C.c_double
+    L.mlo_adam.argtypes = [_P, _P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                           C.c_double]
 
 
 def _ptr(a):
@@ -245,3 +257,40 @@ class Oracle:
         out.update(body_off=self.body_off.copy(), joint_off=self.joint_off.copy(),
                    module_off=self.module_off.copy(), block_off=self.block_off.copy())
         return out
+
+
+# ---------------------------------------------------------------- MLP oracle
+
+def _d(a):
+    return np.ascontiguousarray(np.asarray(a, np.float64))
+
+
+def mlp_param_count() -> int:
+    return int(lib().mlo_param_count())
+
+
+def mlp_norm_stats(x):
+    x = _d(x)
+    mean, std = np.zeros(32), np.zeros(32)
+    lib().mlo_norm_stats(_ptr(x), x.shape[0], _ptr(mean), _ptr(std))
+    return mean, std
+
+
+def mlp_forward(params, mean, std, x):
+    params, mean, std, x = _d(params), _d(mean), _d(std), _d(x)
+    y = np.zeros((x.shape[0], 3))
+    lib().mlo_forward(_ptr(params), _ptr(mean), _ptr(std), _ptr(x), x.shape[0], _ptr(y))
+    return y
+
+
+def mlp_loss_grad(params, mean, std, x, t, with_grad=True):
+    params, mean, std, x, t = _d(params), _d(mean), _d(std), _d(x), _d(t)
+    g = np.zeros(params.size) if with_grad else None
+    loss = lib().mlo_loss_grad(_ptr(params), _ptr(mean), _ptr(std), _ptr(x), _ptr(t), x.shape[0],
+                               _ptr(g))
+    return loss, g
+
+
+def mlp_adam(params, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step in place on float64 arrays."""
+    lib().mlo_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(_d(g)), params.size, int(t), lr, b1, b2, eps)

@@ -263,3 +263,86 @@ class Sim:
         a = np.empty(ln, np.int32)
         _check(self.L.sim_read_index(self.h, k, a.ctypes.data_as(_P), ln))
         return a
+
+
+# ---------------------------------------------------------------- network
+
+MLP_EXPORTS = ["mlp_param_count", "mlp_train_scratch_floats", "mlp_norm_stats", "mlp_forward",
+               "mlp_grad", "mlp_adam", "mlp_last_error"]
+
+
+def _mlp_lib():
+    L = lib()
+    if not getattr(L, "_mlp_declared", False):
+        L.mlp_param_count.restype = C.c_int
+        L.mlp_train_scratch_floats.argtypes = [C.c_int64]
+        L.mlp_train_scratch_floats.restype = C.c_int64
+        L.mlp_norm_stats.argtypes = [_P, C.c_int64, _P, _P]
+        L.mlp_forward.argtypes = [_P, _P, _P, _P, C.c_int64, _P]
+        L.mlp_grad.argtypes = [_P, _P, _P, _P, C.c_int64, _P, _P, _P, C.c_int64, _P]
+        L.mlp_adam.argtypes = [_P, _P, _P, _P, C.c_int32, C.c_float, _P]
+        L.mlp_last_error.restype = C.c_char_p
+        L._mlp_declared = True
+    return L
+
+
+def _mcheck(rc):
+    if rc != SIM_OK:
+        raise SimError(rc, _mlp_lib().mlp_last_error().decode())
+
+
+def _dp(t):
+    assert t.is_cuda and t.is_contiguous() and t.dtype.is_floating_point
+    return _P(t.data_ptr())
+
+
+def _stream(t):
+    import torch
+    return _P(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+class Net:
+    """Device-resident warm-start network: FP32 parameters, normalisation
+    statistics and Adam state in torch tensors; every operation runs in the
+    library's kernels."""
+
+    def __init__(self, params, mean_std, device="cuda"):
+        import torch
+        self.torch = torch
+        self.P = int(_mlp_lib().mlp_param_count())
+        self.params = torch.as_tensor(params, dtype=torch.float32, device=device).contiguous()
+        self.mean_std = torch.as_tensor(mean_std, dtype=torch.float32, device=device).contiguous()
+        assert self.params.numel() == self.P and self.mean_std.numel() == 64
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        self._scratch = None
+
+    @staticmethod
+    def norm_stats(x):
+        import torch
+        ms = torch.empty(64, dtype=torch.float32, device=x.device)
+        _mcheck(_mlp_lib().mlp_norm_stats(_dp(x), x.shape[0], _dp(ms), _stream(x)))
+        return ms
+
+    def forward(self, x):
+        y = self.torch.empty((x.shape[0], 3), dtype=self.torch.float32, device=x.device)
+        _mcheck(_mlp_lib().mlp_forward(_dp(self.params), _dp(self.mean_std), _dp(x), _dp(y),
+                                       x.shape[0], _stream(x)))
+        return y
+
+    def grad(self, x, t):
+        L = _mlp_lib()
+        need = int(L.mlp_train_scratch_floats(x.shape[0]))
+        if self._scratch is None or self._scratch.numel() < need:
+            self._scratch = self.torch.empty(need, dtype=self.torch.float32, device=x.device)
+        g = self.torch.empty_like(self.params)
+        loss = self.torch.empty(1, dtype=self.torch.float32, device=x.device)
+        _mcheck(L.mlp_grad(_dp(self.params), _dp(self.mean_std), _dp(x), _dp(t), x.shape[0], _dp(g),
+                           _dp(loss), _dp(self._scratch), self._scratch.numel(), _stream(x)))
+        return g, loss
+
+    def adam(self, g, lr=1e-3):
+        self.t += 1
+        _mcheck(_mlp_lib().mlp_adam(_dp(self.params), _dp(self.m), _dp(self.v), _dp(g), self.t,
+                                    float(lr), _stream(g)))

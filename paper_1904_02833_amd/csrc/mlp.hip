@@ -1,0 +1,344 @@
+// Warm-start network kernels (gfx950): a 32 -> 64 -> 64 -> 3 perceptron with
+// exact-erf GELU, evaluated and trained with BF16 MFMA (v_mfma_f32_16x16x32_bf16)
+// accumulating in FP32.
+//
+// One wave takes a chunk of 64 samples.  Weights, activations and
+// pre-activations of the chunk sit in LDS; every product is a small GEMM
+// computed tile by tile (16 x 16 output tiles, K in steps of 32).  Operands
+// are rounded to BF16 (round to nearest even) when they enter an MFMA; biases,
+// GELU and the loss are FP32.  Training writes one gradient row per chunk;
+// a second kernel sums the rows in chunk order (deterministic) and a third
+// applies Adam.
+#include "snake_mlp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+namespace {
+
+constexpr int NI = 32, NH = 64, NO = 3;
+constexpr int P_W1 = 0, P_B1 = P_W1 + NH * NI, P_W2 = P_B1 + NH, P_B2 = P_W2 + NH * NH;
+constexpr int P_W3 = P_B2 + NH, P_B3 = P_W3 + NO * NH, P_COUNT = P_B3 + NO;
+constexpr int CH = 64;  // samples per chunk (one wave)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+thread_local std::string g_mlp_err;
+
+int mfail(int code, const std::string& m)
+{
+    g_mlp_err = m;
+    return code;
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float z)
+{
+    return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+}
+
+// C[M x N] = A[M x K] B[K x N] for M, N multiples of 16 and K of 32, on one
+// wave.  Lane l supplies A rows l % 16 and B columns l % 16 for the k-slice
+// 8 (l / 16) .. +8 and receives D rows 4 (l / 16) .. +4 of column l % 16.
+template <class FA, class FB, class FS>
+__device__ __forceinline__ void wave_gemm(int mtiles, int ntiles, int ktiles, FA A, FB Bm, FS store)
+{
+    const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+    for (int mt = 0; mt < mtiles; ++mt)
+        for (int nt = 0; nt < ntiles; ++nt) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            for (int kt = 0; kt < ktiles; ++kt) {
+                bf16x8 a, b;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    a[j] = A(mt * 16 + r, kt * 32 + 8 * g + j);
+                    b[j] = Bm(kt * 32 + 8 * g + j, nt * 16 + r);
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) store(mt * 16 + 4 * g + v, nt * 16 + r, acc[v]);
+        }
+}
+
+struct Lds {
+    __bf16 W1[NH][NI];
+    __bf16 W2[NH][NH];
+    __bf16 W3[16][NH];   // rows >= 3 are zero
+    __bf16 X[CH][NI];
+    __bf16 H1[CH][NH];
+    __bf16 H2[CH][NH];
+    float Z1[CH][NH];    // pre-activation, later d loss / d z1
+    float Z2[CH][NH];
+    __bf16 dY[CH][16];   // columns >= 3 are zero
+    __bf16 dZ[CH][NH];
+    float dYf[CH][NO];
+    float red[64];
+};
+
+__device__ void load_weights(Lds& S, const float* __restrict__ p)
+{
+    const int l = threadIdx.x;
+    for (int e = l; e < NH * NI; e += 64) S.W1[e / NI][e % NI] = (__bf16)p[P_W1 + e];
+    for (int e = l; e < NH * NH; e += 64) S.W2[e / NH][e % NH] = (__bf16)p[P_W2 + e];
+    for (int e = l; e < 16 * NH; e += 64) S.W3[e / NH][e % NH] = e < NO * NH ? (__bf16)p[P_W3 + e] : (__bf16)0.f;
+}
+
+// forward pass of one chunk; samples past n contribute zeros
+__device__ void chunk_forward(Lds& S, const float* __restrict__ p, const float* __restrict__ ms,
+                              const float* __restrict__ x, int64_t base, int64_t n, float* y_out)
+{
+    const int l = threadIdx.x;
+    for (int e = l; e < CH * NI; e += 64) {
+        const int s = e / NI, k = e % NI;
+        const int64_t row = base + s;
+        const float v = row < n ? (x[row * NI + k] - ms[k]) / ms[NI + k] : 0.f;
+        S.X[s][k] = (__bf16)v;
+    }
+    __syncthreads();
+    wave_gemm(4, 4, 1, [&](int i, int k) { return S.X[i][k]; }, [&](int k, int o) { return S.W1[o][k]; },
+              [&](int i, int o, float a) {
+                  const float z = a + p[P_B1 + o];
+                  S.Z1[i][o] = z;
+                  S.H1[i][o] = (__bf16)gelu(z);
+              });
+    __syncthreads();
+    wave_gemm(4, 4, 2, [&](int i, int k) { return S.H1[i][k]; }, [&](int k, int o) { return S.W2[o][k]; },
+              [&](int i, int o, float a) {
+                  const float z = a + p[P_B2 + o];
+                  S.Z2[i][o] = z;
+                  S.H2[i][o] = (__bf16)gelu(z);
+              });
+    __syncthreads();
+    wave_gemm(4, 1, 2, [&](int i, int k) { return S.H2[i][k]; }, [&](int k, int o) { return S.W3[o][k]; },
+              [&](int i, int o, float a) {
+                  if (o < NO) y_out[i * NO + o] = a + p[P_B3 + o];
+              });
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(64) k_mlp_forward(const float* __restrict__ p, const float* __restrict__ ms,
+                                                    const float* __restrict__ x, float* __restrict__ y,
+                                                    int64_t n)
+{
+    __shared__ Lds S;
+    __shared__ float Y[CH * NO];
+    load_weights(S, p);
+    const int64_t chunks = (n + CH - 1) / CH;
+    for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        chunk_forward(S, p, ms, x, c * CH, n, Y);
+        for (int e = threadIdx.x; e < CH * NO; e += 64) {
+            const int64_t row = c * CH + e / NO;
+            if (row < n) y[row * NO + e % NO] = Y[e];
+        }
+        __syncthreads();
+    }
+}
+
+// forward + backward of one chunk per workgroup; one gradient row per chunk
+__global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ p, const float* __restrict__ ms,
+                                                 const float* __restrict__ x, const float* __restrict__ t,
+                                                 int64_t n, float* __restrict__ gpart,
+                                                 float* __restrict__ lpart)
+{
+    __shared__ Lds S;
+    __shared__ float Y[CH * NO];
+    load_weights(S, p);
+    const int l = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    const int64_t base = c * CH;
+    float* g = gpart + c * P_COUNT;
+    chunk_forward(S, p, ms, x, base, n, Y);
+    // d loss / d y for loss = mean over samples and outputs of (y - t)^2
+    const float scale = 2.f / (float)(n * NO);
+    float lsum = 0.f;
+    for (int e = l; e < CH * 16; e += 64) {
+        const int s = e / 16, o = e % 16;
+        const int64_t row = base + s;
+        float d = 0.f;
+        if (o < NO && row < n) {
+            const float err = Y[s * NO + o] - t[row * NO + o];
+            lsum += err * err;
+            d = scale * err;
+        }
+        if (o < NO) S.dYf[s][o] = d;
+        S.dY[s][o] = (__bf16)d;
+    }
+    S.red[l] = lsum;
+    __syncthreads();
+    if (l == 0) {
+        float acc = 0.f;
+        for (int k = 0; k < 64; ++k) acc += S.red[k];
+        lpart[c] = acc;
+    }
+    if (l < NO) {
+        float acc = 0.f;
+        for (int s = 0; s < CH; ++s) acc += S.dYf[s][l];
+        g[P_B3 + l] = acc;
+    }
+    // dW3 = dY^T H2 (M = outputs padded to 16, K = samples)
+    wave_gemm(1, 4, 2, [&](int o, int s) { return S.dY[s][o]; }, [&](int s, int k) { return S.H2[s][k]; },
+              [&](int o, int k, float a) {
+                  if (o < NO) g[P_W3 + o * NH + k] = a;
+              });
+    // dH2 = dY W3 (K = outputs padded to 32); dz2 = dH2 * GELU'(z2)
+    wave_gemm(4, 4, 1, [&](int s, int o) { return o < 16 ? S.dY[s][o] : (__bf16)0.f; },
+              [&](int o, int k) { return o < 16 ? S.W3[o][k] : (__bf16)0.f; },
+              [&](int s, int k, float a) {
+                  const float dz = a * gelu_grad(S.Z2[s][k]);
+                  S.Z2[s][k] = dz;
+                  S.dZ[s][k] = (__bf16)dz;
+              });
+    __syncthreads();
+    if (l < NH) {
+        float acc = 0.f;
+        for (int s = 0; s < CH; ++s) acc += S.Z2[s][l];
+        g[P_B2 + l] = acc;
+    }
+    // dW2 = dZ2^T H1 ; dH1 = dZ2 W2
+    wave_gemm(4, 4, 2, [&](int o, int s) { return S.dZ[s][o]; }, [&](int s, int k) { return S.H1[s][k]; },
+              [&](int o, int k, float a) { g[P_W2 + o * NH + k] = a; });
+    wave_gemm(4, 4, 2, [&](int s, int o) { return S.dZ[s][o]; }, [&](int o, int k) { return S.W2[o][k]; },
+              [&](int s, int k, float a) { S.Z1[s][k] = a * gelu_grad(S.Z1[s][k]); });
+    __syncthreads();
+    for (int e = l; e < CH * NH; e += 64) S.dZ[e / NH][e % NH] = (__bf16)S.Z1[e / NH][e % NH];
+    if (l < NH) {
+        float acc = 0.f;
+        for (int s = 0; s < CH; ++s) acc += S.Z1[s][l];
+        g[P_B1 + l] = acc;
+    }
+    __syncthreads();
+    // dW1 = dZ1^T X
+    wave_gemm(4, 2, 2, [&](int o, int s) { return S.dZ[s][o]; }, [&](int s, int k) { return S.X[s][k]; },
+              [&](int o, int k, float a) { g[P_W1 + o * NI + k] = a; });
+}
+
+// grad[k] = sum over chunks in chunk order; loss likewise
+__global__ void k_mlp_reduce(const float* __restrict__ gpart, const float* __restrict__ lpart, int64_t chunks,
+                             int64_t n, float* __restrict__ grad, float* __restrict__ loss)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < P_COUNT) {
+        float acc = 0.f;
+        for (int64_t c = 0; c < chunks; ++c) acc += gpart[c * P_COUNT + k];
+        grad[k] = acc;
+    }
+    if (k == 0) {
+        float acc = 0.f;
+        for (int64_t c = 0; c < chunks; ++c) acc += lpart[c];
+        *loss = acc / (float)(n * NO);
+    }
+}
+
+// Adam with bias correction (Kingma and Ba), step t counts from 1
+__global__ void k_mlp_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                           const float* __restrict__ g, int t, float lr, float b1, float b2, float eps)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P_COUNT) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.f - b1) * gk;
+    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    const float mh = mk / (1.f - powf(b1, (float)t));
+    const float vh = vk / (1.f - powf(b2, (float)t));
+    p[k] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// per-feature mean and standard deviation, accumulated in double
+__global__ void __launch_bounds__(256) k_mlp_stats(const float* __restrict__ x, int64_t n, float* __restrict__ ms)
+{
+    __shared__ double sh[256];
+    const int k = blockIdx.x;   // feature
+    const int l = threadIdx.x;
+    double s = 0.0;
+    for (int64_t r = l; r < n; r += 256) s += x[r * NI + k];
+    sh[l] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (l < o) sh[l] += sh[l + o];
+        __syncthreads();
+    }
+    const double mean = sh[0] / (double)n;
+    __syncthreads();
+    double q = 0.0;
+    for (int64_t r = l; r < n; r += 256) {
+        const double d = x[r * NI + k] - mean;
+        q += d * d;
+    }
+    sh[l] = q;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (l < o) sh[l] += sh[l + o];
+        __syncthreads();
+    }
+    if (l == 0) {
+        ms[k] = (float)mean;
+        ms[NI + k] = (float)sqrt(sh[0] / (double)n + 1e-12);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mlp_param_count(void) { return P_COUNT; }
+
+const char* mlp_last_error(void) { return g_mlp_err.c_str(); }
+
+int64_t mlp_train_scratch_floats(int64_t n)
+{
+    const int64_t chunks = (n + CH - 1) / CH;
+    return chunks * P_COUNT + chunks;
+}
+
+int mlp_norm_stats(const float* x, int64_t n, float* mean_std, void* stream)
+{
+    if (!x || !mean_std || n < 1) return mfail(SIM_EINVAL, "mlp_norm_stats: bad arguments");
+    hipLaunchKernelGGL(k_mlp_stats, dim3(NI), dim3(256), 0, (hipStream_t)stream, x, n, mean_std);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SIM_OK : mfail(SIM_EDEVICE, hipGetErrorString(e));
+}
+
+int mlp_forward(const float* params, const float* mean_std, const float* x, float* y, int64_t n, void* stream)
+{
+    if (!params || !mean_std || !x || !y || n < 0) return mfail(SIM_EINVAL, "mlp_forward: bad arguments");
+    if (n == 0) return SIM_OK;
+    const int64_t chunks = (n + CH - 1) / CH;
+    const int grid = (int)(chunks < 8192 ? chunks : 8192);
+    hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(64), 0, (hipStream_t)stream, params, mean_std, x, y, n);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SIM_OK : mfail(SIM_EDEVICE, hipGetErrorString(e));
+}
+
+int mlp_grad(const float* params, const float* mean_std, const float* x, const float* t, int64_t n, float* grad,
+             float* loss, float* scratch, int64_t scratch_floats, void* stream)
+{
+    if (!params || !mean_std || !x || !t || !grad || !loss || !scratch || n < 1)
+        return mfail(SIM_EINVAL, "mlp_grad: bad arguments");
+    if (scratch_floats < mlp_train_scratch_floats(n)) return mfail(SIM_ENOMEM, "mlp_grad: scratch too small");
+    const int64_t chunks = (n + CH - 1) / CH;
+    if (chunks > (1 << 30)) return mfail(SIM_EINVAL, "mlp_grad: batch too large");
+    hipStream_t st = (hipStream_t)stream;
+    float* gpart = scratch;
+    float* lpart = scratch + chunks * P_COUNT;
+    hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)chunks), dim3(64), 0, st, params, mean_std, x, t, n, gpart, lpart);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((P_COUNT + 255) / 256), dim3(256), 0, st, gpart, lpart, chunks, n, grad, loss);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SIM_OK : mfail(SIM_EDEVICE, hipGetErrorString(e));
+}
+
+int mlp_adam(float* params, float* m, float* v, const float* grad, int32_t t, float lr, void* stream)
+{
+    if (!params || !m || !v || !grad || t < 1) return mfail(SIM_EINVAL, "mlp_adam: bad arguments");
+    hipLaunchKernelGGL(k_mlp_adam, dim3((P_COUNT + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, m, v,
+                       grad, t, lr, 0.9f, 0.999f, 1e-8f);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SIM_OK : mfail(SIM_EDEVICE, hipGetErrorString(e));
+}
+
+}  // extern "C"

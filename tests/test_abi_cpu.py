@@ -14,6 +14,7 @@ import workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "snake.h")
+MLP_HEADER = os.path.join(ROOT, "include", "snake_mlp.h")
 
 
 @pytest.fixture(scope="module")
@@ -24,17 +25,21 @@ def L():
     return snk.lib()
 
 
-def declared_functions():
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(sim_\w+)\s*\(", text, re.M)))
+def declared_functions(path=HEADER, prefix="sim_"):
+    text = open(path).read()
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+(" + prefix + r"\w+)\s*\(",
+                                 text, re.M)))
 
 
 def test_exports_every_declared_symbol(L):
     names = declared_functions()
     assert set(names) == set(snk.EXPORTS)
+    mlp_names = declared_functions(MLP_HEADER, "mlp_")
+    assert set(mlp_names) == set(snk.MLP_EXPORTS)
+    names = names + mlp_names
     out = subprocess.run(["nm", "-D", "--defined-only", snk.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
-    exported = set(re.findall(r" T (sim_\w+)$", out, re.M))
+    exported = set(re.findall(r" T ((?:sim|mlp)_\w+)$", out, re.M))
     for n in names:
         assert n in exported, n
         assert hasattr(L, n)
