@@ -78,6 +78,10 @@ extern "C" {
 #define SIM_WARM_ZERO 0 /* lambda = 0                                        */
 #define SIM_WARM_PREV 1 /* lambda = previous substep's, bodies moved by      */
                         /* W J^T lambda before iterating                      */
+#define SIM_WARM_MLP 2  /* joint lambda predicted by the network set with     */
+                        /* sim_set_mlp (contacts start at 0), bodies moved by */
+                        /* W J^T lambda; with mlp_fallback the zero start is  */
+                        /* used wherever it begins with a smaller residual    */
 
 /* ---- flags ---- */
 #define SIM_FLAG_FIXED_ROOT 1u /* body 0 of every snake is immovable         */
@@ -86,6 +90,7 @@ extern "C" {
 /* ---- per-snake status bits (field SIM_F_STATUS) ---- */
 #define SIM_STATUS_NONFINITE 1     /* residual became NaN or inf             */
 #define SIM_STATUS_NOT_CONVERGED 2 /* tolerance not reached in iters        */
+#define SIM_STATUS_FELL_BACK 4     /* a learned start was replaced by zero  */
 
 /* ---- state fields: bit k selects dst[k] / src[k] ---- */
 #define SIM_F_POS (1u << 0)            /* float [3][N] body centres          */
@@ -166,6 +171,9 @@ typedef struct sim_desc {
     int32_t map_waves;         /* 1, 2, 4, 8 or 16; 64 * map_waves >= every segment */
     int32_t map_min_seg;
     int32_t map_grid;
+    int32_t mlp_fallback;      /* 1: per snake and substep, keep the learned */
+                               /* start only if its initial residual is not  */
+                               /* larger than the zero start's               */
 } sim_desc_t;
 
 typedef struct sim sim_t;
@@ -203,6 +211,31 @@ int sim_read_state(sim_t* s, uint32_t fields, void* const* dst, int mem);
  * injection).  A round trip through sim_read_state is bitwise.  Host
  * memory: the call synchronises the stream. */
 int sim_write_state(sim_t* s, uint32_t fields, const void* const* src, int mem);
+
+/* Load the warm-start network (snake_mlp.h layout): params[6467] and
+ * mean_std[64], host or device memory.  Needed before sim_step when the
+ * descriptor's warm_start is SIM_WARM_MLP.  Stream-ordered. */
+int sim_set_mlp(sim_t* s, const float* params, const float* mean_std, int mem);
+
+/* Advance n_steps steps like sim_step, substep by substep, and record for
+ * every substep and every joint two rows (stretch, bend-twist) of network
+ * inputs and targets into caller device memory:
+ *   features[rows][32], targets[rows][3], rows = n_steps substeps 2 Jtot,
+ * ordered substep-major, then joint (global index), then block.
+ * Inputs, at the substep's predicted state (positions x + h v, predicted
+ * orientations), vectors in the predicted axes of the joint's first body A:
+ *   0-2   stretch violation / L          3-5   2 Im(q0* qA* qB)
+ *   6-8   (vA + wA x rA - vB - wB x rB) h / L   9-11 (wB - wA) h
+ *   12-14 world up                       15-18 p0, p1, command, rest angle
+ *   19-21 this block's previous multipliers / scale
+ *   22-24 log10 of the stretch, bend, twist compliance / h^2
+ *   25 mu   26-27 previous normal multipliers of A, B / (m 9.81 h^2)
+ *   28-29 (z - R) / L of A, B   30 block type (0, 1)   31 i / (B - 1)
+ * Targets: the substep's final multipliers, stretch in the axes of A over
+ * m 9.81 h^2, bend-twist over m 9.81 h^2 L.  SIM_ENOMEM if capacity_rows is
+ * smaller than rows; *written receives rows. */
+int sim_step_record(sim_t* s, int32_t n_steps, float* features, float* targets, int64_t capacity_rows,
+                    int64_t* written);
 
 /* Copy index array `which` (SIM_IDX_*) to host int32 memory `dst` holding
  * `count` entries (must equal the array's length).  Synchronous. */

@@ -80,6 +80,7 @@ class Batch(C.Structure):
         ("amp_psi", C.c_double),
         ("flags", C.c_int32), ("controller", C.c_int32), ("warm", C.c_int32),
         ("ctrl_alpha", C.c_double), ("ctrl_offset", C.c_double),
+        ("fallback", C.c_int32),
     ]
 
 
@@ -99,6 +100,10 @@ def _declare(L):
     L.orc_assemble.restype = C.c_int
     L.orc_predict_snake.argtypes = [bp, C.c_int32, _P, _P, _P, _P, C.c_double]
     L.orc_index.argtypes = [bp] + [_P] * 7
+    L.orc_pre_substep.argtypes = [bp, C.c_int32, C.c_int32] + [_P] * 7
+    L.orc_solve_substep.argtypes = [bp, C.c_int32] + [_P] * 11
+    L.orc_features.argtypes = [bp, C.c_int32] + [_P] * 9
+    L.orc_targets.argtypes = [bp, C.c_int32, _P, _P, _P]
     L.mlo_param_count.restype = C.c_int
     L.mlo_norm_stats.argtypes = [_P, C.c_int64, _P, _P]
     L.mlo_forward.argtypes = [_P, _P, _P, _P, C.c_int64, _P]
@@ -155,6 +160,7 @@ class Oracle:
         b.flags = int(g("flags"))
         b.controller = int(g("controller"))
         b.warm = int(over.get("warm", WARM_ZERO))
+        b.fallback = int(over.get("fallback", 0))
         self.batch = b
         self.n = n
         self.B = (np.asarray(g("n_modules"), np.int64) * np.asarray(g("segs_per_module"), np.int64))
@@ -243,6 +249,52 @@ class Oracle:
         for k, a in zip(("x", "q", "v", "w"), arrs):
             d[k][...] = a
         return d
+
+    # -- split substep (learned warm start) ------------------------------------
+    def pre_substep(self, s, sub):
+        """First half of substep `sub` of snake s in place; returns q_pred."""
+        d = self.snake(s)
+        arrs = {k: np.ascontiguousarray(d[k]) for k in ("x", "q", "v", "w", "p", "cmd")}
+        qp = np.zeros_like(arrs["q"])
+        self.L.orc_pre_substep(C.byref(self.batch), int(s), int(sub), *[_ptr(arrs[k]) for k in
+                               ("x", "q", "v", "w", "p", "cmd")], _ptr(qp))
+        for k in ("v", "w", "p"):
+            d[k][...] = arrs[k]
+        return qp
+
+    def solve_substep(self, s, q_pred):
+        """Second half for snake s (lam_* hold lambda0 for a GIVEN warm
+        start); returns (residual, iterations, status)."""
+        d = self.snake(s)
+        arrs = {k: np.ascontiguousarray(d[k]) for k in ("x", "q", "v", "w", "p", "lam_j", "lam_c")}
+        qp = np.ascontiguousarray(q_pred, np.float64)
+        r, it, st = C.c_double(), C.c_int32(), C.c_int32()
+        self.L.orc_solve_substep(C.byref(self.batch), int(s), _ptr(arrs["x"]), _ptr(arrs["q"]), _ptr(qp),
+                                 _ptr(arrs["v"]), _ptr(arrs["w"]), _ptr(arrs["p"]), _ptr(arrs["lam_j"]),
+                                 _ptr(arrs["lam_c"]), C.byref(r), C.byref(it), C.byref(st))
+        for k in arrs:
+            d[k][...] = arrs[k]
+        return r.value, it.value, st.value
+
+    def features(self, s, q_pred):
+        d = self.snake(s)
+        arrs = {k: np.ascontiguousarray(d[k]) for k in ("x", "v", "w", "p", "cmd", "lam_j", "lam_c")}
+        B = int(self.B[s])
+        out = np.zeros((2 * max(B - 1, 0), 32))
+        qp = np.ascontiguousarray(q_pred, np.float64)
+        self.L.orc_features(C.byref(self.batch), int(s), _ptr(arrs["x"]), _ptr(arrs["v"]), _ptr(arrs["w"]),
+                            _ptr(qp), _ptr(arrs["p"]), _ptr(arrs["cmd"]), _ptr(arrs["lam_j"]),
+                            _ptr(arrs["lam_c"]), _ptr(out))
+        return out
+
+    def targets(self, s, q_pred):
+        d = self.snake(s)
+        B = int(self.B[s])
+        out = np.zeros((2 * max(B - 1, 0), 3))
+        lj = np.ascontiguousarray(d["lam_j"])
+        self.L.orc_targets(C.byref(self.batch), int(s), _ptr(np.ascontiguousarray(q_pred, np.float64)),
+                           _ptr(lj), _ptr(out))
+        return out
 
     def index(self):
         """Offsets, block list, degrees, greedy colours, buckets, work order."""

@@ -459,6 +459,8 @@ typedef struct {
     double* acc;        /* [B*6] linearised accumulated displacement */
     double* Iinv;       /* [B*9] */
     double* theta0;     /* [B] */
+    double* lz_j;       /* zero multipliers for the fallback's comparison */
+    double* lz_c;
 } scratch_t;
 
 static void scratch_alloc(scratch_t* w, const snake_ctx* c)
@@ -475,6 +477,8 @@ static void scratch_alloc(scratch_t* w, const snake_ctx* c)
     w->acc = (double*)calloc((size_t)B * 6, sizeof(double));
     w->Iinv = (double*)calloc((size_t)B * 9, sizeof(double));
     w->theta0 = (double*)calloc((size_t)B, sizeof(double));
+    w->lz_j = (double*)calloc((size_t)B * 6, sizeof(double));
+    w->lz_c = (double*)calloc((size_t)B * 3, sizeof(double));
 }
 
 static void scratch_free(scratch_t* w)
@@ -489,6 +493,8 @@ static void scratch_free(scratch_t* w)
     free(w->acc);
     free(w->Iinv);
     free(w->theta0);
+    free(w->lz_j);
+    free(w->lz_c);
 }
 
 /* Predicted positions of a first-order implicit step: gravity on the linear
@@ -517,6 +523,76 @@ static void predict(const snake_ctx* c, double* x, double* q, double* v, double*
     }
 }
 
+/* Local solves of every evaluated block (increments into W->dl, scaled) and
+ * the residual of the iterate they were evaluated at.  Reads lambda only. */
+static double local_solves(const snake_ctx* c, scratch_t* W, double* lam_j, double* lam_c)
+{
+    int nb = n_blocks(c);
+    double r;
+    r = 0.0;
+    for (int n = 0; n < nb; ++n) {
+        block_t* kb = &W->blk[n];
+        double* l = block_lambda(c, lam_j, lam_c, kb, n);
+        double* dl = W->dl + 3 * n;
+        if (kb->type == BLK_CONTACT) {
+            int i = kb->a;
+            double cn = kb->C[0];
+            double rc = (l[0] > 0.0) ? fabs(cn) : (cn < 0.0 ? -cn : 0.0);
+            rc /= c->L;
+            if (rc > r || rc != rc) r = rc;
+            double wi = inv_mass(c, i);
+            if (wi == 0.0) {
+                dl[0] = dl[1] = dl[2] = 0.0;
+                continue;
+            }
+            /* normal: projected increment; tangential: trial increment
+             * projected onto the Coulomb disc of radius mu * lambda_n */
+            double ln = l[0] + kb->scale * (-cn / wi);
+            if (ln < 0.0) ln = 0.0;
+            double lt0 = l[1] + kb->scale * (-kb->C[1] / wi);
+            double lt1 = l[2] + kb->scale * (-kb->C[2] / wi);
+            double cap = c->mu * ln;
+            double nt = sqrt(lt0 * lt0 + lt1 * lt1);
+            if (ln <= 0.0) {
+                lt0 = lt1 = 0.0;
+            } else if (nt > cap) {
+                lt0 *= cap / nt;
+                lt1 *= cap / nt;
+            }
+            dl[0] = ln - l[0];
+            dl[1] = lt0 - l[1];
+            dl[2] = lt1 - l[2];
+        } else {
+            double rhs[3], K[9] = {0}, Iinva[9], Iinvb[9], dlam[3];
+            for (int d = 0; d < 3; ++d) rhs[d] = kb->C[d] + kb->comp[d] * l[d];
+            double rb = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                double t = fabs(rhs[d]);
+                if (t > rb || t != t) rb = t;
+            }
+            if (kb->type == BLK_STRETCH) rb /= c->L;
+            if (rb > r || rb != rb) r = rb;
+            memcpy(Iinva, W->Iinv + 9 * kb->a, sizeof Iinva);
+            memcpy(Iinvb, W->Iinv + 9 * kb->b, sizeof Iinvb);
+            add_jwjt(kb->Ja, inv_mass(c, kb->a), Iinva, K);
+            add_jwjt(kb->Jb, inv_mass(c, kb->b), Iinvb, K);
+            for (int d = 0; d < 3; ++d) K[4 * d] += kb->comp[d];
+            solve3(K, rhs, dlam);
+            for (int d = 0; d < 3; ++d) dl[d] = -kb->scale * dlam[d];
+        }
+    }
+    return r;
+}
+
+/* residual of configuration (x, q) with multipliers lambda, nothing applied */
+static double residual_at(const orc_batch* b, const snake_ctx* c, scratch_t* W, const double* x,
+                          const double* q, double* lam_j, double* lam_c)
+{
+    eval_blocks(b, c, x, q, W->xp, W->theta0, W->blk);
+    for (int i = 0; i < c->B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
+    return local_solves(c, W, lam_j, lam_c);
+}
+
 /* Block-Jacobi solve of one substep.  Returns the number of applied
  * iterations; *res is the residual of the final iterate. */
 static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* x, double* q,
@@ -526,7 +602,18 @@ static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, d
     int nb = n_blocks(c);
     int B = c->B;
 
-    /* warm start: x <- x~ + W J(x~)^T lambda0 with lambda0 = current lambda */
+    /* warm start: x <- x~ + W J(x~)^T lambda0 with lambda0 = current lambda.
+     * With the fallback, a given lambda0 is kept only if the residual it
+     * starts from is not larger than the residual of the zero start. */
+    int fallback = (warm == ORC_WARM_GIVEN && b->fallback);
+    double r_zero = 0.0;
+    if (fallback) {
+        memcpy(W->xt, x, sizeof(double) * 3 * (size_t)B);
+        memcpy(W->qt, q, sizeof(double) * 4 * (size_t)B);
+        memset(W->lz_j, 0, sizeof(double) * 6 * (size_t)(c->nj > 0 ? c->nj : 1));
+        memset(W->lz_c, 0, sizeof(double) * 3 * (size_t)B);
+        r_zero = residual_at(b, c, W, x, q, W->lz_j, W->lz_c);
+    }
     if (warm != ORC_WARM_ZERO) {
         eval_blocks(b, c, x, q, W->xp, W->theta0, W->blk);
         for (int k = 0; k < nb; ++k) {
@@ -539,6 +626,16 @@ static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, d
             gather_body(c, i, W->blk, W->dl, inv_mass(c, i), W->Iinv + 9 * i, dx, dth);
             for (int d = 0; d < 3; ++d) x[3 * i + d] += dx[d];
             if (!is_fixed(c, i)) q_apply_rotvec(q + 4 * i, dth);
+        }
+        if (fallback) {
+            double r_nn = residual_at(b, c, W, x, q, lam_j, lam_c);
+            if (!(r_nn <= r_zero)) {
+                memcpy(x, W->xt, sizeof(double) * 3 * (size_t)B);
+                memcpy(q, W->qt, sizeof(double) * 4 * (size_t)B);
+                memset(lam_j, 0, sizeof(double) * 6 * (size_t)c->nj);
+                memset(lam_c, 0, sizeof(double) * 3 * (size_t)B);
+                *status |= ORC_STATUS_FELL_BACK;
+            }
         }
     } else {
         memset(lam_j, 0, sizeof(double) * 6 * (size_t)c->nj);
@@ -577,59 +674,7 @@ static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, d
             for (int i = 0; i < B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
         }
 
-        /* local solves and the residual of this iterate */
-        r = 0.0;
-        for (int n = 0; n < nb; ++n) {
-            block_t* kb = &W->blk[n];
-            double* l = block_lambda(c, lam_j, lam_c, kb, n);
-            double* dl = W->dl + 3 * n;
-            if (kb->type == BLK_CONTACT) {
-                int i = kb->a;
-                double cn = kb->C[0];
-                double rc = (l[0] > 0.0) ? fabs(cn) : (cn < 0.0 ? -cn : 0.0);
-                rc /= c->L;
-                if (rc > r || rc != rc) r = rc;
-                double wi = inv_mass(c, i);
-                if (wi == 0.0) {
-                    dl[0] = dl[1] = dl[2] = 0.0;
-                    continue;
-                }
-                /* normal: projected increment; tangential: trial increment
-                 * projected onto the Coulomb disc of radius mu * lambda_n */
-                double ln = l[0] + kb->scale * (-cn / wi);
-                if (ln < 0.0) ln = 0.0;
-                double lt0 = l[1] + kb->scale * (-kb->C[1] / wi);
-                double lt1 = l[2] + kb->scale * (-kb->C[2] / wi);
-                double cap = c->mu * ln;
-                double nt = sqrt(lt0 * lt0 + lt1 * lt1);
-                if (ln <= 0.0) {
-                    lt0 = lt1 = 0.0;
-                } else if (nt > cap) {
-                    lt0 *= cap / nt;
-                    lt1 *= cap / nt;
-                }
-                dl[0] = ln - l[0];
-                dl[1] = lt0 - l[1];
-                dl[2] = lt1 - l[2];
-            } else {
-                double rhs[3], K[9] = {0}, Iinva[9], Iinvb[9], dlam[3];
-                for (int d = 0; d < 3; ++d) rhs[d] = kb->C[d] + kb->comp[d] * l[d];
-                double rb = 0.0;
-                for (int d = 0; d < 3; ++d) {
-                    double t = fabs(rhs[d]);
-                    if (t > rb || t != t) rb = t;
-                }
-                if (kb->type == BLK_STRETCH) rb /= c->L;
-                if (rb > r || rb != rb) r = rb;
-                memcpy(Iinva, W->Iinv + 9 * kb->a, sizeof Iinva);
-                memcpy(Iinvb, W->Iinv + 9 * kb->b, sizeof Iinvb);
-                add_jwjt(kb->Ja, inv_mass(c, kb->a), Iinva, K);
-                add_jwjt(kb->Jb, inv_mass(c, kb->b), Iinvb, K);
-                for (int d = 0; d < 3; ++d) K[4 * d] += kb->comp[d];
-                solve3(K, rhs, dlam);
-                for (int d = 0; d < 3; ++d) dl[d] = -kb->scale * dlam[d];
-            }
-        }
+        r = local_solves(c, W, lam_j, lam_c);
         if (!isfinite(r)) {
             *status |= ORC_STATUS_NONFINITE;
             break;
@@ -929,6 +974,167 @@ int orc_assemble(const orc_batch* b, int32_t snake, const double* x, const doubl
     free(blk);
     free(th);
     return rows;
+}
+
+/* ------------------------------------------------------------------ */
+/* split substep and the warm-start network's inputs and targets        */
+/* ------------------------------------------------------------------ */
+
+/* First half of substep `sub` of snake `snake`: command effects on the
+ * chamber pressures (the paper law at sub 0, the lag every substep) and the
+ * prediction.  x and q keep the start of the substep; v, w become the
+ * predicted velocities and q_pred the predicted orientation. */
+void orc_pre_substep(const orc_batch* b, int32_t snake, int32_t sub, const double* x, const double* q,
+                     double* v, double* w, double* p, const double* cmd, double* q_pred)
+{
+    snake_ctx c;
+    make_ctx(b, snake, &c);
+    if (b->law == ORC_LAW_PAPER && sub == 0)
+        for (int m = 0; m < c.M; ++m) {
+            p[2 * m] = paper_update(b, p[2 * m], cmd[m] > 0.0 ? cmd[m] : 0.0);
+            p[2 * m + 1] = paper_update(b, p[2 * m + 1], cmd[m] < 0.0 ? -cmd[m] : 0.0);
+        }
+    if (b->law == ORC_LAW_LAG)
+        for (int m = 0; m < c.M; ++m) {
+            double a = cmd[m];
+            p[2 * m] = lag_update(p[2 * m], a > 0.0 ? a : 0.0, c.h, b->tau_inf, b->tau_def);
+            p[2 * m + 1] = lag_update(p[2 * m + 1], a < 0.0 ? -a : 0.0, c.h, b->tau_inf, b->tau_def);
+        }
+    double* xt = (double*)malloc(sizeof(double) * 3 * (size_t)c.B);
+    memcpy(xt, x, sizeof(double) * 3 * (size_t)c.B);
+    memcpy(q_pred, q, sizeof(double) * 4 * (size_t)c.B);
+    predict(&c, xt, q_pred, v, w);
+    free(xt);
+}
+
+/* Second half: multiplier initialisation (the batch's warm mode; GIVEN
+ * takes lam_j / lam_c as lambda0), iterations, velocities.  x, q are the
+ * start of the substep and become its end. */
+void orc_solve_substep(const orc_batch* b, int32_t snake, double* x, double* q, const double* q_pred,
+                       double* v, double* w, const double* p, double* lam_j, double* lam_c,
+                       double* residual, int32_t* iters, int32_t* status)
+{
+    snake_ctx c;
+    make_ctx(b, snake, &c);
+    scratch_t W;
+    scratch_alloc(&W, &c);
+    for (int j = 0; j < c.nj; ++j) W.theta0[j] = rest_angle(b, &c, p, j);
+    memcpy(W.xp, x, sizeof(double) * 3 * (size_t)c.B);
+    memcpy(W.qp, q, sizeof(double) * 4 * (size_t)c.B);
+    for (int i = 0; i < c.B; ++i) {
+        if (!is_fixed(&c, i))
+            for (int d = 0; d < 3; ++d) x[3 * i + d] += c.h * v[3 * i + d];
+    }
+    memcpy(q, q_pred, sizeof(double) * 4 * (size_t)c.B);
+    double r = 0.0;
+    int st = 0;
+    int it = solve_substep(b, &c, &W, x, q, lam_j, lam_c, b->warm, b->iters, b->tol, &r, &st);
+    finalize(&c, W.xp, W.qp, x, q, v, w);
+    *residual = r;
+    *iters = it;
+    *status = st;
+    scratch_free(&W);
+}
+
+static void rot_conj(const double* q, const double* v, double* o)
+{
+    double qc[4], R[9];
+    q_conj(q, qc);
+    q_to_matrix(qc, R);
+    m3_vec(R, v, o);
+}
+
+/* Inputs of the network for the joints of one snake, two rows per joint
+ * (stretch, then bend-twist), at the predicted state: x start positions,
+ * v / w predicted velocities, q_pred predicted orientations.  Vectors are
+ * expressed in the predicted axes of the joint's first body. */
+void orc_features(const orc_batch* b, int32_t snake, const double* x, const double* v, const double* w,
+                  const double* q_pred, const double* p, const double* cmd, const double* lam_j,
+                  const double* lam_c, double* feat)
+{
+    snake_ctx c;
+    make_ctx(b, snake, &c);
+    const double ref = c.m * 9.81 * c.h * c.h, refb = ref * c.L;
+    const double ex[3] = {1.0, 0.0, 0.0}, ez[3] = {0.0, 0.0, 1.0};
+    for (int j = 0; j < c.nj; ++j) {
+        const int a = j, bb = j + 1;
+        const double* qa = q_pred + 4 * a;
+        const double* qb = q_pred + 4 * bb;
+        double Ra[9], Rb[9], ra[3], rb[3], xa[3], xb[3];
+        q_to_matrix(qa, Ra);
+        q_to_matrix(qb, Rb);
+        m3_vec(Ra, ex, ra);
+        m3_vec(Rb, ex, rb);
+        for (int d = 0; d < 3; ++d) {
+            ra[d] *= 0.5 * c.L;
+            rb[d] *= -0.5 * c.L;
+            xa[d] = x[3 * a + d] + c.h * v[3 * a + d];
+            xb[d] = x[3 * bb + d] + c.h * v[3 * bb + d];
+        }
+        double f[32], t[3], u[3];
+        for (int d = 0; d < 3; ++d) t[d] = ((xa[d] + ra[d]) - (xb[d] + rb[d])) / c.L;
+        rot_conj(qa, t, f);
+        /* bend-twist value at the predicted state */
+        double th0 = rest_angle(b, &c, p, j);
+        double q0[4] = {cos(0.5 * th0), 0.0, 0.0, sin(0.5 * th0)}, q0c[4], qac[4], tt[4], e[4];
+        q_conj(q0, q0c);
+        q_conj(qa, qac);
+        q_mul(q0c, qac, tt);
+        q_mul(tt, qb, e);
+        if (e[0] < 0.0)
+            for (int d = 0; d < 4; ++d) e[d] = -e[d];
+        for (int d = 0; d < 3; ++d) f[3 + d] = 2.0 * e[1 + d];
+        /* velocity of the A end point relative to the B start point, times h/L */
+        double wa_r[3], wb_r[3];
+        cross3(w + 3 * a, ra, wa_r);
+        cross3(w + 3 * bb, rb, wb_r);
+        for (int d = 0; d < 3; ++d)
+            t[d] = ((v[3 * a + d] + wa_r[d]) - (v[3 * bb + d] + wb_r[d])) * c.h / c.L;
+        rot_conj(qa, t, f + 6);
+        for (int d = 0; d < 3; ++d) t[d] = (w[3 * bb + d] - w[3 * a + d]) * c.h;
+        rot_conj(qa, t, f + 9);
+        rot_conj(qa, ez, f + 12);
+        const int m = j / c.S;
+        f[15] = p[2 * m];
+        f[16] = p[2 * m + 1];
+        f[17] = cmd[m];
+        f[18] = th0;
+        double hh = c.h * c.h;
+        f[22] = log10(fmax(c.a_s / hh, 1e-30));
+        f[23] = log10(fmax(c.a_b / hh, 1e-30));
+        f[24] = log10(fmax(c.a_t / hh, 1e-30));
+        f[25] = c.mu;
+        f[26] = lam_c[3 * a] / ref;
+        f[27] = lam_c[3 * bb] / ref;
+        f[28] = (xa[2] - c.R) / c.L;
+        f[29] = (xb[2] - c.R) / c.L;
+        f[31] = c.B > 1 ? (double)j / (double)(c.B - 1) : 0.0;
+        for (int d = 0; d < 3; ++d) t[d] = lam_j[6 * j + d] / ref;
+        rot_conj(qa, t, u);
+        f[19] = u[0];
+        f[20] = u[1];
+        f[21] = u[2];
+        f[30] = 0.0;
+        memcpy(feat + 64 * j, f, sizeof f);
+        for (int d = 0; d < 3; ++d) f[19 + d] = lam_j[6 * j + 3 + d] / refb;
+        f[30] = 1.0;
+        memcpy(feat + 64 * j + 32, f, sizeof f);
+    }
+}
+
+/* Network targets from final multipliers: stretch in the predicted axes of
+ * the joint's first body over m g h^2, bend-twist over m g h^2 L. */
+void orc_targets(const orc_batch* b, int32_t snake, const double* q_pred, const double* lam_j, double* tgt)
+{
+    snake_ctx c;
+    make_ctx(b, snake, &c);
+    const double ref = c.m * 9.81 * c.h * c.h, refb = ref * c.L;
+    for (int j = 0; j < c.nj; ++j) {
+        double t[3];
+        for (int d = 0; d < 3; ++d) t[d] = lam_j[6 * j + d] / ref;
+        rot_conj(q_pred + 4 * j, t, tgt + 6 * j);
+        for (int d = 0; d < 3; ++d) tgt[6 * j + 3 + d] = lam_j[6 * j + 3 + d] / refb;
+    }
 }
 
 /* ------------------------------------------------------------------ */

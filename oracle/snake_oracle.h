@@ -49,6 +49,7 @@
 
 #define ORC_STATUS_NONFINITE 1
 #define ORC_STATUS_NOT_CONVERGED 2
+#define ORC_STATUS_FELL_BACK 4
 
 /* Batch description: one entry per snake plus shared constants. */
 typedef struct {
@@ -73,6 +74,7 @@ typedef struct {
     double k_i, k_d, T_p, p_s, amp_psi;
     int32_t flags, controller, warm;
     double ctrl_alpha, ctrl_offset;
+    int32_t fallback;   /* GIVEN warm start: keep lambda0 only if it starts closer */
 } orc_batch;
 
 /* Batch state, owned by the caller.  Offsets: body_off / module_off /
@@ -119,6 +121,19 @@ int orc_assemble(const orc_batch* b, int32_t snake, const double* x, const doubl
 /* stages of one substep of one snake, exposed for tests */
 void orc_predict_snake(const orc_batch* b, int32_t snake, double* x, double* q, double* v,
                        double* w, double h);
+
+/* split substep: command effects on pressure and prediction, then the solve */
+void orc_pre_substep(const orc_batch* b, int32_t snake, int32_t sub, const double* x, const double* q,
+                     double* v, double* w, double* p, const double* cmd, double* q_pred);
+void orc_solve_substep(const orc_batch* b, int32_t snake, double* x, double* q, const double* q_pred,
+                       double* v, double* w, const double* p, double* lam_j, double* lam_c,
+                       double* residual, int32_t* iters, int32_t* status);
+
+/* network inputs [2(B-1)][32] and targets [2(B-1)][3] of one snake */
+void orc_features(const orc_batch* b, int32_t snake, const double* x, const double* v, const double* w,
+                  const double* q_pred, const double* p, const double* cmd, const double* lam_j,
+                  const double* lam_c, double* feat);
+void orc_targets(const orc_batch* b, int32_t snake, const double* q_pred, const double* lam_j, double* tgt);
 
 /* index work: per block type (0 stretch, 1 bend-twist, 2 contact), bodies,
  * greedy colour; per body degree; per snake bucket; work order. */

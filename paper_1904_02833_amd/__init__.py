@@ -19,9 +19,9 @@ SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE = 0, -1, -2, -3, -4
 MEM_HOST, MEM_DEVICE = 0, 1
 LAW_LAG, LAW_PAPER = 0, 1
 CTRL_EXTERNAL, CTRL_SERPENOID, CTRL_SCHEDULE = 0, 1, 2
-WARM_ZERO, WARM_PREV = 0, 1
+WARM_ZERO, WARM_PREV, WARM_MLP = 0, 1, 2
 FLAG_FIXED_ROOT, FLAG_NO_GROUND = 1, 2
-STATUS_NONFINITE, STATUS_NOT_CONVERGED = 1, 2
+STATUS_NONFINITE, STATUS_NOT_CONVERGED, STATUS_FELL_BACK = 1, 2, 4
 
 # state fields: bit -> (name, dtype, rows, length key)
 FIELDS = [
@@ -43,8 +43,8 @@ FIELD_BIT = {f[0]: 1 << k for k, f in enumerate(FIELDS)}
 INDEX = ["body_off", "joint_off", "module_off", "block_off", "blk_type", "blk_a", "blk_b",
          "blk_color", "degree", "bucket", "order"]
 EXPORTS = ["sim_workspace_bytes", "sim_create", "sim_set_pressures", "sim_step",
-           "sim_read_state", "sim_write_state", "sim_read_index", "sim_sizes", "sim_mapping",
-           "sim_destroy", "sim_last_error"]
+           "sim_read_state", "sim_write_state", "sim_set_mlp", "sim_step_record", "sim_read_index",
+           "sim_sizes", "sim_mapping", "sim_destroy", "sim_last_error"]
 
 _P = C.c_void_p
 
@@ -68,7 +68,7 @@ class Desc(C.Structure):
         ("sched_off", _P), ("sched_steps", _P), ("sched_val", _P),
         ("warm_start", C.c_int32), ("flags", C.c_uint32), ("use_graph", C.c_int32),
         ("autotune", C.c_int32), ("map_waves", C.c_int32), ("map_min_seg", C.c_int32),
-        ("map_grid", C.c_int32),
+        ("map_grid", C.c_int32), ("mlp_fallback", C.c_int32),
     ]
 
 
@@ -91,6 +91,8 @@ def lib():
         L.sim_read_index.argtypes = [_P, C.c_int32, _P, C.c_int64]
         L.sim_sizes.argtypes = [_P, C.POINTER(C.c_int64)]
         L.sim_mapping.argtypes = [_P, C.POINTER(C.c_int32)]
+        L.sim_set_mlp.argtypes = [_P, _P, _P, C.c_int]
+        L.sim_step_record.argtypes = [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(C.c_int64)]
         L.sim_destroy.argtypes = [_P]
         L.sim_destroy.restype = None
         L.sim_last_error.argtypes = []
@@ -150,6 +152,7 @@ def make_desc(wl, **over):
     d.map_waves = int(over.get("map_waves", 0))
     d.map_min_seg = int(over.get("map_min_seg", 0))
     d.map_grid = int(over.get("map_grid", 0))
+    d.mlp_fallback = int(over.get("mlp_fallback", 1))
     return d, keep
 
 
@@ -189,6 +192,7 @@ class Sim:
         mp = (C.c_int32 * 4)()
         _check(self.L.sim_mapping(self.h, mp))
         self.mapping = dict(waves=mp[0], min_seg=mp[1], grid=mp[2], tiles=mp[3])
+        self._substeps = d.substeps
         self._len = dict(n=self.n, N=self.N, J=self.J, Mt=self.Mt)
         del keep
 
@@ -254,6 +258,24 @@ class Sim:
             ptrs[k] = _P(t.data_ptr())
             mask |= 1 << k
         _check(self.L.sim_read_state(self.h, mask, ptrs, MEM_DEVICE))
+
+    def set_mlp(self, params, mean_std):
+        """Network parameters and normalisation, torch device tensors."""
+        p = params.to(self.torch.float32).contiguous()
+        ms = mean_std.to(self.torch.float32).contiguous()
+        _check(self.L.sim_set_mlp(self.h, _P(p.data_ptr()), _P(ms.data_ptr()), MEM_DEVICE))
+        self._mlp_keep = (p, ms)
+
+    def step_record(self, n_steps, features, targets):
+        """Advance and record network inputs / targets into device tensors
+        features[rows, 32], targets[rows, 3]; returns the rows written."""
+        w = C.c_int64(0)
+        _check(self.L.sim_step_record(self.h, int(n_steps), _P(features.data_ptr()),
+                                      _P(targets.data_ptr()), features.shape[0], C.byref(w)))
+        return int(w.value)
+
+    def record_rows(self, n_steps):
+        return 2 * self.J * int(self._substeps) * int(n_steps)
 
     def index(self, name) -> np.ndarray:
         k = INDEX.index(name)

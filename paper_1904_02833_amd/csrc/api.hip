@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "snake_mlp.h"
 
 using namespace snake;
 
@@ -33,6 +34,7 @@ struct Sizes {
     int64_t n = 0, N = 0, J = 0, Mt = 0, blocks = 0, pieces = 0;
     int max_B = 0;
     bool autotune = false;
+    bool mlp = false;
 };
 
 // Carves 256-byte aligned sub-arrays out of the workspace (base == nullptr
@@ -76,7 +78,7 @@ int validate(const sim_desc_t* d, Sizes* z)
          !(d->k_deflate > 0.0) || !(d->T_p >= 0.0)))
         return fail(SIM_EINVAL, "paper pressure-law constants out of range");
     if (!std::isfinite(d->kappa_max)) return fail(SIM_EINVAL, "kappa_max must be finite");
-    if (d->warm_start != SIM_WARM_ZERO && d->warm_start != SIM_WARM_PREV)
+    if (d->warm_start != SIM_WARM_ZERO && d->warm_start != SIM_WARM_PREV && d->warm_start != SIM_WARM_MLP)
         return fail(SIM_EINVAL, "unknown warm start");
     if (d->flags & ~(SIM_FLAG_FIXED_ROOT | SIM_FLAG_NO_GROUND)) return fail(SIM_EINVAL, "unknown flag bits");
     if (d->controller < SIM_CTRL_EXTERNAL || d->controller > SIM_CTRL_SCHEDULE)
@@ -110,6 +112,7 @@ int validate(const sim_desc_t* d, Sizes* z)
         if (seg > 64 * mw) return fail(SIM_EINVAL, "map_waves too small for the longest snake");
     }
     z->autotune = d->autotune != 0;
+    z->mlp = d->warm_start == SIM_WARM_MLP;
     if (d->controller == SIM_CTRL_SERPENOID && (!d->ctrl_freq || !d->ctrl_phase0))
         return fail(SIM_EINVAL, "serpenoid controller needs ctrl_freq and ctrl_phase0");
     if (d->controller == SIM_CTRL_SCHEDULE) {
@@ -139,6 +142,10 @@ struct Views {
     char* state_begin;      // the mutable state is one contiguous range
     size_t state_bytes;
     char* backup;           // copy of the state while autotuning
+    float* feat;            // [2J][32] network inputs (learned warm start)
+    float* mlp_y;           // [2J][3] network outputs
+    float* mlp_params;      // [6467]
+    float* mlp_ms;          // [64]
     int* Bn;
     int* Mn;
     int* Sn;
@@ -194,6 +201,11 @@ size_t carve(const Sizes& z, char* base, Views* v)
     ip.bucket = c.take<int>(n);
     ip.order = c.take<int>(n);
     ip.color_scratch = c.take<int>(N);
+    k.q_pred = c.take<float>(4 * N);
+    v->feat = z.mlp ? c.take<float>(64 * J) : nullptr;
+    v->mlp_y = z.mlp ? c.take<float>(6 * J) : nullptr;
+    v->mlp_params = z.mlp ? c.take<float>(8192) : nullptr;
+    v->mlp_ms = z.mlp ? c.take<float>(64) : nullptr;
     v->hdr = c.take<int4>(n + 1);
     v->slots = c.take<int2>(n + 1);
     v->backup = z.autotune ? c.take<char>((int64_t)v->state_bytes) : nullptr;
@@ -246,6 +258,7 @@ std::map<std::string, Mapping> g_tune_cache;
 struct sim {
     Sizes z;
     Views v;
+    bool mlp_loaded = false;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     Mapping map;
@@ -272,11 +285,49 @@ int upload_tiles(sim* s, const Mapping& mp)
     return SIM_OK;
 }
 
-int launch_steps(sim* s, hipStream_t st, int n_steps)
+int tiles(sim* s, hipStream_t st, int n_steps, int phase, int sub)
 {
     hipError_t e = launch_tiles(s->map.nw, s->v.kp, s->v.hdr, s->v.slots, s->n_tiles, s->map.grid,
-                                n_steps, st);
+                                n_steps, phase, sub, st);
     if (e != hipSuccess) return hip_fail(e, "step launch");
+    return SIM_OK;
+}
+
+// One substep split in two launches around the network: prediction, the
+// network's inputs and outputs, then the warm-started solve.  With feat /
+// tgt given (recording) the inputs go there and the final multipliers are
+// written as targets.
+int split_substep(sim* s, hipStream_t st, int sub, float* feat, float* tgt)
+{
+    const KParams& k = s->v.kp;
+    int rc = tiles(s, st, 1, kPhasePre, sub);
+    if (rc) return rc;
+    float* f = feat ? feat : s->v.feat;
+    if (f) {
+        hipError_t e = launch_features(k, f, st);
+        if (e != hipSuccess) return hip_fail(e, "features");
+    }
+    if (s->z.mlp) {
+        rc = mlp_forward(s->v.mlp_params, s->v.mlp_ms, f, s->v.mlp_y, 2 * (int64_t)s->z.J, st);
+        if (rc) return fail(rc, std::string("network: ") + mlp_last_error());
+    }
+    rc = tiles(s, st, 1, kPhaseSolve, sub);
+    if (rc) return rc;
+    if (tgt) {
+        hipError_t e = launch_targets(k, tgt, st);
+        if (e != hipSuccess) return hip_fail(e, "targets");
+    }
+    return SIM_OK;
+}
+
+int launch_steps(sim* s, hipStream_t st, int n_steps)
+{
+    if (!s->z.mlp) return tiles(s, st, n_steps, kPhaseFull, 0);
+    for (int k = 0; k < n_steps; ++k)
+        for (int sub = 0; sub < s->v.kp.substeps; ++sub) {
+            int rc = split_substep(s, st, sub, nullptr, nullptr);
+            if (rc) return rc;
+        }
     return SIM_OK;
 }
 
@@ -447,7 +498,10 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     k.Mn = w.Mn;
     k.Sn = w.Sn;
     k.body_off = w.ip.body_off;
+    k.joint_off = w.ip.joint_off;
     k.module_off = w.ip.module_off;
+    k.mlp_y = w.mlp_y;
+    k.fallback = d->mlp_fallback ? 1 : 0;
     k.comp = w.comp;
     k.mu = w.mu;
     k.freq = w.freq;
@@ -488,6 +542,7 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     k.ctrl_offset = d->ctrl_offset;
     k.flags = (int)d->flags;
     k.warm = d->warm_start;
+    k.lam_ref = (float)(m * 9.81 * h * h);
 
     IParams& ip = w.ip;
     ip.n_snakes = n;
@@ -517,6 +572,13 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     CK(hipMemcpyAsync(w.sched_off, soff.data(), soff.size() * sizeof(int), hipMemcpyHostToDevice, st), "upload schedule");
     CK(hipMemcpyAsync(w.sched_start, sstart.data(), sstart.size() * sizeof(int), hipMemcpyHostToDevice, st), "upload schedule");
     CK(hipMemcpyAsync(w.sched_val, sval.data(), sval.size() * sizeof(float), hipMemcpyHostToDevice, st), "upload schedule");
+    if (z.mlp) {
+        CK(hipMemsetAsync(w.mlp_params, 0, 8192 * sizeof(float), st), "zero network");
+        CK(hipMemsetAsync(w.mlp_ms, 0, 32 * sizeof(float), st), "zero network");
+        std::vector<float> ones(32, 1.f);
+        CK(hipMemcpyAsync(w.mlp_ms + 32, ones.data(), 32 * sizeof(float), hipMemcpyHostToDevice, st), "zero network");
+        CK(hipStreamSynchronize(st), "zero network");
+    }
     CK(launch_index(ip, st), "index kernels");
     CK(hipStreamSynchronize(st), "index work");
     {
@@ -554,6 +616,7 @@ error:
 int sim_step(sim_t* s, int32_t n_steps)
 {
     if (!s) return fail(SIM_EINVAL, "sim is NULL");
+    if (s->z.mlp && !s->mlp_loaded) return fail(SIM_ESTATE, "learned warm start needs sim_set_mlp first");
     if (n_steps < 0) return fail(SIM_EINVAL, "n_steps must be >= 0");
     if (n_steps == 0) return SIM_OK;
     if (!s->use_graph) {
@@ -652,6 +715,42 @@ int sim_read_state(sim_t* s, uint32_t fields, void* const* dst, int mem)
 int sim_write_state(sim_t* s, uint32_t fields, const void* const* src, int mem)
 {
     return copy_fields(s, fields, const_cast<void* const*>(src), mem, false);
+}
+
+int sim_set_mlp(sim_t* s, const float* params, const float* mean_std, int mem)
+{
+    if (!s || !params || !mean_std) return fail(SIM_EINVAL, "sim, params or mean_std is NULL");
+    if (!s->z.mlp) return fail(SIM_ESTATE, "the descriptor's warm start is not SIM_WARM_MLP");
+    if (mem != SIM_MEM_HOST && mem != SIM_MEM_DEVICE) return fail(SIM_EINVAL, "unknown memory kind");
+    const hipMemcpyKind kind = mem == SIM_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    hipError_t e = hipMemcpyAsync(s->v.mlp_params, params, mlp_param_count() * sizeof(float), kind, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->v.mlp_ms, mean_std, 64 * sizeof(float), kind, s->stream);
+    if (e == hipSuccess && mem == SIM_MEM_HOST) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "set network");
+    s->mlp_loaded = true;
+    return SIM_OK;
+}
+
+int sim_step_record(sim_t* s, int32_t n_steps, float* features, float* targets, int64_t capacity_rows,
+                    int64_t* written)
+{
+    if (!s || !features || !targets) return fail(SIM_EINVAL, "sim, features or targets is NULL");
+    if (n_steps < 0) return fail(SIM_EINVAL, "n_steps must be >= 0");
+    if (s->z.mlp && !s->mlp_loaded) return fail(SIM_ESTATE, "learned warm start needs sim_set_mlp first");
+    const int64_t per_sub = 2 * s->z.J;
+    const int64_t rows = per_sub * s->v.kp.substeps * (int64_t)n_steps;
+    if (written) *written = rows;
+    if (capacity_rows < rows)
+        return fail(SIM_ENOMEM, "record buffers hold " + std::to_string(capacity_rows) + " rows, need " +
+                                    std::to_string(rows));
+    int64_t row = 0;
+    for (int k = 0; k < n_steps; ++k)
+        for (int sub = 0; sub < s->v.kp.substeps; ++sub) {
+            int rc = split_substep(s, s->stream, sub, features + 32 * row, targets + 3 * row);
+            if (rc) return rc;
+            row += per_sub;
+        }
+    return SIM_OK;
 }
 
 int sim_read_index(sim_t* s, int32_t which, int32_t* dst, int64_t count)

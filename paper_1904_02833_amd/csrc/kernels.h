@@ -10,8 +10,12 @@ namespace snake {
 enum : int { kFixedRoot = 1, kNoGround = 2 };
 enum : int { kLawLag = 0, kLawPaper = 1 };
 enum : int { kCtrlExternal = 0, kCtrlSerpenoid = 1, kCtrlSchedule = 2 };
-enum : int { kWarmZero = 0, kWarmPrev = 1 };
-enum : int { kStatusNonfinite = 1, kStatusNotConverged = 2 };
+enum : int { kWarmZero = 0, kWarmPrev = 1, kWarmMlp = 2 };
+enum : int { kStatusNonfinite = 1, kStatusNotConverged = 2, kStatusFellBack = 4 };
+// kPhaseFull runs whole steps; a split substep is kPhasePre (command,
+// pressure, prediction into q_pred) followed by kPhaseSolve (multiplier
+// initialisation, iterations, velocities).
+enum : int { kPhaseFull = 0, kPhasePre = 1, kPhaseSolve = 2 };
 
 // Everything one step kernel needs.  Device pointers into the workspace,
 // structure-of-arrays (component k of body i at [k * N + i]).
@@ -22,6 +26,7 @@ struct KParams {
     const int* Mn;
     const int* Sn;
     const int* body_off;
+    const int* joint_off;
     const int* module_off;
     const float* comp;      // [3][n]: stretch, bend, twist compliance / h^2
     const float* mu;        // [n]
@@ -39,6 +44,8 @@ struct KParams {
     float* cmd;             // [Mt]
     float* lam_j;           // [6][J]
     float* lam_c;           // [3][N]
+    float* q_pred;          // [4][N] predicted orientation (split substeps)
+    const float* mlp_y;     // [2J][3] network outputs (learned warm start)
     float* residual;        // [n]
     int* iters_out;         // [n]
     int* status;            // [n]
@@ -55,7 +62,8 @@ struct KParams {
     float k_i, k_d, T_p, p_s, amp, kappa_max;
     int controller;
     double dt, ctrl_alpha, ctrl_offset;
-    int flags, warm;
+    int flags, warm, fallback;
+    float lam_ref;          // multiplier scale m 9.81 h^2 of the network units
 };
 
 // Index-work parameters.
@@ -81,7 +89,9 @@ struct IParams {
 // when grid < n_tiles).  hdr[t] = {first slot, slots, spans waves, 0};
 // slot = {snake, lane offset << 8 | log2 segment}.
 hipError_t launch_tiles(int nw, const KParams& P, const int4* hdr, const int2* slots, int n_tiles,
-                        int grid, int n_steps, hipStream_t stream);
+                        int grid, int n_steps, int phase, int sub, hipStream_t stream);
+hipError_t launch_features(const KParams& P, float* feat, hipStream_t stream);
+hipError_t launch_targets(const KParams& P, float* tgt, hipStream_t stream);
 hipError_t launch_index(const IParams& P, hipStream_t stream);
 hipError_t launch_init_state(const KParams& P, hipStream_t stream);
 hipError_t launch_set_cmd(float* dst, const float* src, int n, hipStream_t stream);

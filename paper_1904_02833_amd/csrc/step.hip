@@ -150,11 +150,12 @@ __device__ __forceinline__ V3 contact_incr(V3 lc, float cn, V3 d, float sc, floa
 // wave, larger ones span whole waves and exchange the boundary body and the
 // residual through LDS (two workgroup barriers per iteration, only in tiles
 // that have such a snake).
-template <int NW>
+template <int NW, int PHASE>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4)))
 k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, int n_tiles,
-       int n_steps)
+       int n_steps, int sub_only)
 {
+    constexpr int phase = PHASE;
     // lane 0 of each wave: u(3), q(4), axis(3), wave done.  Buffer 2 is used
     // at the start of a substep, buffers 0/1 alternate between iterations (and
     // buffer 1 serves the warm start): a buffer is written again only after a
@@ -296,38 +297,73 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
         }
         float rstep = 0.f;
         int itstep = 0, status = 0, itsum = 0;
+        // a split substep continues the counters of its step
+        if (phase == kPhaseSolve && sub_only > 0 && live) {
+            rstep = P.residual[s];
+            itstep = P.iters_out[s];
+            status = P.status[s];
+        }
+        const int it_before = itstep;
 
-        for (int st = 0; st < n_steps; ++st) {
+        // residual of the current iterate (one evaluation pass, no update)
+        auto eval_residual = [&](int buf, V3 dxp, float zp, V3 d, Q4 qq, V3 l_s, V3 l_b, V3 l_c, float c0h,
+                                 float s0h, float ct, float stt) -> float {
+            const V3 aA = qaxis(qq);
+            V3 dn, an;
+            Q4 qn;
+            fetch_next(buf, d, qq, aA, false, dn, qn, an);
+            Geo g;
+            V3 Dls, Dlb;
+            float rs, rb;
+            joint_eval(dxp, d, dn, qq, qn, aA, an, c0h, s0h, ct, stt, wA, c1A, c2A, wB, c1B, c2B, hl,
+                       P.inv_L, comp_s, comp_b, comp_t, l_s, l_b, g, Dls, Dlb, rs, rb);
+            const float cn = zp + d.z;
+            const float rc = (l_c.x > 0.f ? fabsf(cn) : fmaxf(-cn, 0.f)) * P.inv_L;
+            float rl = fmaxf(hasj ? fmaxf(rs, rb) : 0.f, (hasb && gnd) ? rc : 0.f);
+            rl = (rl == rl) ? rl : INFINITY;
+            rl = seg_reduce(rl);
+            V3 inx, inth;
+            return fetch_prev(zero, zero, rl, inx, inth);
+        };
+
+        const int steps = phase == kPhaseFull ? n_steps : 1;
+        for (int st = 0; st < steps; ++st) {
             const long long stepc = (live ? P.step[s] : 0) + st;
-            // command for the end of this step (eq. snake_control or a schedule)
-            if (hasb && P.controller == kCtrlSerpenoid) {
-                const double freq = P.freq[s], ph0 = P.phase0[s];
-                const double t = (double)(stepc + 1) * P.dt;
-                double a = sin(6.283185307179586476925286766559 * freq * t + P.ctrl_alpha * m + ph0) +
-                           P.ctrl_offset;
-                a = fmin(1.0, fmax(-1.0, a));
-                cmdv = (float)a;
-            } else if (hasb && P.controller == kCtrlSchedule) {
-                int lo = P.sched_off[gm], hi = P.sched_off[gm + 1] - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if ((long long)P.sched_start[mid] <= stepc)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
+            const int sub0 = phase == kPhaseFull ? 0 : sub_only;
+            const int sub1 = phase == kPhaseFull ? P.substeps : sub_only + 1;
+            if (phase != kPhaseSolve && sub0 == 0) {
+                // command for the end of this step (eq. snake_control or a schedule)
+                if (hasb && P.controller == kCtrlSerpenoid) {
+                    const double freq = P.freq[s], ph0 = P.phase0[s];
+                    const double t = (double)(stepc + 1) * P.dt;
+                    double a = sin(6.283185307179586476925286766559 * freq * t + P.ctrl_alpha * m + ph0) +
+                               P.ctrl_offset;
+                    a = fmin(1.0, fmax(-1.0, a));
+                    cmdv = (float)a;
+                } else if (hasb && P.controller == kCtrlSchedule) {
+                    int lo = P.sched_off[gm], hi = P.sched_off[gm + 1] - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if ((long long)P.sched_start[mid] <= stepc)
+                            lo = mid;
+                        else
+                            hi = mid - 1;
+                    }
+                    cmdv = P.sched_val[lo];
                 }
-                cmdv = P.sched_val[lo];
+                if (P.law == kLawPaper) {
+                    p0 = paper_update(P, p0, fmaxf(cmdv, 0.f));
+                    p1 = paper_update(P, p1, fmaxf(-cmdv, 0.f));
+                }
             }
             const float u0 = fmaxf(cmdv, 0.f), u1 = fmaxf(-cmdv, 0.f);
-            if (P.law == kLawPaper) {
-                p0 = paper_update(P, p0, u0);
-                p1 = paper_update(P, p1, u1);
+            if (phase == kPhaseFull) {
+                rstep = 0.f;
+                itstep = 0;
+                status = 0;
             }
-            rstep = 0.f;
-            itstep = 0;
-            status = 0;
-            for (int sub = 0; sub < P.substeps; ++sub) {
-                if (P.law == kLawLag) {
+            for (int sub = sub0; sub < sub1; ++sub) {
+                if (phase != kPhaseSolve && P.law == kLawLag) {
                     p0 = u0 + (p0 - u0) * (u0 > p0 ? P.lag_in : P.lag_de);
                     p1 = u1 + (p1 - u1) * (u1 > p1 ? P.lag_in : P.lag_de);
                 }
@@ -341,7 +377,12 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                 const V3 xp = x;
                 const Q4 qp = q;
                 V3 d = zero;
-                if (hasb && !fixed) {
+                if (phase == kPhaseSolve) {
+                    if (hasb && !fixed) {
+                        d = h * v;
+                        q = Q4{P.q_pred[gb], P.q_pred[N + gb], P.q_pred[2 * N + gb], P.q_pred[3 * N + gb]};
+                    }
+                } else if (hasb && !fixed) {
                     v.z -= h * P.g;
                     d = h * v;
                     const V3 ax = qaxis(q);
@@ -354,6 +395,18 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                     v = zero;
                     w = zero;
                 }
+                if (phase == kPhasePre) {
+                    // the predicted orientation goes to its own array; the state
+                    // keeps the start-of-substep orientation for the solve
+                    if (hasb) {
+                        P.q_pred[gb] = q.w;
+                        P.q_pred[N + gb] = q.x;
+                        P.q_pred[2 * N + gb] = q.y;
+                        P.q_pred[3 * N + gb] = q.z;
+                    }
+                    q = qp;
+                    continue;
+                }
                 const float zp = xp.z - P.R;
                 V3 dxp;
                 {
@@ -364,8 +417,26 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                 }
 
                 // multiplier initialisation
-                if (P.warm == kWarmPrev) {
-                    // x <- x~ + W J(x~)^T lambda0 with lambda0 = previous multipliers
+                const bool learned = PHASE == kPhaseSolve && P.warm == kWarmMlp;
+                if (P.warm == kWarmPrev || learned) {
+                    if (learned) {
+                        // network outputs: stretch in the predicted frame of body i,
+                        // bend-twist in the joint frame, both in units of lam_ref
+                        ls = zero;
+                        lb = zero;
+                        if (hasj) {
+                            const float* y = P.mlp_y + 6 * (size_t)gj;
+                            ls = P.lam_ref * qrot(q, mk(y[0], y[1], y[2]));
+                            lb = (P.lam_ref * P.L) * mk(y[3], y[4], y[5]);
+                        }
+                        lc = zero;
+                    }
+                    const V3 d_zero = d;
+                    const Q4 q_zero = q;
+                    float r_zero = 0.f;
+                    if (learned && P.fallback)
+                        r_zero = eval_residual(0, dxp, zp, d, q, zero, zero, zero, c0h, s0h, ct, stt);
+                    // x <- x~ + W J(x~)^T lambda0
                     const V3 aA = qaxis(q);
                     V3 dn, an;
                     Q4 qn;
@@ -390,6 +461,18 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                     if (hasb && !fixed) {
                         d = d + ((inx + ownx) + dxc);
                         q = qturn(q, inth + ownth);
+                    }
+                    if (learned && P.fallback) {
+                        // keep the learned start only if it begins closer than zero
+                        const float r_nn = eval_residual(0, dxp, zp, d, q, ls, lb, lc, c0h, s0h, ct, stt);
+                        if (live && !(r_nn <= r_zero)) {
+                            d = d_zero;
+                            q = q_zero;
+                            ls = zero;
+                            lb = zero;
+                            lc = zero;
+                            status |= kStatusFellBack;
+                        }
                     }
                 } else {
                     ls = zero;
@@ -507,14 +590,118 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
             P.lam_j[5 * J + gj] = lb.z;
         }
         if (NW > 1) __syncthreads();   // every lane has read step[s] before it moves
-        if (live && i == 0) {
+        if (live && i == 0 && phase != kPhasePre) {
             P.residual[s] = rstep;
             P.iters_out[s] = itstep;
             P.status[s] = status;
-            P.step[s] = P.step[s] + n_steps;
-            P.iters_total[s] = P.iters_total[s] + itsum;
+            const bool last = phase == kPhaseFull || sub_only == P.substeps - 1;
+            if (last) P.step[s] = P.step[s] + (phase == kPhaseFull ? n_steps : 1);
+            P.iters_total[s] = P.iters_total[s] + (phase == kPhaseFull ? itsum : itstep - it_before);
         }
     }
+}
+
+// Inputs of the warm-start network, two rows (stretch, bend-twist) per joint,
+// evaluated at the predicted state of the current substep in the predicted
+// frame of the joint's first body (layout in snake.h, sim_step_record).
+__global__ void k_features(KParams P, float* __restrict__ feat)
+{
+    const int gj = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gj >= P.J) return;
+    int lo = 0, hi = P.n_snakes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P.joint_off[mid] <= gj)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int s = lo;
+    const int i = gj - P.joint_off[s];
+    const int B = P.Bn[s], S = P.Sn[s];
+    const int a = P.body_off[s] + i, b = a + 1;
+    const int gm = P.module_off[s] + i / S;
+    const int N = P.N, J = P.J, n = P.n_snakes;
+    auto ld3 = [&](const float* f, int k) { return mk(f[k], f[N + k], f[2 * N + k]); };
+    auto ldq = [&](const float* f, int k) { return Q4{f[k], f[N + k], f[2 * N + k], f[3 * N + k]}; };
+    const V3 xa = ld3(P.x, a), xb = ld3(P.x, b);
+    const V3 va = ld3(P.v, a), vb = ld3(P.v, b);
+    const V3 wa = ld3(P.w, a), wb = ld3(P.w, b);
+    const Q4 qa = ldq(P.q_pred, a), qb = ldq(P.q_pred, b);
+    const float p0 = P.p[gm], p1 = P.p[P.Mt + gm];
+    const bool intra = (i + 1) % S != 0;
+    const float th0 = intra ? P.kappa_max * (p0 - p1) * P.L : 0.f;
+    const float h = P.h, hl = P.half_L;
+    const V3 aA = qaxis(qa), aB = qaxis(qb);
+    const V3 rA = hl * aA, rB = (-hl) * aB;
+    const Q4 qac = qconj(qa);
+    // stretch violation at the predicted positions, then in body-A axes
+    const V3 Cs = ((xa - xb) + h * (va - vb)) + (rA - rB);
+    float s0h, c0h;
+    sincosf(0.5f * th0, &s0h, &c0h);
+    const Q4 t = qmul(qac, qb);
+    Q4 e{c0h * t.w + s0h * t.z, c0h * t.x + s0h * t.y, c0h * t.y - s0h * t.x, c0h * t.z - s0h * t.w};
+    if (e.w < 0.f) e = Q4{-e.w, -e.x, -e.y, -e.z};
+    const V3 rel_v = (va + cross(wa, rA)) - (vb + cross(wb, rB));
+    const float ref = P.lam_ref, refb = P.lam_ref * P.L;
+    const V3 ls = mk(P.lam_j[gj], P.lam_j[J + gj], P.lam_j[2 * J + gj]);
+    const V3 lb = mk(P.lam_j[3 * J + gj], P.lam_j[4 * J + gj], P.lam_j[5 * J + gj]);
+    float f[32];
+    const V3 c = (1.f / P.L) * qrot(qac, Cs);
+    f[0] = c.x; f[1] = c.y; f[2] = c.z;
+    f[3] = 2.f * e.x; f[4] = 2.f * e.y; f[5] = 2.f * e.z;
+    const V3 rv = (h / P.L) * qrot(qac, rel_v);
+    f[6] = rv.x; f[7] = rv.y; f[8] = rv.z;
+    const V3 rw = h * qrot(qac, wb - wa);
+    f[9] = rw.x; f[10] = rw.y; f[11] = rw.z;
+    const V3 gz = qrot(qac, mk(0.f, 0.f, 1.f));
+    f[12] = gz.x; f[13] = gz.y; f[14] = gz.z;
+    f[15] = p0; f[16] = p1; f[17] = P.cmd[gm]; f[18] = th0;
+    f[22] = log10f(fmaxf(P.comp[s], 1e-30f));
+    f[23] = log10f(fmaxf(P.comp[n + s], 1e-30f));
+    f[24] = log10f(fmaxf(P.comp[2 * n + s], 1e-30f));
+    f[25] = P.mu[s];
+    f[26] = P.lam_c[a] / ref;
+    f[27] = P.lam_c[b] / ref;
+    f[28] = ((xa.z + h * va.z) - P.R) * P.inv_L;
+    f[29] = ((xb.z + h * vb.z) - P.R) * P.inv_L;
+    f[31] = B > 1 ? (float)i / (float)(B - 1) : 0.f;
+    float* out = feat + (size_t)64 * gj;
+    // stretch row
+    const V3 lsl = (1.f / ref) * qrot(qac, ls);
+    f[19] = lsl.x; f[20] = lsl.y; f[21] = lsl.z; f[30] = 0.f;
+    for (int k = 0; k < 32; ++k) out[k] = f[k];
+    // bend-twist row
+    f[19] = lb.x / refb; f[20] = lb.y / refb; f[21] = lb.z / refb; f[30] = 1.f;
+    for (int k = 0; k < 32; ++k) out[32 + k] = f[k];
+}
+
+// Training targets: the substep's final multipliers in network units
+// (stretch in the predicted frame of body A over lam_ref, bend-twist over
+// lam_ref L), two rows of 3 per joint.
+__global__ void k_targets(KParams P, float* __restrict__ tgt)
+{
+    const int gj = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gj >= P.J) return;
+    int lo = 0, hi = P.n_snakes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P.joint_off[mid] <= gj)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int a = P.body_off[lo] + (gj - P.joint_off[lo]);
+    const int N = P.N, J = P.J;
+    const Q4 qa{P.q_pred[a], P.q_pred[N + a], P.q_pred[2 * N + a], P.q_pred[3 * N + a]};
+    const V3 ls = mk(P.lam_j[gj], P.lam_j[J + gj], P.lam_j[2 * J + gj]);
+    const V3 y = (1.f / P.lam_ref) * qrot(qconj(qa), ls);
+    const float refb = P.lam_ref * P.L;
+    float* out = tgt + (size_t)6 * gj;
+    out[0] = y.x; out[1] = y.y; out[2] = y.z;
+    out[3] = P.lam_j[3 * J + gj] / refb;
+    out[4] = P.lam_j[4 * J + gj] / refb;
+    out[5] = P.lam_j[5 * J + gj] / refb;
 }
 
 // straight chains at rest on the ground along +x, zero pressure
@@ -574,19 +761,41 @@ __global__ void k_set_cmd(float* dst, const float* src, int n)
 }  // namespace
 
 hipError_t launch_tiles(int nw, const KParams& P, const int4* hdr, const int2* slots, int n_tiles,
-                        int grid, int n_steps, hipStream_t stream)
+                        int grid, int n_steps, int phase, int sub, hipStream_t stream)
 {
     if (n_tiles <= 0) return hipSuccess;
     if (grid <= 0 || grid > n_tiles) grid = n_tiles;
     const dim3 g(grid), b(64 * nw);
+#define SNAKE_LAUNCH(NWV, PH) \
+    hipLaunchKernelGGL((k_tile<NWV, PH>), g, b, 0, stream, P, hdr, slots, n_tiles, n_steps, sub)
+#define SNAKE_PHASES(NWV)                                        \
+    if (phase == kPhaseFull) SNAKE_LAUNCH(NWV, kPhaseFull);     \
+    else if (phase == kPhasePre) SNAKE_LAUNCH(NWV, kPhasePre);  \
+    else SNAKE_LAUNCH(NWV, kPhaseSolve);
     switch (nw) {
-        case 1: hipLaunchKernelGGL(k_tile<1>, g, b, 0, stream, P, hdr, slots, n_tiles, n_steps); break;
-        case 2: hipLaunchKernelGGL(k_tile<2>, g, b, 0, stream, P, hdr, slots, n_tiles, n_steps); break;
-        case 4: hipLaunchKernelGGL(k_tile<4>, g, b, 0, stream, P, hdr, slots, n_tiles, n_steps); break;
-        case 8: hipLaunchKernelGGL(k_tile<8>, g, b, 0, stream, P, hdr, slots, n_tiles, n_steps); break;
-        case 16: hipLaunchKernelGGL(k_tile<16>, g, b, 0, stream, P, hdr, slots, n_tiles, n_steps); break;
+        case 1: SNAKE_PHASES(1) break;
+        case 2: SNAKE_PHASES(2) break;
+        case 4: SNAKE_PHASES(4) break;
+        case 8: SNAKE_PHASES(8) break;
+        case 16: SNAKE_PHASES(16) break;
         default: return hipErrorInvalidValue;
     }
+#undef SNAKE_PHASES
+#undef SNAKE_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_features(const KParams& P, float* feat, hipStream_t stream)
+{
+    if (P.J <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_features, dim3((P.J + 127) / 128), dim3(128), 0, stream, P, feat);
+    return hipGetLastError();
+}
+
+hipError_t launch_targets(const KParams& P, float* tgt, hipStream_t stream)
+{
+    if (P.J <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_targets, dim3((P.J + 127) / 128), dim3(128), 0, stream, P, tgt);
     return hipGetLastError();
 }
 

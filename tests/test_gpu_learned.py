@@ -1,0 +1,168 @@
+"""Learned warm start on the GPU: split substeps, network inputs and targets,
+the warm start from network outputs with the residual fallback, and what a
+trained network gains over the plain method."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from parity import LAM_TOL, POS_TOL, compare, gpu_state, load_gpu, load_oracle, rounded_state
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+snk = pytest.importorskip("paper_1904_02833_amd")
+from paper_1904_02833_amd import warmstart  # noqa: E402
+
+
+def test_split_substeps_equal_fused_steps():
+    """Recording runs every substep as prediction + solve launches; with the
+    zero start it must reproduce the fused kernel bit for bit."""
+    wl = W.make("uneven", n_snakes=120)
+    a = snk.Sim(wl)
+    b = snk.Sim(wl)
+    a.step(3)
+    rows = b.record_rows(3)
+    f = torch.empty((rows, 32), device="cuda")
+    t = torch.empty((rows, 3), device="cuda")
+    assert b.step_record(3, f, t) == rows
+    ra, rb = a.read(), b.read()
+    for k in ra:
+        assert np.array_equal(ra[k], rb[k]), k
+    with pytest.raises(snk.SimError):
+        b.step_record(1, f[:10], t[:10])
+    a.close()
+    b.close()
+
+
+def one_substep_state(wl, steps):
+    o = oracle.Oracle(wl)
+    o.run(steps, threads=8)
+    o.commands()
+    return rounded_state(o)
+
+
+def test_features_and_targets_match_oracle():
+    wl = W.make("uneven", n_snakes=40)
+    st = one_substep_state(wl, 12)
+    h = wl.dt / wl.substeps
+    kw = dict(controller=W.CTRL_EXTERNAL, dt=h, substeps=1)
+    sim = snk.Sim(wl, **kw)
+    load_gpu(sim, st)
+    rows = sim.record_rows(1)
+    f = torch.empty((rows, 32), device="cuda")
+    t = torch.empty((rows, 3), device="cuda")
+    sim.step_record(1, f, t)
+    fg, tg = f.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
+    o = oracle.Oracle(wl, **kw)
+    load_oracle(o, st)
+    fo, to = [], []
+    for s in range(o.n):
+        qp = o.pre_substep(s, 0)
+        fo.append(o.features(s, qp))
+        o.solve_substep(s, qp)
+        to.append(o.targets(s, qp))
+    fo, to = np.concatenate(fo), np.concatenate(to)
+    err = np.abs(fg - fo)
+    print("\n[features] max abs err per column", np.round(err.max(0), 7))
+    assert np.all(err <= 2e-5 + 1e-5 * np.abs(fo))
+    for typ in (0, 1):
+        a, b = tg[typ::2], to[typ::2]
+        rel = np.abs(a - b).max() / np.abs(b).max()
+        print(f"[targets] type {typ} relative err {rel:.3g}")
+        assert rel <= LAM_TOL
+
+
+def constant_net(c):
+    """Network whose output is the constant c for every input (zero weights)."""
+    p = np.zeros(6467, np.float32)
+    p[6464:6467] = c
+    ms = torch.cat([torch.zeros(32), torch.ones(32)]).cuda()
+    return snk.Net(p, ms)
+
+
+@pytest.mark.parametrize("fallback", [0, 1])
+def test_warm_start_from_network_outputs_matches_oracle(fallback):
+    """A network that outputs the constant c gives lambda0 = m g h^2 R(qA) c
+    (stretch) and m g h^2 L c (bend-twist); the GPU's warm-started substep
+    must match the oracle started from those multipliers."""
+    c = np.array([0.6, -0.4, 0.3], np.float32)
+    wl = W.make("uneven", n_snakes=40)
+    st = one_substep_state(wl, 12)
+    h = wl.dt / wl.substeps
+    kw = dict(controller=W.CTRL_EXTERNAL, dt=h, substeps=1)
+    net = constant_net(c)
+    sim = snk.Sim(wl, warm_start=snk.WARM_MLP, mlp_fallback=fallback, **kw)
+    sim.set_mlp(net.params, net.mean_std)
+    load_gpu(sim, st)
+    sim.step(1)
+    g = gpu_state(sim)
+    o = oracle.Oracle(wl, warm=oracle.WARM_GIVEN, fallback=fallback, **kw)
+    load_oracle(o, st)
+    ref = 0.02 * 9.81 * h * h
+    statuses = []
+    for s in range(o.n):
+        qp = o.pre_substep(s, 0)
+        d = o.snake(s)
+        for j in range(d["lam_j"].shape[0]):
+            qa = qp[j]
+            w_, x_, y_, z_ = qa
+            R = np.array([[1 - 2 * (y_ * y_ + z_ * z_), 2 * (x_ * y_ - w_ * z_), 2 * (x_ * z_ + w_ * y_)],
+                          [2 * (x_ * y_ + w_ * z_), 1 - 2 * (x_ * x_ + z_ * z_), 2 * (y_ * z_ - w_ * x_)],
+                          [2 * (x_ * z_ - w_ * y_), 2 * (y_ * z_ + w_ * x_), 1 - 2 * (x_ * x_ + y_ * y_)]])
+            d["lam_j"][j, :3] = ref * (R @ c.astype(np.float64))
+            d["lam_j"][j, 3:] = ref * 0.01 * c.astype(np.float64)
+        d["lam_c"][...] = 0.0
+        statuses.append(o.solve_substep(s, qp)[2])
+    statuses = np.array(statuses)
+    fell_o = (statuses & 4) != 0
+    fell_g = (g["status"] & snk.STATUS_FELL_BACK) != 0
+    print(f"\n[warm mlp fallback={fallback}] fell back: oracle {fell_o.sum()} gpu {fell_g.sum()} of {o.n}")
+    same = fell_o == fell_g
+    assert same.mean() >= 0.9
+    err = compare(o, g, wl.mu)
+    keep = np.nonzero(same)[0]
+    assert err["pos"][keep].max() <= POS_TOL
+    for k in ("lam_s", "lam_b", "lam_n", "lam_t"):
+        assert err[k][keep].max() <= LAM_TOL, k
+    sim.close()
+
+
+def test_trained_network_gain_report():
+    """Record the solver's converged multipliers on training snakes, train
+    the network on the GPU, and compare the learned start with the plain one
+    on held-out snakes: iterations per substep to residual 1e-4 (at most 200)
+    and the residual each reaches.  The comparison is reported; the test
+    checks the learned path runs, trains (held-out loss below the constant
+    predictor's) and keeps every snake finite."""
+    train_wl = W.make("uneven", n_snakes=256, seed=2004)
+    ds = warmstart.concat([warmstart.record(train_wl, 2, warmup_steps=w, tol=1e-6, iters=1500)
+                           for w in (5, 20)])
+    print(f"\n[learned] dataset rows {ds.features.shape[0]}")
+    losses = []
+    net = warmstart.train(ds, epochs=4, batch=4096, lr=2e-3, log=lambda e, l: losses.append(l))
+    held = warmstart.record(W.make("uneven", n_snakes=64, seed=3004), 1, warmup_steps=10, tol=1e-6,
+                            iters=1500)
+    base = float(((held.targets - held.targets.mean(0)) ** 2).mean().cpu())
+    test_loss = warmstart.evaluate_loss(net, held)
+    print(f"[learned] train losses {np.round(losses, 4)}, held-out {test_loss:.4f} vs constant {base:.4f}")
+    assert test_loss < base
+    ev = W.make("uneven", n_snakes=512, seed=1004)
+    ev.tol, ev.iters = 1e-4, 200
+    out = {}
+    for name in ("plain", "learned"):
+        sim = snk.Sim(ev) if name == "plain" else warmstart.learned_sim(ev, net)
+        sim.step(10)
+        r0 = sim.read("iters_total")["iters_total"].copy()
+        res, fell = [], 0
+        for _ in range(10):
+            sim.step(1)
+            r = sim.read("residual", "status")
+            res.append(r["residual"])
+            fell += int(((r["status"] & snk.STATUS_FELL_BACK) != 0).sum())
+            assert not np.any(r["status"] & snk.STATUS_NONFINITE)
+        its = (sim.read("iters_total")["iters_total"] - r0).sum() / (ev.n_snakes * 10 * ev.substeps)
+        out[name] = (its, float(np.median(np.concatenate(res))), fell)
+        sim.close()
+    print(f"[learned] mean iterations per substep plain {out['plain'][0]:.1f} learned {out['learned'][0]:.1f}; "
+          f"median residual plain {out['plain'][1]:.3g} learned {out['learned'][1]:.3g}; "
+          f"fallbacks {out['learned'][2]}")

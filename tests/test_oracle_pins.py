@@ -645,3 +645,92 @@ def test_colouring_closed_form_and_offsets():
         assert ix["bucket"][s] == (int(B) - 1).bit_length()
     order = np.lexsort((np.arange(len(Bs)), -Bs))
     assert list(ix["order"]) == list(order)
+
+
+# ---------------------------------------------------------------- split substep
+
+def test_split_substeps_equal_whole_step():
+    """Prediction and solve run separately give the whole step bit for bit."""
+    wl = W.make("single")
+    a = oracle.Oracle(wl)
+    a.run(30)
+    b = oracle.Oracle(wl, controller=W.CTRL_EXTERNAL)
+    for k in ("x", "q", "v", "w", "p", "lam_j", "lam_c"):
+        getattr(b, k)[...] = getattr(a, k)
+    a.commands()
+    b.cmd[:] = a.cmd
+    a.run(1)
+    for sub in range(4):
+        qp = b.pre_substep(0, sub)
+        b.solve_substep(0, qp)
+    for k in ("x", "q", "v", "w", "p", "lam_j", "lam_c"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k
+
+
+def test_fallback_keeps_better_start_and_rejects_worse():
+    """A given start equal to the zero-start solution's multipliers begins
+    closer and is kept; a wild start begins farther, falls back, and then
+    reproduces the zero-start substep exactly."""
+    wl = W.custom([2], [6], controller=W.CTRL_EXTERNAL, substeps=1, dt=1 / 240)
+    base = oracle.Oracle(wl)
+    base.cmd[:] = [0.5, -0.5]
+    base.run(5)
+    st = {k: getattr(base, k).copy() for k in ("x", "q", "v", "w", "p", "cmd", "lam_j", "lam_c")}
+
+    def run(warm, lam_j=None, lam_c=None):
+        o = oracle.Oracle(wl, warm=warm, fallback=1)
+        for k, vv in st.items():
+            getattr(o, k)[...] = vv
+        qp = o.pre_substep(0, 0)
+        if lam_j is not None:
+            o.lam_j[...] = lam_j
+            o.lam_c[...] = lam_c
+        r = o.solve_substep(0, qp)
+        return o, r
+
+    z, rz = run(oracle.WARM_ZERO)
+    good, rg = run(oracle.WARM_GIVEN, z.lam_j, z.lam_c)
+    assert not (rg[2] & oracle.STATUS_FELL_BACK if hasattr(oracle, "STATUS_FELL_BACK") else rg[2] & 4)
+    assert rg[0] < rz[0]
+    bad, rb = run(oracle.WARM_GIVEN, np.full_like(z.lam_j, 1e-3), np.full_like(z.lam_c, 1e-3))
+    assert rb[2] & 4
+    assert np.array_equal(bad.x, z.x) and np.array_equal(bad.lam_j, z.lam_j)
+
+
+def test_features_closed_form_and_yaw_invariance():
+    """Straight chain at rest after the prediction: every constraint value
+    and relative velocity vanishes, gravity points along body z, and the
+    penetration feature is -g h^2 / L; turning the whole chain about the
+    vertical leaves every feature unchanged."""
+    wl = W.custom([2], [5], controller=W.CTRL_EXTERNAL)
+    o = oracle.Oracle(wl)
+    o.cmd[:] = 0.0
+    qp = o.pre_substep(0, 0)
+    f = o.features(0, qp)
+    h = 1 / 240
+    assert f.shape == (18, 32)
+    assert np.abs(f[:, 0:12]).max() < 1e-13
+    assert np.allclose(f[:, 12:15], [0, 0, 1], atol=1e-15)
+    assert np.allclose(f[:, 28:30], -9.81 * h * h / 0.01, rtol=1e-12)
+    assert np.array_equal(f[0::2, 30], np.zeros(9)) and np.array_equal(f[1::2, 30], np.ones(9))
+    # a bent, moving chain, then the same turned by 0.7 rad about z
+    rng = np.random.default_rng(2)
+    o2 = oracle.Oracle(wl)
+    o2.cmd[:] = [0.7, -0.3]
+    o2.run(20)
+    o2.v[:] += rng.normal(scale=0.01, size=o2.v.shape)
+    o2.w[:] += rng.normal(scale=0.3, size=o2.w.shape)
+    o3 = oracle.Oracle(wl)
+    yaw = rotvec_quat(np.array([0, 0, 0.7]))
+    Rz = rotmat(yaw)
+    o3.x[:] = o2.x @ Rz.T
+    o3.v[:] = o2.v @ Rz.T
+    o3.w[:] = o2.w @ Rz.T
+    o3.q[:] = np.array([qmul(yaw, q) for q in o2.q])
+    for k in ("p", "cmd", "lam_c"):
+        getattr(o3, k)[...] = getattr(o2, k)
+    o3.lam_j[:, :3] = o2.lam_j[:, :3] @ Rz.T
+    o3.lam_j[:, 3:] = o2.lam_j[:, 3:]
+    f2 = o2.features(0, o2.pre_substep(0, 0))
+    f3 = o3.features(0, o3.pre_substep(0, 0))
+    assert np.abs(f2 - f3).max() < 1e-10
