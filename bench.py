@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-snakes", type=int, default=1024)
     ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
+    ap.add_argument("--learned-steps", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three 256 MiB device copies (scale for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -62,6 +66,50 @@ def kernel_digest():
     csrc = os.path.join(ROOT, "paper_1904_02833_amd", "csrc")
     return ":".join(hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()[:16]
                     for f in ("step.hip", "device_math.h", "kernels.h"))
+
+
+def learned_comparison(n_steps):
+    """Learned vs zero warm start on the learned-start workload (the uneven
+    batch, evaluation seed): record the solver's converged multipliers at the
+    states the plain solver visits on training-seed snakes, train the
+    network with the library's kernels, then time both starts."""
+    import torch
+
+    import paper_1904_02833_amd as snk
+    import workloads as W
+    from paper_1904_02833_amd import warmstart
+
+    t0 = time.perf_counter()
+    train_wl = W.make("uneven", n_snakes=1024, seed=2004)
+    ds = warmstart.record_on_policy(train_wl, 10, stride=3, warmup_steps=6, tol=1e-6, iters=1500)
+    losses = []
+    net = warmstart.train(ds, epochs=4, batch=4096, lr=2e-3, log=lambda e, l: losses.append(l))
+    t_train = time.perf_counter() - t0
+    ev = W.make("learned")
+    ev.tol, ev.iters = 1e-4, 200
+    out = {"train": {"rows": int(ds.features.shape[0]), "seconds": t_train, "loss_by_epoch": losses,
+                     "teacher": "tolerance 1e-6 (at most 1500 iterations), first substep of states "
+                                "visited by the plain solver"}}
+    for name in ("plain", "learned"):
+        sim = snk.Sim(ev, autotune=1) if name == "plain" else warmstart.learned_sim(ev, net, autotune=1)
+        sim.step(5)
+        torch.cuda.synchronize()
+        r0 = sim.read("iters_total")["iters_total"].copy()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        for _ in range(n_steps):
+            sim.step(1)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        r = sim.read("iters_total", "residual", "status")
+        its = (r["iters_total"] - r0).sum() / (ev.n_snakes * n_steps * ev.substeps)
+        out[name] = {"snake_steps_per_s": ev.n_snakes * n_steps / (ms / 1e3),
+                     "ms_per_step": ms / n_steps, "mean_iters_per_substep": float(its),
+                     "residual_median_last_step": float(np.median(r["residual"])),
+                     "fell_back_last_step": int(np.sum((r["status"] & 4) != 0))}
+        sim.close()
+    return out
 
 
 def cpu_baseline(wl, n_snakes, n_steps):
@@ -87,6 +135,17 @@ def main():
                           "(snakes are independent, see DESIGN.md for the multi-GPU split)"}))
         sys.exit(2)
     import torch
+
+    if args.copy_calibration:
+        n = 256 << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": n, "dispatches": 3}), flush=True)
+        return
 
     import paper_1904_02833_amd as snk
     import workloads as W
@@ -147,7 +206,7 @@ def main():
                    "tol": wl.tol, "max_iters": wl.iters},
         "constraint_iters_per_s": citers,
         "mean_iters_per_substep": float(its.sum() / (wl.n_snakes * args.steps * wl.substeps)),
-        "not_converged_snakes_last_step": int(np.sum(r["status"] & 2 != 0)),
+        "not_converged_snakes_last_step": int(np.sum((r["status"] & 2) != 0)),
         "residual_last_step": {"median": float(np.median(r["residual"])),
                                "p99": float(np.percentile(r["residual"], 99)),
                                "max": float(np.max(r["residual"]))},
@@ -159,6 +218,8 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_snakes, args.cpu_steps)
+    if not args.no_learned:
+        out["learned_warm_start"] = learned_comparison(args.learned_steps)
     sim.close()
     print(json.dumps(out), flush=True)
 

@@ -44,6 +44,34 @@ def record(wl, n_steps, warmup_steps=0, tol=1e-6, iters=2000, device="cuda", **o
     return Dataset(feats, tgts)
 
 
+def record_on_policy(wl, n_records, stride=1, warmup_steps=0, tol=1e-6, iters=2000, device="cuda",
+                     **over) -> Dataset:
+    """Targets at the states the deployed (plain) solver visits: the batch
+    advances with its own settings; every `stride` steps a teacher copy
+    solves the next step's first substep from that state to `tol`, and only
+    that substep's rows are kept."""
+    import torch
+
+    lead = Sim(wl, device=device, **over)
+    teacher = Sim(wl, device=device, tol=tol, iters=iters, **over)
+    per_sub = 2 * teacher.J
+    rows = teacher.record_rows(1)
+    f = torch.empty((rows, 32), dtype=torch.float32, device=device)
+    t = torch.empty((rows, 3), dtype=torch.float32, device=device)
+    feats, tgts = [], []
+    if warmup_steps:
+        lead.step(warmup_steps)
+    for _ in range(n_records):
+        teacher.write(**lead.read())
+        teacher.step_record(1, f, t)
+        feats.append(f[:per_sub].clone())
+        tgts.append(t[:per_sub].clone())
+        lead.step(stride)
+    lead.close()
+    teacher.close()
+    return Dataset(torch.cat(feats), torch.cat(tgts))
+
+
 def concat(parts) -> Dataset:
     import torch
     return Dataset(torch.cat([p.features for p in parts]), torch.cat([p.targets for p in parts]))
