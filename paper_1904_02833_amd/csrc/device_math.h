@@ -68,7 +68,9 @@ __device__ __forceinline__ V3 sym3_solve(float a, float b, float c, float d, flo
     float c11 = a * f - c * c;
     float c12 = b * c - a * e;
     float c22 = a * d - b * b;
-    float inv = 1.f / (a * c00 + b * c01 + c * c02);
+    // hardware reciprocal (1 ulp): the determinant of an SPD block is far
+    // from the FP32 limits, and the solve's rounding is at that level anyway
+    float inv = __builtin_amdgcn_rcpf(a * c00 + b * c01 + c * c02);
     return V3{(c00 * r.x + c01 * r.y + c02 * r.z) * inv, (c01 * r.x + c11 * r.y + c12 * r.z) * inv,
               (c02 * r.x + c12 * r.y + c22 * r.z) * inv};
 }

@@ -131,12 +131,13 @@ __device__ __forceinline__ V3 contact_incr(V3 lc, float cn, V3 d, float sc, floa
     float t0 = lc.y - sc * m * d.x;
     float t1 = lc.z - sc * m * d.y;
     const float cap = mu * ln;
-    const float nt = sqrtf(t0 * t0 + t1 * t1);
+    const float n2 = t0 * t0 + t1 * t1;
     if (ln <= 0.f) {
         t0 = 0.f;
         t1 = 0.f;
-    } else if (nt > cap) {
-        const float f = cap / nt;
+    } else if (n2 > cap * cap) {
+        // onto the disc of radius cap: scale by cap / |t| (hardware rsqrt)
+        const float f = cap * __builtin_amdgcn_rsqf(n2);
         t0 *= f;
         t1 *= f;
     }
@@ -236,13 +237,20 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                 for (int w = 0; w < (seg >> 6); ++w) r = fmaxf(r, xred[w0 + w]);
             return r;
         };
+        // Max over the lane segment of non-negative values (NaN already
+        // mapped to +inf): on their bit patterns the integer order is the
+        // float order.  Segments are at least 16 lanes and aligned, so the
+        // xor partners below 16 always lie in the same segment.
         auto seg_reduce = [&](float v) -> float {
+            int b = __float_as_int(v);
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                const float t = __shfl_xor(v, o, 64);
-                if (o < seg) v = fmaxf(v, t);
+            for (int o = 32; o >= 16; o >>= 1) {
+                const int t = __shfl_xor(b, o, 64);
+                if (o < seg) b = max(b, t);
             }
-            return v;
+#pragma unroll
+            for (int o = 8; o >= 1; o >>= 1) b = max(b, __shfl_xor(b, o, 64));
+            return __int_as_float(b);
         };
 
         int B = 0, S = 1, bo = 0, mo = 0;

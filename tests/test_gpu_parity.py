@@ -10,7 +10,8 @@ import pytest
 
 import oracle
 import workloads as W
-from parity import LAM_TOL, POS_TOL, advance_both, compare, gpu_state, load_gpu, rounded_state
+from parity import (LAM_TOL, POS_TOL, advance_both, compare, f32, gpu_state, load_gpu, load_oracle,
+                    rounded_state)
 
 pytestmark = pytest.mark.gpu
 
@@ -387,3 +388,49 @@ def test_uneven_full_batch_residuals_stay_bounded():
         assert r["residual"].max() < 1.0, (n, int(np.argmax(r["residual"])), float(r["residual"].max()))
     print(f"\n[uneven-full] worst residual over 30 steps {worst:.3g}")
     sim.close()
+
+
+def slice_snakes(st, o_full, sample):
+    """Concatenate the per-snake rows of state dict st (whole batch) for the
+    sampled snakes, in sample order."""
+    out = {}
+    for key, off in (("x", o_full.body_off), ("q", o_full.body_off), ("v", o_full.body_off),
+                     ("w", o_full.body_off), ("lam_c", o_full.body_off), ("lam_j", o_full.joint_off),
+                     ("p", o_full.module_off), ("cmd", o_full.module_off)):
+        if key in st:
+            out[key] = np.concatenate([st[key][off[s]:off[s + 1]] for s in sample])
+    return out
+
+
+def test_full_uniform_batch_sampled_parity():
+    """The benchmark's workload in its launch configuration: 4096 snakes of
+    64 bodies, autotuned mapping, residual 1e-4 or at most 200 iterations.
+    After 10 steps on the GPU, the whole batch takes one more substep on the
+    GPU, and sampled snakes (first, last, middle, random) take it in the
+    oracle from the same FP32 state and commands."""
+    wl = W.make("uniform")
+    wl.tol, wl.iters = 1e-4, 200
+    lead = snk.Sim(wl, autotune=1)
+    lead.step(10)
+    st = gpu_state(lead)
+    lead.close()
+    o_full = oracle.Oracle(wl)
+    o_full.step[:] = 10
+    st["cmd"] = f32(o_full.commands())
+    rng = np.random.default_rng(11)
+    sample = sorted({0, 1, 2047, 4095, *rng.choice(4096, 8, replace=False).tolist()})
+    h = wl.dt / wl.substeps
+    kw = dict(controller=W.CTRL_EXTERNAL, dt=h, substeps=1)
+    sim = snk.Sim(wl, autotune=1, **kw)
+    load_gpu(sim, st)
+    sim.step(1)
+    print(f"\n[full-uniform] mapping {sim.mapping}")
+    gs = gpu_state(sim)
+    g = slice_snakes(gs, o_full, sample)
+    sim.close()
+    sub = wl.take(np.array(sample))
+    o = oracle.Oracle(sub, **kw)
+    load_oracle(o, slice_snakes(st, o_full, sample))
+    o.run(1, threads=8)
+    assert np.array_equal(o.iters, gs["iters"][sample])
+    assert_parity("full-uniform-sampled", compare(o, g, sub.mu), n_bodies=sub.total_bodies)
