@@ -36,8 +36,8 @@ PEAK_FP32 = 157.3e12       # MI355X FP32 vector, packed; 78.6e12 without packed 
 # WRITE_SIZE runs scaled by a device copy of known size (summaries in
 # profiles/), keyed by workload and waves per workgroup, with the digest of
 # the kernel sources they were taken on; a changed kernel reports null.
-MEASURED_TRAFFIC = {("uniform", 4): 136.3e6, ("uneven", 4): 913.9e6}
-TRAFFIC_SOURCES_DIGEST = "174bdb2cebbfaff4:46f9fd9afa94955f:fcc196db1ba34bbf"
+MEASURED_TRAFFIC = {("uniform", 4): 134.8e6, ("uneven", 4): 911.8e6}
+TRAFFIC_SOURCES_DIGEST = "d71e092676cd7c08:959545d7849e09a9:c9b7935adf4c92cd"
 PEAK_HBM = 8.0e12
 STATE_BYTES = 4 * (13 + 13 + 9 + 9)   # per body: state in/out, multipliers in/out
 
