@@ -25,11 +25,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "snake-steps/s & constraint-iters/s at residual≤1e-4, plain vs NN warm-start"
 # FP32 operations per body per iteration (evaluation of its joint's stretch
-# and bend-twist blocks, its contact, the increments and the gathered
-# update; a fused multiply-add counts 2), per final evaluation-only pass, and
-# per body per substep outside the iterations.  Counted from the kernel.
-FLOP_ITER = 542
-FLOP_EVAL = 336
+# and bend-twist blocks, its contact, the joint torques, the increments and
+# the gathered update), per final evaluation-only pass (evaluation and
+# torques), and per body per substep outside the iterations.  Counted from
+# the compiled iteration loop: add, sub, mul = 1, fused multiply-add = 2.
+FLOP_ITER = 462
+FLOP_EVAL = 320
 FLOP_SUBSTEP = 100
 PEAK_FP32 = 157.3e12       # MI355X FP32 vector, packed; 78.6e12 without packed FP32
 # HBM bytes per launch of the solver kernel, from rocprofv3 FETCH_SIZE and

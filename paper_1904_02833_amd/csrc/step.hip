@@ -31,8 +31,7 @@ namespace {
 // geometry of joint i needed again by the increment application
 struct Geo {
     V3 aA, aB;   // body axes; the attachment offsets are +-L/2 along them
-    Q4 e, qA;
-    float ct, st;
+    Q4 e, qA0;   // joint error quaternion; qA q0 (body A's frame turned by the rest rotation)
 };
 
 __device__ __forceinline__ float paper_update(const KParams& P, float pf, float uf)
@@ -62,25 +61,33 @@ __device__ __forceinline__ void joint_eval(V3 dxp, V3 dA, V3 dB, Q4 qA, Q4 qB, V
     g.aA = aA;   // body x axes R(q) e_x of A and B
     g.aB = aB;
     const V3 rA = hl * aA, rB = (-hl) * aB;
-    g.qA = qA;
-    g.ct = ct;
-    g.st = st;
 
     // stretch: end point of A minus start point of B (eq. rigid_to_particle form)
     const V3 C = (dxp + (dA - dB)) + (rA - rB);
     const V3 rhs = C + comp_s * ls;
-    // K = (wA + wB) I + c1A hl^2 (I - aA aA^T) + c1B hl^2 (I - aB aB^T)
+    // K + alpha~ = (wA + wB + comp_s) I + kA (I - a a^T) + kB (I - b b^T) with the unit
+    // axes a, b and kX = c1X hl^2, i.e. dg I - U diag(kA, kB) U^T with U = [a b].
+    // Woodbury: (K + alpha~)^-1 r = (r + U M^-1 diag(kA, kB) U^T r) / dg with the
+    // 2x2 matrix M = [[dg - kA, -kA g], [-kB g, dg - kB]], g = a.b (det M > 0).
     const float kA = c1A * (hl * hl), kB = c1B * (hl * hl);
     const float dg = wA + wB + kA + kB + comp_s;
     const V3 a = g.aA, b = g.aB;
-    Dls = -sym3_solve(dg - kA * a.x * a.x - kB * b.x * b.x, -kA * a.x * a.y - kB * b.x * b.y,
-                      -kA * a.x * a.z - kB * b.x * b.z, dg - kA * a.y * a.y - kB * b.y * b.y,
-                      -kA * a.y * a.z - kB * b.y * b.z, dg - kA * a.z * a.z - kB * b.z * b.z, rhs);
+    const float ar = dot(a, rhs), br = dot(b, rhs), gab = dot(a, b);
+    const float pA = dg - kA, pB = dg - kB;
+    const float det = pA * pB - (kA * kB) * (gab * gab);
+    const float u1 = kA * ar, u2 = kB * br;
+    const float f = __builtin_amdgcn_rcpf(det * dg);
+    const float y1 = (pB * u1 + (kA * gab) * u2) * f;
+    const float y2 = ((kB * gab) * u1 + pA * u2) * f;
+    const float inv_dg = __builtin_amdgcn_rcpf(dg);
+    Dls = -((inv_dg * rhs + y1 * a) + y2 * b);
     rs = amax3(rhs) * inv_L;
 
-    // bend-twist: e = conj(q0) conj(qA) qB with q0 = (c0h, 0, 0, s0h)
-    const Q4 t = qmul(qconj(qA), qB);
-    Q4 e{c0h * t.w + s0h * t.z, c0h * t.x + s0h * t.y, c0h * t.y - s0h * t.x, c0h * t.z - s0h * t.w};
+    // bend-twist: e = conj(qA q0) qB with q0 = (c0h, 0, 0, s0h)
+    const Q4 qA0{qA.w * c0h - qA.z * s0h, qA.x * c0h + qA.y * s0h, qA.y * c0h - qA.x * s0h,
+                 qA.z * c0h + qA.w * s0h};
+    g.qA0 = qA0;
+    Q4 e = qmul(qconj(qA0), qB);
     if (e.w < 0.f) e = Q4{-e.w, -e.x, -e.y, -e.z};
     g.e = e;
     const V3 ev{e.x, e.y, e.z};
@@ -103,25 +110,23 @@ __device__ __forceinline__ void joint_eval(V3 dxp, V3 dA, V3 dB, Q4 qA, Q4 qB, V
     rb = amax3(rhsb);
 }
 
-// W J^T of joint increments (dls, dlb) on bodies A and B
-__device__ __forceinline__ void joint_corr(const Geo& g, V3 dls, V3 dlb, float wA, float c1A,
-                                           float c2A, float wB, float c1B, float c2B, float hl,
-                                           V3& dxA, V3& dthA, V3& dxB, V3& dthB)
+// J^T of joint increments (dls, dlb): the force on body A is dls (on B, -dls);
+// the torques on A and B are tA, tB.  Stretch: rA x dl with rA = hl aA (and
+// -rB x dl with rB = -hl aB); bend-twist: -/+ z with z = R(qA q0) G^T dlb,
+// G = e_w I - [e]x.  Each body applies its inverse mass and inertia to the
+// sum of what its joints send it.
+__device__ __forceinline__ void joint_torques(const Geo& g, V3 dls, V3 dlb, float hl, V3& tA, V3& tB)
 {
-    dxA = wA * dls;
-    dxB = (-wB) * dls;
-    // Ia^-1 (rA x dl) with rA = hl aA, and -Ib^-1 (rB x dl) with rB = -hl aB
-    // (the axis component of r x dl vanishes)
-    const V3 thsA = (c1A * hl) * cross(g.aA, dls);
-    const V3 thsB = (c1B * hl) * cross(g.aB, dls);
     const V3 ev{g.e.x, g.e.y, g.e.z};
-    const V3 y = g.e.w * dlb + cross(ev, dlb);
-    const V3 y0{g.ct * y.x - g.st * y.y, g.st * y.x + g.ct * y.y, y.z};
-    const V3 z = qrot(g.qA, y0);
-    const V3 thbA = -(c1A * z + (c2A * dot(g.aA, z)) * g.aA);
-    const V3 thbB = c1B * z + (c2B * dot(g.aB, z)) * g.aB;
-    dthA = thsA + thbA;
-    dthB = thsB + thbB;
+    const V3 z = qrot(g.qA0, g.e.w * dlb + cross(ev, dlb));
+    tA = hl * cross(g.aA, dls) - z;
+    tB = hl * cross(g.aB, dls) + z;
+}
+
+// I^-1 t = c1 t + c2 (a . t) a for a body with axis a (c1 = c2 = 0: fixed)
+__device__ __forceinline__ V3 inv_inertia(V3 t, V3 a, float c1, float c2)
+{
+    return c1 * t + (c2 * dot(a, t)) * a;
 }
 
 // increments of the contact block of a body (normal, tangent x, tangent y)
@@ -454,21 +459,17 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                     float rs, rb;
                     joint_eval(dxp, d, dn, q, qn, aA, an, c0h, s0h, ct, stt, wA, c1A, c2A, wB, c1B,
                                c2B, hl, P.inv_L, comp_s, comp_b, comp_t, ls, lb, g, Dls, Dlb, rs, rb);
-                    V3 dxA, dthA, dxB, dthB;
-                    joint_corr(g, ls, lb, wA, c1A, c2A, wB, c1B, c2B, hl, dxA, dthA, dxB, dthB);
-                    dxB = sel(hasj, dxB, zero);
-                    dthB = sel(hasj, dthB, zero);
-                    V3 inx, inth;
-                    fetch_prev(dxB, dthB, 0.f, inx, inth);
+                    V3 tA, tB;
+                    joint_torques(g, ls, lb, hl, tA, tB);
+                    V3 inf, intq;
+                    fetch_prev(sel(hasj, -ls, zero), sel(hasj, tB, zero), 0.f, inf, intq);
                     const bool recv = hasb && i > 0;
-                    inx = sel(recv, inx, zero);
-                    inth = sel(recv, inth, zero);
-                    const V3 ownx = sel(hasj, dxA, zero);
-                    const V3 ownth = sel(hasj, dthA, zero);
+                    const V3 fsum = sel(recv, inf, zero) + sel(hasj, ls, zero);
+                    const V3 tsum = sel(recv, intq, zero) + sel(hasj, tA, zero);
                     const V3 dxc = (gnd && !fixed) ? P.inv_m * mk(lc.y, lc.z, lc.x) : zero;
                     if (hasb && !fixed) {
-                        d = d + ((inx + ownx) + dxc);
-                        q = qturn(q, inth + ownth);
+                        d = d + (wA * fsum + dxc);
+                        q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
                     }
                     if (learned && P.fallback) {
                         // keep the learned start only if it begins closer than zero
@@ -510,12 +511,10 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                     rl = seg_reduce(rl);
 
                     const V3 dls = sj * Dls, dlb = sj * Dlb;
-                    V3 dxA, dthA, dxB, dthB;
-                    joint_corr(g, dls, dlb, wA, c1A, c2A, wB, c1B, c2B, hl, dxA, dthA, dxB, dthB);
-                    dxB = sel(hasj, dxB, zero);
-                    dthB = sel(hasj, dthB, zero);
-                    V3 inx, inth;
-                    const float r = fetch_prev(dxB, dthB, rl, inx, inth);
+                    V3 tA, tB;
+                    joint_torques(g, dls, dlb, hl, tA, tB);
+                    V3 inf, intq;
+                    const float r = fetch_prev(sel(hasj, -dls, zero), sel(hasj, tB, zero), rl, inf, intq);
 
                     if (!done) {
                         const bool bad = !(r < INFINITY);
@@ -533,21 +532,20 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                     if (!done) {
                         V3 dlc = zero;
                         if (gnd && !fixed) dlc = contact_incr(lc, cn, d, sc, mass, mu);
-                        const V3 dxc = P.inv_m * mk(dlc.y, dlc.z, dlc.x);
-                        // gather in the fixed order: joint i-1, joint i, contact
+                        // gather in a fixed order: forces of joint i-1 (received),
+                        // joint i and the contact through the inverse mass; torques
+                        // of the two joints through the inverse inertia
                         const bool recv = hasb && i > 0;
-                        inx = sel(recv, inx, zero);
-                        inth = sel(recv, inth, zero);
-                        const V3 ownx = sel(hasj, dxA, zero);
-                        const V3 ownth = sel(hasj, dthA, zero);
+                        const V3 fsum = sel(recv, inf, zero) + sel(hasj, dls, zero);
+                        const V3 tsum = sel(recv, intq, zero) + sel(hasj, tA, zero);
                         if (hasj) {
                             ls = ls + dls;
                             lb = lb + dlb;
                         }
                         if (hasb && gnd) lc = lc + dlc;
                         if (hasb && !fixed) {
-                            d = d + ((inx + ownx) + dxc);
-                            q = qturn(q, inth + ownth);
+                            d = d + wA * (fsum + mk(dlc.y, dlc.z, dlc.x));
+                            q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
                         }
                     }
                 }
