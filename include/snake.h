@@ -161,12 +161,13 @@ typedef struct sim_desc {
     int32_t use_graph;         /* 1: replay sim_step launches from a graph  */
     /* Mapping of snakes to lanes.  A workgroup of map_waves wavefronts takes
      * tiles of snakes; each snake owns an aligned power-of-two lane segment
-     * of at least map_min_seg lanes (16, 32 or 64); map_grid workgroups loop
-     * over the tiles (0: one workgroup per tile).  0 selects the default.
-     * autotune = 1 times the candidate mappings on the real batch inside
-     * sim_create (the state is restored afterwards) and keeps the fastest;
-     * explicit map_* values are then ignored.  Every mapping gives
-     * bit-identical results. */
+     * of at least map_min_seg lanes (16, 32 or 64), or with map_rows = 1 a
+     * segment of its length rounded up to 16 lanes, placed without
+     * alignment; map_grid workgroups loop over the tiles (0: one workgroup
+     * per tile).  0 selects the default.  autotune = 1 times the candidate
+     * mappings on the real batch inside sim_create (the state is restored
+     * afterwards) and keeps the fastest; explicit map_* values are then
+     * ignored.  Every mapping gives bit-identical results. */
     int32_t autotune;
     int32_t map_waves;         /* 1, 2, 4, 8 or 16; 64 * map_waves >= every segment */
     int32_t map_min_seg;
@@ -174,6 +175,7 @@ typedef struct sim_desc {
     int32_t mlp_fallback;      /* 1: per snake and substep, keep the learned */
                                /* start only if its initial residual is not  */
                                /* larger than the zero start's               */
+    int32_t map_rows;          /* 0 or 1, see the mapping above             */
 } sim_desc_t;
 
 typedef struct sim sim_t;
@@ -244,9 +246,9 @@ int sim_read_index(sim_t* s, int32_t which, int32_t* dst, int64_t count);
 /* Sizes: n_snakes, N, Jtot, Mtot, n_blocks (host int64 out[5]). */
 int sim_sizes(const sim_t* s, int64_t* out5);
 
-/* Mapping in use: waves per workgroup, minimum segment, grid, tiles
- * (host int32 out[4]). */
-int sim_mapping(const sim_t* s, int32_t* out4);
+/* Mapping in use: waves per workgroup, minimum segment, grid, tiles,
+ * rows layout (host int32 out[5]). */
+int sim_mapping(const sim_t* s, int32_t* out5);
 
 /* Release host resources (the caller frees the workspace).  NULL is a
  * no-op.  Waits for the stream. */

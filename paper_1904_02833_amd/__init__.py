@@ -68,7 +68,7 @@ class Desc(C.Structure):
         ("sched_off", _P), ("sched_steps", _P), ("sched_val", _P),
         ("warm_start", C.c_int32), ("flags", C.c_uint32), ("use_graph", C.c_int32),
         ("autotune", C.c_int32), ("map_waves", C.c_int32), ("map_min_seg", C.c_int32),
-        ("map_grid", C.c_int32), ("mlp_fallback", C.c_int32),
+        ("map_grid", C.c_int32), ("mlp_fallback", C.c_int32), ("map_rows", C.c_int32),
     ]
 
 
@@ -153,6 +153,7 @@ def make_desc(wl, **over):
     d.map_min_seg = int(over.get("map_min_seg", 0))
     d.map_grid = int(over.get("map_grid", 0))
     d.mlp_fallback = int(over.get("mlp_fallback", 1))
+    d.map_rows = int(over.get("map_rows", 0))
     return d, keep
 
 
@@ -189,9 +190,9 @@ class Sim:
         sz = (C.c_int64 * 5)()
         _check(self.L.sim_sizes(self.h, sz))
         self.n, self.N, self.J, self.Mt, self.n_blocks = (int(v) for v in sz)
-        mp = (C.c_int32 * 4)()
+        mp = (C.c_int32 * 5)()
         _check(self.L.sim_mapping(self.h, mp))
-        self.mapping = dict(waves=mp[0], min_seg=mp[1], grid=mp[2], tiles=mp[3])
+        self.mapping = dict(waves=mp[0], min_seg=mp[1], grid=mp[2], tiles=mp[3], rows=mp[4])
         self._substeps = d.substeps
         self._len = dict(n=self.n, N=self.N, J=self.J, Mt=self.Mt)
         del keep

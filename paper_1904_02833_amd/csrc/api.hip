@@ -106,6 +106,7 @@ int validate(const sim_desc_t* d, Sizes* z)
     if (d->map_min_seg != 0 && d->map_min_seg != 16 && d->map_min_seg != 32 && d->map_min_seg != 64)
         return fail(SIM_EINVAL, "map_min_seg must be 0, 16, 32 or 64");
     if (d->map_grid < 0) return fail(SIM_EINVAL, "map_grid must be >= 0");
+    if (d->map_rows != 0 && d->map_rows != 1) return fail(SIM_EINVAL, "map_rows must be 0 or 1");
     if (mw != 0 && !d->autotune) {
         int seg = 16;
         while (seg < z->max_B) seg <<= 1;
@@ -220,33 +221,74 @@ int pow2_at_least(int b, int lo)
 }
 
 struct Mapping {
-    int nw = 1, min_seg = 16, grid = 0;
+    int nw = 1, min_seg = 16, grid = 0, rows = 0;
 };
 
 // Pack snakes, in work order (longest first), into tiles of 64*nw lanes.
-// Each snake gets max(min_seg, 2^ceil(log2 B)) lanes; segments arrive in
-// non-increasing size, so placing them one after another keeps every
-// segment aligned to its own size.
+// Aligned layout: each snake gets max(min_seg, 2^ceil(log2 B)) lanes;
+// segments arrive in non-increasing size, so placing them one after another
+// keeps every segment aligned to its own size.  Rows layout: each snake gets
+// B rounded up to 16 lanes, placed one after another.
+// Tile header: first slot, slot count, some segment crosses a wave
+// boundary, rows layout.  Slot: snake, lane offset << 16 | lanes.
 void build_tiles(const std::vector<int>& order, const std::vector<int>& Bn, const Mapping& mp,
                  std::vector<int4>& hdr, std::vector<int2>& slots)
 {
     hdr.clear();
     slots.clear();
     const int cap = 64 * mp.nw;
-    int pos = cap;
-    for (int sidx : order) {
-        const int seg = pow2_at_least(Bn[sidx], mp.min_seg);
-        if (pos + seg > cap) {
-            hdr.push_back(make_int4((int)slots.size(), 0, 0, 0));
-            pos = 0;
+    if (!mp.rows) {
+        int pos = cap;
+        for (int sidx : order) {
+            const int seg = pow2_at_least(Bn[sidx], mp.min_seg);
+            if (pos + seg > cap) {
+                hdr.push_back(make_int4((int)slots.size(), 0, 0, 0));
+                pos = 0;
+            }
+            slots.push_back(make_int2(sidx, (pos << 16) | seg));
+            int4& h = hdr.back();
+            h.y += 1;
+            if (seg > 64) h.z = 1;
+            pos += seg;
         }
-        int lg = 0;
-        while ((1 << lg) < seg) ++lg;
-        slots.push_back(make_int2(sidx, (pos << 8) | lg));
-        int4& h = hdr.back();
-        h.y += 1;
-        if (seg > 64) h.z = 1;
-        pos += seg;
+        return;
+    }
+    // Rows layout: best fit in decreasing size.  Each segment goes to the
+    // open tile with the least free room that still holds it (a new tile
+    // if none does); tiles keep the order in which they were opened, so the
+    // longest snakes come first.  Open tiles are bucketed by free rows.
+    const int nrow = cap / 16;
+    std::vector<std::vector<int>> slot_of_tile;
+    std::vector<int> fill;
+    std::vector<std::vector<int>> free_rows(nrow + 1);   // tiles by free rows
+    for (int sidx : order) {
+        const int need = (Bn[sidx] + 15) / 16;
+        int t = -1;
+        for (int r = need; r <= nrow && t < 0; ++r)
+            if (!free_rows[r].empty()) {
+                t = free_rows[r].back();
+                free_rows[r].pop_back();
+            }
+        if (t < 0) {
+            t = (int)fill.size();
+            fill.push_back(0);
+            slot_of_tile.emplace_back();
+        }
+        slot_of_tile[t].push_back(sidx);
+        slot_of_tile[t].push_back(fill[t]);
+        fill[t] += need;
+        free_rows[nrow - fill[t]].push_back(t);
+    }
+    for (size_t t = 0; t < fill.size(); ++t) {
+        int4 h = make_int4((int)slots.size(), 0, 0, 1);
+        const std::vector<int>& v = slot_of_tile[t];
+        for (size_t k = 0; k < v.size(); k += 2) {
+            const int sidx = v[k], pos = 16 * v[k + 1], seg = (Bn[sidx] + 15) / 16 * 16;
+            slots.push_back(make_int2(sidx, (pos << 16) | seg));
+            h.y += 1;
+            if ((pos >> 6) != ((pos + seg - 1) >> 6)) h.z = 1;
+        }
+        hdr.push_back(h);
     }
 }
 
@@ -287,7 +329,7 @@ int upload_tiles(sim* s, const Mapping& mp)
 
 int tiles(sim* s, hipStream_t st, int n_steps, int phase, int sub)
 {
-    hipError_t e = launch_tiles(s->map.nw, s->v.kp, s->v.hdr, s->v.slots, s->n_tiles, s->map.grid,
+    hipError_t e = launch_tiles(s->map.nw, s->map.rows, s->v.kp, s->v.hdr, s->v.slots, s->n_tiles, s->map.grid,
                                 n_steps, phase, sub, st);
     if (e != hipSuccess) return hip_fail(e, "step launch");
     return SIM_OK;
@@ -357,11 +399,12 @@ int autotune(sim* s)
     for (int b : s->B_host) min_pow2 = std::min(min_pow2, pow2_at_least(b, 16));
     std::vector<Mapping> cand;
     for (int nw = nw_min; nw <= 16 && nw <= 4 * nw_min; nw <<= 1)
-        for (int ms : {16, 32, 64}) {
-            if (ms != 16 && ms <= min_pow2) continue;   // same packing as 16
+        for (int ms : {16, 32, 64, 0}) {
+            if (ms != 16 && ms != 0 && ms <= min_pow2) continue;   // same packing as 16
             Mapping m;
             m.nw = nw;
-            m.min_seg = ms;
+            m.min_seg = ms ? ms : 16;
+            m.rows = ms == 0;   // rows layout
             cand.push_back(m);
             // persistent variant: one resident wave set per SIMD slot
             Mapping p = m;
@@ -599,6 +642,7 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
         mp.nw = d->map_waves ? d->map_waves : (max_seg > 64 ? max_seg / 64 : 1);
         mp.min_seg = d->map_min_seg ? d->map_min_seg : 16;
         mp.grid = d->map_grid;
+        mp.rows = d->map_rows ? 1 : 0;
         rc = upload_tiles(s, mp);
         if (rc) goto error;
     }
@@ -780,13 +824,14 @@ int sim_sizes(const sim_t* s, int64_t* out5)
     return SIM_OK;
 }
 
-int sim_mapping(const sim_t* s, int32_t* out4)
+int sim_mapping(const sim_t* s, int32_t* out5)
 {
-    if (!s || !out4) return fail(SIM_EINVAL, "sim or out is NULL");
-    out4[0] = s->map.nw;
-    out4[1] = s->map.min_seg;
-    out4[2] = s->map.grid;
-    out4[3] = s->n_tiles;
+    if (!s || !out5) return fail(SIM_EINVAL, "sim or out is NULL");
+    out5[0] = s->map.nw;
+    out5[1] = s->map.min_seg;
+    out5[2] = s->map.grid;
+    out5[3] = s->n_tiles;
+    out5[4] = s->map.rows;
     return SIM_OK;
 }
 

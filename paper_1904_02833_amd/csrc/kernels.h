@@ -86,10 +86,12 @@ struct IParams {
 };
 
 // Solver launch: workgroups of nw waves over n_tiles tiles (grid-stride
-// when grid < n_tiles).  hdr[t] = {first slot, slots, spans waves, 0};
-// slot = {snake, lane offset << 8 | log2 segment}.
-hipError_t launch_tiles(int nw, const KParams& P, const int4* hdr, const int2* slots, int n_tiles,
-                        int grid, int n_steps, int phase, int sub, hipStream_t stream);
+// when grid < n_tiles), aligned power-of-two layout or (rows = 1) segments
+// of whole 16-lane rows placed without alignment.
+// hdr[t] = {first slot, slots, some segment crosses a wave boundary, rows};
+// slot = {snake, lane offset << 16 | segment lanes}.
+hipError_t launch_tiles(int nw, int rows, const KParams& P, const int4* hdr, const int2* slots,
+                        int n_tiles, int grid, int n_steps, int phase, int sub, hipStream_t stream);
 hipError_t launch_features(const KParams& P, float* feat, hipStream_t stream);
 hipError_t launch_targets(const KParams& P, float* tgt, hipStream_t stream);
 hipError_t launch_index(const IParams& P, hipStream_t stream);

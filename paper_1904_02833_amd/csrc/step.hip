@@ -151,12 +151,15 @@ __device__ __forceinline__ V3 contact_incr(V3 lc, float cn, V3 d, float sc, floa
 
 // Tile kernel.  A workgroup of NW waves takes tiles from the cost-ordered
 // tile list (grid-stride, so a grid smaller than the list is persistent).
-// A tile holds snakes in power-of-two lane segments placed largest first, so
-// each segment is aligned to its size: segments of <= 64 lanes stay inside a
-// wave, larger ones span whole waves and exchange the boundary body and the
+// A tile holds snakes in lane segments made of whole 16-lane rows, in one of
+// two layouts: power-of-two segments placed largest first, so each is
+// aligned to its size (segments of <= 64 lanes stay inside a wave), or
+// segments of the snake's length rounded up to 16 lanes, placed one after
+// another (fewer idle lanes, and a segment may cross a wave boundary).  A
+// segment that crosses a wave boundary exchanges the boundary body and the
 // residual through LDS (two workgroup barriers per iteration, only in tiles
 // that have such a snake).
-template <int NW, int PHASE>
+template <int NW, int PHASE, int ROWS>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4)))
 k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, int n_tiles,
        int n_steps, int sub_only)
@@ -168,7 +171,8 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
     // barrier that every reader of its previous contents has passed.
     __shared__ float xnext[3][NW][12];
     __shared__ float xprev[NW][6];   // lane 63 of each wave: increments on the next body
-    __shared__ float xred[NW];       // per-wave residual maximum
+    __shared__ float xfirst[NW];     // residual maximum of the segment piece holding lane 0
+    __shared__ float xlast[NW];      // ... and of the piece holding lane 63
     const int L = threadIdx.x;
     const int lane = L & 63;
     const int wv = L >> 6;
@@ -178,20 +182,26 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
         const bool xw = (NW > 1) && H.z != 0;
         if (NW > 1) __syncthreads();
 
-        int s = -1, i = 0, lg = 6, off = 0;
+        // slot: snake, lane offset << 16 | segment lanes; lanes outside every
+        // segment form whole rows of their own
+        int s = -1, i = 0, seg = 16, off = L & ~15;
         for (int k = 0; k < H.y; ++k) {
             const int2 sl = slots[H.x + k];
-            const int o = sl.y >> 8, l2 = sl.y & 0xff;
-            if (L >= o && L < o + (1 << l2)) {
+            const int o = sl.y >> 16, n = sl.y & 0xffff;
+            if (L >= o && L < o + n) {
                 s = sl.x;
                 i = L - o;
-                lg = l2;
+                seg = n;
                 off = o;
             }
         }
-        const int seg = 1 << lg;
-        const int w0 = off >> 6;            // first wave of a multi-wave segment
         const bool live = s >= 0;
+        constexpr bool packed = ROWS != 0;  // rows layout (segments not aligned)
+        // waves wa..wb hold the segment; in this wave it covers rows ra..rb
+        const int wa = off >> 6, wb = (off + seg - 1) >> 6;
+        const int wbase = wv << 6, row = lane >> 4;
+        const int ra = (max(off, wbase) - wbase) >> 4;
+        const int rb = (min(off + seg, wbase + 64) - 1 - wbase) >> 4;
 
         // neighbour exchange: body i+1 of the same snake lives in lane+1, or
         // for lane 63 of a spanning segment in lane 0 of the next wave
@@ -230,7 +240,8 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                 e[0] = dxB.x; e[1] = dxB.y; e[2] = dxB.z;
                 e[3] = dthB.x; e[4] = dthB.y; e[5] = dthB.z;
             }
-            if (lane == 0) xred[wv] = rw;
+            if (lane == 0) xfirst[wv] = rw;
+            if (lane == 63) xlast[wv] = rw;
             __syncthreads();
             if (lane == 0 && wv > 0) {
                 const float* e = xprev[wv - 1];
@@ -238,23 +249,41 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                 inth = mk(e[3], e[4], e[5]);
             }
             float r = rw;
-            if (seg > 64)
-                for (int w = 0; w < (seg >> 6); ++w) r = fmaxf(r, xred[w0 + w]);
+            if (wa != wb) {
+                // the segment's piece in wave wa holds that wave's lane 63, the
+                // pieces in the following waves hold their lane 0
+                r = xlast[wa];
+                for (int w = wa + 1; w <= wb; ++w) r = fmaxf(r, xfirst[w]);
+            }
             return r;
         };
-        // Max over the lane segment of non-negative values (NaN already
-        // mapped to +inf): on their bit patterns the integer order is the
-        // float order.  Segments are at least 16 lanes and aligned, so the
-        // xor partners below 16 always lie in the same segment.
+        // Max over the segment's piece in this wave of non-negative values
+        // (NaN already mapped to +inf): on their bit patterns the integer
+        // order is the float order.  Rows of 16 lanes reduce by xor swaps;
+        // aligned power-of-two segments join rows by xor swaps too, packed
+        // segments by a prefix and a suffix maximum over their rows.
         auto seg_reduce = [&](float v) -> float {
             int b = __float_as_int(v);
 #pragma unroll
-            for (int o = 32; o >= 16; o >>= 1) {
-                const int t = __shfl_xor(b, o, 64);
-                if (o < seg) b = max(b, t);
-            }
-#pragma unroll
             for (int o = 8; o >= 1; o >>= 1) b = max(b, __shfl_xor(b, o, 64));
+            if (!packed) {
+#pragma unroll
+                for (int o = 16; o <= 32; o <<= 1) {
+                    const int t = __shfl_xor(b, o, 64);
+                    if (o < seg) b = max(b, t);
+                }
+            } else {
+                int p = b, q = b, t;
+                t = __shfl_up(p, 16, 64);
+                if (row > ra) p = max(p, t);
+                t = __shfl_up(p, 32, 64);
+                if (row > ra + 1) p = max(p, t);
+                t = __shfl_down(q, 16, 64);
+                if (row < rb) q = max(q, t);
+                t = __shfl_down(q, 32, 64);
+                if (row < rb - 1) q = max(q, t);
+                b = max(p, q);
+            }
             return __int_as_float(b);
         };
 
@@ -766,26 +795,30 @@ __global__ void k_set_cmd(float* dst, const float* src, int n)
 
 }  // namespace
 
-hipError_t launch_tiles(int nw, const KParams& P, const int4* hdr, const int2* slots, int n_tiles,
-                        int grid, int n_steps, int phase, int sub, hipStream_t stream)
+hipError_t launch_tiles(int nw, int rows, const KParams& P, const int4* hdr, const int2* slots,
+                        int n_tiles, int grid, int n_steps, int phase, int sub, hipStream_t stream)
 {
     if (n_tiles <= 0) return hipSuccess;
     if (grid <= 0 || grid > n_tiles) grid = n_tiles;
     const dim3 g(grid), b(64 * nw);
-#define SNAKE_LAUNCH(NWV, PH) \
-    hipLaunchKernelGGL((k_tile<NWV, PH>), g, b, 0, stream, P, hdr, slots, n_tiles, n_steps, sub)
-#define SNAKE_PHASES(NWV)                                        \
-    if (phase == kPhaseFull) SNAKE_LAUNCH(NWV, kPhaseFull);     \
-    else if (phase == kPhasePre) SNAKE_LAUNCH(NWV, kPhasePre);  \
-    else SNAKE_LAUNCH(NWV, kPhaseSolve);
+#define SNAKE_LAUNCH(NWV, PH, RW) \
+    hipLaunchKernelGGL((k_tile<NWV, PH, RW>), g, b, 0, stream, P, hdr, slots, n_tiles, n_steps, sub)
+#define SNAKE_PHASES(NWV, RW)                                        \
+    if (phase == kPhaseFull) SNAKE_LAUNCH(NWV, kPhaseFull, RW);     \
+    else if (phase == kPhasePre) SNAKE_LAUNCH(NWV, kPhasePre, RW);  \
+    else SNAKE_LAUNCH(NWV, kPhaseSolve, RW);
+#define SNAKE_LAYOUTS(NWV)                \
+    if (rows) { SNAKE_PHASES(NWV, 1) }     \
+    else { SNAKE_PHASES(NWV, 0) }
     switch (nw) {
-        case 1: SNAKE_PHASES(1) break;
-        case 2: SNAKE_PHASES(2) break;
-        case 4: SNAKE_PHASES(4) break;
-        case 8: SNAKE_PHASES(8) break;
-        case 16: SNAKE_PHASES(16) break;
+        case 1: SNAKE_LAYOUTS(1) break;
+        case 2: SNAKE_LAYOUTS(2) break;
+        case 4: SNAKE_LAYOUTS(4) break;
+        case 8: SNAKE_LAYOUTS(8) break;
+        case 16: SNAKE_LAYOUTS(16) break;
         default: return hipErrorInvalidValue;
     }
+#undef SNAKE_LAYOUTS
 #undef SNAKE_PHASES
 #undef SNAKE_LAUNCH
     return hipGetLastError();

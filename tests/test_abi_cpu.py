@@ -110,6 +110,7 @@ def test_workspace_bytes_valid_and_monotone(L):
     ("tau_inflate", 0.0, "tau"),
     ("controller", 7, "controller"),
     ("flags", 64, "flag"),
+    ("map_rows", 2, "map_rows"),
 ])
 def test_descriptor_validation(L, field, value, msg):
     wl = W.custom([2, 2], 8)

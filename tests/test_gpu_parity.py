@@ -337,7 +337,9 @@ def test_tolerance_mode_matches_oracle_iterations():
 
 MAPPINGS = [dict(map_waves=4, map_min_seg=16), dict(map_waves=4, map_min_seg=64),
             dict(map_waves=8, map_min_seg=32), dict(map_waves=16, map_min_seg=16),
-            dict(map_waves=4, map_min_seg=16, map_grid=64)]
+            dict(map_waves=4, map_min_seg=16, map_grid=64),
+            dict(map_waves=4, map_rows=1), dict(map_waves=16, map_rows=1),
+            dict(map_waves=8, map_rows=1, map_grid=64)]
 
 
 def test_all_mappings_bit_identical():
