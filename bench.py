@@ -32,13 +32,13 @@ METRIC = "snake-steps/s & constraint-iters/s at residual≤1e-4, plain vs NN war
 FLOP_ITER = 462
 FLOP_EVAL = 320
 FLOP_SUBSTEP = 100
-PEAK_FP32 = 157.3e12       # MI355X FP32 vector, packed; 78.6e12 without packed FP32
+PEAK_FP32 = 157.3e12       # MI355X FP32 vector (published)
 # HBM bytes per launch of the solver kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a device copy of known size (summaries in
-# profiles/), keyed by workload and waves per workgroup, with the digest of
+# profiles/), keyed by workload, waves per workgroup and layout, with the digest of
 # the kernel sources they were taken on; a changed kernel reports null.
-MEASURED_TRAFFIC = {("uniform", 4): 134.8e6, ("uneven", 4): 911.8e6}
-TRAFFIC_SOURCES_DIGEST = "d71e092676cd7c08:959545d7849e09a9:c9b7935adf4c92cd"
+MEASURED_TRAFFIC = {("uniform", 4, 1): 113.8e6, ("uneven", 4, 1): 696.3e6, ("stiff", 16, 1): 123.4e6}
+TRAFFIC_SOURCES_DIGEST = "4dac038d285dcd91:959545d7849e09a9:01ca15902ffdffb3"
 PEAK_HBM = 8.0e12
 STATE_BYTES = 4 * (13 + 13 + 9 + 9)   # per body: state in/out, multipliers in/out
 
@@ -183,7 +183,7 @@ def main():
     per_launch_ms = ms / args.steps
     achieved = flops / args.steps / (per_launch_ms / 1e3)
     hbm_bytes = float(B.sum()) * STATE_BYTES
-    traffic = MEASURED_TRAFFIC.get((args.workload, sim.mapping["waves"]))
+    traffic = MEASURED_TRAFFIC.get((args.workload, sim.mapping["waves"], sim.mapping["rows"]))
     if traffic is not None and kernel_digest() != TRAFFIC_SOURCES_DIGEST:
         traffic = None
     out = {
@@ -213,7 +213,7 @@ def main():
                                "max": float(np.max(r["residual"]))},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic,
-                     "kernel": f"k_tile<{sim.mapping['waves']}>", "mapping": sim.mapping,
+                     "kernel": f"k_tile<{sim.mapping['waves']}, 0, {sim.mapping['rows']}>", "mapping": sim.mapping,
                      "flop_per_body_iter": FLOP_ITER,
                      "hbm_frac_algorithmic": hbm_bytes / (per_launch_ms / 1e3) / PEAK_HBM},
     }

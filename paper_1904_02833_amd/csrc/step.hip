@@ -149,6 +149,25 @@ __device__ __forceinline__ V3 contact_incr(V3 lc, float cn, V3 d, float sc, floa
     return V3{ln - lc.x, t0 - lc.y, t1 - lc.z};
 }
 
+// Copy NW floats from 16-byte aligned LDS into registers with vector reads.
+template <int NW>
+__device__ __forceinline__ void lds_row(const float* src, float* dst)
+{
+    if constexpr (NW % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < NW / 4; ++k) {
+            const float4 t = reinterpret_cast<const float4*>(src)[k];
+            dst[4 * k] = t.x;
+            dst[4 * k + 1] = t.y;
+            dst[4 * k + 2] = t.z;
+            dst[4 * k + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NW; ++k) dst[k] = src[k];
+    }
+}
+
 // Tile kernel.  A workgroup of NW waves takes tiles from the cost-ordered
 // tile list (grid-stride, so a grid smaller than the list is persistent).
 // A tile holds snakes in lane segments made of whole 16-lane rows, in one of
@@ -170,8 +189,9 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
     // buffer 1 serves the warm start): a buffer is written again only after a
     // barrier that every reader of its previous contents has passed.
     __shared__ float xnext[3][NW][12];
+    __shared__ __align__(16) float xdone[3][NW];   // wave done flags, buffered as xnext
     __shared__ float xprev[NW][6];   // lane 63 of each wave: increments on the next body
-    __shared__ float xfirst[NW];     // residual maximum of the segment piece holding lane 0
+    __shared__ __align__(16) float xfirst[NW];     // residual maximum of the segment piece holding lane 0
     __shared__ float xlast[NW];      // ... and of the piece holding lane 63
     const int L = threadIdx.x;
     const int lane = L & 63;
@@ -216,12 +236,15 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                 e[0] = u.x; e[1] = u.y; e[2] = u.z;
                 e[3] = qq.w; e[4] = qq.x; e[5] = qq.y; e[6] = qq.z;
                 e[7] = a.x; e[8] = a.y; e[9] = a.z;
-                e[10] = wave_done ? 1.f : 0.f;
+                xdone[buf][wv] = wave_done ? 1.f : 0.f;
             }
             __syncthreads();
+            // all flags in vector reads, so the latencies overlap
+            float fl[NW];
+            lds_row<NW>(xdone[buf], fl);
             bool all = true;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) all = all && (xnext[buf][w][10] != 0.f);
+            for (int w = 0; w < NW; ++w) all &= fl[w] != 0.f;
             if (lane == 63 && wv + 1 < NW) {
                 const float* e = xnext[buf][wv + 1];
                 un = mk(e[0], e[1], e[2]);
@@ -251,21 +274,35 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
             float r = rw;
             if (wa != wb) {
                 // the segment's piece in wave wa holds that wave's lane 63, the
-                // pieces in the following waves hold their lane 0
+                // pieces in the following waves hold their lane 0 (all NW
+                // entries are read at once, so the reads overlap)
+                float fv[NW];
+                lds_row<NW>(xfirst, fv);
                 r = xlast[wa];
-                for (int w = wa + 1; w <= wb; ++w) r = fmaxf(r, xfirst[w]);
+#pragma unroll
+                for (int w = 1; w < NW; ++w)
+                    if (w > wa && w <= wb) r = fmaxf(r, fv[w]);
             }
             return r;
         };
         // Max over the segment's piece in this wave of non-negative values
         // (NaN already mapped to +inf): on their bit patterns the integer
-        // order is the float order.  Rows of 16 lanes reduce by xor swaps;
+        // order is the float order.  Rows of 16 lanes reduce by xor swaps
+        // (aligned layout: lane shuffles; rows layout: DPP quad swaps and
+        // half-row / row mirrors, which reach the same lanes within a row);
         // aligned power-of-two segments join rows by xor swaps too, packed
         // segments by a prefix and a suffix maximum over their rows.
         auto seg_reduce = [&](float v) -> float {
             int b = __float_as_int(v);
+            if (packed) {
+                b = max(b, __builtin_amdgcn_update_dpp(0, b, 0xB1, 0xf, 0xf, false));   // quad [1,0,3,2]
+                b = max(b, __builtin_amdgcn_update_dpp(0, b, 0x4E, 0xf, 0xf, false));   // quad [2,3,0,1]
+                b = max(b, __builtin_amdgcn_update_dpp(0, b, 0x141, 0xf, 0xf, false));  // half-row mirror
+                b = max(b, __builtin_amdgcn_update_dpp(0, b, 0x140, 0xf, 0xf, false));  // row mirror
+            } else {
 #pragma unroll
-            for (int o = 8; o >= 1; o >>= 1) b = max(b, __shfl_xor(b, o, 64));
+                for (int o = 8; o >= 1; o >>= 1) b = max(b, __shfl_xor(b, o, 64));
+            }
             if (!packed) {
 #pragma unroll
                 for (int o = 16; o <= 32; o <<= 1) {
