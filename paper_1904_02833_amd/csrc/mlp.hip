@@ -2,7 +2,7 @@
 // exact-erf GELU, evaluated and trained with BF16 MFMA (v_mfma_f32_16x16x32_bf16)
 // accumulating in FP32.
 //
-// One wave takes a chunk of 64 samples.  Weights, activations and
+// Training: one wave takes a chunk of 64 samples.  Weights, activations and
 // pre-activations of the chunk sit in LDS; every product is a small GEMM
 // computed tile by tile (16 x 16 output tiles, K in steps of 32).  Operands
 // are rounded to BF16 (round to nearest even) when they enter an MFMA; biases,
@@ -120,21 +120,98 @@ __device__ void chunk_forward(Lds& S, const float* __restrict__ p, const float* 
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(64) k_mlp_forward(const float* __restrict__ p, const float* __restrict__ ms,
-                                                    const float* __restrict__ x, float* __restrict__ y,
-                                                    int64_t n)
+// Inference: four waves per workgroup, each taking tiles of 16 samples in a
+// grid-stride loop.  The weights stay in registers as MFMA B operands for
+// the whole launch; a 16 x 64 BF16 buffer per wave in LDS turns each layer's
+// output (D layout: lane l holds rows 4 (l / 16) .. +4 of column l % 16) into
+// the next layer's A operand (row l % 16, columns 8 (l / 16) .. +8).  Same
+// arithmetic as the training pass: BF16 operands, FP32 accumulation, bias
+// and GELU.
+constexpr int FW_WAVES = 4, FW_ROW = NH + 8;   // padded row (144 bytes)
+
+__global__ void __launch_bounds__(64 * FW_WAVES) __attribute__((amdgpu_waves_per_eu(4))) k_mlp_forward(const float* __restrict__ p,
+                                                               const float* __restrict__ ms,
+                                                               const float* __restrict__ x,
+                                                               float* __restrict__ y, int64_t n)
 {
-    __shared__ Lds S;
-    __shared__ float Y[CH * NO];
-    load_weights(S, p);
-    const int64_t chunks = (n + CH - 1) / CH;
-    for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
-        chunk_forward(S, p, ms, x, c * CH, n, Y);
-        for (int e = threadIdx.x; e < CH * NO; e += 64) {
-            const int64_t row = c * CH + e / NO;
-            if (row < n) y[row * NO + e % NO] = Y[e];
+    __shared__ __align__(16) __bf16 Hs[FW_WAVES][16][FW_ROW];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, r = l & 15, g = l >> 4;
+    __bf16 (*H)[FW_ROW] = Hs[w];
+    bf16x8 B1[4], B2[4][2], B3[2];
+    float bb1[4], bb2[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int o = nt * 16 + r;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            B1[nt][j] = (__bf16)p[P_W1 + o * NI + 8 * g + j];
+            B2[nt][0][j] = (__bf16)p[P_W2 + o * NH + 8 * g + j];
+            B2[nt][1][j] = (__bf16)p[P_W2 + o * NH + 32 + 8 * g + j];
         }
-        __syncthreads();
+        bb1[nt] = p[P_B1 + o];
+        bb2[nt] = p[P_B2 + o];
+    }
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) B3[kt][j] = r < NO ? (__bf16)p[P_W3 + r * NH + kt * 32 + 8 * g + j] : (__bf16)0.f;
+    const float bb3 = r < NO ? p[P_B3 + r] : 0.f;
+    float mu[8], is[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        mu[j] = ms[8 * g + j];
+        is[j] = 1.f / ms[NI + 8 * g + j];
+    }
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    const int64_t tiles = (n + 15) / 16;
+    for (int64_t t = (int64_t)blockIdx.x * FW_WAVES + w; t < tiles; t += (int64_t)gridDim.x * FW_WAVES) {
+        const int64_t row = t * 16 + r;
+        bf16x8 a;
+        if (row < n) {
+            const float4* xp = reinterpret_cast<const float4*>(x + row * NI + 8 * g);
+            const float4 u0 = xp[0], u1 = xp[1];
+            const float xv[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] = (__bf16)((xv[j] - mu[j]) * is[j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] = (__bf16)0.f;
+        }
+        // layer 1: h1 = GELU(W1 x + b1)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B1[nt], zero, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) H[4 * g + v][nt * 16 + r] = (__bf16)gelu(acc[v] + bb1[nt]);
+        }
+        // (memcpy: the vector read may not be reordered with the element stores)
+        bf16x8 a2[2];
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) __builtin_memcpy(&a2[kt], &H[r][kt * 32 + 8 * g], sizeof(bf16x8));
+        // layer 2: h2 = GELU(W2 h1 + b2)
+        f32x4 acc2[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            acc2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[0], B2[nt][0], zero, 0, 0, 0);
+            acc2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[1], B2[nt][1], acc2[nt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) H[4 * g + v][nt * 16 + r] = (__bf16)gelu(acc2[nt][v] + bb2[nt]);
+        bf16x8 a3[2];
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) __builtin_memcpy(&a3[kt], &H[r][kt * 32 + 8 * g], sizeof(bf16x8));
+        // layer 3: y = W3 h2 + b3 (columns >= 3 are padding)
+        f32x4 acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[0], B3[0], zero, 0, 0, 0);
+        acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[1], B3[1], acc3, 0, 0, 0);
+        if (r < NO) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t rr = t * 16 + 4 * g + v;
+                if (rr < n) y[rr * NO + r] = acc3[v] + bb3;
+            }
+        }
     }
 }
 
@@ -308,9 +385,10 @@ int mlp_forward(const float* params, const float* mean_std, const float* x, floa
 {
     if (!params || !mean_std || !x || !y || n < 0) return mfail(SIM_EINVAL, "mlp_forward: bad arguments");
     if (n == 0) return SIM_OK;
-    const int64_t chunks = (n + CH - 1) / CH;
-    const int grid = (int)(chunks < 8192 ? chunks : 8192);
-    hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(64), 0, (hipStream_t)stream, params, mean_std, x, y, n);
+    const int64_t groups = ((n + 15) / 16 + FW_WAVES - 1) / FW_WAVES;
+    const int grid = (int)(groups < 2048 ? groups : 2048);
+    hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(64 * FW_WAVES), 0, (hipStream_t)stream, params, mean_std,
+                       x, y, n);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SIM_OK : mfail(SIM_EDEVICE, hipGetErrorString(e));
 }
