@@ -246,6 +246,19 @@ int sim_read_index(sim_t* s, int32_t which, int32_t* dst, int64_t count);
 /* Sizes: n_snakes, N, Jtot, Mtot, n_blocks (host int64 out[5]). */
 int sim_sizes(const sim_t* s, int64_t* out5);
 
+/* Tile plan of a descriptor for a mapping, on the host (no device, no
+ * state): snakes in work order (longest first, ties by index) packed into
+ * tiles of 64 * waves lanes, aligned power-of-two segments of at least
+ * min_seg lanes (rows = 0) or segments of the length rounded up to 16 lanes,
+ * best fit (rows = 1) -- the layout sim_create builds for that mapping.
+ * Outputs in caller host memory with room for n_snakes entries:
+ *   hdr[tile][4] = {first slot, slot count, some segment crosses a wave
+ *                   boundary, rows}
+ *   slots[slot][2] = {snake, lane offset << 16 | segment lanes}
+ * and *n_tiles.  SIM_EINVAL for a bad descriptor or mapping. */
+int sim_plan_tiles(const sim_desc_t* d, int32_t waves, int32_t min_seg, int32_t rows, int32_t* hdr,
+                   int32_t* slots, int64_t* n_tiles);
+
 /* Mapping in use: waves per workgroup, minimum segment, grid, tiles,
  * rows layout (host int32 out[5]). */
 int sim_mapping(const sim_t* s, int32_t* out5);

@@ -44,7 +44,7 @@ INDEX = ["body_off", "joint_off", "module_off", "block_off", "blk_type", "blk_a"
          "blk_color", "degree", "bucket", "order"]
 EXPORTS = ["sim_workspace_bytes", "sim_create", "sim_set_pressures", "sim_step",
            "sim_read_state", "sim_write_state", "sim_set_mlp", "sim_step_record", "sim_read_index",
-           "sim_sizes", "sim_mapping", "sim_destroy", "sim_last_error"]
+           "sim_sizes", "sim_mapping", "sim_plan_tiles", "sim_destroy", "sim_last_error"]
 
 _P = C.c_void_p
 
@@ -91,6 +91,8 @@ def lib():
         L.sim_read_index.argtypes = [_P, C.c_int32, _P, C.c_int64]
         L.sim_sizes.argtypes = [_P, C.POINTER(C.c_int64)]
         L.sim_mapping.argtypes = [_P, C.POINTER(C.c_int32)]
+        L.sim_plan_tiles.argtypes = [C.POINTER(Desc), C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.sim_set_mlp.argtypes = [_P, _P, _P, C.c_int]
         L.sim_step_record.argtypes = [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(C.c_int64)]
         L.sim_destroy.argtypes = [_P]
@@ -155,6 +157,22 @@ def make_desc(wl, **over):
     d.mlp_fallback = int(over.get("mlp_fallback", 1))
     d.map_rows = int(over.get("map_rows", 0))
     return d, keep
+
+
+def plan_tiles(wl, waves, min_seg=16, rows=0, **over):
+    """Host-side tile plan (no device): (hdr [tiles, 4], slots [n, 2]) int32,
+    as described with sim_plan_tiles in include/snake.h."""
+    L = lib()
+    d, keep = make_desc(wl, **over)
+    n = d.n_snakes
+    hdr = np.zeros((n, 4), np.int32)
+    slots = np.zeros((n, 2), np.int32)
+    nt = C.c_int64(0)
+    _check(L.sim_plan_tiles(C.byref(d), int(waves), int(min_seg), int(rows),
+                            hdr.ctypes.data_as(C.POINTER(C.c_int32)), slots.ctypes.data_as(C.POINTER(C.c_int32)),
+                            C.byref(nt)))
+    del keep
+    return hdr[:nt.value].copy(), slots
 
 
 def workspace_bytes(wl, **over) -> int:

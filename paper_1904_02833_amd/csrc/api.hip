@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -821,6 +822,47 @@ int sim_sizes(const sim_t* s, int64_t* out5)
     out5[2] = s->z.J;
     out5[3] = s->z.Mt;
     out5[4] = s->z.blocks;
+    return SIM_OK;
+}
+
+int sim_plan_tiles(const sim_desc_t* d, int32_t waves, int32_t min_seg, int32_t rows, int32_t* hdr,
+                   int32_t* slots, int64_t* n_tiles)
+{
+    if (!hdr || !slots || !n_tiles) return fail(SIM_EINVAL, "output is NULL");
+    Sizes z;
+    int rc = validate(d, &z);
+    if (rc) return rc;
+    if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
+        return fail(SIM_EINVAL, "waves must be 1, 2, 4, 8 or 16");
+    if (min_seg != 16 && min_seg != 32 && min_seg != 64) return fail(SIM_EINVAL, "min_seg must be 16, 32 or 64");
+    if (rows != 0 && rows != 1) return fail(SIM_EINVAL, "rows must be 0 or 1");
+    const int n = (int)z.n;
+    std::vector<int> Bn(n), order(n);
+    for (int k = 0; k < n; ++k) {
+        Bn[k] = d->n_modules[k] * d->segs_per_module[k];
+        order[k] = k;
+    }
+    if (pow2_at_least((int)z.max_B, 16) > 64 * waves) return fail(SIM_EINVAL, "waves too few for the longest snake");
+    // work order: longest first, ties by snake index
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return Bn[a] > Bn[b]; });
+    Mapping mp;
+    mp.nw = waves;
+    mp.min_seg = min_seg;
+    mp.rows = rows;
+    std::vector<int4> h;
+    std::vector<int2> sl;
+    build_tiles(order, Bn, mp, h, sl);
+    for (size_t t = 0; t < h.size(); ++t) {
+        hdr[4 * t] = h[t].x;
+        hdr[4 * t + 1] = h[t].y;
+        hdr[4 * t + 2] = h[t].z;
+        hdr[4 * t + 3] = h[t].w;
+    }
+    for (size_t k = 0; k < sl.size(); ++k) {
+        slots[2 * k] = sl[k].x;
+        slots[2 * k + 1] = sl[k].y;
+    }
+    *n_tiles = (int64_t)h.size();
     return SIM_OK;
 }
 
