@@ -2,7 +2,7 @@
 // exact-erf GELU, evaluated and trained with BF16 MFMA (v_mfma_f32_16x16x32_bf16)
 // accumulating in FP32.
 //
-// Training: one wave takes a chunk of 64 samples.  Weights, activations and
+// Training: one wave takes a chunk of 32 samples.  Weights, activations and
 // pre-activations of the chunk sit in LDS; every product is a small GEMM
 // computed tile by tile (16 x 16 output tiles, K in steps of 32).  Operands
 // are rounded to BF16 (round to nearest even) when they enter an MFMA; biases,
@@ -20,7 +20,8 @@ namespace {
 constexpr int NI = 32, NH = 64, NO = 3;
 constexpr int P_W1 = 0, P_B1 = P_W1 + NH * NI, P_W2 = P_B1 + NH, P_B2 = P_W2 + NH * NH;
 constexpr int P_W3 = P_B2 + NH, P_B3 = P_W3 + NO * NH, P_COUNT = P_B3 + NO;
-constexpr int CH = 64;  // samples per chunk (one wave)
+constexpr int CH = 32;  // samples per training chunk (one wave)
+constexpr int MT = CH / 16, KS = CH / 32;   // sample row tiles; sample K steps
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -79,12 +80,40 @@ struct Lds {
     float red[64];
 };
 
+// Weight matrices to LDS as BF16.  Each lane loads its float4 groups before
+// converting any, so the loads are in flight together.
+template <int ROWS, int COLS, int PROWS>
+__device__ __forceinline__ void load_matrix(__bf16 (*dst)[COLS], const float* __restrict__ src)
+{
+    constexpr int G = ROWS * COLS / 4;   // float4 groups of the stored rows
+    constexpr int PER = (G + 63) / 64;
+    const int l = threadIdx.x;
+    float4 v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int gi = l + 64 * k;
+        v[k] = (gi < G && 4 * gi < PROWS * COLS) ? reinterpret_cast<const float4*>(src)[gi]
+                                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int gi = l + 64 * k;
+        if (gi < G) {
+            const int e = 4 * gi;
+            __bf16* d = &dst[e / COLS][e % COLS];
+            d[0] = (__bf16)v[k].x;
+            d[1] = (__bf16)v[k].y;
+            d[2] = (__bf16)v[k].z;
+            d[3] = (__bf16)v[k].w;
+        }
+    }
+}
+
 __device__ void load_weights(Lds& S, const float* __restrict__ p)
 {
-    const int l = threadIdx.x;
-    for (int e = l; e < NH * NI; e += 64) S.W1[e / NI][e % NI] = (__bf16)p[P_W1 + e];
-    for (int e = l; e < NH * NH; e += 64) S.W2[e / NH][e % NH] = (__bf16)p[P_W2 + e];
-    for (int e = l; e < 16 * NH; e += 64) S.W3[e / NH][e % NH] = e < NO * NH ? (__bf16)p[P_W3 + e] : (__bf16)0.f;
+    load_matrix<NH, NI, NH>(S.W1, p + P_W1);
+    load_matrix<NH, NH, NH>(S.W2, p + P_W2);
+    load_matrix<16, NH, NO>(S.W3, p + P_W3);   // rows >= 3 are zero
 }
 
 // forward pass of one chunk; samples past n contribute zeros
@@ -99,21 +128,21 @@ __device__ void chunk_forward(Lds& S, const float* __restrict__ p, const float* 
         S.X[s][k] = (__bf16)v;
     }
     __syncthreads();
-    wave_gemm(4, 4, 1, [&](int i, int k) { return S.X[i][k]; }, [&](int k, int o) { return S.W1[o][k]; },
+    wave_gemm(MT, 4, 1, [&](int i, int k) { return S.X[i][k]; }, [&](int k, int o) { return S.W1[o][k]; },
               [&](int i, int o, float a) {
                   const float z = a + p[P_B1 + o];
                   S.Z1[i][o] = z;
                   S.H1[i][o] = (__bf16)gelu(z);
               });
     __syncthreads();
-    wave_gemm(4, 4, 2, [&](int i, int k) { return S.H1[i][k]; }, [&](int k, int o) { return S.W2[o][k]; },
+    wave_gemm(MT, 4, 2, [&](int i, int k) { return S.H1[i][k]; }, [&](int k, int o) { return S.W2[o][k]; },
               [&](int i, int o, float a) {
                   const float z = a + p[P_B2 + o];
                   S.Z2[i][o] = z;
                   S.H2[i][o] = (__bf16)gelu(z);
               });
     __syncthreads();
-    wave_gemm(4, 1, 2, [&](int i, int k) { return S.H2[i][k]; }, [&](int k, int o) { return S.W3[o][k]; },
+    wave_gemm(MT, 1, 2, [&](int i, int k) { return S.H2[i][k]; }, [&](int k, int o) { return S.W3[o][k]; },
               [&](int i, int o, float a) {
                   if (o < NO) y_out[i * NO + o] = a + p[P_B3 + o];
               });
@@ -257,12 +286,12 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ p, co
         g[P_B3 + l] = acc;
     }
     // dW3 = dY^T H2 (M = outputs padded to 16, K = samples)
-    wave_gemm(1, 4, 2, [&](int o, int s) { return S.dY[s][o]; }, [&](int s, int k) { return S.H2[s][k]; },
+    wave_gemm(1, 4, KS, [&](int o, int s) { return S.dY[s][o]; }, [&](int s, int k) { return S.H2[s][k]; },
               [&](int o, int k, float a) {
                   if (o < NO) g[P_W3 + o * NH + k] = a;
               });
     // dH2 = dY W3 (K = outputs padded to 32); dz2 = dH2 * GELU'(z2)
-    wave_gemm(4, 4, 1, [&](int s, int o) { return o < 16 ? S.dY[s][o] : (__bf16)0.f; },
+    wave_gemm(MT, 4, 1, [&](int s, int o) { return o < 16 ? S.dY[s][o] : (__bf16)0.f; },
               [&](int o, int k) { return o < 16 ? S.W3[o][k] : (__bf16)0.f; },
               [&](int s, int k, float a) {
                   const float dz = a * gelu_grad(S.Z2[s][k]);
@@ -276,9 +305,9 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ p, co
         g[P_B2 + l] = acc;
     }
     // dW2 = dZ2^T H1 ; dH1 = dZ2 W2
-    wave_gemm(4, 4, 2, [&](int o, int s) { return S.dZ[s][o]; }, [&](int s, int k) { return S.H1[s][k]; },
+    wave_gemm(4, 4, KS, [&](int o, int s) { return S.dZ[s][o]; }, [&](int s, int k) { return S.H1[s][k]; },
               [&](int o, int k, float a) { g[P_W2 + o * NH + k] = a; });
-    wave_gemm(4, 4, 2, [&](int s, int o) { return S.dZ[s][o]; }, [&](int o, int k) { return S.W2[o][k]; },
+    wave_gemm(MT, 4, 2, [&](int s, int o) { return S.dZ[s][o]; }, [&](int o, int k) { return S.W2[o][k]; },
               [&](int s, int k, float a) { S.Z1[s][k] = a * gelu_grad(S.Z1[s][k]); });
     __syncthreads();
     for (int e = l; e < CH * NH; e += 64) S.dZ[e / NH][e % NH] = (__bf16)S.Z1[e / NH][e % NH];
@@ -289,25 +318,34 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ p, co
     }
     __syncthreads();
     // dW1 = dZ1^T X
-    wave_gemm(4, 2, 2, [&](int o, int s) { return S.dZ[s][o]; }, [&](int s, int k) { return S.X[s][k]; },
+    wave_gemm(4, 2, KS, [&](int o, int s) { return S.dZ[s][o]; }, [&](int s, int k) { return S.X[s][k]; },
               [&](int o, int k, float a) { g[P_W1 + o * NI + k] = a; });
 }
 
-// grad[k] = sum over chunks in chunk order; loss likewise
+// grad[k] = sum over chunks, loss likewise, in a fixed order: eight partial
+// sums over chunks c = j mod 8 (loads in flight together), then combined
+// pairwise.  The same inputs give the same bits on every call.
+__device__ __forceinline__ float ordered_sum(const float* __restrict__ a, int64_t stride, int64_t count)
+{
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int64_t c = 0;
+    for (; c + 8 <= count; c += 8) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = a[(c + j) * stride];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] += v[j];
+    }
+    for (int j = 0; c < count; ++c, ++j) acc[j] += a[c * stride];
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
 __global__ void k_mlp_reduce(const float* __restrict__ gpart, const float* __restrict__ lpart, int64_t chunks,
                              int64_t n, float* __restrict__ grad, float* __restrict__ loss)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < P_COUNT) {
-        float acc = 0.f;
-        for (int64_t c = 0; c < chunks; ++c) acc += gpart[c * P_COUNT + k];
-        grad[k] = acc;
-    }
-    if (k == 0) {
-        float acc = 0.f;
-        for (int64_t c = 0; c < chunks; ++c) acc += lpart[c];
-        *loss = acc / (float)(n * NO);
-    }
+    if (k < P_COUNT) grad[k] = ordered_sum(gpart + k, P_COUNT, chunks);
+    if (k == 0) *loss = ordered_sum(lpart, 1, chunks) / (float)(n * NO);
 }
 
 // Adam with bias correction (Kingma and Ba), step t counts from 1
