@@ -40,6 +40,9 @@ PEAK_FP32 = 157.3e12       # MI355X FP32 vector (published)
 MEASURED_TRAFFIC = {("uniform", 4, 1): 113.8e6, ("uneven", 4, 1): 696.3e6, ("stiff", 16, 1): 123.4e6}
 TRAFFIC_SOURCES_DIGEST = "4dac038d285dcd91:959545d7849e09a9:01ca15902ffdffb3"
 PEAK_HBM = 8.0e12
+# learned start kept only where its residual after this many iterations is not
+# larger than the zero start's (both probes' iterations count in the totals)
+FALLBACK_K = 2
 STATE_BYTES = 4 * (13 + 13 + 9 + 9)   # per body: state in/out, multipliers in/out
 
 
@@ -88,11 +91,13 @@ def learned_comparison(n_steps):
     t_train = time.perf_counter() - t0
     ev = W.make("learned")
     ev.tol, ev.iters = 1e-4, 200
-    out = {"train": {"rows": int(ds.features.shape[0]), "seconds": t_train, "loss_by_epoch": losses,
+    out = {"fallback_k": FALLBACK_K,
+           "train": {"rows": int(ds.features.shape[0]), "seconds": t_train, "loss_by_epoch": losses,
                      "teacher": "tolerance 1e-6 (at most 1500 iterations), first substep of states "
                                 "visited by the plain solver"}}
     for name in ("plain", "learned"):
-        sim = snk.Sim(ev, autotune=1) if name == "plain" else warmstart.learned_sim(ev, net, autotune=1)
+        sim = (snk.Sim(ev, autotune=1) if name == "plain"
+               else warmstart.learned_sim(ev, net, autotune=1, mlp_fallback_k=FALLBACK_K))
         sim.step(5)
         torch.cuda.synchronize()
         r0 = sim.read("iters_total")["iters_total"].copy()

@@ -81,7 +81,8 @@ extern "C" {
 #define SIM_WARM_MLP 2  /* joint lambda predicted by the network set with     */
                         /* sim_set_mlp (contacts start at 0), bodies moved by */
                         /* W J^T lambda; with mlp_fallback the zero start is  */
-                        /* used wherever it begins with a smaller residual    */
+                        /* used wherever it has the smaller residual after    */
+                        /* mlp_fallback_k iterations (0: at the start)        */
 
 /* ---- flags ---- */
 #define SIM_FLAG_FIXED_ROOT 1u /* body 0 of every snake is immovable         */
@@ -173,9 +174,16 @@ typedef struct sim_desc {
     int32_t map_min_seg;
     int32_t map_grid;
     int32_t mlp_fallback;      /* 1: per snake and substep, keep the learned */
-                               /* start only if its initial residual is not  */
-                               /* larger than the zero start's               */
+                               /* start only if its residual is not larger   */
+                               /* than the zero start's ...                  */
     int32_t map_rows;          /* 0 or 1, see the mapping above             */
+    int32_t mlp_fallback_k;    /* ... after this many iterations from each   */
+                               /* start (0: the starts themselves; at most   */
+                               /* iters).  For k > 0 the zero start runs k   */
+                               /* iterations, then the learned start k; the  */
+                               /* solve continues from the learned iterate k */
+                               /* or runs again from zero, and the probes'   */
+                               /* iterations count in SIM_F_ITERS.           */
 } sim_desc_t;
 
 typedef struct sim sim_t;

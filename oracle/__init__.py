@@ -80,7 +80,7 @@ class Batch(C.Structure):
         ("amp_psi", C.c_double),
         ("flags", C.c_int32), ("controller", C.c_int32), ("warm", C.c_int32),
         ("ctrl_alpha", C.c_double), ("ctrl_offset", C.c_double),
-        ("fallback", C.c_int32),
+        ("fallback", C.c_int32), ("fallback_k", C.c_int32),
     ]
 
 
@@ -161,6 +161,7 @@ class Oracle:
         b.controller = int(g("controller"))
         b.warm = int(over.get("warm", WARM_ZERO))
         b.fallback = int(over.get("fallback", 0))
+        b.fallback_k = int(over.get("fallback_k", 0))
         self.batch = b
         self.n = n
         self.B = (np.asarray(g("n_modules"), np.int64) * np.asarray(g("segs_per_module"), np.int64))

@@ -461,6 +461,10 @@ typedef struct {
     double* theta0;     /* [B] */
     double* lz_j;       /* zero multipliers for the fallback's comparison */
     double* lz_c;
+    double* xs;         /* [B*3] predicted state kept for the fallback's probes */
+    double* qs;         /* [B*4] */
+    double* l0_j;       /* lambda0 kept for the fallback's probes */
+    double* l0_c;
 } scratch_t;
 
 static void scratch_alloc(scratch_t* w, const snake_ctx* c)
@@ -479,6 +483,10 @@ static void scratch_alloc(scratch_t* w, const snake_ctx* c)
     w->theta0 = (double*)calloc((size_t)B, sizeof(double));
     w->lz_j = (double*)calloc((size_t)B * 6, sizeof(double));
     w->lz_c = (double*)calloc((size_t)B * 3, sizeof(double));
+    w->xs = (double*)calloc((size_t)B * 3, sizeof(double));
+    w->qs = (double*)calloc((size_t)B * 4, sizeof(double));
+    w->l0_j = (double*)calloc((size_t)B * 6, sizeof(double));
+    w->l0_c = (double*)calloc((size_t)B * 3, sizeof(double));
 }
 
 static void scratch_free(scratch_t* w)
@@ -495,6 +503,10 @@ static void scratch_free(scratch_t* w)
     free(w->theta0);
     free(w->lz_j);
     free(w->lz_c);
+    free(w->xs);
+    free(w->qs);
+    free(w->l0_j);
+    free(w->l0_c);
 }
 
 /* Predicted positions of a first-order implicit step: gravity on the linear
@@ -593,55 +605,35 @@ static double residual_at(const orc_batch* b, const snake_ctx* c, scratch_t* W, 
     return local_solves(c, W, lam_j, lam_c);
 }
 
-/* Block-Jacobi solve of one substep.  Returns the number of applied
- * iterations; *res is the residual of the final iterate. */
-static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* x, double* q,
-                         double* lam_j, double* lam_c, int warm, int kmax, double tol, double* res,
-                         int* status)
+/* x <- x + W J(x)^T lambda: the bodies take the displacement of the
+ * multipliers currently in lam_j / lam_c (the warm start). */
+static void apply_start(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* x, double* q,
+                        double* lam_j, double* lam_c)
+{
+    int nb = n_blocks(c);
+    eval_blocks(b, c, x, q, W->xp, W->theta0, W->blk);
+    for (int k = 0; k < nb; ++k) {
+        double* l = block_lambda(c, lam_j, lam_c, &W->blk[k], k);
+        for (int d = 0; d < 3; ++d) W->dl[3 * k + d] = l[d];
+    }
+    for (int i = 0; i < c->B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
+    for (int i = 0; i < c->B; ++i) {
+        double dx[3], dth[3];
+        gather_body(c, i, W->blk, W->dl, inv_mass(c, i), W->Iinv + 9 * i, dx, dth);
+        for (int d = 0; d < 3; ++d) x[3 * i + d] += dx[d];
+        if (!is_fixed(c, i)) q_apply_rotvec(q + 4 * i, dth);
+    }
+}
+
+/* Block-Jacobi iterations from iterate k0 of the current (x, q, lambda):
+ * evaluate, stop at the first iterate k with residual <= tol or k >= kmax
+ * (probe: exactly at k = kmax, no convergence status), else apply.
+ * Returns the index of the final iterate; *res is its residual. */
+static int jacobi(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* x, double* q, double* lam_j,
+                  double* lam_c, int k0, int kmax, double tol, int probe, double* res, int* status)
 {
     int nb = n_blocks(c);
     int B = c->B;
-
-    /* warm start: x <- x~ + W J(x~)^T lambda0 with lambda0 = current lambda.
-     * With the fallback, a given lambda0 is kept only if the residual it
-     * starts from is not larger than the residual of the zero start. */
-    int fallback = (warm == ORC_WARM_GIVEN && b->fallback);
-    double r_zero = 0.0;
-    if (fallback) {
-        memcpy(W->xt, x, sizeof(double) * 3 * (size_t)B);
-        memcpy(W->qt, q, sizeof(double) * 4 * (size_t)B);
-        memset(W->lz_j, 0, sizeof(double) * 6 * (size_t)(c->nj > 0 ? c->nj : 1));
-        memset(W->lz_c, 0, sizeof(double) * 3 * (size_t)B);
-        r_zero = residual_at(b, c, W, x, q, W->lz_j, W->lz_c);
-    }
-    if (warm != ORC_WARM_ZERO) {
-        eval_blocks(b, c, x, q, W->xp, W->theta0, W->blk);
-        for (int k = 0; k < nb; ++k) {
-            double* l = block_lambda(c, lam_j, lam_c, &W->blk[k], k);
-            for (int d = 0; d < 3; ++d) W->dl[3 * k + d] = l[d];
-        }
-        for (int i = 0; i < B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
-        for (int i = 0; i < B; ++i) {
-            double dx[3], dth[3];
-            gather_body(c, i, W->blk, W->dl, inv_mass(c, i), W->Iinv + 9 * i, dx, dth);
-            for (int d = 0; d < 3; ++d) x[3 * i + d] += dx[d];
-            if (!is_fixed(c, i)) q_apply_rotvec(q + 4 * i, dth);
-        }
-        if (fallback) {
-            double r_nn = residual_at(b, c, W, x, q, lam_j, lam_c);
-            if (!(r_nn <= r_zero)) {
-                memcpy(x, W->xt, sizeof(double) * 3 * (size_t)B);
-                memcpy(q, W->qt, sizeof(double) * 4 * (size_t)B);
-                memset(lam_j, 0, sizeof(double) * 6 * (size_t)c->nj);
-                memset(lam_c, 0, sizeof(double) * 3 * (size_t)B);
-                *status |= ORC_STATUS_FELL_BACK;
-            }
-        }
-    } else {
-        memset(lam_j, 0, sizeof(double) * 6 * (size_t)c->nj);
-        memset(lam_c, 0, sizeof(double) * 3 * (size_t)B);
-    }
-
     if (c->linear) {
         memcpy(W->xt, x, sizeof(double) * 3 * (size_t)B);
         memcpy(W->qt, q, sizeof(double) * 4 * (size_t)B);
@@ -650,7 +642,7 @@ static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, d
         for (int i = 0; i < B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
     }
 
-    int k = 0;
+    int k = k0;
     double r = 0.0;
     for (;; ++k) {
         /* evaluate every block at the current iterate */
@@ -679,9 +671,9 @@ static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, d
             *status |= ORC_STATUS_NONFINITE;
             break;
         }
-        int stop = (tol > 0.0) ? (r <= tol || k >= kmax) : (k >= kmax);
+        int stop = probe ? (k >= kmax) : (tol > 0.0) ? (r <= tol || k >= kmax) : (k >= kmax);
         if (stop) {
-            if (tol > 0.0 && r > tol) *status |= ORC_STATUS_NOT_CONVERGED;
+            if (!probe && tol > 0.0 && r > tol) *status |= ORC_STATUS_NOT_CONVERGED;
             break;
         }
 
@@ -714,6 +706,87 @@ static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, d
     }
     *res = r;
     return k;
+}
+
+/* Block-Jacobi solve of one substep from the predicted (x, q).  Returns the
+ * number of iterations run; *res is the residual of the final iterate.
+ *
+ * Multiplier initialisation: zero, or lambda0 = the current lambda with
+ * x <- x~ + W J(x~)^T lambda0.  With the fallback, a given lambda0 is kept
+ * only if, after fallback_k iterations, its residual is not larger than the
+ * zero start's after as many; fallback_k = 0 compares the starts themselves.
+ * For fallback_k > 0 the zero start runs first (fallback_k iterations), then
+ * the given start (fallback_k iterations): if the given start wins the solve
+ * continues from its iterate fallback_k, else it runs again from the zero
+ * start; the iterations of the probes count in the total. */
+static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* x, double* q,
+                         double* lam_j, double* lam_c, int warm, int kmax, double tol, double* res,
+                         int* status)
+{
+    int B = c->B;
+    size_t nj6 = sizeof(double) * 6 * (size_t)(c->nj > 0 ? c->nj : 1);
+    size_t nc3 = sizeof(double) * 3 * (size_t)B;
+    int fallback = (warm == ORC_WARM_GIVEN && b->fallback);
+
+    if (fallback && b->fallback_k > 0) {
+        int K = b->fallback_k;
+        double rz = 0.0, rw = 0.0;
+        int st = 0;
+        memcpy(W->xs, x, sizeof(double) * 3 * (size_t)B);
+        memcpy(W->qs, q, sizeof(double) * 4 * (size_t)B);
+        memcpy(W->l0_j, lam_j, nj6);
+        memcpy(W->l0_c, lam_c, nc3);
+        /* probe: zero start */
+        memset(lam_j, 0, nj6);
+        memset(lam_c, 0, nc3);
+        jacobi(b, c, W, x, q, lam_j, lam_c, 0, K, 0.0, 1, &rz, &st);
+        /* probe: given start */
+        memcpy(x, W->xs, sizeof(double) * 3 * (size_t)B);
+        memcpy(q, W->qs, sizeof(double) * 4 * (size_t)B);
+        memcpy(lam_j, W->l0_j, nj6);
+        memcpy(lam_c, W->l0_c, nc3);
+        apply_start(b, c, W, x, q, lam_j, lam_c);
+        st = 0;
+        jacobi(b, c, W, x, q, lam_j, lam_c, 0, K, 0.0, 1, &rw, &st);
+        /* keep the given start if it is finite and not farther than zero */
+        if (isfinite(rw) && (!isfinite(rz) || rw <= rz)) {
+            /* continue from the given start's iterate K; the zero probe's
+             * K iterations count on top */
+            return jacobi(b, c, W, x, q, lam_j, lam_c, K, kmax, tol, 0, res, status) + K;
+        }
+        memcpy(x, W->xs, sizeof(double) * 3 * (size_t)B);
+        memcpy(q, W->qs, sizeof(double) * 4 * (size_t)B);
+        memset(lam_j, 0, nj6);
+        memset(lam_c, 0, nc3);
+        *status |= ORC_STATUS_FELL_BACK;
+        return jacobi(b, c, W, x, q, lam_j, lam_c, 0, kmax, tol, 0, res, status) + 2 * K;
+    }
+
+    double r_zero = 0.0;
+    if (fallback) {
+        memcpy(W->xs, x, sizeof(double) * 3 * (size_t)B);
+        memcpy(W->qs, q, sizeof(double) * 4 * (size_t)B);
+        memset(W->lz_j, 0, nj6);
+        memset(W->lz_c, 0, nc3);
+        r_zero = residual_at(b, c, W, x, q, W->lz_j, W->lz_c);
+    }
+    if (warm != ORC_WARM_ZERO) {
+        apply_start(b, c, W, x, q, lam_j, lam_c);
+        if (fallback) {
+            double r_nn = residual_at(b, c, W, x, q, lam_j, lam_c);
+            if (!(r_nn <= r_zero)) {
+                memcpy(x, W->xs, sizeof(double) * 3 * (size_t)B);
+                memcpy(q, W->qs, sizeof(double) * 4 * (size_t)B);
+                memset(lam_j, 0, sizeof(double) * 6 * (size_t)c->nj);
+                memset(lam_c, 0, nc3);
+                *status |= ORC_STATUS_FELL_BACK;
+            }
+        }
+    } else {
+        memset(lam_j, 0, sizeof(double) * 6 * (size_t)c->nj);
+        memset(lam_c, 0, nc3);
+    }
+    return jacobi(b, c, W, x, q, lam_j, lam_c, 0, kmax, tol, 0, res, status);
 }
 
 /* velocities of the implicit step from the substep displacement */

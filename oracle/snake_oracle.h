@@ -74,7 +74,8 @@ typedef struct {
     double k_i, k_d, T_p, p_s, amp_psi;
     int32_t flags, controller, warm;
     double ctrl_alpha, ctrl_offset;
-    int32_t fallback;   /* GIVEN warm start: keep lambda0 only if it starts closer */
+    int32_t fallback;   /* GIVEN warm start: keep lambda0 only if it is closer */
+    int32_t fallback_k; /* ... after this many iterations (0: at the start) */
 } orc_batch;
 
 /* Batch state, owned by the caller.  Offsets: body_off / module_off /

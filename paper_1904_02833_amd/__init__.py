@@ -69,6 +69,7 @@ class Desc(C.Structure):
         ("warm_start", C.c_int32), ("flags", C.c_uint32), ("use_graph", C.c_int32),
         ("autotune", C.c_int32), ("map_waves", C.c_int32), ("map_min_seg", C.c_int32),
         ("map_grid", C.c_int32), ("mlp_fallback", C.c_int32), ("map_rows", C.c_int32),
+        ("mlp_fallback_k", C.c_int32),
     ]
 
 
@@ -156,6 +157,7 @@ def make_desc(wl, **over):
     d.map_grid = int(over.get("map_grid", 0))
     d.mlp_fallback = int(over.get("mlp_fallback", 1))
     d.map_rows = int(over.get("map_rows", 0))
+    d.mlp_fallback_k = int(over.get("mlp_fallback_k", 0))
     return d, keep
 
 

@@ -108,6 +108,8 @@ int validate(const sim_desc_t* d, Sizes* z)
         return fail(SIM_EINVAL, "map_min_seg must be 0, 16, 32 or 64");
     if (d->map_grid < 0) return fail(SIM_EINVAL, "map_grid must be >= 0");
     if (d->map_rows != 0 && d->map_rows != 1) return fail(SIM_EINVAL, "map_rows must be 0 or 1");
+    if (d->mlp_fallback_k < 0 || d->mlp_fallback_k > d->iters)
+        return fail(SIM_EINVAL, "mlp_fallback_k must be in [0, iters]");
     if (mw != 0 && !d->autotune) {
         int seg = 16;
         while (seg < z->max_B) seg <<= 1;
@@ -546,6 +548,7 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     k.module_off = w.ip.module_off;
     k.mlp_y = w.mlp_y;
     k.fallback = d->mlp_fallback ? 1 : 0;
+    k.fallback_k = d->mlp_fallback_k;
     k.comp = w.comp;
     k.mu = w.mu;
     k.freq = w.freq;

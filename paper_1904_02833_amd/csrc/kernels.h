@@ -62,7 +62,7 @@ struct KParams {
     float k_i, k_d, T_p, p_s, amp, kappa_max;
     int controller;
     double dt, ctrl_alpha, ctrl_offset;
-    int flags, warm, fallback;
+    int flags, warm, fallback, fallback_k;
     float lam_ref;          // multiplier scale m 9.81 h^2 of the network units
 };
 

@@ -497,25 +497,8 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
 
                 // multiplier initialisation
                 const bool learned = PHASE == kPhaseSolve && P.warm == kWarmMlp;
-                if (P.warm == kWarmPrev || learned) {
-                    if (learned) {
-                        // network outputs: stretch in the predicted frame of body i,
-                        // bend-twist in the joint frame, both in units of lam_ref
-                        ls = zero;
-                        lb = zero;
-                        if (hasj) {
-                            const float* y = P.mlp_y + 6 * (size_t)gj;
-                            ls = P.lam_ref * qrot(q, mk(y[0], y[1], y[2]));
-                            lb = (P.lam_ref * P.L) * mk(y[3], y[4], y[5]);
-                        }
-                        lc = zero;
-                    }
-                    const V3 d_zero = d;
-                    const Q4 q_zero = q;
-                    float r_zero = 0.f;
-                    if (learned && P.fallback)
-                        r_zero = eval_residual(0, dxp, zp, d, q, zero, zero, zero, c0h, s0h, ct, stt);
-                    // x <- x~ + W J(x~)^T lambda0
+                // x <- x~ + W J(x~)^T lambda0 for the multipliers in ls, lb, lc
+                auto apply_start = [&]() {
                     const V3 aA = qaxis(q);
                     V3 dn, an;
                     Q4 qn;
@@ -537,16 +520,48 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                         d = d + (wA * fsum + dxc);
                         q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
                     }
-                    if (learned && P.fallback) {
-                        // keep the learned start only if it begins closer than zero
-                        const float r_nn = eval_residual(0, dxp, zp, d, q, ls, lb, lc, c0h, s0h, ct, stt);
-                        if (live && !(r_nn <= r_zero)) {
-                            d = d_zero;
-                            q = q_zero;
-                            ls = zero;
-                            lb = zero;
-                            lc = zero;
-                            status |= kStatusFellBack;
+                };
+                // fallback after K iterations: probe the zero start, then the
+                // learned start, K iterations each
+                const bool probe = learned && P.fallback && P.fallback_k > 0;
+                int koff = 0, extra = 0;
+                V3 ls0 = zero, lb0 = zero;
+                const V3 d_zero = d;
+                const Q4 q_zero = q;
+                if (P.warm == kWarmPrev || learned) {
+                    if (learned) {
+                        // network outputs: stretch in the predicted frame of body i,
+                        // bend-twist in the joint frame, both in units of lam_ref
+                        ls = zero;
+                        lb = zero;
+                        if (hasj) {
+                            const float* y = P.mlp_y + 6 * (size_t)gj;
+                            ls = P.lam_ref * qrot(q, mk(y[0], y[1], y[2]));
+                            lb = (P.lam_ref * P.L) * mk(y[3], y[4], y[5]);
+                        }
+                        lc = zero;
+                    }
+                    if (probe) {
+                        ls0 = ls;
+                        lb0 = lb;
+                        ls = zero;
+                        lb = zero;
+                    } else {
+                        float r_zero = 0.f;
+                        if (learned && P.fallback)
+                            r_zero = eval_residual(0, dxp, zp, d, q, zero, zero, zero, c0h, s0h, ct, stt);
+                        apply_start();
+                        if (learned && P.fallback) {
+                            // keep the learned start only if it begins closer than zero
+                            const float r_nn = eval_residual(0, dxp, zp, d, q, ls, lb, lc, c0h, s0h, ct, stt);
+                            if (live && !(r_nn <= r_zero)) {
+                                d = d_zero;
+                                q = q_zero;
+                                ls = zero;
+                                lb = zero;
+                                lc = zero;
+                                status |= kStatusFellBack;
+                            }
                         }
                     }
                 } else {
@@ -555,9 +570,15 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                     lc = zero;
                 }
 
+                // Jacobi iterations from iterate koff of the current state.  A probe
+                // (kprobe >= 0) runs exactly kprobe iterations, records no status
+                // and returns the residual of iterate kprobe; the solve stops at
+                // the tolerance or the iteration cap.  kdone receives the index
+                // of the final iterate, rdone its residual.
+                auto run_loop = [&](int koff_, int kprobe, int& kdone, float& rdone) {
                 bool done = !live;
-                int kdone = 0;
-                float rdone = 0.f;
+                kdone = 0;
+                rdone = 0.f;
                 for (int k = 0;; ++k) {
                     const V3 aA = qaxis(q);
                     V3 dn, an;
@@ -583,16 +604,23 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                     const float r = fetch_prev(sel(hasj, -dls, zero), sel(hasj, tB, zero), rl, inf, intq);
 
                     if (!done) {
+                        const int kl = k + koff_;
                         const bool bad = !(r < INFINITY);
-                        const bool stop = bad || (P.tol > 0.f ? (r <= P.tol || k >= P.iters) : (k >= P.iters));
+                        bool stop;
+                        if (kprobe >= 0)
+                            stop = bad || k >= kprobe;
+                        else
+                            stop = bad || (P.tol > 0.f ? (r <= P.tol || kl >= P.iters) : (kl >= P.iters));
                         if (stop) {
                             done = true;
-                            kdone = k;
-                            rdone = r;
-                            if (bad)
-                                status |= kStatusNonfinite;
-                            else if (P.tol > 0.f && r > P.tol)
-                                status |= kStatusNotConverged;
+                            kdone = kl;
+                            rdone = bad ? INFINITY : r;
+                            if (kprobe < 0) {
+                                if (bad)
+                                    status |= kStatusNonfinite;
+                                else if (P.tol > 0.f && r > P.tol)
+                                    status |= kStatusNotConverged;
+                            }
                         }
                     }
                     if (!done) {
@@ -615,6 +643,38 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                         }
                     }
                 }
+                };
+                if (probe) {
+                    int kz, kw;
+                    float rz, rw;
+                    run_loop(0, P.fallback_k, kz, rz);              // zero start
+                    d = d_zero;
+                    q = q_zero;
+                    ls = ls0;
+                    lb = lb0;
+                    lc = zero;
+                    if (xw) __syncthreads();   // every wave has read the last exchange
+                    apply_start();
+                    run_loop(0, P.fallback_k, kw, rw);              // learned start
+                    // keep the learned start if it is finite and not farther than zero
+                    if (rw < INFINITY && (rz >= INFINITY || rw <= rz)) {
+                        koff = P.fallback_k;
+                        extra = P.fallback_k;
+                    } else {
+                        d = d_zero;
+                        q = q_zero;
+                        ls = zero;
+                        lb = zero;
+                        lc = zero;
+                        if (live) status |= kStatusFellBack;
+                        extra = 2 * P.fallback_k;
+                    }
+                    if (xw) __syncthreads();
+                }
+                int kdone;
+                float rdone;
+                run_loop(koff, -1, kdone, rdone);
+                if (live) kdone += extra;
                 itstep += kdone;
                 rstep = fmaxf(rstep, rdone);
 

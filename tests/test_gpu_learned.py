@@ -80,26 +80,27 @@ def constant_net(c):
     return snk.Net(p, ms)
 
 
-@pytest.mark.parametrize("fallback", [0, 1])
-def test_warm_start_from_network_outputs_matches_oracle(fallback):
+@pytest.mark.parametrize("fallback,fallback_k", [(0, 0), (1, 0), (1, 3)])
+def test_warm_start_from_network_outputs_matches_oracle(fallback, fallback_k):
     """A network that outputs the constant c gives lambda0 = m g h^2 R(qA) c
     (stretch) and m g h^2 L c (bend-twist); the GPU's warm-started substep
-    must match the oracle started from those multipliers."""
+    must match the oracle started from those multipliers, with the fallback
+    judged at the start or after fallback_k iterations from each start."""
     c = np.array([0.6, -0.4, 0.3], np.float32)
     wl = W.make("uneven", n_snakes=40)
     st = one_substep_state(wl, 12)
     h = wl.dt / wl.substeps
     kw = dict(controller=W.CTRL_EXTERNAL, dt=h, substeps=1)
     net = constant_net(c)
-    sim = snk.Sim(wl, warm_start=snk.WARM_MLP, mlp_fallback=fallback, **kw)
+    sim = snk.Sim(wl, warm_start=snk.WARM_MLP, mlp_fallback=fallback, mlp_fallback_k=fallback_k, **kw)
     sim.set_mlp(net.params, net.mean_std)
     load_gpu(sim, st)
     sim.step(1)
     g = gpu_state(sim)
-    o = oracle.Oracle(wl, warm=oracle.WARM_GIVEN, fallback=fallback, **kw)
+    o = oracle.Oracle(wl, warm=oracle.WARM_GIVEN, fallback=fallback, fallback_k=fallback_k, **kw)
     load_oracle(o, st)
     ref = 0.02 * 9.81 * h * h
-    statuses = []
+    statuses, iters = [], []
     for s in range(o.n):
         qp = o.pre_substep(s, 0)
         d = o.snake(s)
@@ -112,13 +113,17 @@ def test_warm_start_from_network_outputs_matches_oracle(fallback):
             d["lam_j"][j, :3] = ref * (R @ c.astype(np.float64))
             d["lam_j"][j, 3:] = ref * 0.01 * c.astype(np.float64)
         d["lam_c"][...] = 0.0
-        statuses.append(o.solve_substep(s, qp)[2])
+        res = o.solve_substep(s, qp)
+        statuses.append(res[2])
+        iters.append(res[1])
     statuses = np.array(statuses)
     fell_o = (statuses & 4) != 0
     fell_g = (g["status"] & snk.STATUS_FELL_BACK) != 0
     print(f"\n[warm mlp fallback={fallback}] fell back: oracle {fell_o.sum()} gpu {fell_g.sum()} of {o.n}")
     same = fell_o == fell_g
     assert same.mean() >= 0.9
+    # iterations include the probes: K on top when kept, 2K when fallen back
+    assert np.array_equal(np.asarray(g["iters"])[same], np.array(iters)[same])
     err = compare(o, g, wl.mu)
     keep = np.nonzero(same)[0]
     assert err["pos"][keep].max() <= POS_TOL

@@ -734,3 +734,48 @@ def test_features_closed_form_and_yaw_invariance():
     f2 = o2.features(0, o2.pre_substep(0, 0))
     f3 = o3.features(0, o3.pre_substep(0, 0))
     assert np.abs(f2 - f3).max() < 1e-10
+
+
+def test_fallback_after_k_iterations_follows_the_probes():
+    """With fallback_k = K the start is chosen by the residuals after K
+    iterations from each start (computed here by separate runs), and the
+    substep then equals the chosen start's plain solve, with the probes'
+    iterations counted on top (K when the given start is kept, 2K when the
+    solve runs again from zero)."""
+    K, iters = 4, 25
+    wl = W.custom([2], [6], controller=W.CTRL_EXTERNAL, substeps=1, dt=1 / 240)
+    base = oracle.Oracle(wl)
+    base.cmd[:] = [0.5, -0.5]
+    base.run(5)
+    st = {k: getattr(base, k).copy() for k in ("x", "q", "v", "w", "p", "cmd", "lam_j", "lam_c")}
+
+    def run(warm, n, lam=None, **kw):
+        o = oracle.Oracle(wl, warm=warm, iters=n, tol=0.0, **kw)
+        for k, vv in st.items():
+            getattr(o, k)[...] = vv
+        qp = o.pre_substep(0, 0)
+        if lam is not None:
+            o.lam_j[...] = lam[0]
+            o.lam_c[...] = lam[1]
+        r = o.solve_substep(0, qp)
+        return o, r
+
+    zero_long, _ = run(oracle.WARM_ZERO, 200)
+    starts = {"good": (zero_long.lam_j.copy(), zero_long.lam_c.copy()),
+              "wild": (np.full_like(zero_long.lam_j, 1e-3), np.full_like(zero_long.lam_c, 1e-3))}
+    kept = set()
+    for name, lam in starts.items():
+        _, rz = run(oracle.WARM_ZERO, K)
+        _, rw = run(oracle.WARM_GIVEN, K, lam)
+        o, r = run(oracle.WARM_GIVEN, iters, lam, fallback=1, fallback_k=K)
+        if rw[0] <= rz[0]:
+            ref, rr = run(oracle.WARM_GIVEN, iters, lam)
+            assert not (r[2] & 4) and r[1] == iters + K
+            kept.add(name)
+        else:
+            ref, rr = run(oracle.WARM_ZERO, iters)
+            assert (r[2] & 4) and r[1] == iters + 2 * K
+        for k in ("x", "q", "lam_j", "lam_c"):
+            assert np.array_equal(getattr(o, k), getattr(ref, k)), (name, k)
+        assert r[0] == rr[0]
+    assert kept == {"good"}
