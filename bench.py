@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--snakes", type=int, default=None)
     ap.add_argument("--fixed", action="store_true", help="fixed 20 iterations per substep")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--mapping", default=None,
+                    help="force a mapping instead of autotuning: waves,min_seg,rows (e.g. 4,16,1)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-snakes", type=int, default=1024)
     ap.add_argument("--cpu-steps", type=int, default=12)
@@ -161,7 +163,11 @@ def main():
         wl.tol, wl.iters = 0.0, 20
     else:
         wl.tol, wl.iters = 1e-4, 200
-    sim = snk.Sim(wl, use_graph=1, autotune=0 if args.no_autotune else 1)
+    if args.mapping:
+        mw, ms, mr = (int(v) for v in args.mapping.split(","))
+        sim = snk.Sim(wl, use_graph=1, autotune=0, map_waves=mw, map_min_seg=ms, map_rows=mr)
+    else:
+        sim = snk.Sim(wl, use_graph=1, autotune=0 if args.no_autotune else 1)
     stream = sim.stream
     for _ in range(args.warmup):
         sim.step(1)

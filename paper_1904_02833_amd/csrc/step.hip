@@ -497,37 +497,11 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
 
                 // multiplier initialisation
                 const bool learned = PHASE == kPhaseSolve && P.warm == kWarmMlp;
-                // x <- x~ + W J(x~)^T lambda0 for the multipliers in ls, lb, lc
-                auto apply_start = [&]() {
-                    const V3 aA = qaxis(q);
-                    V3 dn, an;
-                    Q4 qn;
-                    fetch_next(1, d, q, aA, false, dn, qn, an);
-                    Geo g;
-                    V3 Dls, Dlb;
-                    float rs, rb;
-                    joint_eval(dxp, d, dn, q, qn, aA, an, c0h, s0h, ct, stt, wA, c1A, c2A, wB, c1B,
-                               c2B, hl, P.inv_L, comp_s, comp_b, comp_t, ls, lb, g, Dls, Dlb, rs, rb);
-                    V3 tA, tB;
-                    joint_torques(g, ls, lb, hl, tA, tB);
-                    V3 inf, intq;
-                    fetch_prev(sel(hasj, -ls, zero), sel(hasj, tB, zero), 0.f, inf, intq);
-                    const bool recv = hasb && i > 0;
-                    const V3 fsum = sel(recv, inf, zero) + sel(hasj, ls, zero);
-                    const V3 tsum = sel(recv, intq, zero) + sel(hasj, tA, zero);
-                    const V3 dxc = (gnd && !fixed) ? P.inv_m * mk(lc.y, lc.z, lc.x) : zero;
-                    if (hasb && !fixed) {
-                        d = d + (wA * fsum + dxc);
-                        q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
-                    }
-                };
-                // fallback after K iterations: probe the zero start, then the
-                // learned start, K iterations each
+                // fallback after K iterations (below): keep lambda0 aside
                 const bool probe = learned && P.fallback && P.fallback_k > 0;
-                int koff = 0, extra = 0;
                 V3 ls0 = zero, lb0 = zero;
-                const V3 d_zero = d;
-                const Q4 q_zero = q;
+                V3 d_zero = d;
+                Q4 q_zero = q;
                 if (P.warm == kWarmPrev || learned) {
                     if (learned) {
                         // network outputs: stretch in the predicted frame of body i,
@@ -550,7 +524,30 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                         float r_zero = 0.f;
                         if (learned && P.fallback)
                             r_zero = eval_residual(0, dxp, zp, d, q, zero, zero, zero, c0h, s0h, ct, stt);
-                        apply_start();
+                        // x <- x~ + W J(x~)^T lambda0
+                        {
+                            const V3 aA = qaxis(q);
+                            V3 dn, an;
+                            Q4 qn;
+                            fetch_next(1, d, q, aA, false, dn, qn, an);
+                            Geo g;
+                            V3 Dls, Dlb;
+                            float rs, rb;
+                            joint_eval(dxp, d, dn, q, qn, aA, an, c0h, s0h, ct, stt, wA, c1A, c2A, wB, c1B,
+                                       c2B, hl, P.inv_L, comp_s, comp_b, comp_t, ls, lb, g, Dls, Dlb, rs, rb);
+                            V3 tA, tB;
+                            joint_torques(g, ls, lb, hl, tA, tB);
+                            V3 inf, intq;
+                            fetch_prev(sel(hasj, -ls, zero), sel(hasj, tB, zero), 0.f, inf, intq);
+                            const bool recv = hasb && i > 0;
+                            const V3 fsum = sel(recv, inf, zero) + sel(hasj, ls, zero);
+                            const V3 tsum = sel(recv, intq, zero) + sel(hasj, tA, zero);
+                            const V3 dxc = (gnd && !fixed) ? P.inv_m * mk(lc.y, lc.z, lc.x) : zero;
+                            if (hasb && !fixed) {
+                                d = d + (wA * fsum + dxc);
+                                q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
+                            }
+                        }
                         if (learned && P.fallback) {
                             // keep the learned start only if it begins closer than zero
                             const float r_nn = eval_residual(0, dxp, zp, d, q, ls, lb, lc, c0h, s0h, ct, stt);
@@ -570,15 +567,41 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                     lc = zero;
                 }
 
-                // Jacobi iterations from iterate koff of the current state.  A probe
-                // (kprobe >= 0) runs exactly kprobe iterations, records no status
-                // and returns the residual of iterate kprobe; the solve stops at
-                // the tolerance or the iteration cap.  kdone receives the index
-                // of the final iterate, rdone its residual.
-                auto run_loop = [&](int koff_, int kprobe, int& kdone, float& rdone) {
-                bool done = !live;
-                kdone = 0;
-                rdone = 0.f;
+                // Fallback after K iterations: the zero start, then the learned
+                // start, K iterations each (solve phase only; the full-step
+                // kernels never take the learned start).  run_probe repeats the
+                // iteration below for exactly kprobe iterations, without status,
+                // and returns the residual of iterate kprobe.
+                int koff = 0, extra = 0;
+                if constexpr (PHASE == kPhaseSolve) {
+                    if (probe) {
+                        // x <- x~ + W J(x~)^T lambda0 for the multipliers in ls, lb, lc
+                        auto apply_start = [&]() {
+                            const V3 aA = qaxis(q);
+                            V3 dn, an;
+                            Q4 qn;
+                            fetch_next(1, d, q, aA, false, dn, qn, an);
+                            Geo g;
+                            V3 Dls, Dlb;
+                            float rs, rb;
+                            joint_eval(dxp, d, dn, q, qn, aA, an, c0h, s0h, ct, stt, wA, c1A, c2A, wB, c1B,
+                                       c2B, hl, P.inv_L, comp_s, comp_b, comp_t, ls, lb, g, Dls, Dlb, rs, rb);
+                            V3 tA, tB;
+                            joint_torques(g, ls, lb, hl, tA, tB);
+                            V3 inf, intq;
+                            fetch_prev(sel(hasj, -ls, zero), sel(hasj, tB, zero), 0.f, inf, intq);
+                            const bool recv = hasb && i > 0;
+                            const V3 fsum = sel(recv, inf, zero) + sel(hasj, ls, zero);
+                            const V3 tsum = sel(recv, intq, zero) + sel(hasj, tA, zero);
+                            const V3 dxc = (gnd && !fixed) ? P.inv_m * mk(lc.y, lc.z, lc.x) : zero;
+                            if (hasb && !fixed) {
+                                d = d + (wA * fsum + dxc);
+                                q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
+                            }
+                        };
+                        auto run_probe = [&](int kprobe) -> float {
+                    bool done = !live;
+                    float rdone = 0.f;
                 for (int k = 0;; ++k) {
                     const V3 aA = qaxis(q);
                     V3 dn, an;
@@ -604,23 +627,10 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                     const float r = fetch_prev(sel(hasj, -dls, zero), sel(hasj, tB, zero), rl, inf, intq);
 
                     if (!done) {
-                        const int kl = k + koff_;
                         const bool bad = !(r < INFINITY);
-                        bool stop;
-                        if (kprobe >= 0)
-                            stop = bad || k >= kprobe;
-                        else
-                            stop = bad || (P.tol > 0.f ? (r <= P.tol || kl >= P.iters) : (kl >= P.iters));
-                        if (stop) {
+                        if (bad || k >= kprobe) {
                             done = true;
-                            kdone = kl;
                             rdone = bad ? INFINITY : r;
-                            if (kprobe < 0) {
-                                if (bad)
-                                    status |= kStatusNonfinite;
-                                else if (P.tol > 0.f && r > P.tol)
-                                    status |= kStatusNotConverged;
-                            }
                         }
                     }
                     if (!done) {
@@ -643,37 +653,95 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                         }
                     }
                 }
-                };
-                if (probe) {
-                    int kz, kw;
-                    float rz, rw;
-                    run_loop(0, P.fallback_k, kz, rz);              // zero start
-                    d = d_zero;
-                    q = q_zero;
-                    ls = ls0;
-                    lb = lb0;
-                    lc = zero;
-                    if (xw) __syncthreads();   // every wave has read the last exchange
-                    apply_start();
-                    run_loop(0, P.fallback_k, kw, rw);              // learned start
-                    // keep the learned start if it is finite and not farther than zero
-                    if (rw < INFINITY && (rz >= INFINITY || rw <= rz)) {
-                        koff = P.fallback_k;
-                        extra = P.fallback_k;
-                    } else {
+                            return rdone;
+                        };
+                        const float rz = run_probe(P.fallback_k);   // zero start
                         d = d_zero;
                         q = q_zero;
-                        ls = zero;
-                        lb = zero;
+                        ls = ls0;
+                        lb = lb0;
                         lc = zero;
-                        if (live) status |= kStatusFellBack;
-                        extra = 2 * P.fallback_k;
+                        if (xw) __syncthreads();   // every wave has read the last exchange
+                        apply_start();
+                        const float rw = run_probe(P.fallback_k);   // learned start
+                        // keep the learned start if it is finite and not farther than zero
+                        if (rw < INFINITY && (rz >= INFINITY || rw <= rz)) {
+                            koff = P.fallback_k;
+                            extra = P.fallback_k;
+                        } else {
+                            d = d_zero;
+                            q = q_zero;
+                            ls = zero;
+                            lb = zero;
+                            lc = zero;
+                            if (live) status |= kStatusFellBack;
+                            extra = 2 * P.fallback_k;
+                        }
+                        if (xw) __syncthreads();
                     }
-                    if (xw) __syncthreads();
                 }
-                int kdone;
-                float rdone;
-                run_loop(koff, -1, kdone, rdone);
+
+                bool done = !live;
+                int kdone = 0;
+                float rdone = 0.f;
+                for (int k = 0;; ++k) {
+                    const V3 aA = qaxis(q);
+                    V3 dn, an;
+                    Q4 qn;
+                    const bool wave_done = __all(done);
+                    const bool all_done = fetch_next(k & 1, d, q, aA, wave_done, dn, qn, an);
+                    if (xw ? all_done : wave_done) break;
+                    Geo g;
+                    V3 Dls, Dlb;
+                    float rs, rb;
+                    joint_eval(dxp, d, dn, q, qn, aA, an, c0h, s0h, ct, stt, wA, c1A, c2A, wB, c1B,
+                               c2B, hl, P.inv_L, comp_s, comp_b, comp_t, ls, lb, g, Dls, Dlb, rs, rb);
+                    const float cn = zp + d.z;
+                    const float rc = (lc.x > 0.f ? fabsf(cn) : fmaxf(-cn, 0.f)) * P.inv_L;
+                    float rl = fmaxf(hasj ? fmaxf(rs, rb) : 0.f, (hasb && gnd) ? rc : 0.f);
+                    rl = (rl == rl) ? rl : INFINITY;
+                    rl = seg_reduce(rl);
+
+                    const V3 dls = sj * Dls, dlb = sj * Dlb;
+                    V3 tA, tB;
+                    joint_torques(g, dls, dlb, hl, tA, tB);
+                    V3 inf, intq;
+                    const float r = fetch_prev(sel(hasj, -dls, zero), sel(hasj, tB, zero), rl, inf, intq);
+
+                    if (!done) {
+                        const int kl = k + koff;
+                        const bool bad = !(r < INFINITY);
+                        const bool stop = bad || (P.tol > 0.f ? (r <= P.tol || kl >= P.iters) : (kl >= P.iters));
+                        if (stop) {
+                            done = true;
+                            kdone = kl;
+                            rdone = r;
+                            if (bad)
+                                status |= kStatusNonfinite;
+                            else if (P.tol > 0.f && r > P.tol)
+                                status |= kStatusNotConverged;
+                        }
+                    }
+                    if (!done) {
+                        V3 dlc = zero;
+                        if (gnd && !fixed) dlc = contact_incr(lc, cn, d, sc, mass, mu);
+                        // gather in a fixed order: forces of joint i-1 (received),
+                        // joint i and the contact through the inverse mass; torques
+                        // of the two joints through the inverse inertia
+                        const bool recv = hasb && i > 0;
+                        const V3 fsum = sel(recv, inf, zero) + sel(hasj, dls, zero);
+                        const V3 tsum = sel(recv, intq, zero) + sel(hasj, tA, zero);
+                        if (hasj) {
+                            ls = ls + dls;
+                            lb = lb + dlb;
+                        }
+                        if (hasb && gnd) lc = lc + dlc;
+                        if (hasb && !fixed) {
+                            d = d + wA * (fsum + mk(dlc.y, dlc.z, dlc.x));
+                            q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
+                        }
+                    }
+                }
                 if (live) kdone += extra;
                 itstep += kdone;
                 rstep = fmaxf(rstep, rdone);

@@ -111,6 +111,8 @@ def test_workspace_bytes_valid_and_monotone(L):
     ("controller", 7, "controller"),
     ("flags", 64, "flag"),
     ("map_rows", 2, "map_rows"),
+    ("mlp_fallback_k", 21, "mlp_fallback_k"),
+    ("mlp_fallback_k", -1, "mlp_fallback_k"),
 ])
 def test_descriptor_validation(L, field, value, msg):
     wl = W.custom([2, 2], 8)
@@ -204,3 +206,15 @@ def test_tile_plan_rejects_bad_mapping(L):
     for args in [(3, 16, 0), (4, 8, 0), (4, 16, 2), (1, 16, 0)]:
         with pytest.raises(snk.SimError):
             snk.plan_tiles(wl, *args)
+
+
+def test_empty_and_oversized_batches_rejected(L):
+    wl = W.custom([2], 8)
+    rc, _, err = ws_bytes(L, wl, n_modules=np.zeros(0, np.int32), segs_per_module=np.zeros(0, np.int32))
+    assert rc == snk.SIM_EINVAL
+    big = W.custom([9], 128)             # 1152 bodies
+    rc, _, err = ws_bytes(L, big)
+    assert rc == snk.SIM_EINVAL and "1024" in err
+    edge = W.custom([8], 128)            # exactly 1024 bodies
+    rc, b, _ = ws_bytes(L, edge)
+    assert rc == 0 and b > 0

@@ -436,3 +436,37 @@ def test_full_uniform_batch_sampled_parity():
     o.run(1, threads=8)
     assert np.array_equal(o.iters, gs["iters"][sample])
     assert_parity("full-uniform-sampled", compare(o, g, sub.mu), n_bodies=sub.total_bodies)
+
+
+def test_rows_layout_on_tiny_and_odd_sizes_bit_identical():
+    """Snakes of 1, 2, 3, 15, 17, 63 and 64 bodies in the rows layout (segments
+    rounded to 16 lanes, unaligned, crossing waves) give the same bits as
+    the aligned layout."""
+    wl = W.custom([1, 1, 1, 1, 1, 3, 1, 4] * 20, [1, 2, 3, 15, 17, 5, 63, 16] * 20, mu=0.4)
+    ref = None
+    for mp in (dict(map_waves=1), dict(map_waves=1, map_rows=1), dict(map_waves=2, map_rows=1),
+               dict(map_waves=4, map_rows=1, map_grid=8)):
+        sim = snk.Sim(wl, **mp)
+        sim.step(6)
+        r = sim.read()
+        print(mp, sim.mapping)
+        if ref is None:
+            ref = r
+        else:
+            for k in r:
+                assert np.array_equal(r[k], ref[k]), (mp, k)
+        sim.close()
+
+
+def test_zero_iterations_evaluates_only():
+    """iters = 0: every substep only evaluates the predicted state; positions
+    follow the unconstrained prediction and the residual is that state's."""
+    wl = W.make("uneven", n_snakes=60)
+    o = oracle.Oracle(wl)
+    o.run(10, threads=8)
+    o.commands()
+    oo, g = advance_both(wl, rounded_state(o), iters=0)
+    assert np.all(oo.iters == 0) and np.all(g["iters"] == 0)
+    assert_parity("iters0", compare(oo, g, wl.mu), n_bodies=wl.total_bodies)
+    rel = np.abs(g["residual"] - oo.residual) / np.maximum(oo.residual, 1e-6)
+    assert rel.max() <= 1e-3
