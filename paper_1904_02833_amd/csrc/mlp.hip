@@ -34,11 +34,33 @@ int mfail(int code, const std::string& m)
     return code;
 }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+// erf(x) by Abramowitz and Stegun, Handbook of Mathematical Functions,
+// formula 7.1.26: 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p |x|),
+// odd in x; absolute error at most 1.5e-7 (far below the BF16 rounding of
+// the activations).  exp(-x^2) also serves GELU's derivative.
+__device__ __forceinline__ float erf_as(float x, float& e)
+{
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.f));
+    const float poly =
+        t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
+                 0.254829592f);
+    e = __builtin_amdgcn_exp2f(-1.4426950408889634f * (x * x));   // exp(-x^2)
+    return copysignf(fmaf(-poly, e, 1.f), x);
+}
 
+__device__ __forceinline__ float gelu(float z)
+{
+    float e;
+    return 0.5f * z * (1.f + erf_as(z * 0.70710678118654752f, e));
+}
+
+// d GELU / dz = Phi(z) + z phi(z), phi(z) = exp(-z^2 / 2) / sqrt(2 pi)
 __device__ __forceinline__ float gelu_grad(float z)
 {
-    return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+    float e;
+    const float phi = 0.5f * (1.f + erf_as(z * 0.70710678118654752f, e));
+    return phi + z * 0.39894228040143268f * e;
 }
 
 // C[M x N] = A[M x K] B[K x N] for M, N multiples of 16 and K of 32, on one
