@@ -676,14 +676,22 @@ int sim_step(sim_t* s, int32_t n_steps)
     }
     auto it = s->graphs.find(n_steps);
     if (it == s->graphs.end()) {
-        hipGraph_t graph;
+        // a few step counts are kept; a new one beyond that replaces them
+        if (s->graphs.size() >= 8) {
+            (void)hipStreamSynchronize(s->stream);
+            for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+            s->graphs.clear();
+        }
+        hipGraph_t graph = nullptr;
         hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "begin capture");
         int rc = SIM_OK;
         for (int k = 0; k < n_steps && rc == SIM_OK; ++k) rc = launch_steps(s, s->cap_stream, 1);
         e = hipStreamEndCapture(s->cap_stream, &graph);
-        if (rc) return rc;
-        if (e != hipSuccess) return hip_fail(e, "end capture");
+        if (rc || e != hipSuccess) {
+            if (e == hipSuccess && graph) (void)hipGraphDestroy(graph);
+            return rc ? rc : hip_fail(e, "end capture");
+        }
         hipGraphExec_t exec;
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
