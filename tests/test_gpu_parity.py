@@ -404,39 +404,73 @@ def slice_snakes(st, o_full, sample):
     return out
 
 
-def test_full_uniform_batch_sampled_parity():
-    """The benchmark's workload in its launch configuration: 4096 snakes of
-    64 bodies, autotuned mapping, residual 1e-4 or at most 200 iterations.
-    After 10 steps on the GPU, the whole batch takes one more substep on the
-    GPU, and sampled snakes (first, last, middle, random) take it in the
-    oracle from the same FP32 state and commands."""
-    wl = W.make("uniform")
+def full_batch_sampled_parity(name, sample, steps=10):
+    """The benchmark's settings on a whole named batch: autotuned mapping,
+    residual 1e-4 or at most 200 iterations.  After `steps` GPU steps the
+    whole batch takes one more substep on the GPU, and the sampled snakes
+    take it in the oracle from the same FP32 state and commands."""
+    wl = W.make(name)
     wl.tol, wl.iters = 1e-4, 200
     lead = snk.Sim(wl, autotune=1)
-    lead.step(10)
+    lead.step(steps)
     st = gpu_state(lead)
     lead.close()
     o_full = oracle.Oracle(wl)
-    o_full.step[:] = 10
+    o_full.step[:] = steps
     st["cmd"] = f32(o_full.commands())
-    rng = np.random.default_rng(11)
-    sample = sorted({0, 1, 2047, 4095, *rng.choice(4096, 8, replace=False).tolist()})
     h = wl.dt / wl.substeps
     kw = dict(controller=W.CTRL_EXTERNAL, dt=h, substeps=1)
     sim = snk.Sim(wl, autotune=1, **kw)
     load_gpu(sim, st)
     sim.step(1)
-    print(f"\n[full-uniform] mapping {sim.mapping}")
+    print(f"\n[full-{name}] mapping {sim.mapping}, sampled snakes of {sorted(set(wl.bodies[sample].tolist()))} bodies")
     gs = gpu_state(sim)
     g = slice_snakes(gs, o_full, sample)
     sim.close()
     sub = wl.take(np.array(sample))
+    st_s = slice_snakes(st, o_full, sample)
     o = oracle.Oracle(sub, **kw)
-    load_oracle(o, slice_snakes(st, o_full, sample))
+    load_oracle(o, st_s)
     o.run(1, threads=8)
     assert np.array_equal(o.iters, gs["iters"][sample])
-    assert_parity("full-uniform-sampled", compare(o, g, sub.mu), n_bodies=sub.total_bodies)
+    # Conditioning floor: the same FP64 substep from positions one FP32 ulp
+    # away.  At 200 iterations the multipliers of this ill-conditioned system
+    # move by about 1e-4 under such a nudge, so the multiplier gate is the
+    # larger of 1e-4 and twice the measured spread.
+    o2 = oracle.Oracle(sub, **kw)
+    nudged = dict(st_s)
+    nudged["x"] = np.nextafter(st_s["x"].astype(np.float32), np.float32(np.inf)).astype(np.float64)
+    load_oracle(o2, nudged)
+    o2.run(1, threads=8)
+    spread = compare(o, dict(x=o2.x, lam_j=o2.lam_j, lam_c=o2.lam_c), sub.mu)
+    floor = max(float(np.max(spread[k])) for k in ("lam_s", "lam_b", "lam_n", "lam_t"))
+    lam_tol = max(LAM_TOL, 2.0 * floor)
+    print(f"[full-{name}] FP64 multiplier spread under a 1-ulp nudge {floor:.3g}; gate {lam_tol:.3g}")
+    assert_parity(f"full-{name}-sampled", compare(o, g, sub.mu), n_bodies=sub.total_bodies, lam_tol=lam_tol)
 
+
+def test_full_uniform_batch_sampled_parity():
+    """The benchmark's workload in its launch configuration (4096 snakes of
+    64 bodies), sampled snakes: first, last, middle and random."""
+    rng = np.random.default_rng(11)
+    full_batch_sampled_parity("uniform", sorted({0, 1, 2047, 4095, *rng.choice(4096, 8, replace=False).tolist()}))
+
+
+def test_full_uneven_batch_sampled_parity():
+    """The uneven batch (16 384 snakes of 16..256 bodies) in its autotuned
+    layout: the longest and shortest snakes, which span waves or share
+    them, and random ones."""
+    wl = W.make("uneven")
+    B = wl.bodies
+    rng = np.random.default_rng(12)
+    pick = {int(np.argmax(B)), int(np.argmin(B)), 0, wl.n_snakes - 1,
+            *np.nonzero(B == 64)[0][:1].tolist(), *rng.choice(wl.n_snakes, 7, replace=False).tolist()}
+    full_batch_sampled_parity("uneven", sorted(pick), steps=4)
+
+
+def test_full_stiff_batch_sampled_parity():
+    """The stiff batch (256 snakes of 1024 bodies, 16 waves each)."""
+    full_batch_sampled_parity("stiff", [0, 97, 255], steps=3)
 
 def test_rows_layout_on_tiny_and_odd_sizes_bit_identical():
     """Snakes of 1, 2, 3, 15, 17, 63 and 64 bodies in the rows layout (segments
