@@ -24,6 +24,11 @@ batches stand in for it):
                U[1e-8,1e-6], mu 0.6, serpenoid with the uniform-batch draws,
                residual tolerance 1e-4 (at most 200 iterations), 500 steps.
 * ``learned``  the uneven batch, used with the learned warm start.
+* ``short``    4096 snakes of 2 modules x U{3,4} segments (6 or 8 bodies),
+               the uneven batch's parameter draws and commands: chains short
+               enough that the solve reaches residual 1e-4 within a few
+               thousand iterations (a setting for the learned warm start;
+               not one of the paper's configurations).
 """
 from __future__ import annotations
 
@@ -46,7 +51,7 @@ CTRL_SCHEDULE = 2
 LAW_LAG = 0
 LAW_PAPER = 1
 
-WORKLOAD_NAMES = ("single", "uniform", "uneven", "stiff", "learned")
+WORKLOAD_NAMES = ("single", "uniform", "uneven", "stiff", "learned", "short")
 
 
 class SplitMix64:
@@ -199,13 +204,17 @@ def make(name: str, seed: int | None = None, n_snakes: int | None = None) -> Wor
         if name == "stiff":
             w.tol = 1e-4
             w.iters = 200
-    else:  # uneven / learned
-        n = 16384 if n_snakes is None else int(n_snakes)
+    else:  # uneven / learned / short
+        n = (4096 if name == "short" else 16384) if n_snakes is None else int(n_snakes)
         Ms, Ss, rows, offs, steps, vals = [], [], [], [0], [], []
         horizon = 1000
         for _ in range(n):
-            M = rng.integer(2, 8)
-            S = rng.integer(8, 32)
+            if name == "short":
+                M = 2
+                S = rng.integer(3, 4)
+            else:
+                M = rng.integer(2, 8)
+                S = rng.integer(8, 32)
             Ms.append(M)
             Ss.append(S)
             rows.append(_draw_params(rng, 1e-6, 1e-4, True, 0.0))
