@@ -181,9 +181,9 @@ typedef struct sim_desc {
                                /* start (0: the starts themselves; at most   */
                                /* iters).  For k > 0 the zero start runs k   */
                                /* iterations, then the learned start k; the  */
-                               /* solve continues from the learned iterate k */
-                               /* or runs again from zero, and the probes'   */
-                               /* iterations count in SIM_F_ITERS.           */
+                               /* solve continues from the winner's iterate  */
+                               /* k, and the other start's k iterations      */
+                               /* count in SIM_F_ITERS.                      */
 } sim_desc_t;
 
 typedef struct sim sim_t;

@@ -465,6 +465,8 @@ typedef struct {
     double* qs;         /* [B*4] */
     double* l0_j;       /* lambda0 kept for the fallback's probes */
     double* l0_c;
+    double* xz;         /* [B*3] the zero start's iterate K, kept for a fallback */
+    double* qz;         /* [B*4] */
 } scratch_t;
 
 static void scratch_alloc(scratch_t* w, const snake_ctx* c)
@@ -487,6 +489,8 @@ static void scratch_alloc(scratch_t* w, const snake_ctx* c)
     w->qs = (double*)calloc((size_t)B * 4, sizeof(double));
     w->l0_j = (double*)calloc((size_t)B * 6, sizeof(double));
     w->l0_c = (double*)calloc((size_t)B * 3, sizeof(double));
+    w->xz = (double*)calloc((size_t)B * 3, sizeof(double));
+    w->qz = (double*)calloc((size_t)B * 4, sizeof(double));
 }
 
 static void scratch_free(scratch_t* w)
@@ -507,6 +511,8 @@ static void scratch_free(scratch_t* w)
     free(w->qs);
     free(w->l0_j);
     free(w->l0_c);
+    free(w->xz);
+    free(w->qz);
 }
 
 /* Predicted positions of a first-order implicit step: gravity on the linear
@@ -716,9 +722,9 @@ static int jacobi(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* 
  * only if, after fallback_k iterations, its residual is not larger than the
  * zero start's after as many; fallback_k = 0 compares the starts themselves.
  * For fallback_k > 0 the zero start runs first (fallback_k iterations), then
- * the given start (fallback_k iterations): if the given start wins the solve
- * continues from its iterate fallback_k, else it runs again from the zero
- * start; the iterations of the probes count in the total. */
+ * the given start (fallback_k iterations); the solve continues from the
+ * winner's iterate fallback_k, and the loser's fallback_k iterations count
+ * on top of the total. */
 static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* x, double* q,
                          double* lam_j, double* lam_c, int warm, int kmax, double tol, double* res,
                          int* status)
@@ -740,6 +746,10 @@ static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, d
         memset(lam_j, 0, nj6);
         memset(lam_c, 0, nc3);
         jacobi(b, c, W, x, q, lam_j, lam_c, 0, K, 0.0, 1, &rz, &st);
+        memcpy(W->xz, x, sizeof(double) * 3 * (size_t)B);
+        memcpy(W->qz, q, sizeof(double) * 4 * (size_t)B);
+        memcpy(W->lz_j, lam_j, nj6);
+        memcpy(W->lz_c, lam_c, nc3);
         /* probe: given start */
         memcpy(x, W->xs, sizeof(double) * 3 * (size_t)B);
         memcpy(q, W->qs, sizeof(double) * 4 * (size_t)B);
@@ -754,12 +764,14 @@ static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, d
              * K iterations count on top */
             return jacobi(b, c, W, x, q, lam_j, lam_c, K, kmax, tol, 0, res, status) + K;
         }
-        memcpy(x, W->xs, sizeof(double) * 3 * (size_t)B);
-        memcpy(q, W->qs, sizeof(double) * 4 * (size_t)B);
-        memset(lam_j, 0, nj6);
-        memset(lam_c, 0, nc3);
+        /* continue from the zero start's iterate K; the given start's K
+         * probe iterations count on top */
+        memcpy(x, W->xz, sizeof(double) * 3 * (size_t)B);
+        memcpy(q, W->qz, sizeof(double) * 4 * (size_t)B);
+        memcpy(lam_j, W->lz_j, nj6);
+        memcpy(lam_c, W->lz_c, nc3);
         *status |= ORC_STATUS_FELL_BACK;
-        return jacobi(b, c, W, x, q, lam_j, lam_c, 0, kmax, tol, 0, res, status) + 2 * K;
+        return jacobi(b, c, W, x, q, lam_j, lam_c, K, kmax, tol, 0, res, status) + K;
     }
 
     double r_zero = 0.0;

@@ -206,6 +206,7 @@ size_t carve(const Sizes& z, char* base, Views* v)
     ip.order = c.take<int>(n);
     ip.color_scratch = c.take<int>(N);
     k.q_pred = c.take<float>(4 * N);
+    k.probe = z.mlp ? c.take<float>(16 * N) : nullptr;
     v->feat = z.mlp ? c.take<float>(64 * J) : nullptr;
     v->mlp_y = z.mlp ? c.take<float>(6 * J) : nullptr;
     v->mlp_params = z.mlp ? c.take<float>(8192) : nullptr;

@@ -45,6 +45,7 @@ struct KParams {
     float* lam_j;           // [6][J]
     float* lam_c;           // [3][N]
     float* q_pred;          // [4][N] predicted orientation (split substeps)
+    float* probe;           // [16][N] zero start's iterate K (fallback after K iterations)
     const float* mlp_y;     // [2J][3] network outputs (learned warm start)
     float* residual;        // [n]
     int* iters_out;         // [n]

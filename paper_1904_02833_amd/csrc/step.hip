@@ -656,6 +656,14 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                             return rdone;
                         };
                         const float rz = run_probe(P.fallback_k);   // zero start
+                        // keep the zero start's iterate K for a fallback
+                        if (hasb) {
+                            float* ps = P.probe + gb;
+                            const float keep[16] = {d.x, d.y, d.z, q.w, q.x, q.y, q.z, ls.x, ls.y, ls.z,
+                                                    lb.x, lb.y, lb.z, lc.x, lc.y, lc.z};
+#pragma unroll
+                            for (int c = 0; c < 16; ++c) ps[(size_t)c * N] = keep[c];
+                        }
                         d = d_zero;
                         q = q_zero;
                         ls = ls0;
@@ -669,13 +677,21 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                             koff = P.fallback_k;
                             extra = P.fallback_k;
                         } else {
-                            d = d_zero;
-                            q = q_zero;
-                            ls = zero;
-                            lb = zero;
-                            lc = zero;
+                            // continue from the zero start's iterate K
+                            if (hasb) {
+                                const float* ps = P.probe + gb;
+                                float kept[16];
+#pragma unroll
+                                for (int c = 0; c < 16; ++c) kept[c] = ps[(size_t)c * N];
+                                d = mk(kept[0], kept[1], kept[2]);
+                                q = Q4{kept[3], kept[4], kept[5], kept[6]};
+                                ls = mk(kept[7], kept[8], kept[9]);
+                                lb = mk(kept[10], kept[11], kept[12]);
+                                lc = mk(kept[13], kept[14], kept[15]);
+                            }
                             if (live) status |= kStatusFellBack;
-                            extra = 2 * P.fallback_k;
+                            koff = P.fallback_k;
+                            extra = P.fallback_k;
                         }
                         if (xw) __syncthreads();
                     }

@@ -122,7 +122,7 @@ def test_warm_start_from_network_outputs_matches_oracle(fallback, fallback_k):
     print(f"\n[warm mlp fallback={fallback}] fell back: oracle {fell_o.sum()} gpu {fell_g.sum()} of {o.n}")
     same = fell_o == fell_g
     assert same.mean() >= 0.9
-    # iterations include the probes: K on top when kept, 2K when fallen back
+    # iterations include the other start's probe: K on top either way
     assert np.array_equal(np.asarray(g["iters"])[same], np.array(iters)[same])
     err = compare(o, g, wl.mu)
     keep = np.nonzero(same)[0]

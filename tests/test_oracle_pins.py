@@ -739,9 +739,8 @@ def test_features_closed_form_and_yaw_invariance():
 def test_fallback_after_k_iterations_follows_the_probes():
     """With fallback_k = K the start is chosen by the residuals after K
     iterations from each start (computed here by separate runs), and the
-    substep then equals the chosen start's plain solve, with the probes'
-    iterations counted on top (K when the given start is kept, 2K when the
-    solve runs again from zero)."""
+    substep then equals the chosen start's plain solve (continued from its
+    iterate K), with the other start's K iterations counted on top."""
     K, iters = 4, 25
     wl = W.custom([2], [6], controller=W.CTRL_EXTERNAL, substeps=1, dt=1 / 240)
     base = oracle.Oracle(wl)
@@ -774,7 +773,7 @@ def test_fallback_after_k_iterations_follows_the_probes():
             kept.add(name)
         else:
             ref, rr = run(oracle.WARM_ZERO, iters)
-            assert (r[2] & 4) and r[1] == iters + 2 * K
+            assert (r[2] & 4) and r[1] == iters + K
         for k in ("x", "q", "lam_j", "lam_c"):
             assert np.array_equal(getattr(o, k), getattr(ref, k)), (name, k)
         assert r[0] == rr[0]
