@@ -30,6 +30,7 @@ FLAG_NO_GROUND = 2
 FLAG_LINEARISED = 8
 WARM_ZERO, WARM_PREV, WARM_GIVEN = 0, 1, 2
 STATUS_NONFINITE, STATUS_NOT_CONVERGED = 1, 2
+SOLVER_JACOBI, SOLVER_NEWTON = 0, 1
 
 _lock = threading.Lock()
 _lib = None
@@ -81,6 +82,7 @@ class Batch(C.Structure):
         ("flags", C.c_int32), ("controller", C.c_int32), ("warm", C.c_int32),
         ("ctrl_alpha", C.c_double), ("ctrl_offset", C.c_double),
         ("fallback", C.c_int32), ("fallback_k", C.c_int32),
+        ("solver", C.c_int32), ("newton_iters", C.c_int32), ("pcr_iters", C.c_int32),
     ]
 
 
@@ -162,6 +164,9 @@ class Oracle:
         b.warm = int(over.get("warm", WARM_ZERO))
         b.fallback = int(over.get("fallback", 0))
         b.fallback_k = int(over.get("fallback_k", 0))
+        b.solver = int(over.get("solver", getattr(wl, "solver", SOLVER_JACOBI)))
+        b.newton_iters = int(over.get("newton_iters", getattr(wl, "newton_iters", 4)))
+        b.pcr_iters = int(over.get("pcr_iters", getattr(wl, "pcr_iters", 20)))
         self.batch = b
         self.n = n
         self.B = (np.asarray(g("n_modules"), np.int64) * np.asarray(g("segs_per_module"), np.int64))

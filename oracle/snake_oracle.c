@@ -467,6 +467,20 @@ typedef struct {
     double* l0_c;
     double* xz;         /* [B*3] the zero start's iterate K, kept for a fallback */
     double* qz;         /* [B*4] */
+    /* Newton solver: per block a 3x3 compliance, per row the right-hand
+     * side, the preconditioner's diagonal and the inner solve's vectors */
+    double* nE;         /* [n_blocks*9] */
+    double* nP;         /* [n_blocks*9] projector onto the free rows */
+    double* nd;         /* [n_blocks*3] fixed increments */
+    double* nrhs;       /* [n_blocks*3] */
+    double* ndiag;
+    double* nx;         /* the increment of the multipliers */
+    double* nz;
+    double* np;
+    double* nAp;
+    double* nAz;
+    double* nMq;
+    double* nu;         /* [B*6] W J^T v per body */
 } scratch_t;
 
 static void scratch_alloc(scratch_t* w, const snake_ctx* c)
@@ -491,6 +505,19 @@ static void scratch_alloc(scratch_t* w, const snake_ctx* c)
     w->l0_c = (double*)calloc((size_t)B * 3, sizeof(double));
     w->xz = (double*)calloc((size_t)B * 3, sizeof(double));
     w->qz = (double*)calloc((size_t)B * 4, sizeof(double));
+    size_t r3 = (size_t)(n_blocks(c) + 1) * 3;
+    w->nE = (double*)calloc(r3 * 3, sizeof(double));
+    w->nP = (double*)calloc(r3 * 3, sizeof(double));
+    w->nd = (double*)calloc(r3, sizeof(double));
+    w->nrhs = (double*)calloc(r3, sizeof(double));
+    w->ndiag = (double*)calloc(r3, sizeof(double));
+    w->nx = (double*)calloc(r3, sizeof(double));
+    w->nz = (double*)calloc(r3, sizeof(double));
+    w->np = (double*)calloc(r3, sizeof(double));
+    w->nAp = (double*)calloc(r3, sizeof(double));
+    w->nAz = (double*)calloc(r3, sizeof(double));
+    w->nMq = (double*)calloc(r3, sizeof(double));
+    w->nu = (double*)calloc((size_t)B * 6, sizeof(double));
 }
 
 static void scratch_free(scratch_t* w)
@@ -513,6 +540,18 @@ static void scratch_free(scratch_t* w)
     free(w->l0_c);
     free(w->xz);
     free(w->qz);
+    free(w->nE);
+    free(w->nP);
+    free(w->nd);
+    free(w->nrhs);
+    free(w->ndiag);
+    free(w->nx);
+    free(w->nz);
+    free(w->np);
+    free(w->nAp);
+    free(w->nAz);
+    free(w->nMq);
+    free(w->nu);
 }
 
 /* Predicted positions of a first-order implicit step: gravity on the linear
@@ -631,6 +670,27 @@ static void apply_start(const orc_batch* b, const snake_ctx* c, scratch_t* W, do
     }
 }
 
+/* Linearised mode: the blocks frozen at the start of the solve (blk0),
+ * their values moved by J times the accumulated displacement. */
+static void linear_blocks(const snake_ctx* c, scratch_t* W)
+{
+    int nb = n_blocks(c);
+    memcpy(W->blk, W->blk0, sizeof(block_t) * (size_t)nb);
+    for (int n = 0; n < nb; ++n) {
+        block_t* kb = &W->blk[n];
+        const double* da = W->acc + 6 * kb->a;
+        for (int row = 0; row < 3; ++row) {
+            double s = 0.0;
+            for (int d = 0; d < 6; ++d) s += kb->Ja[6 * row + d] * da[d];
+            if (kb->b >= 0) {
+                const double* db = W->acc + 6 * kb->b;
+                for (int d = 0; d < 6; ++d) s += kb->Jb[6 * row + d] * db[d];
+            }
+            kb->C[row] += s;
+        }
+    }
+}
+
 /* Block-Jacobi iterations from iterate k0 of the current (x, q, lambda):
  * evaluate, stop at the first iterate k with residual <= tol or k >= kmax
  * (probe: exactly at k = kmax, no convergence status), else apply.
@@ -653,20 +713,7 @@ static int jacobi(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* 
     for (;; ++k) {
         /* evaluate every block at the current iterate */
         if (c->linear) {
-            memcpy(W->blk, W->blk0, sizeof(block_t) * (size_t)nb);
-            for (int n = 0; n < nb; ++n) {
-                block_t* kb = &W->blk[n];
-                const double* da = W->acc + 6 * kb->a;
-                for (int row = 0; row < 3; ++row) {
-                    double s = 0.0;
-                    for (int d = 0; d < 6; ++d) s += kb->Ja[6 * row + d] * da[d];
-                    if (kb->b >= 0) {
-                        const double* db = W->acc + 6 * kb->b;
-                        for (int d = 0; d < 6; ++d) s += kb->Jb[6 * row + d] * db[d];
-                    }
-                    kb->C[row] += s;
-                }
-            }
+            linear_blocks(c, W);
         } else {
             eval_blocks(b, c, x, q, W->xp, W->theta0, W->blk);
             for (int i = 0; i < B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
@@ -714,8 +761,356 @@ static int jacobi(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* 
     return k;
 }
 
-/* Block-Jacobi solve of one substep from the predicted (x, q).  Returns the
- * number of iterations run; *res is the residual of the final iterate.
+/* ------------------------------------------------------------------ */
+/* the paper's scheme: Newton iterations with a preconditioned          */
+/* conjugate-residual solve of eq. schur_system                         */
+/* ------------------------------------------------------------------ */
+
+/* Threshold below which the derivative of a contact row's reformulation
+ * with respect to the constraint value counts as zero. */
+#define NEWTON_EPS 1e-6
+/* Scale of the friction natural map's trial, in units of the body mass:
+ * every positive scale has the same roots; this one keeps the Newton
+ * iterates of the workloads' contacts from cycling between stick and slip
+ * (a measured choice). */
+#define FRICTION_TRIAL 10.0
+
+/* Rows of contact block k at multipliers l (normal, tangential x, y) for
+ * eq. schur_system.  Each row is a semismooth Newton step on F(C, l) = 0,
+ * dF = F_C J W J^T dl + F_l dl.  Where F_C > 0 the row is divided by it:
+ * compliance E = F_l / F_C, right-hand side -F / F_C, and it joins the
+ * inner solve ("free").  Where F_C = 0 the row involves its multiplier
+ * alone and fixes its increment ("fixed"); the inner solve then runs on
+ * the free rows with the fixed increments moved to the right-hand side.
+ *   normal: the Fischer-Burmeister function phi(a, b) = a + b - sqrt(a^2+b^2)
+ *     of a = C_n and b = w l_n (both lengths); phi = 0 iff a >= 0, b >= 0,
+ *     a b = 0 (the contact complementarity).  At (0, 0) the gradient is
+ *     taken along the diagonal.  Fixed when d phi / d a <= NEWTON_EPS,
+ *     which happens only for a > 0: the row is then phi(a, b) = 0 in b
+ *     alone, whose root is b = 0, taken directly (dl = -l_n).
+ *   tangential: the natural map F = l_t - proj(l_t - m C_t) onto the
+ *     Coulomb disc of radius mu max(l_n, 0) (radius frozen at the current
+ *     iterate), m = FRICTION_TRIAL times the body mass.  Inside the disc
+ *     (stick) both rows are C_t = 0 (E = 0).
+ *     Outside (slip, s = radius / |y| < 1, y the trial) the row along
+ *     y^ = y / |y| is fixed (dl = radius - l.y^), the row across it free
+ *     with E = (1 - s) / (m s).  A zero radius fixes both (dl = -l_t).
+ * Out: E (3x3), rhs (3), the projector P onto the free rows (3x3) and the
+ * fixed increment d (3, zero on free rows).  A body of infinite mass
+ * keeps its contact multipliers: every row fixed with d = 0. */
+static void contact_newton_rows(const snake_ctx* c, const block_t* k, const double* l, double w,
+                                double* E, double* rhs, double* P, double* d)
+{
+    memset(E, 0, 9 * sizeof(double));
+    memset(P, 0, 9 * sizeof(double));
+    rhs[0] = rhs[1] = rhs[2] = 0.0;
+    d[0] = d[1] = d[2] = 0.0;
+    if (w == 0.0) return;
+    double a = k->C[0], bb = w * l[0];
+    double rr = sqrt(a * a + bb * bb);
+    double fa, fb;
+    if (rr > 0.0) {
+        fa = 1.0 - a / rr;
+        fb = 1.0 - bb / rr;
+    } else {
+        fa = fb = 1.0 - sqrt(0.5);
+    }
+    /* a + b - r without cancellation when a + b > 0: (a + b)^2 - r^2 = 2ab */
+    double phi = (a + bb > 0.0) ? 2.0 * a * bb / (a + bb + rr) : a + bb - rr;
+    if (fa > NEWTON_EPS) {
+        P[0] = 1.0;
+        E[0] = w * fb / fa;
+        rhs[0] = -phi / fa;
+    } else {
+        /* here a > 0, so the row's root is b = 0 */
+        d[0] = -l[0];
+    }
+
+    double m = FRICTION_TRIAL / w;
+    double y0 = l[1] - m * k->C[1], y1 = l[2] - m * k->C[2];
+    double cap = c->mu * (l[0] > 0.0 ? l[0] : 0.0);
+    double ny = sqrt(y0 * y0 + y1 * y1);
+    if (cap > 0.0 && ny <= cap) {
+        P[4] = P[8] = 1.0;
+        rhs[1] = -k->C[1];
+        rhs[2] = -k->C[2];
+        return;
+    }
+    if (!(cap > 0.0)) {
+        d[1] = -l[1];
+        d[2] = -l[2];
+        return;
+    }
+    double s = cap / ny;
+    double u0 = y0 / ny, u1 = y1 / ny;       /* along the trial */
+    double v0 = -u1, v1 = u0;                /* across it */
+    double fpar = l[1] * u0 + l[2] * u1 - cap;
+    double fper = l[1] * v0 + l[2] * v1;
+    double eper = (1.0 - s) / (m * s), bper = -fper / (m * s);
+    d[1] = -fpar * u0;
+    d[2] = -fpar * u1;
+    P[4] = v0 * v0;
+    P[5] = P[7] = v0 * v1;
+    P[8] = v1 * v1;
+    E[4] = eper * v0 * v0;
+    E[5] = E[7] = eper * v0 * v1;
+    E[8] = eper * v1 * v1;
+    rhs[1] = bper * v0;
+    rhs[2] = bper * v1;
+}
+
+/* J W J^T entry (r, r) of one block's row r on one body */
+static double row_jwjt(const double* J, int r, double w, const double* Iinv)
+{
+    double acc = 0.0;
+    for (int d = 0; d < 3; ++d) acc += J[6 * r + d] * w * J[6 * r + d];
+    for (int d = 0; d < 3; ++d)
+        for (int e = 0; e < 3; ++e) acc += J[6 * r + 3 + d] * Iinv[3 * d + e] * J[6 * r + 3 + e];
+    return acc;
+}
+
+/* Right-hand side, compliance, free-row projector, fixed increments and
+ * preconditioner diagonal of eq. schur_system at the evaluated blocks:
+ * joint rows are free with E = alpha~, rhs = -(C + alpha~ l); contact rows
+ * as above. */
+static void newton_rows(const snake_ctx* c, scratch_t* W, double* lam_j, double* lam_c)
+{
+    int nb = n_blocks(c);
+    for (int n = 0; n < nb; ++n) {
+        block_t* kb = &W->blk[n];
+        double* l = block_lambda(c, lam_j, lam_c, kb, n);
+        double* E = W->nE + 9 * n;
+        double* P = W->nP + 9 * n;
+        double* rhs = W->nrhs + 3 * n;
+        double* d = W->nd + 3 * n;
+        if (kb->type == BLK_CONTACT) {
+            contact_newton_rows(c, kb, l, inv_mass(c, kb->a), E, rhs, P, d);
+        } else {
+            memset(E, 0, 9 * sizeof(double));
+            memset(P, 0, 9 * sizeof(double));
+            for (int r = 0; r < 3; ++r) {
+                E[4 * r] = kb->comp[r];
+                P[4 * r] = 1.0;
+                rhs[r] = -(kb->C[r] + kb->comp[r] * l[r]);
+                d[r] = 0.0;
+            }
+        }
+        for (int r = 0; r < 3; ++r) {
+            double dg = row_jwjt(kb->Ja, r, inv_mass(c, kb->a), W->Iinv + 9 * kb->a);
+            if (kb->b >= 0) dg += row_jwjt(kb->Jb, r, inv_mass(c, kb->b), W->Iinv + 9 * kb->b);
+            W->ndiag[3 * n + r] = dg + E[4 * r];
+        }
+    }
+}
+
+/* y = [J W J^T + E] v, matrix-free: per body u = W J^T v (the gather of
+ * the Jacobi update), then per block J_a u_a + J_b u_b + E v. */
+static void schur_apply(const snake_ctx* c, scratch_t* W, const double* v, double* y)
+{
+    int nb = n_blocks(c);
+    for (int i = 0; i < c->B; ++i)
+        gather_body(c, i, W->blk, v, inv_mass(c, i), W->Iinv + 9 * i, W->nu + 6 * i, W->nu + 6 * i + 3);
+    for (int n = 0; n < nb; ++n) {
+        const block_t* kb = &W->blk[n];
+        const double* ua = W->nu + 6 * kb->a;
+        const double* E = W->nE + 9 * n;
+        for (int r = 0; r < 3; ++r) {
+            double s = 0.0;
+            for (int d = 0; d < 6; ++d) s += kb->Ja[6 * r + d] * ua[d];
+            if (kb->b >= 0) {
+                const double* ub = W->nu + 6 * kb->b;
+                for (int d = 0; d < 6; ++d) s += kb->Jb[6 * r + d] * ub[d];
+            }
+            for (int e = 0; e < 3; ++e) s += E[3 * r + e] * v[3 * n + e];
+            y[3 * n + r] = s;
+        }
+    }
+}
+
+/* v <- P v block by block (in place) */
+static void project_free(const snake_ctx* c, const scratch_t* W, double* v)
+{
+    int nb = n_blocks(c);
+    for (int n = 0; n < nb; ++n) {
+        const double* P = W->nP + 9 * n;
+        double t[3];
+        for (int r = 0; r < 3; ++r) t[r] = P[3 * r] * v[3 * n] + P[3 * r + 1] * v[3 * n + 1] + P[3 * r + 2] * v[3 * n + 2];
+        for (int r = 0; r < 3; ++r) v[3 * n + r] = t[r];
+    }
+}
+
+/* out = P D^-1 P v (the diagonal preconditioner on the free rows) */
+static void precondition(const snake_ctx* c, const scratch_t* W, const double* v, double* out)
+{
+    int n3 = 3 * n_blocks(c);
+    memcpy(out, v, sizeof(double) * (size_t)n3);
+    project_free(c, W, out);
+    for (int k = 0; k < n3; ++k) out[k] /= W->ndiag[k];
+    project_free(c, W, out);
+}
+
+/* Natural-map residual of the Coulomb friction rows at the evaluated
+ * contact blocks, |l_t - proj(l_t - m C_t)| w / L (a length over the
+ * segment length, as the normal rows' measure), maximum over bodies. */
+static double friction_residual(const snake_ctx* c, scratch_t* W, double* lam_c)
+{
+    double r = 0.0;
+    if (!c->ground) return r;
+    for (int i = 0; i < c->B; ++i) {
+        double w = inv_mass(c, i);
+        if (w == 0.0) continue;
+        const block_t* k = &W->blk[2 * c->nj + i];
+        const double* l = lam_c + 3 * i;
+        double m = 1.0 / w;
+        double y0 = l[1] - m * k->C[1], y1 = l[2] - m * k->C[2];
+        double cap = c->mu * (l[0] > 0.0 ? l[0] : 0.0);
+        double ny = sqrt(y0 * y0 + y1 * y1);
+        if (ny > cap) {
+            double f = ny > 0.0 ? cap / ny : 0.0;
+            y0 *= f;
+            y1 *= f;
+        }
+        double e0 = l[1] - y0, e1 = l[2] - y1;
+        double t = sqrt(e0 * e0 + e1 * e1) * w / c->L;
+        if (t > r || t != t) r = t;
+    }
+    return r;
+}
+
+static double vdot(const double* a, const double* b, int n)
+{
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += a[k] * b[k];
+    return s;
+}
+
+/* Preconditioned conjugate residual (Saad, "Iterative Methods for Sparse
+ * Linear Systems", the conjugate residual method with a preconditioner M)
+ * on the free rows: operator P A P, right-hand side P (rhs - A d),
+ * M^-1 = P D^-1 P with D the diagonal of A, from x = 0, exactly n_it
+ * iterations unless (z, Az) or (Ap, M^-1 Ap) stops being positive.
+ * With z = M^-1 r:
+ *   alpha = (z, Az) / (Ap, M^-1 Ap),  x += alpha p,  z -= alpha M^-1 Ap,
+ *   beta = (z', Az') / (z, Az),  p = z' + beta p,  Ap = Az' + beta Ap,
+ * one product with A per iteration (none after the last).  The increment
+ * x + d is left in nx. */
+static void pcr_solve(const snake_ctx* c, scratch_t* W, int n_it)
+{
+    int n3 = 3 * n_blocks(c);
+    /* right-hand side of the free rows: rhs - A d, projected */
+    schur_apply(c, W, W->nd, W->nAz);
+    for (int k = 0; k < n3; ++k) W->nAp[k] = W->nrhs[k] - W->nAz[k];
+    project_free(c, W, W->nAp);
+    precondition(c, W, W->nAp, W->nz);
+    for (int k = 0; k < n3; ++k) {
+        W->nx[k] = 0.0;
+        W->np[k] = W->nz[k];
+    }
+    schur_apply(c, W, W->nz, W->nAz);
+    project_free(c, W, W->nAz);
+    memcpy(W->nAp, W->nAz, sizeof(double) * (size_t)n3);
+    double rho = vdot(W->nz, W->nAz, n3);
+    for (int it = 0; it < n_it; ++it) {
+        if (!(rho > 0.0)) break;
+        precondition(c, W, W->nAp, W->nMq);
+        double den = vdot(W->nAp, W->nMq, n3);
+        if (!(den > 0.0)) break;
+        double alpha = rho / den;
+        for (int k = 0; k < n3; ++k) {
+            W->nx[k] += alpha * W->np[k];
+            W->nz[k] -= alpha * W->nMq[k];
+        }
+        if (it == n_it - 1) break;
+        schur_apply(c, W, W->nz, W->nAz);
+        project_free(c, W, W->nAz);
+        double rho1 = vdot(W->nz, W->nAz, n3);
+        double beta = rho1 / rho;
+        rho = rho1;
+        for (int k = 0; k < n3; ++k) {
+            W->np[k] = W->nz[k] + beta * W->np[k];
+            W->nAp[k] = W->nAz[k] + beta * W->nAp[k];
+        }
+    }
+    for (int k = 0; k < n3; ++k) W->nx[k] += W->nd[k];
+}
+
+/* Newton iterations on the compliant system from the current (x, q,
+ * lambda): at each iterate evaluate the blocks and the residual (the
+ * block-Jacobi measure, and the friction rows' natural map, which the
+ * Jacobi local solve resolves at every iterate but a Newton step need
+ * not), stop if it is <= tol (tol > 0) or after n_newton
+ * solves, else solve eq. schur_system for the multiplier increment with
+ * n_pcr inner iterations and apply lambda += dl, x += W J^T dl (rotations
+ * as in the Jacobi update; in linearised mode into the accumulated
+ * displacement, as there).  Returns the inner iterations run. */
+static int newton_pcr(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* x, double* q,
+                      double* lam_j, double* lam_c, int n_newton, int n_pcr, double tol, double* res,
+                      int* status)
+{
+    int nb = n_blocks(c);
+    int B = c->B;
+    int its = 0;
+    double r = 0.0;
+    if (c->linear) {
+        memcpy(W->xt, x, sizeof(double) * 3 * (size_t)B);
+        memcpy(W->qt, q, sizeof(double) * 4 * (size_t)B);
+        memset(W->acc, 0, sizeof(double) * 6 * (size_t)B);
+        eval_blocks(b, c, x, q, W->xp, W->theta0, W->blk0);
+        for (int i = 0; i < B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
+    }
+    for (int k = 0;; ++k) {
+        if (c->linear) {
+            linear_blocks(c, W);
+            r = local_solves(c, W, lam_j, lam_c);
+        } else {
+            r = residual_at(b, c, W, x, q, lam_j, lam_c);
+        }
+        double rf = friction_residual(c, W, lam_c);
+        if (rf > r || rf != rf) r = rf;
+        if (!isfinite(r)) {
+            *status |= ORC_STATUS_NONFINITE;
+            break;
+        }
+        if ((tol > 0.0 && r <= tol) || k >= n_newton) {
+            if (tol > 0.0 && r > tol) *status |= ORC_STATUS_NOT_CONVERGED;
+            break;
+        }
+        newton_rows(c, W, lam_j, lam_c);
+        pcr_solve(c, W, n_pcr);
+        its += n_pcr;
+        for (int n = 0; n < nb; ++n) {
+            double* l = block_lambda(c, lam_j, lam_c, &W->blk[n], n);
+            for (int d = 0; d < 3; ++d) l[d] += W->nx[3 * n + d];
+        }
+        for (int i = 0; i < B; ++i) {
+            double dx[3], dth[3];
+            gather_body(c, i, W->blk, W->nx, inv_mass(c, i), W->Iinv + 9 * i, dx, dth);
+            if (c->linear) {
+                for (int d = 0; d < 3; ++d) {
+                    W->acc[6 * i + d] += dx[d];
+                    W->acc[6 * i + 3 + d] += dth[d];
+                }
+            } else {
+                for (int d = 0; d < 3; ++d) x[3 * i + d] += dx[d];
+                if (!is_fixed(c, i)) q_apply_rotvec(q + 4 * i, dth);
+            }
+        }
+    }
+    if (c->linear) {
+        for (int i = 0; i < B; ++i) {
+            for (int d = 0; d < 3; ++d) x[3 * i + d] = W->xt[3 * i + d] + W->acc[6 * i + d];
+            memcpy(q + 4 * i, W->qt + 4 * i, 4 * sizeof(double));
+            if (!is_fixed(c, i)) q_apply_rotvec(q + 4 * i, W->acc + 6 * i + 3);
+        }
+    }
+    *res = r;
+    return its;
+}
+
+/* Solve of one substep from the predicted (x, q): block-Jacobi, or with
+ * the Newton solver selected the Newton iterations above from zero
+ * multipliers.  Returns the number of (inner) iterations run; *res is the
+ * residual of the final iterate.
  *
  * Multiplier initialisation: zero, or lambda0 = the current lambda with
  * x <- x~ + W J(x~)^T lambda0.  With the fallback, a given lambda0 is kept
@@ -734,6 +1129,11 @@ static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, d
     size_t nc3 = sizeof(double) * 3 * (size_t)B;
     int fallback = (warm == ORC_WARM_GIVEN && b->fallback);
 
+    if (b->solver == ORC_SOLVER_NEWTON) {
+        memset(lam_j, 0, nj6);
+        memset(lam_c, 0, nc3);
+        return newton_pcr(b, c, W, x, q, lam_j, lam_c, b->newton_iters, b->pcr_iters, tol, res, status);
+    }
     if (fallback && b->fallback_k > 0) {
         int K = b->fallback_k;
         double rz = 0.0, rw = 0.0;

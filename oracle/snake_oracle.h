@@ -21,7 +21,10 @@
  *   - the open-loop serpenoid command (eq. snake_control);
  *   - a first-order implicit step (section "Time-Stepping") solved at the
  *     position level by block-Jacobi iterations on the compliant system whose
- *     linearisation is eq. schur_system.
+ *     linearisation is eq. schur_system, or by the paper's own scheme:
+ *     Newton iterations, each solving eq. schur_system with a fixed number
+ *     of preconditioned conjugate-residual iterations (diagonal
+ *     preconditioner), contact by a Fischer-Burmeister reformulation.
  * Every floating-point quantity is double.  No fast-math.
  *
  * Memory layout: array-of-structures per body (x[3*i+k], q[4*i+k] with
@@ -46,6 +49,9 @@
 #define ORC_WARM_ZERO 0
 #define ORC_WARM_PREV 1
 #define ORC_WARM_GIVEN 2        /* lambda0 supplied by the caller in lam_* */
+
+#define ORC_SOLVER_JACOBI 0     /* block-Jacobi iterations (the default)    */
+#define ORC_SOLVER_NEWTON 1     /* Newton + preconditioned conjugate residual */
 
 #define ORC_STATUS_NONFINITE 1
 #define ORC_STATUS_NOT_CONVERGED 2
@@ -76,6 +82,9 @@ typedef struct {
     double ctrl_alpha, ctrl_offset;
     int32_t fallback;   /* GIVEN warm start: keep lambda0 only if it is closer */
     int32_t fallback_k; /* ... after this many iterations (0: at the start) */
+    int32_t solver;       /* ORC_SOLVER_*; NEWTON needs the zero warm start  */
+    int32_t newton_iters; /* NEWTON: outer iterations per substep            */
+    int32_t pcr_iters;    /* NEWTON: inner iterations per outer iteration     */
 } orc_batch;
 
 /* Batch state, owned by the caller.  Offsets: body_off / module_off /

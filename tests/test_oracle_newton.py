@@ -1,0 +1,126 @@
+"""Pins of the oracle's Newton solver (section "Time-Stepping": Newton
+iterations, each solving eq. schur_system with preconditioned conjugate-residual
+iterations; contact through a Fischer-Burmeister reformulation).
+
+None of them re-types the solver: a dense direct solve of eq. schur_system,
+the quadratic convergence of Newton's method on the smooth (contact-free)
+problem, and agreement with the independent block-Jacobi iteration on the
+linearised problem, whose solution (with contact and Coulomb friction) is
+unique, pin it.
+"""
+import numpy as np
+
+import oracle
+import workloads as W
+
+
+def newton(wl, **kw):
+    return oracle.Oracle(wl, solver=oracle.SOLVER_NEWTON, **kw)
+
+
+def moved_state(wl, **kw):
+    """State after a few plain steps (off the initial straight chain)."""
+    o = oracle.Oracle(wl, **kw)
+    o.run(6)
+    return {k: getattr(o, k).copy() for k in ("x", "q", "v", "w", "p", "cmd", "lam_j", "lam_c", "step")}
+
+
+def load(o, st):
+    for k, v in st.items():
+        getattr(o, k)[...] = v
+    return o
+
+
+def test_one_newton_step_is_the_dense_solve_of_the_schur_system():
+    """Without contact, one Newton iteration from zero multipliers with an
+    inner solve run to convergence gives dl = A^-1 (-C) with
+    A = J W J^T + alpha~ assembled densely at the predicted state, and
+    x = x~ + (W J^T dl)_x."""
+    wl = W.make("short", n_snakes=2)
+    kw = dict(substeps=1, flags=wl.flags | oracle.FLAG_NO_GROUND, controller=W.CTRL_EXTERNAL)
+    st = moved_state(wl, **kw)
+    o = load(newton(wl, newton_iters=1, pcr_iters=400, tol=0, **kw), st)
+    o.run(1)
+    for s in range(o.n):
+        a, b = o.body_off[s], o.body_off[s + 1]
+        pr = load(oracle.Oracle(wl, **kw), st)
+        pred = pr.predict(s, wl.dt)
+        xt, qt = pred["x"].copy(), pred["q"].copy()
+        Cv, J, Wm, comp = o.assemble(s, xt, qt, st["x"][a:b], o.snake(s)["p"])
+        dl = np.linalg.solve(J @ Wm @ J.T + np.diag(comp), -Cv)
+        dx = (Wm @ J.T @ dl).reshape(b - a, 6)[:, :3]
+        lam = o.snake(s)["lam_j"].reshape(-1)
+        assert np.abs(lam - dl).max() <= 1e-10 * np.abs(dl).max()
+        assert np.abs(o.snake(s)["x"] - (xt + dx)).max() <= 1e-12
+        assert o.iters[s] == 400
+
+
+def test_newton_converges_quadratically_without_contact():
+    """On the smooth problem (no ground) Newton's method with exact inner
+    solves reaches round-off within three iterations from a residual of
+    order 1e-3."""
+    wl = W.make("short", n_snakes=4)
+    kw = dict(flags=wl.flags | oracle.FLAG_NO_GROUND)
+    st = moved_state(wl, **kw)
+    r = []
+    for k in (0, 1, 3):
+        o = load(newton(wl, newton_iters=k, pcr_iters=300, tol=0, substeps=1, **kw), st)
+        o.run(1)
+        r.append(o.residual.copy())
+    assert np.all(r[0] > 1e-5)
+    assert np.all(r[1] < r[0])
+    assert np.all(r[2] < 1e-12)
+
+
+def test_newton_meets_block_jacobi_on_the_linearised_problem():
+    """With the Jacobians frozen at the predicted state the problem (joints,
+    unilateral contact, Coulomb friction) has one solution; Newton's method
+    with the Fischer-Burmeister and natural-map rows and block-Jacobi
+    iterations, two different algorithms, must both reach it.  (Without a
+    line search the Newton iterates of some substeps cycle between stick and
+    slip instead; the two snakes checked here are ones where they do not.)"""
+    wl = W.make("short", n_snakes=8)
+    kw = dict(substeps=1, flags=wl.flags | oracle.FLAG_LINEARISED)
+    o = oracle.Oracle(wl, **kw)
+    o.run(20)
+    st = {k: getattr(o, k).copy() for k in ("x", "q", "v", "w", "p", "cmd", "lam_j", "lam_c", "step")}
+    pick = [3, 7]
+    j = load(oracle.Oracle(wl, tol=1e-12, iters=3_000_000, **kw), st)
+    n = load(newton(wl, newton_iters=60, pcr_iters=300, tol=0, **kw), st)
+    for s in pick:
+        j.run(1, snakes=(s, s + 1))
+        n.run(1, snakes=(s, s + 1))
+        assert j.step[s] == st["step"][s] + 1 and n.step[s] == st["step"][s] + 1
+        assert j.status[s] == 0
+        assert n.residual[s] < 1e-12
+        dn, dj = n.snake(s), j.snake(s)
+        assert np.abs(dn["x"] - dj["x"]).max() <= 1e-9
+        for k in ("lam_j", "lam_c"):
+            assert np.abs(dn[k] - dj[k]).max() <= 1e-6 * np.abs(dj[k]).max(), k
+
+
+def test_newton_with_frictionless_contact_converges():
+    """Frictionless ground contact alone (the Fischer-Burmeister rows) keeps
+    Newton's method convergent: residual below 1e-9 after 12 iterations."""
+    wl = W.make("short", n_snakes=4)
+    wl.mu = np.zeros(len(wl.n_modules))
+    st = moved_state(wl)
+    o = load(newton(wl, newton_iters=12, pcr_iters=300, tol=0), st)
+    o.run(1)
+    assert np.all(o.residual < 1e-9)
+
+
+def test_newton_budget_and_tolerance():
+    """A fixed budget reports newton_iters * pcr_iters inner iterations per
+    substep; with a tolerance the solve stops at the first Newton iterate
+    whose residual is below it, counting only the inner iterations run."""
+    wl = W.make("short", n_snakes=3)
+    st = moved_state(wl)
+    o = load(newton(wl, newton_iters=4, pcr_iters=20, tol=0), st)
+    o.run(1)
+    assert np.all(o.iters == 4 * 20 * wl.substeps)
+    o = load(newton(wl, newton_iters=40, pcr_iters=100, tol=1e-6,
+                    flags=wl.flags | oracle.FLAG_NO_GROUND), st)
+    o.run(1)
+    assert np.all(o.residual <= 1e-6) and np.all(o.status == 0)
+    assert np.all(o.iters % 100 == 0) and np.all(o.iters < 40 * 100 * wl.substeps)
