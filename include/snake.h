@@ -84,6 +84,22 @@ extern "C" {
                         /* used wherever it has the smaller residual after    */
                         /* mlp_fallback_k iterations (0: at the start)        */
 
+/* ---- solver of the implicit step (section "Time-Stepping") ---- */
+#define SIM_SOLVER_JACOBI 0 /* block-Jacobi iterations on the compliant      */
+                            /* system (iters, tol, relax, warm_start)        */
+#define SIM_SOLVER_NEWTON 1 /* the paper's scheme: newton_iters Newton       */
+                            /* iterations, each solving eq. schur_system     */
+                            /* [J W J^T + E] dl = b with pcr_iters           */
+                            /* preconditioned conjugate-residual iterations  */
+                            /* (diagonal preconditioner); normal contact by  */
+                            /* the Fischer-Burmeister function, friction by  */
+                            /* the natural map onto the Coulomb disc.  Stops */
+                            /* early at a Newton iterate with residual <= tol*/
+                            /* (tol > 0); the residual adds the friction     */
+                            /* rows' natural map to the Jacobi measure.      */
+                            /* Computes in double.  Needs SIM_WARM_ZERO; no  */
+                            /* split substeps (sim_step_record).             */
+
 /* ---- flags ---- */
 #define SIM_FLAG_FIXED_ROOT 1u /* body 0 of every snake is immovable         */
 #define SIM_FLAG_NO_GROUND 2u  /* no ground plane: no contact blocks         */
@@ -184,6 +200,12 @@ typedef struct sim_desc {
                                /* solve continues from the winner's iterate  */
                                /* k, and the other start's k iterations      */
                                /* count in SIM_F_ITERS.                      */
+    int32_t solver;            /* SIM_SOLVER_* (0: Jacobi)                  */
+    int32_t newton_iters;      /* NEWTON: Newton iterations per substep,    */
+                               /* [0, 10000]                                */
+    int32_t pcr_iters;         /* NEWTON: inner iterations per Newton       */
+                               /* iteration, [1, 100000]; SIM_F_ITERS counts */
+                               /* these                                     */
 } sim_desc_t;
 
 typedef struct sim sim_t;

@@ -898,7 +898,10 @@ static void newton_rows(const snake_ctx* c, scratch_t* W, double* lam_j, double*
         for (int r = 0; r < 3; ++r) {
             double dg = row_jwjt(kb->Ja, r, inv_mass(c, kb->a), W->Iinv + 9 * kb->a);
             if (kb->b >= 0) dg += row_jwjt(kb->Jb, r, inv_mass(c, kb->b), W->Iinv + 9 * kb->b);
-            W->ndiag[3 * n + r] = dg + E[4 * r];
+            /* zero only on the rows of a body of infinite mass, which are
+             * fixed (projected out); 1 keeps the division finite there */
+            double v = dg + E[4 * r];
+            W->ndiag[3 * n + r] = v > 0.0 ? v : 1.0;
         }
     }
 }

@@ -20,6 +20,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 LAW_LAG, LAW_PAPER = 0, 1
 CTRL_EXTERNAL, CTRL_SERPENOID, CTRL_SCHEDULE = 0, 1, 2
 WARM_ZERO, WARM_PREV, WARM_MLP = 0, 1, 2
+SOLVER_JACOBI, SOLVER_NEWTON = 0, 1
 FLAG_FIXED_ROOT, FLAG_NO_GROUND = 1, 2
 STATUS_NONFINITE, STATUS_NOT_CONVERGED, STATUS_FELL_BACK = 1, 2, 4
 
@@ -69,7 +70,8 @@ class Desc(C.Structure):
         ("warm_start", C.c_int32), ("flags", C.c_uint32), ("use_graph", C.c_int32),
         ("autotune", C.c_int32), ("map_waves", C.c_int32), ("map_min_seg", C.c_int32),
         ("map_grid", C.c_int32), ("mlp_fallback", C.c_int32), ("map_rows", C.c_int32),
-        ("mlp_fallback_k", C.c_int32),
+        ("mlp_fallback_k", C.c_int32), ("solver", C.c_int32), ("newton_iters", C.c_int32),
+        ("pcr_iters", C.c_int32),
     ]
 
 
@@ -158,6 +160,9 @@ def make_desc(wl, **over):
     d.mlp_fallback = int(over.get("mlp_fallback", 1))
     d.map_rows = int(over.get("map_rows", 0))
     d.mlp_fallback_k = int(over.get("mlp_fallback_k", 0))
+    d.solver = int(over.get("solver", getattr(wl, "solver", SOLVER_JACOBI)))
+    d.newton_iters = int(over.get("newton_iters", getattr(wl, "newton_iters", 4)))
+    d.pcr_iters = int(over.get("pcr_iters", getattr(wl, "pcr_iters", 20)))
     return d, keep
 
 

@@ -36,6 +36,7 @@ struct Sizes {
     int max_B = 0;
     bool autotune = false;
     bool mlp = false;
+    bool newton = false;
 };
 
 // Carves 256-byte aligned sub-arrays out of the workspace (base == nullptr
@@ -110,6 +111,15 @@ int validate(const sim_desc_t* d, Sizes* z)
     if (d->map_rows != 0 && d->map_rows != 1) return fail(SIM_EINVAL, "map_rows must be 0 or 1");
     if (d->mlp_fallback_k < 0 || d->mlp_fallback_k > d->iters)
         return fail(SIM_EINVAL, "mlp_fallback_k must be in [0, iters]");
+    if (d->solver != SIM_SOLVER_JACOBI && d->solver != SIM_SOLVER_NEWTON)
+        return fail(SIM_EINVAL, "unknown solver");
+    if (d->solver == SIM_SOLVER_NEWTON) {
+        if (d->warm_start != SIM_WARM_ZERO) return fail(SIM_EINVAL, "the Newton solver starts from zero multipliers");
+        if (d->newton_iters < 0 || d->newton_iters > 10000)
+            return fail(SIM_EINVAL, "newton_iters must be in [0, 10000]");
+        if (d->pcr_iters < 1 || d->pcr_iters > 100000) return fail(SIM_EINVAL, "pcr_iters must be in [1, 100000]");
+    }
+    z->newton = d->solver == SIM_SOLVER_NEWTON;
     if (mw != 0 && !d->autotune) {
         int seg = 16;
         while (seg < z->max_B) seg <<= 1;
@@ -146,6 +156,9 @@ struct Views {
     char* state_begin;      // the mutable state is one contiguous range
     size_t state_bytes;
     char* backup;           // copy of the state while autotuning
+    NParams np;
+    int* newton_list;       // [n] snakes by lane class (Newton solver)
+    double* comp_d;         // [4][n] compliances / h^2 and mu in double
     float* feat;            // [2J][32] network inputs (learned warm start)
     float* mlp_y;           // [2J][3] network outputs
     float* mlp_params;      // [6467]
@@ -211,6 +224,8 @@ size_t carve(const Sizes& z, char* base, Views* v)
     v->mlp_y = z.mlp ? c.take<float>(6 * J) : nullptr;
     v->mlp_params = z.mlp ? c.take<float>(8192) : nullptr;
     v->mlp_ms = z.mlp ? c.take<float>(64) : nullptr;
+    v->newton_list = z.newton ? c.take<int>(n) : nullptr;
+    v->comp_d = z.newton ? c.take<double>(4 * n) : nullptr;
     v->hdr = c.take<int4>(n + 1);
     v->slots = c.take<int2>(n + 1);
     v->backup = z.autotune ? c.take<char>((int64_t)v->state_bytes) : nullptr;
@@ -313,6 +328,7 @@ struct sim {
     std::map<int, hipGraphExec_t> graphs;
     std::vector<int> order_host;
     std::vector<int> B_host;
+    int newton_off[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // lane classes 16 << c
 };
 
 namespace {
@@ -368,6 +384,11 @@ int split_substep(sim* s, hipStream_t st, int sub, float* feat, float* tgt)
 
 int launch_steps(sim* s, hipStream_t st, int n_steps)
 {
+    if (s->z.newton) {
+        hipError_t e = launch_newton(s->v.kp, s->v.np, s->v.newton_list, s->newton_off, n_steps, st);
+        if (e != hipSuccess) return hip_fail(e, "Newton step launch");
+        return SIM_OK;
+    }
     if (!s->z.mlp) return tiles(s, st, n_steps, kPhaseFull, 0);
     for (int k = 0; k < n_steps; ++k)
         for (int sub = 0; sub < s->v.kp.substeps; ++sub) {
@@ -591,6 +612,27 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     k.flags = (int)d->flags;
     k.warm = d->warm_start;
     k.lam_ref = (float)(m * 9.81 * h * h);
+    NParams& np = w.np;
+    np.comp = w.comp_d;
+    np.mu = w.comp_d ? w.comp_d + 3 * (size_t)n : nullptr;
+    np.h = h;
+    np.m = m;
+    np.L = L;
+    np.R = R;
+    np.g = d->gravity;
+    np.I_ax = I_ax;
+    np.I_pe = I_pe;
+    np.tol = d->tol;
+    np.lag_in = d->pressure_law == SIM_LAW_LAG ? std::exp(-h / d->tau_inflate) : 0.0;
+    np.lag_de = d->pressure_law == SIM_LAW_LAG ? std::exp(-h / d->tau_deflate) : 0.0;
+    np.amp = d->pressure_law == SIM_LAW_PAPER ? d->amplitude_psi : 1.0;
+    np.p_s = d->p_source;
+    np.k_i = d->k_inflate;
+    np.k_d = d->k_deflate;
+    np.T_p = d->T_p;
+    np.kappa_max = d->kappa_max;
+    np.newton_iters = d->newton_iters;
+    np.pcr_iters = d->pcr_iters;
 
     IParams& ip = w.ip;
     ip.n_snakes = n;
@@ -620,6 +662,30 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     CK(hipMemcpyAsync(w.sched_off, soff.data(), soff.size() * sizeof(int), hipMemcpyHostToDevice, st), "upload schedule");
     CK(hipMemcpyAsync(w.sched_start, sstart.data(), sstart.size() * sizeof(int), hipMemcpyHostToDevice, st), "upload schedule");
     CK(hipMemcpyAsync(w.sched_val, sval.data(), sval.size() * sizeof(float), hipMemcpyHostToDevice, st), "upload schedule");
+    if (z.newton) {
+        // snakes grouped by lane class (power of two >= B, at least 16)
+        std::vector<double> cd(4 * (size_t)n);
+        std::vector<int> cls(n), list;
+        for (int q = 0; q < n; ++q) {
+            cd[q] = d->alpha_stretch[q] * d->seg_length / (h * h);
+            cd[n + q] = d->alpha_bend[q] * d->seg_length / (h * h);
+            cd[2 * (size_t)n + q] = d->alpha_twist[q] * d->seg_length / (h * h);
+            cd[3 * (size_t)n + q] = d->mu[q];
+            int c = 0;
+            while ((16 << c) < Bn[q]) ++c;
+            cls[q] = c;
+        }
+        for (int c = 0; c < 7; ++c) {
+            s->newton_off[c] = (int)list.size();
+            for (int q = 0; q < n; ++q)
+                if (cls[q] == c) list.push_back(q);
+        }
+        s->newton_off[7] = (int)list.size();
+        CK(hipMemcpyAsync(w.comp_d, cd.data(), cd.size() * sizeof(double), hipMemcpyHostToDevice, st),
+           "upload compliance");
+        CK(hipMemcpyAsync(w.newton_list, list.data(), n * sizeof(int), hipMemcpyHostToDevice, st),
+           "upload snake classes");
+    }
     if (z.mlp) {
         CK(hipMemsetAsync(w.mlp_params, 0, 8192 * sizeof(float), st), "zero network");
         CK(hipMemsetAsync(w.mlp_ms, 0, 32 * sizeof(float), st), "zero network");
@@ -638,7 +704,7 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     }
     CK(launch_init_state(k, st), "init state");
     CK(hipStreamSynchronize(st), "init state");
-    if (z.autotune) {
+    if (z.autotune && !z.newton) {
         rc = autotune(s);
         if (rc) goto error;
     } else {
@@ -794,6 +860,7 @@ int sim_step_record(sim_t* s, int32_t n_steps, float* features, float* targets, 
     if (!s || !features || !targets) return fail(SIM_EINVAL, "sim, features or targets is NULL");
     if (n_steps < 0) return fail(SIM_EINVAL, "n_steps must be >= 0");
     if (s->z.mlp && !s->mlp_loaded) return fail(SIM_ESTATE, "learned warm start needs sim_set_mlp first");
+    if (s->z.newton) return fail(SIM_EINVAL, "recording needs the Jacobi solver");
     const int64_t per_sub = 2 * s->z.J;
     const int64_t rows = per_sub * s->v.kp.substeps * (int64_t)n_steps;
     if (written) *written = rows;

@@ -67,6 +67,18 @@ struct KParams {
     float lam_ref;          // multiplier scale m 9.81 h^2 of the network units
 };
 
+// Constants of the Newton solver kernel, which computes in double: the
+// body constants again at full precision, per-snake compliances / h^2 and
+// the iteration budget.
+struct NParams {
+    const double* comp;     // [3][n]: stretch, bend, twist compliance / h^2
+    const double* mu;       // [n]
+    double h, m, L, R, g, I_ax, I_pe, tol;
+    double lag_in, lag_de;  // exp(-h / tau)
+    double amp, p_s, k_i, k_d, T_p, kappa_max;
+    int newton_iters, pcr_iters;
+};
+
 // Index-work parameters.
 struct IParams {
     int n_snakes, N, n_blocks, ground;
@@ -93,6 +105,11 @@ struct IParams {
 // slot = {snake, lane offset << 16 | segment lanes}.
 hipError_t launch_tiles(int nw, int rows, const KParams& P, const int4* hdr, const int2* slots,
                         int n_tiles, int grid, int n_steps, int phase, int sub, hipStream_t stream);
+// Newton solver: one launch per class of snakes whose lane count (the
+// power of two >= B, at least 16) is 16 << c; list holds the snakes class by
+// class, class c at [off[c], off[c+1]).  Runs n_steps whole steps.
+hipError_t launch_newton(const KParams& P, const NParams& Q, const int* list, const int* off,
+                         int n_steps, hipStream_t stream);
 hipError_t launch_features(const KParams& P, float* feat, hipStream_t stream);
 hipError_t launch_targets(const KParams& P, float* tgt, hipStream_t stream);
 hipError_t launch_index(const IParams& P, hipStream_t stream);

@@ -121,6 +121,26 @@ def test_descriptor_validation(L, field, value, msg):
     assert msg in err
 
 
+@pytest.mark.parametrize("over,msg", [
+    (dict(solver=2), "solver"),
+    (dict(solver=1, warm_start=1), "zero multipliers"),
+    (dict(solver=1, newton_iters=-1), "newton_iters"),
+    (dict(solver=1, newton_iters=10001), "newton_iters"),
+    (dict(solver=1, pcr_iters=0), "pcr_iters"),
+])
+def test_newton_descriptor_validation(L, over, msg):
+    rc, _, err = ws_bytes(L, W.custom([2, 2], 8), **over)
+    assert rc == snk.SIM_EINVAL
+    assert msg in err
+
+
+def test_newton_workspace_adds_its_arrays(L):
+    wl = W.make("uneven", n_snakes=40)
+    rc0, b0, _ = ws_bytes(L, wl)
+    rc1, b1, _ = ws_bytes(L, wl, solver=1, newton_iters=4, pcr_iters=20)
+    assert rc0 == rc1 == 0 and b1 > b0
+
+
 def test_schedule_validation(L):
     wl = W.custom([1, 1], 8, controller=W.CTRL_SCHEDULE)
     wl.sched_off = np.array([0, 1, 1], np.int32)     # second module has no piece

@@ -1,0 +1,115 @@
+"""GPU parity of the Newton solver (section "Time-Stepping": Newton
+iterations, each solving eq. schur_system with preconditioned
+conjugate-residual iterations) against the FP64 oracle's Newton solver.
+
+Both sides compute in double from the same FP32-rounded state and differ
+by summation order only; the GPU then rounds its result to its FP32 state
+arrays (relative 6e-8).  The bound, 1e-6 on positions and multipliers (in
+the parity helpers' relative measures), leaves room for the inner solve to
+amplify the summation-order differences a few times.  Lane classes: 16 to
+256 lanes (uneven and short batches), 1024 lanes (workgroups of 16 waves
+joined through LDS)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from parity import advance_both, compare, rounded_state
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+snk = pytest.importorskip("paper_1904_02833_amd")
+
+NEWTON = dict(solver=snk.SOLVER_NEWTON, newton_iters=4, pcr_iters=20)
+TOL = 1e-6
+
+
+def state_after(wl, steps, **over):
+    o = oracle.Oracle(wl, **over)
+    o.run(steps, threads=8)
+    o.commands()
+    return rounded_state(o)
+
+
+def check(o, g, wl, label, strict_branch=True):
+    err = compare(o, g, np.asarray(wl.mu, np.float64))
+    worst = {k: float(err[k].max()) for k in ("pos", "lam_s", "lam_b", "lam_n", "lam_t")}
+    print(f"\n[{label}] worst {worst} branch mismatches {int(err['branch'].sum())}")
+    assert np.array_equal(np.asarray(g["iters"]), o.iters), "iteration counts differ"
+    assert np.array_equal(np.asarray(g["status"]), o.status), "status bits differ"
+    for k in ("pos", "lam_s", "lam_b", "lam_n", "lam_t"):
+        assert err[k].max() <= TOL, k
+    if strict_branch:
+        assert err["branch"].sum() == 0
+
+
+@pytest.mark.parametrize("name,n,steps", [("short", 48, 8), ("uneven", 40, 12), ("uniform", 12, 12)])
+def test_newton_substep_parity(name, n, steps):
+    wl = W.make(name, n_snakes=n)
+    st = state_after(wl, steps)
+    o, g = advance_both(wl, st, **NEWTON)
+    check(o, g, wl, f"newton substep {name}")
+
+
+def test_newton_step_parity_uneven():
+    """A whole step (four substeps, pressures and commands between them)."""
+    wl = W.make("uneven", n_snakes=24)
+    st = state_after(wl, 10)
+    o, g = advance_both(wl, st, one_substep=False, **NEWTON)
+    check(o, g, wl, "newton step uneven")
+
+
+def test_newton_stiff_1024_lanes():
+    wl = W.make("stiff", n_snakes=2)
+    st = state_after(wl, 3)
+    o, g = advance_both(wl, st, **NEWTON)
+    check(o, g, wl, "newton stiff 1024")
+
+
+def test_newton_tolerance_stop_counts():
+    """With a tolerance the solve stops at the first Newton iterate below it;
+    both sides stop at the same iterate (same inner-iteration counts)."""
+    wl = W.make("short", n_snakes=32)
+    flags = wl.flags | oracle.FLAG_NO_GROUND
+    st = state_after(wl, 6, flags=flags)
+    o, g = advance_both(wl, st, flags=flags, solver=snk.SOLVER_NEWTON, newton_iters=20, pcr_iters=100,
+                        tol=1e-7)
+    assert np.all(o.status == 0)
+    check(o, g, wl, "newton tolerance")
+    assert np.all(o.iters < 20 * 100)
+
+
+def test_newton_fixed_root_and_edge_budgets():
+    """Fixed root (infinite mass, contact rows all fixed), a single inner
+    iteration, and zero Newton iterations (prediction only)."""
+    wl = W.make("short", n_snakes=16)
+    flags = wl.flags | oracle.FLAG_FIXED_ROOT
+    st = state_after(wl, 5, flags=flags)
+    o, g = advance_both(wl, st, flags=flags, **NEWTON)
+    check(o, g, wl, "newton fixed root")
+    for ni, npc in ((1, 1), (0, 20)):
+        o, g = advance_both(wl, st, solver=snk.SOLVER_NEWTON, newton_iters=ni, pcr_iters=npc)
+        check(o, g, wl, f"newton {ni}x{npc}")
+
+
+def test_newton_graph_equals_direct_and_is_deterministic():
+    wl = W.make("uneven", n_snakes=64)
+    out = []
+    for use_graph in (0, 1, 1):
+        sim = snk.Sim(wl, use_graph=use_graph, **NEWTON)
+        sim.step(3)
+        out.append(sim.read("pos", "quat", "lambda_joint", "lambda_contact", "iters_total"))
+        sim.close()
+    for r in out[1:]:
+        for k in out[0]:
+            assert np.array_equal(out[0][k], r[k]), k
+
+
+def test_newton_rejects_recording():
+    wl = W.make("short", n_snakes=4)
+    sim = snk.Sim(wl, **NEWTON)
+    f = torch.empty((1024, 32), device="cuda")
+    t = torch.empty((1024, 3), device="cuda")
+    with pytest.raises(snk.SimError):
+        sim.step_record(1, f, t)
+    sim.close()
