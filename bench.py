@@ -8,8 +8,10 @@ default) and the velocity update.  The state lives in HBM between steps.
 Prints one JSON line: snake-steps/s (value), constraint-iterations/s, the
 dominant kernel's roofline position (measured with HIP events on the
 solver's stream) and the FP64 CPU oracle timed on a bounded sample of the
-same workload on this machine's host cores.  Two comparisons of the learned
-warm start against the zero start ride along: on the uneven batch at the
+same workload on this machine's host cores.  Comparisons ride along: the
+paper's own solver (Newton with a preconditioned conjugate-residual inner
+solve, FP64) against block Jacobi at fixed budgets on the same batch, and the
+learned warm start against the zero start on the uneven batch at the
 headline setting (at most 200 iterations, which no snake's solve reaches
 1e-4 within) and on short snakes whose solve converges within its budget.
 """
@@ -43,6 +45,18 @@ PEAK_FP32 = 157.3e12       # MI355X FP32 vector (published)
 MEASURED_TRAFFIC = {("uniform", 4, 1): 113.7e6, ("uneven", 4, 1): 696.3e6, ("stiff", 16, 1): 123.4e6}
 TRAFFIC_SOURCES_DIGEST = "2d39a34934636883:959545d7849e09a9:ed8d7ecc89e8e002"
 PEAK_HBM = 8.0e12
+# Newton solver (FP64): operations per body per inner conjugate-residual
+# iteration and per Newton iteration outside it (block evaluation, residual,
+# rows, the two initial products, the update), counted from the compiled
+# loops (add, mul = 1, fma = 2, a division or square root once); per body per
+# substep outside the Newton iterations (prediction, final evaluation,
+# velocities).
+FLOP_PCR_ITER = 307
+FLOP_NEWTON_ITER = 1050
+FLOP_NEWTON_SUBSTEP = 450
+PEAK_FP64 = 78.6e12        # MI355X FP64 vector (published)
+# the paper's budget (4 Newton iterations of 20 inner iterations) and two larger ones
+NEWTON_BUDGETS = ((4, 20), (8, 50), (16, 50))
 # learned start kept only where its residual after this many iterations is not
 # larger than the zero start's (both probes' iterations count in the totals)
 FALLBACK_K = 2
@@ -66,6 +80,9 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
     ap.add_argument("--learned-steps", type=int, default=20)
+    ap.add_argument("--no-newton", action="store_true", help="skip the Newton solver comparison")
+    ap.add_argument("--solver", default="jacobi", choices=("jacobi", "newton"),
+                    help="solver of the timed loop (newton: the paper's budget, 4 x 20, FP64)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 256 MiB device copies (scale for the HBM byte counters)")
     return ap.parse_args()
@@ -176,6 +193,61 @@ def learned_converging(n_steps=6):
     return out
 
 
+def newton_comparison(wl, n_steps=5):
+    """The paper's own solver (Newton iterations, each solving the
+    Schur-complement system with preconditioned conjugate-residual
+    iterations, FP64) against block Jacobi (FP32) on the same batch, from the
+    same state (20 plain steps in), at several fixed budgets: time per step
+    and the residual each reaches."""
+    import torch
+
+    import paper_1904_02833_amd as snk
+
+    lead = snk.Sim(wl)
+    lead.step(20)
+    state = lead.read()
+    lead.close()
+    B = wl.bodies.astype(np.float64)
+    rows = []
+
+    def run(label, **kw):
+        sim = snk.Sim(wl, **kw)
+        sim.write(**state)
+        sim.step(1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        for _ in range(n_steps):
+            sim.step(1)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n_steps
+        r = sim.read("residual", "status")
+        sim.close()
+        row = {"solver": label, "ms_per_step": ms, "snake_steps_per_s": wl.n_snakes / (ms / 1e3),
+               "residual_last_step": {"median": float(np.median(r["residual"])),
+                                      "p99": float(np.percentile(r["residual"], 99)),
+                                      "max": float(np.max(r["residual"]))},
+               "nonfinite_snakes": int(np.sum((r["status"] & 1) != 0))}
+        if kw.get("solver") == snk.SOLVER_NEWTON:
+            ni, npc = kw["newton_iters"], kw["pcr_iters"]
+            per_body = wl.substeps * (ni * (FLOP_NEWTON_ITER + npc * FLOP_PCR_ITER) + FLOP_NEWTON_SUBSTEP)
+            ach = float(B.sum()) * per_body / (ms / 1e3)
+            row["roofline"] = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12,
+                               "unit": "TFLOP/s", "frac": ach / PEAK_FP64, "traffic": None,
+                               "kernel": "k_newton<SEG>", "dtype": "f64"}
+        rows.append(row)
+
+    run("jacobi, 200 iterations", tol=0.0, iters=200)
+    run("jacobi, 2000 iterations", tol=0.0, iters=2000)
+    for ni, npc in NEWTON_BUDGETS:
+        run(f"newton, {ni} x {npc} inner iterations", solver=snk.SOLVER_NEWTON, newton_iters=ni, pcr_iters=npc,
+            tol=0.0)
+    return {"workload": f"{wl.name}: {wl.n_snakes} snakes, {int(B.sum())} bodies, {wl.substeps} substeps, "
+                        "fixed budgets from the state after 20 plain steps",
+            "rows": rows}
+
+
 def cpu_baseline(wl, n_snakes, n_steps):
     import oracle
 
@@ -219,7 +291,12 @@ def main():
         wl.tol, wl.iters = 0.0, 20
     else:
         wl.tol, wl.iters = 1e-4, 200
-    if args.mapping:
+    newton = args.solver == "newton"
+    if newton:
+        wl.tol = 0.0
+        ni, npc = NEWTON_BUDGETS[0]
+        sim = snk.Sim(wl, use_graph=1, solver=snk.SOLVER_NEWTON, newton_iters=ni, pcr_iters=npc)
+    elif args.mapping:
         mw, ms, mr = (int(v) for v in args.mapping.split(","))
         sim = snk.Sim(wl, use_graph=1, autotune=0, map_waves=mw, map_min_seg=ms, map_rows=mr)
     else:
@@ -247,11 +324,14 @@ def main():
     snake_steps = wl.n_snakes * args.steps / secs
     citers = float(np.sum(rows * its)) / secs
     flops = float(np.sum(B * (its * FLOP_ITER + args.steps * wl.substeps * (FLOP_EVAL + FLOP_SUBSTEP))))
+    if newton:
+        flops = float(B.sum()) * args.steps * wl.substeps * (
+            ni * (FLOP_NEWTON_ITER + npc * FLOP_PCR_ITER) + FLOP_NEWTON_SUBSTEP)
     per_launch_ms = ms / args.steps
     achieved = flops / args.steps / (per_launch_ms / 1e3)
     hbm_bytes = float(B.sum()) * STATE_BYTES
     traffic = MEASURED_TRAFFIC.get((args.workload, sim.mapping["waves"], sim.mapping["rows"]))
-    if traffic is not None and kernel_digest() != TRAFFIC_SOURCES_DIGEST:
+    if newton or (traffic is not None and kernel_digest() != TRAFFIC_SOURCES_DIGEST):
         traffic = None
     out = {
         "metric": METRIC,
@@ -264,11 +344,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if newton else "f32",
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.n_snakes} snakes, {int(B.sum())} bodies, "
                                f"{wl.substeps} substeps, "
-                               + ("20 iterations" if args.fixed else "residual<=1e-4, max 200 iterations")
+                               + (f"Newton {ni} x {npc} inner iterations" if newton
+                                  else "20 iterations" if args.fixed else "residual<=1e-4, max 200 iterations")
                                + ", plain (zero warm start)",
                    "snakes": wl.n_snakes, "bodies": int(B.sum()), "substeps": wl.substeps,
                    "tol": wl.tol, "max_iters": wl.iters},
@@ -278,14 +359,17 @@ def main():
         "residual_last_step": {"median": float(np.median(r["residual"])),
                                "p99": float(np.percentile(r["residual"], 99)),
                                "max": float(np.max(r["residual"]))},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic,
-                     "kernel": f"k_tile<{sim.mapping['waves']}, 0, {sim.mapping['rows']}>", "mapping": sim.mapping,
-                     "flop_per_body_iter": FLOP_ITER,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": (PEAK_FP64 if newton else PEAK_FP32) / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64 if newton else PEAK_FP32), "traffic": traffic,
+                     "kernel": "k_newton<64>" if newton else f"k_tile<{sim.mapping['waves']}, 0, {sim.mapping['rows']}>",
+                     "mapping": sim.mapping,
+                     "flop_per_body_iter": FLOP_PCR_ITER if newton else FLOP_ITER,
                      "hbm_frac_algorithmic": hbm_bytes / (per_launch_ms / 1e3) / PEAK_HBM},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_snakes, args.cpu_steps)
+    if not args.no_newton:
+        out["newton_pcr"] = newton_comparison(wl)
     if not args.no_learned:
         out["learned_warm_start"] = learned_comparison(args.learned_steps)
         out["learned_warm_start_converging"] = learned_converging()

@@ -483,9 +483,9 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
                     dg[7] = wA + Et00;
                     dg[8] = wA + Et11;
                 }
+                // the preconditioner as reciprocals, once per Newton iteration
 #pragma unroll
-                for (int k2 = 0; k2 < 9; ++k2)
-                    if (!(dg[k2] > 0.0)) dg[k2] = 1.0;
+                for (int k2 = 0; k2 < 9; ++k2) dg[k2] = dg[k2] > 0.0 ? 1.0 / dg[k2] : 1.0;
                 auto project = [&](double (&u)[9]) {
 #pragma unroll
                     for (int k2 = 0; k2 < 6; ++k2) u[k2] *= pj;
@@ -499,7 +499,7 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
                     for (int k2 = 0; k2 < 9; ++k2) o[k2] = u[k2];
                     project(o);
 #pragma unroll
-                    for (int k2 = 0; k2 < 9; ++k2) o[k2] /= dg[k2];
+                    for (int k2 = 0; k2 < 9; ++k2) o[k2] *= dg[k2];
                     project(o);
                 };
                 auto sdot = [&](const double (&a)[9], const double (&b)[9]) {
