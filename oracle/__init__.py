@@ -30,7 +30,7 @@ FLAG_NO_GROUND = 2
 FLAG_LINEARISED = 8
 WARM_ZERO, WARM_PREV, WARM_GIVEN = 0, 1, 2
 STATUS_NONFINITE, STATUS_NOT_CONVERGED = 1, 2
-SOLVER_JACOBI, SOLVER_NEWTON = 0, 1
+SOLVER_JACOBI, SOLVER_NEWTON, SOLVER_GS = 0, 1, 2
 
 _lock = threading.Lock()
 _lib = None

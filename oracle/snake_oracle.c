@@ -1110,9 +1110,118 @@ static int newton_pcr(const orc_batch* b, const snake_ctx* c, scratch_t* W, doub
     return its;
 }
 
+/* Greedy colouring of one snake's blocks in block order (stretch_j, bend_j
+ * for every joint, then the contacts): each block takes the smallest colour
+ * not taken by an earlier block sharing a body.  Returns the colour count. */
+static int block_colours(const snake_ctx* c, const block_t* blk, int* colour)
+{
+    int nb = n_blocks(c), ncol = 0;
+    for (int k = 0; k < nb; ++k) {
+        int col = 0;
+        for (;;) {
+            int clash = 0;
+            for (int e = 0; e < k && !clash; ++e) {
+                int share = blk[e].a == blk[k].a || (blk[k].b >= 0 && blk[e].a == blk[k].b) ||
+                            (blk[e].b >= 0 && (blk[e].b == blk[k].a || blk[e].b == blk[k].b));
+                if (share && colour[e] == col) clash = 1;
+            }
+            if (!clash) break;
+            ++col;
+        }
+        colour[k] = col;
+        if (col + 1 > ncol) ncol = col + 1;
+    }
+    return ncol;
+}
+
+/* Block Gauss-Seidel sweeps from the current (x, q, lambda), the blocks
+ * visited colour by colour (blocks of one colour share no body, so their
+ * order within the colour does not matter): at iterate k evaluate every
+ * block and the residual (the block-Jacobi measure), stop as the Jacobi
+ * iteration does, else for each colour evaluate every block at the current
+ * state, take the local solutions of that colour's blocks scaled by relax
+ * (no averaging: a body takes one of them per colour) and apply them to
+ * the multipliers and the bodies at once.  Returns the sweeps run. */
+static int gauss_seidel(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* x, double* q,
+                        double* lam_j, double* lam_c, int kmax, double tol, double* res, int* status)
+{
+    int nb = n_blocks(c);
+    int B = c->B;
+    int* colour = (int*)calloc((size_t)nb + 1, sizeof(int));
+    eval_blocks(b, c, x, q, W->xp, W->theta0, W->blk);
+    int ncol = block_colours(c, W->blk, colour);
+    if (c->linear) {
+        memcpy(W->xt, x, sizeof(double) * 3 * (size_t)B);
+        memcpy(W->qt, q, sizeof(double) * 4 * (size_t)B);
+        memset(W->acc, 0, sizeof(double) * 6 * (size_t)B);
+        eval_blocks(b, c, x, q, W->xp, W->theta0, W->blk0);
+        for (int i = 0; i < B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
+    }
+    int k = 0;
+    double r = 0.0;
+    for (;; ++k) {
+        if (c->linear) {
+            linear_blocks(c, W);
+            r = local_solves(c, W, lam_j, lam_c);
+        } else {
+            r = residual_at(b, c, W, x, q, lam_j, lam_c);
+        }
+        if (!isfinite(r)) {
+            *status |= ORC_STATUS_NONFINITE;
+            break;
+        }
+        int stop = (tol > 0.0) ? (r <= tol || k >= kmax) : (k >= kmax);
+        if (stop) {
+            if (tol > 0.0 && r > tol) *status |= ORC_STATUS_NOT_CONVERGED;
+            break;
+        }
+        for (int col = 0; col < ncol; ++col) {
+            if (c->linear) {
+                linear_blocks(c, W);
+            } else {
+                eval_blocks(b, c, x, q, W->xp, W->theta0, W->blk);
+                for (int i = 0; i < B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
+            }
+            for (int n = 0; n < nb; ++n) W->blk[n].scale = c->relax;
+            local_solves(c, W, lam_j, lam_c);
+            for (int n = 0; n < nb; ++n) {
+                double* l = block_lambda(c, lam_j, lam_c, &W->blk[n], n);
+                if (colour[n] != col) {
+                    W->dl[3 * n] = W->dl[3 * n + 1] = W->dl[3 * n + 2] = 0.0;
+                    continue;
+                }
+                for (int d = 0; d < 3; ++d) l[d] += W->dl[3 * n + d];
+            }
+            for (int i = 0; i < B; ++i) {
+                double dx[3], dth[3];
+                gather_body(c, i, W->blk, W->dl, inv_mass(c, i), W->Iinv + 9 * i, dx, dth);
+                if (c->linear) {
+                    for (int d = 0; d < 3; ++d) {
+                        W->acc[6 * i + d] += dx[d];
+                        W->acc[6 * i + 3 + d] += dth[d];
+                    }
+                } else {
+                    for (int d = 0; d < 3; ++d) x[3 * i + d] += dx[d];
+                    if (!is_fixed(c, i)) q_apply_rotvec(q + 4 * i, dth);
+                }
+            }
+        }
+    }
+    if (c->linear) {
+        for (int i = 0; i < B; ++i) {
+            for (int d = 0; d < 3; ++d) x[3 * i + d] = W->xt[3 * i + d] + W->acc[6 * i + d];
+            memcpy(q + 4 * i, W->qt + 4 * i, 4 * sizeof(double));
+            if (!is_fixed(c, i)) q_apply_rotvec(q + 4 * i, W->acc + 6 * i + 3);
+        }
+    }
+    free(colour);
+    *res = r;
+    return k;
+}
+
 /* Solve of one substep from the predicted (x, q): block-Jacobi, or with
  * the Newton solver selected the Newton iterations above from zero
- * multipliers.  Returns the number of (inner) iterations run; *res is the
+ * multipliers, or with Gauss-Seidel selected its sweeps from zero.  Returns the number of (inner) iterations run; *res is the
  * residual of the final iterate.
  *
  * Multiplier initialisation: zero, or lambda0 = the current lambda with
@@ -1136,6 +1245,11 @@ static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, d
         memset(lam_j, 0, nj6);
         memset(lam_c, 0, nc3);
         return newton_pcr(b, c, W, x, q, lam_j, lam_c, b->newton_iters, b->pcr_iters, tol, res, status);
+    }
+    if (b->solver == ORC_SOLVER_GS) {
+        memset(lam_j, 0, nj6);
+        memset(lam_c, 0, nc3);
+        return gauss_seidel(b, c, W, x, q, lam_j, lam_c, kmax, tol, res, status);
     }
     if (fallback && b->fallback_k > 0) {
         int K = b->fallback_k;

@@ -24,7 +24,8 @@
  *     linearisation is eq. schur_system, or by the paper's own scheme:
  *     Newton iterations, each solving eq. schur_system with a fixed number
  *     of preconditioned conjugate-residual iterations (diagonal
- *     preconditioner), contact by a Fischer-Burmeister reformulation.
+ *     preconditioner), contact by a Fischer-Burmeister reformulation; or
+ *     block Gauss-Seidel sweeps over the greedy block colouring.
  * Every floating-point quantity is double.  No fast-math.
  *
  * Memory layout: array-of-structures per body (x[3*i+k], q[4*i+k] with
@@ -52,6 +53,7 @@
 
 #define ORC_SOLVER_JACOBI 0     /* block-Jacobi iterations (the default)    */
 #define ORC_SOLVER_NEWTON 1     /* Newton + preconditioned conjugate residual */
+#define ORC_SOLVER_GS 2         /* block Gauss-Seidel over the block colouring */
 
 #define ORC_STATUS_NONFINITE 1
 #define ORC_STATUS_NOT_CONVERGED 2
@@ -82,7 +84,7 @@ typedef struct {
     double ctrl_alpha, ctrl_offset;
     int32_t fallback;   /* GIVEN warm start: keep lambda0 only if it is closer */
     int32_t fallback_k; /* ... after this many iterations (0: at the start) */
-    int32_t solver;       /* ORC_SOLVER_*; NEWTON needs the zero warm start  */
+    int32_t solver;       /* ORC_SOLVER_*; NEWTON and GS need the zero warm start */
     int32_t newton_iters; /* NEWTON: outer iterations per substep            */
     int32_t pcr_iters;    /* NEWTON: inner iterations per outer iteration     */
 } orc_batch;
