@@ -99,6 +99,13 @@ extern "C" {
                             /* rows' natural map to the Jacobi measure.      */
                             /* Computes in double.  Needs SIM_WARM_ZERO; no  */
                             /* split substeps (sim_step_record).             */
+#define SIM_SOLVER_GS 2     /* block Gauss-Seidel: sweeps over the greedy    */
+                            /* block colouring (SIM_IDX_BLK_COLOR), each     */
+                            /* colour's blocks taking their local solutions  */
+                            /* scaled by relax (no averaging) at the current */
+                            /* state; iters / tol count and stop sweeps as   */
+                            /* the Jacobi solver does its iterations.  FP32. */
+                            /* Needs SIM_WARM_ZERO; no split substeps.       */
 
 /* ---- flags ---- */
 #define SIM_FLAG_FIXED_ROOT 1u /* body 0 of every snake is immovable         */

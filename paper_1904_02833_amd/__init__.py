@@ -20,7 +20,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 LAW_LAG, LAW_PAPER = 0, 1
 CTRL_EXTERNAL, CTRL_SERPENOID, CTRL_SCHEDULE = 0, 1, 2
 WARM_ZERO, WARM_PREV, WARM_MLP = 0, 1, 2
-SOLVER_JACOBI, SOLVER_NEWTON = 0, 1
+SOLVER_JACOBI, SOLVER_NEWTON, SOLVER_GS = 0, 1, 2
 FLAG_FIXED_ROOT, FLAG_NO_GROUND = 1, 2
 STATUS_NONFINITE, STATUS_NOT_CONVERGED, STATUS_FELL_BACK = 1, 2, 4
 

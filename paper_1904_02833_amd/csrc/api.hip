@@ -37,6 +37,7 @@ struct Sizes {
     bool autotune = false;
     bool mlp = false;
     bool newton = false;
+    bool gs = false;
 };
 
 // Carves 256-byte aligned sub-arrays out of the workspace (base == nullptr
@@ -111,8 +112,11 @@ int validate(const sim_desc_t* d, Sizes* z)
     if (d->map_rows != 0 && d->map_rows != 1) return fail(SIM_EINVAL, "map_rows must be 0 or 1");
     if (d->mlp_fallback_k < 0 || d->mlp_fallback_k > d->iters)
         return fail(SIM_EINVAL, "mlp_fallback_k must be in [0, iters]");
-    if (d->solver != SIM_SOLVER_JACOBI && d->solver != SIM_SOLVER_NEWTON)
+    if (d->solver != SIM_SOLVER_JACOBI && d->solver != SIM_SOLVER_NEWTON && d->solver != SIM_SOLVER_GS)
         return fail(SIM_EINVAL, "unknown solver");
+    if (d->solver == SIM_SOLVER_GS && d->warm_start != SIM_WARM_ZERO)
+        return fail(SIM_EINVAL, "the Gauss-Seidel solver starts from zero multipliers");
+    z->gs = d->solver == SIM_SOLVER_GS;
     if (d->solver == SIM_SOLVER_NEWTON) {
         if (d->warm_start != SIM_WARM_ZERO) return fail(SIM_EINVAL, "the Newton solver starts from zero multipliers");
         if (d->newton_iters < 0 || d->newton_iters > 10000)
@@ -157,7 +161,7 @@ struct Views {
     size_t state_bytes;
     char* backup;           // copy of the state while autotuning
     NParams np;
-    int* newton_list;       // [n] snakes by lane class (Newton solver)
+    int* newton_list;       // [n] snakes by lane class (Newton and Gauss-Seidel solvers)
     double* comp_d;         // [4][n] compliances / h^2 and mu in double
     float* feat;            // [2J][32] network inputs (learned warm start)
     float* mlp_y;           // [2J][3] network outputs
@@ -224,7 +228,7 @@ size_t carve(const Sizes& z, char* base, Views* v)
     v->mlp_y = z.mlp ? c.take<float>(6 * J) : nullptr;
     v->mlp_params = z.mlp ? c.take<float>(8192) : nullptr;
     v->mlp_ms = z.mlp ? c.take<float>(64) : nullptr;
-    v->newton_list = z.newton ? c.take<int>(n) : nullptr;
+    v->newton_list = (z.newton || z.gs) ? c.take<int>(n) : nullptr;
     v->comp_d = z.newton ? c.take<double>(4 * n) : nullptr;
     v->hdr = c.take<int4>(n + 1);
     v->slots = c.take<int2>(n + 1);
@@ -387,6 +391,12 @@ int launch_steps(sim* s, hipStream_t st, int n_steps)
     if (s->z.newton) {
         hipError_t e = launch_newton(s->v.kp, s->v.np, s->v.newton_list, s->newton_off, n_steps, st);
         if (e != hipSuccess) return hip_fail(e, "Newton step launch");
+        return SIM_OK;
+    }
+    if (s->z.gs) {
+        hipError_t e = launch_gs(s->v.kp, s->v.ip.block_off, s->v.ip.blk_color, s->v.newton_list, s->newton_off,
+                                 n_steps, st);
+        if (e != hipSuccess) return hip_fail(e, "Gauss-Seidel step launch");
         return SIM_OK;
     }
     if (!s->z.mlp) return tiles(s, st, n_steps, kPhaseFull, 0);
@@ -662,7 +672,7 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     CK(hipMemcpyAsync(w.sched_off, soff.data(), soff.size() * sizeof(int), hipMemcpyHostToDevice, st), "upload schedule");
     CK(hipMemcpyAsync(w.sched_start, sstart.data(), sstart.size() * sizeof(int), hipMemcpyHostToDevice, st), "upload schedule");
     CK(hipMemcpyAsync(w.sched_val, sval.data(), sval.size() * sizeof(float), hipMemcpyHostToDevice, st), "upload schedule");
-    if (z.newton) {
+    if (z.newton || z.gs) {
         // snakes grouped by lane class (power of two >= B, at least 16)
         std::vector<double> cd(4 * (size_t)n);
         std::vector<int> cls(n), list;
@@ -681,8 +691,9 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
                 if (cls[q] == c) list.push_back(q);
         }
         s->newton_off[7] = (int)list.size();
-        CK(hipMemcpyAsync(w.comp_d, cd.data(), cd.size() * sizeof(double), hipMemcpyHostToDevice, st),
-           "upload compliance");
+        if (z.newton)
+            CK(hipMemcpyAsync(w.comp_d, cd.data(), cd.size() * sizeof(double), hipMemcpyHostToDevice, st),
+               "upload compliance");
         CK(hipMemcpyAsync(w.newton_list, list.data(), n * sizeof(int), hipMemcpyHostToDevice, st),
            "upload snake classes");
     }
@@ -704,7 +715,7 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     }
     CK(launch_init_state(k, st), "init state");
     CK(hipStreamSynchronize(st), "init state");
-    if (z.autotune && !z.newton) {
+    if (z.autotune && !z.newton && !z.gs) {
         rc = autotune(s);
         if (rc) goto error;
     } else {
@@ -860,7 +871,7 @@ int sim_step_record(sim_t* s, int32_t n_steps, float* features, float* targets, 
     if (!s || !features || !targets) return fail(SIM_EINVAL, "sim, features or targets is NULL");
     if (n_steps < 0) return fail(SIM_EINVAL, "n_steps must be >= 0");
     if (s->z.mlp && !s->mlp_loaded) return fail(SIM_ESTATE, "learned warm start needs sim_set_mlp first");
-    if (s->z.newton) return fail(SIM_EINVAL, "recording needs the Jacobi solver");
+    if (s->z.newton || s->z.gs) return fail(SIM_EINVAL, "recording needs the Jacobi solver");
     const int64_t per_sub = 2 * s->z.J;
     const int64_t rows = per_sub * s->v.kp.substeps * (int64_t)n_steps;
     if (written) *written = rows;

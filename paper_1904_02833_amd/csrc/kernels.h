@@ -110,6 +110,10 @@ hipError_t launch_tiles(int nw, int rows, const KParams& P, const int4* hdr, con
 // class, class c at [off[c], off[c+1]).  Runs n_steps whole steps.
 hipError_t launch_newton(const KParams& P, const NParams& Q, const int* list, const int* off,
                          int n_steps, hipStream_t stream);
+// Block Gauss-Seidel solver, same lane classes and snake list as the Newton
+// solver; colours from the index work (block_off, blk_color).
+hipError_t launch_gs(const KParams& P, const int* block_off, const int* blk_color, const int* list,
+                     const int* off, int n_steps, hipStream_t stream);
 hipError_t launch_features(const KParams& P, float* feat, hipStream_t stream);
 hipError_t launch_targets(const KParams& P, float* tgt, hipStream_t stream);
 hipError_t launch_index(const IParams& P, hipStream_t stream);

@@ -122,13 +122,14 @@ def test_descriptor_validation(L, field, value, msg):
 
 
 @pytest.mark.parametrize("over,msg", [
-    (dict(solver=2), "solver"),
+    (dict(solver=3), "solver"),
     (dict(solver=1, warm_start=1), "zero multipliers"),
+    (dict(solver=2, warm_start=1), "zero multipliers"),
     (dict(solver=1, newton_iters=-1), "newton_iters"),
     (dict(solver=1, newton_iters=10001), "newton_iters"),
     (dict(solver=1, pcr_iters=0), "pcr_iters"),
 ])
-def test_newton_descriptor_validation(L, over, msg):
+def test_solver_descriptor_validation(L, over, msg):
     rc, _, err = ws_bytes(L, W.custom([2, 2], 8), **over)
     assert rc == snk.SIM_EINVAL
     assert msg in err
