@@ -10,7 +10,8 @@ dominant kernel's roofline position (measured with HIP events on the
 solver's stream) and the FP64 CPU oracle timed on a bounded sample of the
 same workload on this machine's host cores.  Comparisons ride along: the
 paper's own solver (Newton with a preconditioned conjugate-residual inner
-solve, FP64) against block Jacobi at fixed budgets on the same batch, and the
+solve, FP64) and block Gauss-Seidel against block Jacobi at fixed budgets on
+the same batch, and the
 learned warm start against the zero start on the uneven batch at the
 headline setting (at most 200 iterations, which no snake's solve reaches
 1e-4 within) and on short snakes whose solve converges within its budget.
@@ -57,6 +58,12 @@ FLOP_NEWTON_SUBSTEP = 450
 PEAK_FP64 = 78.6e12        # MI355X FP64 vector (published)
 # the paper's budget (4 Newton iterations of 20 inner iterations) and two larger ones
 NEWTON_BUDGETS = ((4, 20), (8, 50), (16, 50))
+# block Gauss-Seidel sweeps (colour by colour over the block colouring), and
+# FP32 operations per body per sweep: the residual pass and the two colour
+# passes that evaluate the body's joint (FLOP_EVAL each), plus its contact
+# and the five gathered updates
+GS_BUDGETS = (40, 200)
+FLOP_GS_SWEEP = 3 * FLOP_EVAL + 100
 # learned start kept only where its residual after this many iterations is not
 # larger than the zero start's (both probes' iterations count in the totals)
 FALLBACK_K = 2
@@ -81,8 +88,9 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
     ap.add_argument("--learned-steps", type=int, default=20)
     ap.add_argument("--no-newton", action="store_true", help="skip the Newton solver comparison")
-    ap.add_argument("--solver", default="jacobi", choices=("jacobi", "newton"),
-                    help="solver of the timed loop (newton: the paper's budget, 4 x 20, FP64)")
+    ap.add_argument("--solver", default="jacobi", choices=("jacobi", "newton", "gs"),
+                    help="solver of the timed loop (newton: the paper's budget, 4 x 20, FP64; "
+                         "gs: block Gauss-Seidel, 40 sweeps)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 256 MiB device copies (scale for the HBM byte counters)")
     return ap.parse_args()
@@ -196,9 +204,10 @@ def learned_converging(n_steps=6):
 def newton_comparison(wl, n_steps=5):
     """The paper's own solver (Newton iterations, each solving the
     Schur-complement system with preconditioned conjugate-residual
-    iterations, FP64) against block Jacobi (FP32) on the same batch, from the
-    same state (20 plain steps in), at several fixed budgets: time per step
-    and the residual each reaches."""
+    iterations, FP64) and block Gauss-Seidel over the block colouring (FP32)
+    against block Jacobi (FP32) on the same batch, from the same state (20
+    plain steps in), at several fixed budgets: time per step and the
+    residual each reaches."""
     import torch
 
     import paper_1904_02833_amd as snk
@@ -240,6 +249,8 @@ def newton_comparison(wl, n_steps=5):
 
     run("jacobi, 200 iterations", tol=0.0, iters=200)
     run("jacobi, 2000 iterations", tol=0.0, iters=2000)
+    for sweeps in GS_BUDGETS:
+        run(f"gauss-seidel, {sweeps} sweeps", solver=snk.SOLVER_GS, tol=0.0, iters=sweeps)
     for ni, npc in NEWTON_BUDGETS:
         run(f"newton, {ni} x {npc} inner iterations", solver=snk.SOLVER_NEWTON, newton_iters=ni, pcr_iters=npc,
             tol=0.0)
@@ -292,7 +303,11 @@ def main():
     else:
         wl.tol, wl.iters = 1e-4, 200
     newton = args.solver == "newton"
-    if newton:
+    gs = args.solver == "gs"
+    if gs:
+        wl.tol, wl.iters = 0.0, GS_BUDGETS[0]
+        sim = snk.Sim(wl, use_graph=1, solver=snk.SOLVER_GS)
+    elif newton:
         wl.tol = 0.0
         ni, npc = NEWTON_BUDGETS[0]
         sim = snk.Sim(wl, use_graph=1, solver=snk.SOLVER_NEWTON, newton_iters=ni, pcr_iters=npc)
@@ -327,11 +342,13 @@ def main():
     if newton:
         flops = float(B.sum()) * args.steps * wl.substeps * (
             ni * (FLOP_NEWTON_ITER + npc * FLOP_PCR_ITER) + FLOP_NEWTON_SUBSTEP)
+    elif gs:
+        flops = float(np.sum(B * (its * FLOP_GS_SWEEP + args.steps * wl.substeps * (FLOP_EVAL + FLOP_SUBSTEP))))
     per_launch_ms = ms / args.steps
     achieved = flops / args.steps / (per_launch_ms / 1e3)
     hbm_bytes = float(B.sum()) * STATE_BYTES
     traffic = MEASURED_TRAFFIC.get((args.workload, sim.mapping["waves"], sim.mapping["rows"]))
-    if newton or (traffic is not None and kernel_digest() != TRAFFIC_SOURCES_DIGEST):
+    if newton or gs or (traffic is not None and kernel_digest() != TRAFFIC_SOURCES_DIGEST):
         traffic = None
     out = {
         "metric": METRIC,
@@ -349,6 +366,7 @@ def main():
         "config": {"workload": f"{wl.name}: {wl.n_snakes} snakes, {int(B.sum())} bodies, "
                                f"{wl.substeps} substeps, "
                                + (f"Newton {ni} x {npc} inner iterations" if newton
+                                  else f"Gauss-Seidel {wl.iters} sweeps" if gs
                                   else "20 iterations" if args.fixed else "residual<=1e-4, max 200 iterations")
                                + ", plain (zero warm start)",
                    "snakes": wl.n_snakes, "bodies": int(B.sum()), "substeps": wl.substeps,
@@ -361,9 +379,10 @@ def main():
                                "max": float(np.max(r["residual"]))},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": (PEAK_FP64 if newton else PEAK_FP32) / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64 if newton else PEAK_FP32), "traffic": traffic,
-                     "kernel": "k_newton<64>" if newton else f"k_tile<{sim.mapping['waves']}, 0, {sim.mapping['rows']}>",
+                     "kernel": "k_newton<64>" if newton else "k_gs<64>" if gs
+                     else f"k_tile<{sim.mapping['waves']}, 0, {sim.mapping['rows']}>",
                      "mapping": sim.mapping,
-                     "flop_per_body_iter": FLOP_PCR_ITER if newton else FLOP_ITER,
+                     "flop_per_body_iter": FLOP_PCR_ITER if newton else FLOP_GS_SWEEP if gs else FLOP_ITER,
                      "hbm_frac_algorithmic": hbm_bytes / (per_launch_ms / 1e3) / PEAK_HBM},
     }
     if not args.no_cpu:
