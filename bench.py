@@ -43,8 +43,8 @@ PEAK_FP32 = 157.3e12       # MI355X FP32 vector (published)
 # WRITE_SIZE runs scaled by a device copy of known size (summaries in
 # profiles/), keyed by workload, waves per workgroup and layout, with the digest of
 # the kernel sources they were taken on; a changed kernel reports null.
-MEASURED_TRAFFIC = {("uniform", 4, 1): 113.7e6, ("uneven", 4, 1): 696.3e6, ("stiff", 16, 1): 123.4e6}
-TRAFFIC_SOURCES_DIGEST = "2d39a34934636883:959545d7849e09a9:ed8d7ecc89e8e002"
+MEASURED_TRAFFIC = {("uniform", 4, 1): 113.8e6, ("uneven", 4, 1): 696.3e6, ("stiff", 16, 1): 123.3e6}
+TRAFFIC_SOURCES_DIGEST = "904ab355d20c1f78:645b5d19a26be76c:959545d7849e09a9:88568938c3414506"
 PEAK_HBM = 8.0e12
 # Newton solver (FP64): operations per body per inner conjugate-residual
 # iteration and per Newton iteration outside it (block evaluation, residual,
@@ -100,7 +100,7 @@ def kernel_digest():
     import hashlib
     csrc = os.path.join(ROOT, "paper_1904_02833_amd", "csrc")
     return ":".join(hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()[:16]
-                    for f in ("step.hip", "device_math.h", "kernels.h"))
+                    for f in ("step.hip", "blocks.h", "device_math.h", "kernels.h"))
 
 
 def learned_comparison(n_steps):
