@@ -116,3 +116,50 @@ def test_gs_graph_equals_direct_and_is_deterministic():
     for r in out[1:]:
         for k in out[0]:
             assert np.array_equal(out[0][k], r[k]), k
+
+
+def test_gs_serpenoid_and_paper_law_whole_step():
+    """A whole step with the command computed on the device (serpenoid) and
+    the paper's pressure law.  The GPU carries its state in FP32 through the
+    four substeps; the multiplier gate is twice the difference between the
+    FP64 oracle's step and the same step with its state rounded to FP32
+    after every substep (split substeps), or 1e-4 where larger."""
+    from parity import f32, gpu_state, load_gpu
+
+    wl = W.make("uniform", n_snakes=8)
+    wl.pressure_law = W.LAW_PAPER
+    base = oracle.Oracle(wl)
+    base.run(30, threads=8)
+    base.commands()
+    st = rounded_state(base)
+    o = oracle.Oracle(wl, solver=oracle.SOLVER_GS)
+    load_oracle(o, st)
+    o.step[...] = base.step
+    o.run(1, threads=8)
+    r = oracle.Oracle(wl, solver=oracle.SOLVER_GS)
+    load_oracle(r, st)
+    r.step[...] = base.step
+    r.commands()
+    for sub in range(wl.substeps):
+        for s_ in range(r.n):
+            r.solve_substep(s_, r.pre_substep(s_, sub))
+        for k in ("x", "q", "v", "w", "lam_j", "lam_c"):
+            getattr(r, k)[...] = f32(getattr(r, k))
+    sim = snk.Sim(wl, **GS)
+    load_gpu(sim, st)
+    sim.write(step=base.step.copy())
+    sim.step(1)
+    g = gpu_state(sim)
+    cmd = sim.read("cmd")["cmd"]
+    sim.close()
+    mu = np.asarray(wl.mu, np.float64)
+    spread = compare(o, dict(x=r.x, lam_j=r.lam_j, lam_c=r.lam_c), mu)
+    err = compare(o, g, mu)
+    print("\n[gs serpenoid paper law] worst", {k: float(err[k].max()) for k in err if k != "branch"},
+          "FP32-trajectory spread", {k: float(spread[k].max()) for k in ("lam_s", "lam_b", "lam_n", "lam_t")})
+    assert np.abs(cmd - o.cmd).max() <= 1e-6
+    assert np.abs(g["p"] - o.p).max() <= 1e-6
+    assert np.array_equal(np.asarray(g["iters"]), o.iters)
+    assert err["pos"].max() <= POS_TOL
+    for k in ("lam_s", "lam_b", "lam_n", "lam_t"):
+        assert err[k].max() <= max(LAM_TOL, 2 * spread[k].max()), k

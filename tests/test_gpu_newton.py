@@ -113,3 +113,31 @@ def test_newton_rejects_recording():
     with pytest.raises(snk.SimError):
         sim.step_record(1, f, t)
     sim.close()
+
+
+def test_newton_serpenoid_and_paper_law_whole_steps():
+    """A whole step (four substeps in one launch, the state in double
+    throughout) with the command computed on the device (serpenoid, phase
+    from the step counter) and the paper's once-per-step pressure law."""
+    from parity import gpu_state, load_gpu, load_oracle
+
+    wl = W.make("uniform", n_snakes=8)
+    wl.pressure_law = W.LAW_PAPER
+    base = oracle.Oracle(wl)
+    base.run(30, threads=8)
+    base.commands()
+    st = rounded_state(base)
+    o = oracle.Oracle(wl, solver=oracle.SOLVER_NEWTON, newton_iters=4, pcr_iters=20)
+    load_oracle(o, st)
+    o.step[...] = base.step
+    o.run(1, threads=8)
+    sim = snk.Sim(wl, **NEWTON)
+    load_gpu(sim, st)
+    sim.write(step=base.step.copy())
+    sim.step(1)
+    g = gpu_state(sim)
+    cmd = sim.read("cmd")["cmd"]
+    sim.close()
+    assert np.abs(cmd - o.cmd).max() <= 1e-6
+    assert np.abs(g["p"] - o.p).max() <= 1e-6
+    check(o, g, wl, "newton serpenoid paper law")
