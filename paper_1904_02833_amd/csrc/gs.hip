@@ -25,40 +25,44 @@ namespace {
 constexpr int kColours = 5;   // greedy colouring of a chain: at most 5
 
 template <int SEG, int K>
-__device__ __forceinline__ void gs_from_next(float (&v)[K], int lane, int wv, float* buf)
+__device__ __forceinline__ void gs_from_next(float (&v)[K], int lane, int wv, float* buf, int& ph)
 {
     float r[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) r[k] = __shfl_down(v[k], 1, 64);
     if constexpr (SEG > 64) {
+        // two buffers used in turn: the one written here was last read
+        // before the previous exchange's barrier
+        float* b = buf + (ph & 1) * (SEG / 64) * 12;
+        ++ph;
         if (lane == 0)
 #pragma unroll
-            for (int k = 0; k < K; ++k) buf[wv * 12 + k] = v[k];
+            for (int k = 0; k < K; ++k) b[wv * 12 + k] = v[k];
         __syncthreads();
         if (lane == 63 && wv + 1 < SEG / 64)
 #pragma unroll
-            for (int k = 0; k < K; ++k) r[k] = buf[(wv + 1) * 12 + k];
-        __syncthreads();
+            for (int k = 0; k < K; ++k) r[k] = b[(wv + 1) * 12 + k];
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = r[k];
 }
 
 template <int SEG, int K>
-__device__ __forceinline__ void gs_from_prev(float (&v)[K], int lane, int wv, float* buf)
+__device__ __forceinline__ void gs_from_prev(float (&v)[K], int lane, int wv, float* buf, int& ph)
 {
     float r[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) r[k] = __shfl_up(v[k], 1, 64);
     if constexpr (SEG > 64) {
+        float* b = buf + (ph & 1) * (SEG / 64) * 12;
+        ++ph;
         if (lane == 63)
 #pragma unroll
-            for (int k = 0; k < K; ++k) buf[wv * 12 + k] = v[k];
+            for (int k = 0; k < K; ++k) b[wv * 12 + k] = v[k];
         __syncthreads();
         if (lane == 0 && wv > 0)
 #pragma unroll
-            for (int k = 0; k < K; ++k) r[k] = buf[(wv - 1) * 12 + k];
-        __syncthreads();
+            for (int k = 0; k < K; ++k) r[k] = b[(wv - 1) * 12 + k];
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = r[k];
@@ -67,18 +71,20 @@ __device__ __forceinline__ void gs_from_prev(float (&v)[K], int lane, int wv, fl
 // maximum over the snake's lanes of non-negative values (NaN mapped to +inf
 // before), the same in every lane
 template <int SEG>
-__device__ __forceinline__ float gs_seg_max(float v, int lane, int wv, float* red)
+__device__ __forceinline__ float gs_seg_max(float v, int lane, int wv, float* red, int& ph)
 {
     constexpr int W = SEG < 64 ? SEG : 64;
 #pragma unroll
     for (int o = 1; o < W; o <<= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
     if constexpr (SEG > 64) {
-        if (lane == 0) red[wv] = v;
+        // two partial arrays used in turn, as the exchange buffers
+        float* r = red + (ph & 1) * (SEG / 64);
+        ++ph;
+        if (lane == 0) r[wv] = v;
         __syncthreads();
-        float a = red[0];
+        float a = r[0];
 #pragma unroll
-        for (int w = 1; w < SEG / 64; ++w) a = fmaxf(a, red[w]);
-        __syncthreads();
+        for (int w = 1; w < SEG / 64; ++w) a = fmaxf(a, r[w]);
         v = a;
     }
     return v;
@@ -91,8 +97,9 @@ k_gs(KParams P, const int* __restrict__ block_off, const int* __restrict__ blk_c
 {
     constexpr int WG = SEG > 64 ? SEG : 256;
     constexpr int NWV = SEG > 64 ? SEG / 64 : 1;
-    __shared__ float xbuf[NWV * 12];
-    __shared__ float red[NWV];
+    __shared__ float xbuf[2 * NWV * 12];   // two buffers used in turn
+    __shared__ float red[2 * NWV];
+    int xph = 0, rph = 0;   // which buffer the next exchange / reduction takes
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int idx = blockIdx.x * (WG / SEG) + t / SEG;
     const int i = t % SEG;
@@ -216,13 +223,13 @@ k_gs(KParams P, const int* __restrict__ block_off, const int* __restrict__ blk_c
             V3 dxp;
             {
                 float e[3] = {xp.x, xp.y, xp.z};
-                gs_from_next<SEG, 3>(e, lane, wv, xbuf);
+                gs_from_next<SEG, 3>(e, lane, wv, xbuf, xph);
                 dxp = xp - mk(e[0], e[1], e[2]);
             }
             // state of body i+1 at the current iterate
             auto next_body = [&](V3& dn, Q4& qn, V3& an, V3 aA) {
                 float e[10] = {d.x, d.y, d.z, q.w, q.x, q.y, q.z, aA.x, aA.y, aA.z};
-                gs_from_next<SEG, 10>(e, lane, wv, xbuf);
+                gs_from_next<SEG, 10>(e, lane, wv, xbuf, xph);
                 dn = mk(e[0], e[1], e[2]);
                 qn = Q4{e[3], e[4], e[5], e[6]};
                 an = mk(e[7], e[8], e[9]);
@@ -246,7 +253,7 @@ k_gs(KParams P, const int* __restrict__ block_off, const int* __restrict__ blk_c
                     const float rc = (lc.x > 0.f ? fabsf(cn) : fmaxf(-cn, 0.f)) * P.inv_L;
                     float rl = fmaxf(hasj ? fmaxf(rs, rb) : 0.f, (hasb && gnd) ? rc : 0.f);
                     rl = (rl == rl) ? rl : INFINITY;
-                    r = gs_seg_max<SEG>(rl, lane, wv, red);
+                    r = gs_seg_max<SEG>(rl, lane, wv, red, rph);
                 }
                 if (!(r < INFINITY)) {
                     status |= kStatusNonfinite;
@@ -287,7 +294,7 @@ k_gs(KParams P, const int* __restrict__ block_off, const int* __restrict__ blk_c
                     }
                     V3 dlc = zero;
                     if (cc == col && !fixed) dlc = contact_incr(lc, zp + d.z, d, sc, mass, mu);
-                    gs_from_prev<SEG, 6>(out, lane, wv, xbuf);
+                    gs_from_prev<SEG, 6>(out, lane, wv, xbuf, xph);
                     if (hasb && i > 0) {
                         fA = fA + mk(out[0], out[1], out[2]);
                         tA = tA + mk(out[3], out[4], out[5]);

@@ -100,40 +100,44 @@ __device__ __forceinline__ double paper_pressure(const NParams& Q, double pf, do
 // the boundary lanes through LDS (every lane of the workgroup calls these
 // together, so the barriers are uniform).
 template <int SEG, int K>
-__device__ __forceinline__ void from_next(double (&v)[K], int lane, int wv, double* buf)
+__device__ __forceinline__ void from_next(double (&v)[K], int lane, int wv, double* buf, int& ph)
 {
     double r[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) r[k] = __shfl_down(v[k], 1, 64);
     if constexpr (SEG > 64) {
+        // two buffers used in turn: the one written here was last read
+        // before the previous exchange's barrier
+        double* b = buf + (ph & 1) * (SEG / 64) * 8;
+        ++ph;
         if (lane == 0)
 #pragma unroll
-            for (int k = 0; k < K; ++k) buf[wv * 8 + k] = v[k];
+            for (int k = 0; k < K; ++k) b[wv * 8 + k] = v[k];
         __syncthreads();
         if (lane == 63 && wv + 1 < SEG / 64)
 #pragma unroll
-            for (int k = 0; k < K; ++k) r[k] = buf[(wv + 1) * 8 + k];
-        __syncthreads();
+            for (int k = 0; k < K; ++k) r[k] = b[(wv + 1) * 8 + k];
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = r[k];
 }
 
 template <int SEG, int K>
-__device__ __forceinline__ void from_prev(double (&v)[K], int lane, int wv, double* buf)
+__device__ __forceinline__ void from_prev(double (&v)[K], int lane, int wv, double* buf, int& ph)
 {
     double r[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) r[k] = __shfl_up(v[k], 1, 64);
     if constexpr (SEG > 64) {
+        double* b = buf + (ph & 1) * (SEG / 64) * 8;
+        ++ph;
         if (lane == 63)
 #pragma unroll
-            for (int k = 0; k < K; ++k) buf[wv * 8 + k] = v[k];
+            for (int k = 0; k < K; ++k) b[wv * 8 + k] = v[k];
         __syncthreads();
         if (lane == 0 && wv > 0)
 #pragma unroll
-            for (int k = 0; k < K; ++k) r[k] = buf[(wv - 1) * 8 + k];
-        __syncthreads();
+            for (int k = 0; k < K; ++k) r[k] = b[(wv - 1) * 8 + k];
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = r[k];
@@ -143,7 +147,7 @@ __device__ __forceinline__ void from_prev(double (&v)[K], int lane, int wv, doub
 // every lane: xor butterflies within the wave, then the waves' partials in
 // order.
 template <int SEG, bool MAX>
-__device__ __forceinline__ double seg_reduce(double v, int lane, int wv, double* red)
+__device__ __forceinline__ double seg_reduce(double v, int lane, int wv, double* red, int& ph)
 {
     constexpr int W = SEG < 64 ? SEG : 64;
 #pragma unroll
@@ -152,12 +156,14 @@ __device__ __forceinline__ double seg_reduce(double v, int lane, int wv, double*
         v = MAX ? fmax(v, t) : v + t;
     }
     if constexpr (SEG > 64) {
-        if (lane == 0) red[wv] = v;
+        // two partial arrays used in turn, as the exchange buffers
+        double* r = red + (ph & 1) * (SEG / 64);
+        ++ph;
+        if (lane == 0) r[wv] = v;
         __syncthreads();
-        double a = red[0];
+        double a = r[0];
 #pragma unroll
-        for (int w = 1; w < SEG / 64; ++w) a = MAX ? fmax(a, red[w]) : a + red[w];
-        __syncthreads();
+        for (int w = 1; w < SEG / 64; ++w) a = MAX ? fmax(a, r[w]) : a + r[w];
         v = a;
     }
     return v;
@@ -169,8 +175,9 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
 {
     constexpr int WG = SEG > 64 ? SEG : 256;
     constexpr int NWV = SEG > 64 ? SEG / 64 : 1;
-    __shared__ double xbuf[NWV * 8];
-    __shared__ double red[NWV];
+    __shared__ double xbuf[2 * NWV * 8];   // two buffers used in turn
+    __shared__ double red[2 * NWV];
+    int xph = 0, rph = 0;   // which buffer the next exchange / reduction takes
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int idx = blockIdx.x * (WG / SEG) + t / SEG;
     const int i = t % SEG;
@@ -245,7 +252,7 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
             nb6[4] = tB.y;
             nb6[5] = tB.z;
         }
-        from_prev<SEG, 6>(nb6, lane, wv, xbuf);
+        from_prev<SEG, 6>(nb6, lane, wv, xbuf, xph);
         D3 f = fA, tq = tA;
         if (hasb && i > 0) {
             f = d3(nb6[0], nb6[1], nb6[2]) + f;
@@ -260,7 +267,7 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
         D3 uf, ut;
         gather(vs, vb, vc, uf, ut);
         double un[6] = {uf.x, uf.y, uf.z, ut.x, ut.y, ut.z};
-        from_next<SEG, 6>(un, lane, wv, xbuf);
+        from_next<SEG, 6>(un, lane, wv, xbuf, xph);
         const D3 ufn = d3(un[0], un[1], un[2]), utn = d3(un[3], un[4], un[5]);
         if (hasj) {
             const D3 ys = (uf - cross(ra, ut)) - (ufn - cross(rb, utn)) + comp_s * vs;
@@ -345,7 +352,7 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
             for (int k = 0;; ++k) {
                 // blocks at the current iterate
                 double nbq[7] = {x.x, x.y, x.z, q.w, q.x, q.y, q.z};
-                from_next<SEG, 7>(nbq, lane, wv, xbuf);
+                from_next<SEG, 7>(nbq, lane, wv, xbuf, xph);
                 const D3 xB = d3(nbq[0], nbq[1], nbq[2]);
                 const DQ qB{nbq[3], nbq[4], nbq[5], nbq[6]};
                 aA = qaxis(q);
@@ -398,7 +405,7 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
                     }
                 }
                 if (!(rl <= INFINITY)) rl = INFINITY;   // NaN
-                r = seg_reduce<SEG, true>(rl, lane, wv, red);
+                r = seg_reduce<SEG, true>(rl, lane, wv, red, rph);
                 if (!(r < INFINITY)) {
                     status |= kStatusNonfinite;
                     break;
@@ -506,7 +513,7 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
                     double acc = 0.0;
 #pragma unroll
                     for (int k2 = 0; k2 < 9; ++k2) acc += a[k2] * b[k2];
-                    return seg_reduce<SEG, false>(acc, lane, wv, red);
+                    return seg_reduce<SEG, false>(acc, lane, wv, red, rph);
                 };
 
                 // preconditioned conjugate residual on the free rows
