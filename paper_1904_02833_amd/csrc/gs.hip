@@ -91,7 +91,7 @@ __device__ __forceinline__ float gs_seg_max(float v, int lane, int wv, float* re
 }
 
 template <int SEG>
-__global__ void __launch_bounds__(SEG > 64 ? SEG : 256)
+__global__ void __launch_bounds__(SEG > 64 ? SEG : 256) __attribute__((amdgpu_waves_per_eu(3)))
 k_gs(KParams P, const int* __restrict__ block_off, const int* __restrict__ blk_color,
      const int* __restrict__ list, int count, int n_steps)
 {

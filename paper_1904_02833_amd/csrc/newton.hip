@@ -170,7 +170,7 @@ __device__ __forceinline__ double seg_reduce(double v, int lane, int wv, double*
 }
 
 template <int SEG>
-__global__ void __launch_bounds__(SEG > 64 ? SEG : 256)
+__global__ void __launch_bounds__(SEG > 64 ? SEG : 256) __attribute__((amdgpu_waves_per_eu(2)))
 k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_steps)
 {
     constexpr int WG = SEG > 64 ? SEG : 256;
