@@ -46,6 +46,11 @@ PEAK_FP32 = 157.3e12       # MI355X FP32 vector (published)
 MEASURED_TRAFFIC = {("uniform", 4, 1): 113.8e6, ("uneven", 4, 1): 696.3e6, ("stiff", 16, 1): 123.3e6}
 TRAFFIC_SOURCES_DIGEST = "904ab355d20c1f78:645b5d19a26be76c:959545d7849e09a9:88568938c3414506"
 PEAK_HBM = 8.0e12
+# the same for the other solvers' kernels on the uniform batch (--solver),
+# with the digest of their sources
+SOLVER_TRAFFIC = {"newton": (477.9e6, ("newton.hip", "kernels.h"), "d108cbfb071f4c14:88568938c3414506"),
+                  "gs": (52.8e6, ("gs.hip", "blocks.h", "device_math.h", "kernels.h"),
+                         "45a4798bc66a6286:645b5d19a26be76c:959545d7849e09a9:88568938c3414506")}
 # Newton solver (FP64): operations per body per inner conjugate-residual
 # iteration and per Newton iteration outside it (block evaluation, residual,
 # rows, the two initial products, the update), counted from the compiled
@@ -96,11 +101,10 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_digest():
+def kernel_digest(files=("step.hip", "blocks.h", "device_math.h", "kernels.h")):
     import hashlib
     csrc = os.path.join(ROOT, "paper_1904_02833_amd", "csrc")
-    return ":".join(hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()[:16]
-                    for f in ("step.hip", "blocks.h", "device_math.h", "kernels.h"))
+    return ":".join(hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()[:16] for f in files)
 
 
 def learned_comparison(n_steps):
@@ -348,7 +352,12 @@ def main():
     achieved = flops / args.steps / (per_launch_ms / 1e3)
     hbm_bytes = float(B.sum()) * STATE_BYTES
     traffic = MEASURED_TRAFFIC.get((args.workload, sim.mapping["waves"], sim.mapping["rows"]))
-    if newton or gs or (traffic is not None and kernel_digest() != TRAFFIC_SOURCES_DIGEST):
+    if newton or gs:
+        traffic = None
+        if args.workload == "uniform":
+            t, files, digest = SOLVER_TRAFFIC[args.solver]
+            traffic = t if kernel_digest(files) == digest else None
+    elif traffic is not None and kernel_digest() != TRAFFIC_SOURCES_DIGEST:
         traffic = None
     out = {
         "metric": METRIC,
