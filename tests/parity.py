@@ -104,3 +104,49 @@ def advance_both(wl, st, one_substep=True, threads=8, **over):
     g = gpu_state(sim)
     sim.close()
     return o, g
+
+
+def slice_rows(st, o_full, sample):
+    """Concatenate the per-snake rows of state dict st (whole batch) for the
+    sampled snakes, in sample order."""
+    out = {}
+    for key, off in (("x", o_full.body_off), ("q", o_full.body_off), ("v", o_full.body_off),
+                     ("w", o_full.body_off), ("lam_c", o_full.body_off), ("lam_j", o_full.joint_off),
+                     ("p", o_full.module_off), ("cmd", o_full.module_off)):
+        if key in st:
+            out[key] = np.concatenate([st[key][off[s]:off[s + 1]] for s in sample])
+    return out
+
+
+def full_batch_substep(name, sample, steps, gpu_over, orc_over):
+    """A whole named batch on the GPU: `steps` plain steps, then one substep
+    of the whole batch with the solver settings gpu_over; the sampled snakes
+    take the same substep in the oracle (settings orc_over) from the same
+    FP32 state and commands.  Returns the oracle of the sample, the GPU
+    state of the sample, the sampled workload, the sampled FP32 state and
+    the oracle keyword arguments of the substep."""
+    import paper_1904_02833_amd as snk
+
+    wl = W.make(name)
+    lead = snk.Sim(wl)
+    lead.step(steps)
+    st = gpu_state(lead)
+    lead.close()
+    o_full = oracle.Oracle(wl)
+    o_full.step[:] = steps
+    st["cmd"] = f32(o_full.commands())
+    kw = dict(controller=W.CTRL_EXTERNAL, dt=wl.dt / wl.substeps, substeps=1)
+    sim = snk.Sim(wl, **kw, **gpu_over)
+    load_gpu(sim, st)
+    sim.step(1)
+    g_all = gpu_state(sim)
+    sim.close()
+    g = slice_rows(g_all, o_full, sample)
+    for k in ("residual", "iters", "status"):
+        g[k] = np.asarray(g_all[k])[sample]
+    sub = wl.take(np.array(sample))
+    st_s = slice_rows(st, o_full, sample)
+    o = oracle.Oracle(sub, **kw, **orc_over)
+    load_oracle(o, st_s)
+    o.run(1, threads=8)
+    return o, g, sub, st_s, dict(kw, **orc_over)

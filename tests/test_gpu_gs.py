@@ -163,3 +163,27 @@ def test_gs_serpenoid_and_paper_law_whole_step():
     assert err["pos"].max() <= POS_TOL
     for k in ("lam_s", "lam_b", "lam_n", "lam_t"):
         assert err[k].max() <= max(LAM_TOL, 2 * spread[k].max()), k
+
+
+def test_gs_full_uniform_batch_sampled():
+    """The whole uniform batch in the benchmark's Gauss-Seidel configuration
+    (40 sweeps), sampled snakes against the oracle, with the 1-ulp spread
+    gate of the other Gauss-Seidel tests."""
+    from parity import full_batch_substep
+
+    rng = np.random.default_rng(22)
+    pick = sorted({0, 4095, *rng.choice(4096, 6, replace=False).tolist()})
+    o, g, sub, st_s, kw = full_batch_substep("uniform", pick, 6, dict(GS, tol=0.0, iters=40),
+                                             dict(solver=oracle.SOLVER_GS, tol=0.0, iters=40))
+    o2 = oracle.Oracle(sub, **kw)
+    load_oracle(o2, dict(st_s, x=np.nextafter(st_s["x"].astype(np.float32), np.float32(np.inf)).astype(np.float64)))
+    o2.run(1, threads=8)
+    mu = np.asarray(sub.mu, np.float64)
+    spread = compare(o, dict(x=o2.x, lam_j=o2.lam_j, lam_c=o2.lam_c), mu)
+    err = compare(o, g, mu)
+    print("\n[gs full uniform] worst", {k: float(err[k].max()) for k in err if k != "branch"},
+          "spread", {k: float(spread[k].max()) for k in ("lam_s", "lam_b", "lam_n", "lam_t")})
+    assert np.array_equal(np.asarray(g["iters"]), o.iters)
+    assert err["pos"].max() <= POS_TOL
+    for k in ("lam_s", "lam_b", "lam_n", "lam_t"):
+        assert err[k].max() <= max(LAM_TOL, 2 * spread[k].max()), k

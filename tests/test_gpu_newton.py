@@ -141,3 +141,20 @@ def test_newton_serpenoid_and_paper_law_whole_steps():
     assert np.abs(cmd - o.cmd).max() <= 1e-6
     assert np.abs(g["p"] - o.p).max() <= 1e-6
     check(o, g, wl, "newton serpenoid paper law")
+
+
+@pytest.mark.parametrize("name", ["uniform", "uneven"])
+def test_newton_full_batch_sampled(name):
+    """The whole batch in the benchmark's Newton configuration (4 x 20,
+    every lane class of the batch launched), sampled snakes against the
+    oracle: first, last, the longest and shortest, random ones."""
+    from parity import full_batch_substep
+
+    wl = W.make(name)
+    rng = np.random.default_rng(21)
+    B = wl.bodies
+    pick = sorted({0, wl.n_snakes - 1, int(np.argmax(B)), int(np.argmin(B)),
+                   *rng.choice(wl.n_snakes, 6, replace=False).tolist()})
+    o, g, sub, _, _ = full_batch_substep(name, pick, 6, dict(NEWTON, tol=0.0),
+                                         dict(solver=oracle.SOLVER_NEWTON, newton_iters=4, pcr_iters=20, tol=0.0))
+    check(o, g, sub, f"newton full {name}")
