@@ -95,6 +95,20 @@ __device__ __forceinline__ double paper_pressure(const NParams& Q, double pf, do
     return p / Q.amp;
 }
 
+// One DPP move of a double (its two halves): lane permutations that run on
+// the VALU with a few cycles of latency, where a lane shuffle goes through the
+// LDS pipe and waits on its round trip.  Sources outside the wave read 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kDppWaveShl1 = 0x130;   // lane i takes lane i+1
+constexpr int kDppWaveShr1 = 0x138;   // lane i takes lane i-1
+
 // Exchanges along the chain.  A snake of SEG <= 64 lanes sits inside one
 // wave; a longer one spans SEG / 64 waves of its own workgroup and passes
 // the boundary lanes through LDS (every lane of the workgroup calls these
@@ -104,7 +118,7 @@ __device__ __forceinline__ void from_next(double (&v)[K], int lane, int wv, doub
 {
     double r[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) r[k] = __shfl_down(v[k], 1, 64);
+    for (int k = 0; k < K; ++k) r[k] = dpp_move<kDppWaveShl1>(v[k]);
     if constexpr (SEG > 64) {
         // two buffers used in turn: the one written here was last read
         // before the previous exchange's barrier
@@ -127,7 +141,7 @@ __device__ __forceinline__ void from_prev(double (&v)[K], int lane, int wv, doub
 {
     double r[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) r[k] = __shfl_up(v[k], 1, 64);
+    for (int k = 0; k < K; ++k) r[k] = dpp_move<kDppWaveShr1>(v[k]);
     if constexpr (SEG > 64) {
         double* b = buf + (ph & 1) * (SEG / 64) * 8;
         ++ph;
@@ -144,17 +158,22 @@ __device__ __forceinline__ void from_prev(double (&v)[K], int lane, int wv, doub
 }
 
 // Sum (MAX = false) or maximum over the snake's lanes, the same bits in
-// every lane: xor butterflies within the wave, then the waves' partials in
-// order.
+// every lane: within rows of 16 lanes by DPP swaps (quad [1,0,3,2], quad
+// [2,3,0,1], then the half-row and row mirrors, which pair lanes already
+// holding equal values, so each stage combines disjoint sets and every lane
+// adds the same two operands), rows by xor shuffles, then the waves'
+// partials in order.
 template <int SEG, bool MAX>
 __device__ __forceinline__ double seg_reduce(double v, int lane, int wv, double* red, int& ph)
 {
     constexpr int W = SEG < 64 ? SEG : 64;
+    auto join = [](double a, double b) { return MAX ? fmax(a, b) : a + b; };
+    v = join(v, dpp_move<0xB1>(v));
+    v = join(v, dpp_move<0x4E>(v));
+    v = join(v, dpp_move<0x141>(v));
+    v = join(v, dpp_move<0x140>(v));
 #pragma unroll
-    for (int o = 1; o < W; o <<= 1) {
-        const double t = __shfl_xor(v, o, 64);
-        v = MAX ? fmax(v, t) : v + t;
-    }
+    for (int o = 16; o < W; o <<= 1) v = join(v, __shfl_xor(v, o, 64));
     if constexpr (SEG > 64) {
         // two partial arrays used in turn, as the exchange buffers
         double* r = red + (ph & 1) * (SEG / 64);
