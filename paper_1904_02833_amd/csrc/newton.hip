@@ -106,6 +106,14 @@ __device__ __forceinline__ double dpp_move(double v)
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+// the value of lane l (uniform across the wave)
+__device__ __forceinline__ double row_value(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 constexpr int kDppWaveShl1 = 0x130;   // lane i takes lane i+1
 constexpr int kDppWaveShr1 = 0x138;   // lane i takes lane i-1
 
@@ -161,8 +169,8 @@ __device__ __forceinline__ void from_prev(double (&v)[K], int lane, int wv, doub
 // every lane: within rows of 16 lanes by DPP swaps (quad [1,0,3,2], quad
 // [2,3,0,1], then the half-row and row mirrors, which pair lanes already
 // holding equal values, so each stage combines disjoint sets and every lane
-// adds the same two operands), rows by xor shuffles, then the waves'
-// partials in order.
+// adds the same two operands), the rows of the snake read lane by lane and
+// joined in a fixed order, then the waves' partials in order.
 template <int SEG, bool MAX>
 __device__ __forceinline__ double seg_reduce(double v, int lane, int wv, double* red, int& ph)
 {
@@ -172,8 +180,18 @@ __device__ __forceinline__ double seg_reduce(double v, int lane, int wv, double*
     v = join(v, dpp_move<0x4E>(v));
     v = join(v, dpp_move<0x141>(v));
     v = join(v, dpp_move<0x140>(v));
-#pragma unroll
-    for (int o = 16; o < W; o <<= 1) v = join(v, __shfl_xor(v, o, 64));
+    if constexpr (W >= 32) {
+        // every lane of a row now holds its row's value: read the four rows
+        // into scalar registers and join them in a fixed order
+        const double r0 = row_value(v, 0), r1 = row_value(v, 16);
+        if constexpr (W == 32) {
+            const double r2 = row_value(v, 32), r3 = row_value(v, 48);
+            v = lane < 32 ? join(r0, r1) : join(r2, r3);
+        } else {
+            const double r2 = row_value(v, 32), r3 = row_value(v, 48);
+            v = join(join(r0, r1), join(r2, r3));
+        }
+    }
     if constexpr (SEG > 64) {
         // two partial arrays used in turn, as the exchange buffers
         double* r = red + (ph & 1) * (SEG / 64);
