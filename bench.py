@@ -48,7 +48,7 @@ TRAFFIC_SOURCES_DIGEST = "904ab355d20c1f78:645b5d19a26be76c:959545d7849e09a9:885
 PEAK_HBM = 8.0e12
 # the same for the other solvers' kernels on the uniform batch (--solver),
 # with the digest of their sources
-SOLVER_TRAFFIC = {"newton": (477.9e6, ("newton.hip", "kernels.h"), "d108cbfb071f4c14:88568938c3414506"),
+SOLVER_TRAFFIC = {"newton": (323.7e6, ("newton.hip", "kernels.h"), "d399c20554576341:88568938c3414506"),
                   "gs": (52.8e6, ("gs.hip", "blocks.h", "device_math.h", "kernels.h"),
                          "45a4798bc66a6286:645b5d19a26be76c:959545d7849e09a9:88568938c3414506")}
 # Newton solver (FP64): operations per body per inner conjugate-residual
