@@ -97,8 +97,9 @@ extern "C" {
                             /* early at a Newton iterate with residual <= tol*/
                             /* (tol > 0); the residual adds the friction     */
                             /* rows' natural map to the Jacobi measure.      */
-                            /* Computes in double.  Needs SIM_WARM_ZERO; no  */
-                            /* split substeps (sim_step_record).             */
+                            /* Computes in double.  Takes SIM_WARM_ZERO or   */
+                            /* SIM_WARM_PREV; no split substeps              */
+                            /* (sim_step_record).                            */
 #define SIM_SOLVER_GS 2     /* block Gauss-Seidel: sweeps over the greedy    */
                             /* block colouring (SIM_IDX_BLK_COLOR), each     */
                             /* colour's blocks taking their local solutions  */

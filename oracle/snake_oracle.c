@@ -1220,8 +1220,10 @@ static int gauss_seidel(const orc_batch* b, const snake_ctx* c, scratch_t* W, do
 }
 
 /* Solve of one substep from the predicted (x, q): block-Jacobi, or with
- * the Newton solver selected the Newton iterations above from zero
- * multipliers, or with Gauss-Seidel selected its sweeps from zero.  Returns the number of (inner) iterations run; *res is the
+ * the Newton solver selected the Newton iterations above (from zero
+ * multipliers, or from the previous substep's with the bodies moved by
+ * W J^T lambda0 as for Jacobi), or with Gauss-Seidel selected its sweeps
+ * from zero.  Returns the number of (inner) iterations run; *res is the
  * residual of the final iterate.
  *
  * Multiplier initialisation: zero, or lambda0 = the current lambda with
@@ -1242,8 +1244,12 @@ static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, d
     int fallback = (warm == ORC_WARM_GIVEN && b->fallback);
 
     if (b->solver == ORC_SOLVER_NEWTON) {
-        memset(lam_j, 0, nj6);
-        memset(lam_c, 0, nc3);
+        if (warm == ORC_WARM_PREV) {
+            apply_start(b, c, W, x, q, lam_j, lam_c);
+        } else {
+            memset(lam_j, 0, nj6);
+            memset(lam_c, 0, nc3);
+        }
         return newton_pcr(b, c, W, x, q, lam_j, lam_c, b->newton_iters, b->pcr_iters, tol, res, status);
     }
     if (b->solver == ORC_SOLVER_GS) {

@@ -84,7 +84,8 @@ typedef struct {
     double ctrl_alpha, ctrl_offset;
     int32_t fallback;   /* GIVEN warm start: keep lambda0 only if it is closer */
     int32_t fallback_k; /* ... after this many iterations (0: at the start) */
-    int32_t solver;       /* ORC_SOLVER_*; NEWTON and GS need the zero warm start */
+    int32_t solver;       /* ORC_SOLVER_*; NEWTON takes the zero or previous  */
+                          /* warm start, GS the zero one                      */
     int32_t newton_iters; /* NEWTON: outer iterations per substep            */
     int32_t pcr_iters;    /* NEWTON: inner iterations per outer iteration     */
 } orc_batch;

@@ -118,7 +118,8 @@ int validate(const sim_desc_t* d, Sizes* z)
         return fail(SIM_EINVAL, "the Gauss-Seidel solver starts from zero multipliers");
     z->gs = d->solver == SIM_SOLVER_GS;
     if (d->solver == SIM_SOLVER_NEWTON) {
-        if (d->warm_start != SIM_WARM_ZERO) return fail(SIM_EINVAL, "the Newton solver starts from zero multipliers");
+        if (d->warm_start != SIM_WARM_ZERO && d->warm_start != SIM_WARM_PREV)
+            return fail(SIM_EINVAL, "the Newton solver starts from zero or the previous multipliers");
         if (d->newton_iters < 0 || d->newton_iters > 10000)
             return fail(SIM_EINVAL, "newton_iters must be in [0, 10000]");
         if (d->pcr_iters < 1 || d->pcr_iters > 100000) return fail(SIM_EINVAL, "pcr_iters must be in [1, 100000]");

@@ -327,6 +327,39 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
         }
     };
 
+    // Joint blocks at the current (x, q): constraint values, and the
+    // geometry the products use (axes, attachment arms, bend Jacobian rows).
+    auto evaluate = [&](DQ q0, D3& Cs, D3& Cb) {
+        double nbq[7] = {x.x, x.y, x.z, q.w, q.x, q.y, q.z};
+        from_next<SEG, 7>(nbq, lane, wv, xbuf, xph);
+        const D3 xB = d3(nbq[0], nbq[1], nbq[2]);
+        const DQ qB{nbq[3], nbq[4], nbq[5], nbq[6]};
+        aA = qaxis(q);
+        aB = qaxis(qB);
+        ra = hl * aA;
+        rb = -hl * aB;
+        Cs = zero;
+        Cb = zero;
+        if (hasj) {
+            Cs = (x + ra) - (xB + rb);
+            DQ e = qmul(qmul(qconj(q0), qconj(q)), qB);
+            if (e.w < 0.0) e = DQ{-e.w, -e.x, -e.y, -e.z};
+            Cb = d3(2.0 * e.x, 2.0 * e.y, 2.0 * e.z);
+            // d C_b = G F^T (dth_B - dth_A), G = e_w I - [e_xyz]x, F = R(q q0)
+            const DQ f = qmul(q, q0);
+            const D3 F0 = qaxis(f);   // columns of R(f)
+            const D3 F1{2.0 * (f.x * f.y - f.w * f.z), 1.0 - 2.0 * (f.x * f.x + f.z * f.z),
+                        2.0 * (f.y * f.z + f.w * f.x)};
+            const D3 F2{2.0 * (f.x * f.z + f.w * f.y), 2.0 * (f.y * f.z - f.w * f.x),
+                        1.0 - 2.0 * (f.x * f.x + f.y * f.y)};
+            // row k of G F^T = sum_c G[k][c] F_c^T
+            const D3 G0{e.w, e.z, -e.y}, G1{-e.z, e.w, e.x}, G2{e.y, -e.x, e.w};
+            A0 = G0.x * F0 + G0.y * F1 + G0.z * F2;
+            A1 = G1.x * F0 + G1.y * F1 + G1.z * F2;
+            A2 = G2.x * F0 + G2.y * F1 + G2.z * F2;
+        }
+    };
+
     float rstep = 0.f;
     int itstep = 0, status = 0, itsum = 0;
     for (int st = 0; st < n_steps; ++st) {
@@ -380,41 +413,28 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
                 v = zero;
                 w = zero;
             }
-            ls = zero;
-            lb = zero;
-            lc = zero;
+            if (P.warm == kWarmPrev) {
+                // the previous substep's multipliers, bodies moved by
+                // W J(x~)^T lambda0 at the predicted state
+                D3 Cs, Cb, uf, ut;
+                evaluate(q0, Cs, Cb);
+                gather(hasj ? ls : zero, hasj ? lb : zero, hasb && gnd ? lc : zero, uf, ut);
+                if (hasb && !fixed) {
+                    x = x + uf;
+                    q = qturn(q, ut);
+                }
+            } else {
+                ls = zero;
+                lb = zero;
+                lc = zero;
+            }
 
             double r = 0.0;
             int its = 0;
             for (int k = 0;; ++k) {
                 // blocks at the current iterate
-                double nbq[7] = {x.x, x.y, x.z, q.w, q.x, q.y, q.z};
-                from_next<SEG, 7>(nbq, lane, wv, xbuf, xph);
-                const D3 xB = d3(nbq[0], nbq[1], nbq[2]);
-                const DQ qB{nbq[3], nbq[4], nbq[5], nbq[6]};
-                aA = qaxis(q);
-                aB = qaxis(qB);
-                ra = hl * aA;
-                rb = -hl * aB;
-                D3 Cs = zero, Cb = zero;
-                if (hasj) {
-                    Cs = (x + ra) - (xB + rb);
-                    DQ e = qmul(qmul(qconj(q0), qconj(q)), qB);
-                    if (e.w < 0.0) e = DQ{-e.w, -e.x, -e.y, -e.z};
-                    Cb = d3(2.0 * e.x, 2.0 * e.y, 2.0 * e.z);
-                    // d C_b = G F^T (dth_B - dth_A), G = e_w I - [e_xyz]x, F = R(q q0)
-                    const DQ f = qmul(q, q0);
-                    const D3 F0 = qaxis(f);   // columns of R(f)
-                    const D3 F1{2.0 * (f.x * f.y - f.w * f.z), 1.0 - 2.0 * (f.x * f.x + f.z * f.z),
-                                2.0 * (f.y * f.z + f.w * f.x)};
-                    const D3 F2{2.0 * (f.x * f.z + f.w * f.y), 2.0 * (f.y * f.z - f.w * f.x),
-                                1.0 - 2.0 * (f.x * f.x + f.y * f.y)};
-                    // row k of G F^T = sum_c G[k][c] F_c^T
-                    const D3 G0{e.w, e.z, -e.y}, G1{-e.z, e.w, e.x}, G2{e.y, -e.x, e.w};
-                    A0 = G0.x * F0 + G0.y * F1 + G0.z * F2;
-                    A1 = G1.x * F0 + G1.y * F1 + G1.z * F2;
-                    A2 = G2.x * F0 + G2.y * F1 + G2.z * F2;
-                }
+                D3 Cs, Cb;
+                evaluate(q0, Cs, Cb);
                 const D3 Cc = d3(x.z - Q.R, x.x - xp.x, x.y - xp.y);
 
                 // residual: the block-Jacobi measure and the friction natural map

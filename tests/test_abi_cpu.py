@@ -123,7 +123,7 @@ def test_descriptor_validation(L, field, value, msg):
 
 @pytest.mark.parametrize("over,msg", [
     (dict(solver=3), "solver"),
-    (dict(solver=1, warm_start=1), "zero multipliers"),
+    (dict(solver=1, warm_start=2), "zero or the previous"),
     (dict(solver=2, warm_start=1), "zero multipliers"),
     (dict(solver=1, newton_iters=-1), "newton_iters"),
     (dict(solver=1, newton_iters=10001), "newton_iters"),

@@ -158,3 +158,39 @@ def test_newton_full_batch_sampled(name):
     o, g, sub, _, _ = full_batch_substep(name, pick, 6, dict(NEWTON, tol=0.0),
                                          dict(solver=oracle.SOLVER_NEWTON, newton_iters=4, pcr_iters=20, tol=0.0))
     check(o, g, sub, f"newton full {name}")
+
+
+def test_newton_previous_multiplier_start_substep():
+    """The previous substep's multipliers as the start (bodies moved by
+    W J(x~)^T lambda0), one substep."""
+    wl = W.make("uneven", n_snakes=24)
+    st = state_after(wl, 10)
+    assert np.abs(st["lam_j"]).max() > 0
+    o, g = advance_both(wl, st, warm_start=snk.WARM_PREV, **NEWTON)
+    check(o, g, wl, "newton previous start, substep")
+
+
+def test_newton_previous_multiplier_start_whole_step():
+    """A whole step with the previous-multiplier start: each substep starts
+    from the last one's multipliers, whose ill-conditioning carries the two
+    sides' different summation orders forward.  The gate is twice the
+    oracle's own spread when its input positions move by one FP64 ulp (or
+    1e-6 where larger)."""
+    from parity import load_oracle
+
+    wl = W.make("uneven", n_snakes=24)
+    st = state_after(wl, 10)
+    o, g = advance_both(wl, st, one_substep=False, warm_start=snk.WARM_PREV, **NEWTON)
+    o2 = oracle.Oracle(wl, controller=W.CTRL_EXTERNAL, solver=oracle.SOLVER_NEWTON, newton_iters=4, pcr_iters=20,
+                       warm=oracle.WARM_PREV)
+    load_oracle(o2, dict(st, x=np.nextafter(st["x"], np.inf)))
+    o2.run(1, threads=8)
+    mu = np.asarray(wl.mu, np.float64)
+    spread = compare(o, dict(x=o2.x, lam_j=o2.lam_j, lam_c=o2.lam_c), mu)
+    err = compare(o, g, mu)
+    keys = ("pos", "lam_s", "lam_b", "lam_n", "lam_t")
+    print("\n[newton previous start, step] worst", {k: float(err[k].max()) for k in keys},
+          "FP64 1-ulp spread", {k: float(spread[k].max()) for k in keys})
+    assert np.array_equal(np.asarray(g["iters"]), o.iters)
+    for k in keys:
+        assert err[k].max() <= max(TOL, 2 * spread[k].max()), k

@@ -124,3 +124,30 @@ def test_newton_budget_and_tolerance():
     o.run(1)
     assert np.all(o.residual <= 1e-6) and np.all(o.status == 0)
     assert np.all(o.iters % 100 == 0) and np.all(o.iters < 40 * 100 * wl.substeps)
+
+
+def test_newton_previous_multipliers_start_as_jacobi_does():
+    """The previous-multiplier start moves the predicted bodies by
+    W J(x~)^T lambda0, as the Jacobi solver's does (pinned with it): zero
+    Newton iterations from it give the Jacobi solver's zero-iteration state
+    and residual exactly, and from zero multipliers it is the zero start
+    (up to the renormalisation of a zero turn)."""
+    wl = W.make("short", n_snakes=4)
+    st = moved_state(wl)
+    assert np.abs(st["lam_j"]).max() > 0 and np.abs(st["lam_c"]).max() > 0
+    p = load(newton(wl, newton_iters=0, pcr_iters=1, tol=0, warm=oracle.WARM_PREV), st)
+    p.run(1)
+    j = load(oracle.Oracle(wl, iters=0, tol=0, warm=oracle.WARM_PREV), st)
+    j.run(1)
+    for k in ("x", "q", "lam_j", "lam_c", "residual"):
+        assert np.array_equal(getattr(p, k), getattr(j, k)), k
+    zero = dict(st, lam_j=np.zeros_like(st["lam_j"]), lam_c=np.zeros_like(st["lam_c"]))
+    a = load(newton(wl, warm=oracle.WARM_PREV, substeps=1), zero)
+    a.run(1)
+    b = load(newton(wl, substeps=1), zero)
+    b.run(1)
+    # (equal up to the renormalisation of q after a zero turn)
+    assert np.array_equal(a.iters, b.iters)
+    for k in ("x", "q", "lam_j", "lam_c"):
+        ref = np.abs(getattr(b, k)).max()
+        assert np.abs(getattr(a, k) - getattr(b, k)).max() <= 1e-9 * ref, k
