@@ -131,4 +131,30 @@ __device__ __forceinline__ V3 contact_incr(V3 lc, float cn, V3 d, float sc, floa
     return V3{ln - lc.x, t0 - lc.y, t1 - lc.z};
 }
 
+// Command of module m of snake s for the end of step stepc (eq.
+// snake_control): clamp(sin(2 pi f t + alpha m + phase0) + offset, -1, 1),
+// t = (stepc + 1) dt, evaluated in double.
+__device__ __forceinline__ double serpenoid_command(const KParams& P, int s, int m, long long stepc)
+{
+    const double freq = P.freq[s], ph0 = P.phase0[s];
+    const double t = (double)(stepc + 1) * P.dt;
+    const double a = sin(6.283185307179586476925286766559 * freq * t + P.ctrl_alpha * m + ph0) + P.ctrl_offset;
+    return fmin(1.0, fmax(-1.0, a));
+}
+
+// Command of global module gm at step stepc from a piecewise-constant
+// schedule: the last piece starting at or before stepc (binary search).
+__device__ __forceinline__ float schedule_command(const KParams& P, int gm, long long stepc)
+{
+    int lo = P.sched_off[gm], hi = P.sched_off[gm + 1] - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((long long)P.sched_start[mid] <= stepc)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return P.sched_val[lo];
+}
+
 }  // namespace snake

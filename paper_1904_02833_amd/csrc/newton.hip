@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "blocks.h"
 #include "kernels.h"
 
 namespace snake {
@@ -365,22 +366,10 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
     for (int st = 0; st < n_steps; ++st) {
         const long long stepc = (live ? P.step[s] : 0) + st;
         // command for the end of this step (eq. snake_control or a schedule)
-        if (hasb && P.controller == kCtrlSerpenoid) {
-            const double tt = (double)(stepc + 1) * P.dt;
-            double a = sin(6.283185307179586476925286766559 * P.freq[s] * tt + P.ctrl_alpha * m + P.phase0[s]) +
-                       P.ctrl_offset;
-            cmdv = fmin(1.0, fmax(-1.0, a));
-        } else if (hasb && P.controller == kCtrlSchedule) {
-            int lo = P.sched_off[gm], hi = P.sched_off[gm + 1] - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if ((long long)P.sched_start[mid] <= stepc)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            cmdv = P.sched_val[lo];
-        }
+        if (hasb && P.controller == kCtrlSerpenoid)
+            cmdv = serpenoid_command(P, s, m, stepc);
+        else if (hasb && P.controller == kCtrlSchedule)
+            cmdv = schedule_command(P, gm, stepc);
         if (P.law == kLawPaper) {
             p0 = paper_pressure(Q, p0, fmax(cmdv, 0.0));
             p1 = paper_pressure(Q, p1, fmax(-cmdv, 0.0));

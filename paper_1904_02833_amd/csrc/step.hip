@@ -292,24 +292,10 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
             const int sub1 = phase == kPhaseFull ? P.substeps : sub_only + 1;
             if (phase != kPhaseSolve && sub0 == 0) {
                 // command for the end of this step (eq. snake_control or a schedule)
-                if (hasb && P.controller == kCtrlSerpenoid) {
-                    const double freq = P.freq[s], ph0 = P.phase0[s];
-                    const double t = (double)(stepc + 1) * P.dt;
-                    double a = sin(6.283185307179586476925286766559 * freq * t + P.ctrl_alpha * m + ph0) +
-                               P.ctrl_offset;
-                    a = fmin(1.0, fmax(-1.0, a));
-                    cmdv = (float)a;
-                } else if (hasb && P.controller == kCtrlSchedule) {
-                    int lo = P.sched_off[gm], hi = P.sched_off[gm + 1] - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if ((long long)P.sched_start[mid] <= stepc)
-                            lo = mid;
-                        else
-                            hi = mid - 1;
-                    }
-                    cmdv = P.sched_val[lo];
-                }
+                if (hasb && P.controller == kCtrlSerpenoid)
+                    cmdv = (float)serpenoid_command(P, s, m, stepc);
+                else if (hasb && P.controller == kCtrlSchedule)
+                    cmdv = schedule_command(P, gm, stepc);
                 if (P.law == kLawPaper) {
                     p0 = paper_update(P, p0, fmaxf(cmdv, 0.f));
                     p1 = paper_update(P, p1, fmaxf(-cmdv, 0.f));
