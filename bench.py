@@ -44,13 +44,14 @@ PEAK_FP32 = 157.3e12       # MI355X FP32 vector (published)
 # profiles/), keyed by workload, waves per workgroup and layout, with the digest of
 # the kernel sources they were taken on; a changed kernel reports null.
 MEASURED_TRAFFIC = {("uniform", 4, 1): 113.8e6, ("uneven", 4, 1): 696.3e6, ("stiff", 16, 1): 123.3e6}
-TRAFFIC_SOURCES_DIGEST = "904ab355d20c1f78:645b5d19a26be76c:959545d7849e09a9:88568938c3414506"
+TRAFFIC_SOURCES_DIGEST = "6f9961ac0237831e:d9b1e61db4cc8d70:959545d7849e09a9:88568938c3414506"
 PEAK_HBM = 8.0e12
 # the same for the other solvers' kernels on the uniform batch (--solver),
 # with the digest of their sources
-SOLVER_TRAFFIC = {"newton": (323.7e6, ("newton.hip", "kernels.h"), "d399c20554576341:88568938c3414506"),
+SOLVER_TRAFFIC = {"newton": (323.9e6, ("newton.hip", "blocks.h", "device_math.h", "kernels.h"),
+                             "98730c19aa984fa0:d9b1e61db4cc8d70:959545d7849e09a9:88568938c3414506"),
                   "gs": (52.8e6, ("gs.hip", "blocks.h", "device_math.h", "kernels.h"),
-                         "45a4798bc66a6286:645b5d19a26be76c:959545d7849e09a9:88568938c3414506")}
+                         "a2a8923ebb111535:d9b1e61db4cc8d70:959545d7849e09a9:88568938c3414506")}
 # Newton solver (FP64): operations per body per inner conjugate-residual
 # iteration and per Newton iteration outside it (block evaluation, residual,
 # rows, the two initial products, the update), counted from the compiled
