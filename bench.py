@@ -262,6 +262,9 @@ def newton_comparison(wl, n_steps=5):
     ni, npc = NEWTON_BUDGETS[0]
     run(f"newton, {ni} x {npc} inner iterations, previous multipliers", solver=snk.SOLVER_NEWTON,
         newton_iters=ni, pcr_iters=npc, tol=0.0, warm_start=snk.WARM_PREV)
+    for ni, npc in NEWTON_BUDGETS[:2]:
+        run(f"newton, {ni} x {npc} inner iterations, best iterate kept", solver=snk.SOLVER_NEWTON,
+            newton_iters=ni, pcr_iters=npc, tol=0.0, newton_keep_best=1)
     return {"workload": f"{wl.name}: {wl.n_snakes} snakes, {int(B.sum())} bodies, {wl.substeps} substeps, "
                         "fixed budgets from the state after 20 plain steps",
             "rows": rows}

@@ -214,6 +214,10 @@ typedef struct sim_desc {
     int32_t pcr_iters;         /* NEWTON: inner iterations per Newton       */
                                /* iteration, [1, 100000]; SIM_F_ITERS counts */
                                /* these                                     */
+    int32_t newton_keep_best;  /* NEWTON, 0 or 1: end each substep at the   */
+                               /* evaluated Newton iterate of smallest      */
+                               /* residual (the earliest of equals), not at */
+                               /* the last; 0 is the paper's fixed budget   */
 } sim_desc_t;
 
 typedef struct sim sim_t;

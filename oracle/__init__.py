@@ -83,6 +83,7 @@ class Batch(C.Structure):
         ("ctrl_alpha", C.c_double), ("ctrl_offset", C.c_double),
         ("fallback", C.c_int32), ("fallback_k", C.c_int32),
         ("solver", C.c_int32), ("newton_iters", C.c_int32), ("pcr_iters", C.c_int32),
+        ("newton_keep_best", C.c_int32),
     ]
 
 
@@ -167,6 +168,7 @@ class Oracle:
         b.solver = int(over.get("solver", getattr(wl, "solver", SOLVER_JACOBI)))
         b.newton_iters = int(over.get("newton_iters", getattr(wl, "newton_iters", 4)))
         b.pcr_iters = int(over.get("pcr_iters", getattr(wl, "pcr_iters", 20)))
+        b.newton_keep_best = int(over.get("newton_keep_best", 0))
         self.batch = b
         self.n = n
         self.B = (np.asarray(g("n_modules"), np.int64) * np.asarray(g("segs_per_module"), np.int64))

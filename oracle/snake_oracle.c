@@ -481,6 +481,11 @@ typedef struct {
     double* nAz;
     double* nMq;
     double* nu;         /* [B*6] W J^T v per body */
+    double* kx;         /* [B*6] the kept (best) Newton iterate: x or the
+                         * linearised displacement */
+    double* kq;         /* [B*4] */
+    double* kl_j;       /* [B*6] */
+    double* kl_c;       /* [B*3] */
 } scratch_t;
 
 static void scratch_alloc(scratch_t* w, const snake_ctx* c)
@@ -518,6 +523,10 @@ static void scratch_alloc(scratch_t* w, const snake_ctx* c)
     w->nAz = (double*)calloc(r3, sizeof(double));
     w->nMq = (double*)calloc(r3, sizeof(double));
     w->nu = (double*)calloc((size_t)B * 6, sizeof(double));
+    w->kx = (double*)calloc((size_t)B * 6, sizeof(double));
+    w->kq = (double*)calloc((size_t)B * 4, sizeof(double));
+    w->kl_j = (double*)calloc((size_t)B * 6, sizeof(double));
+    w->kl_c = (double*)calloc((size_t)B * 3, sizeof(double));
 }
 
 static void scratch_free(scratch_t* w)
@@ -552,6 +561,10 @@ static void scratch_free(scratch_t* w)
     free(w->nAz);
     free(w->nMq);
     free(w->nu);
+    free(w->kx);
+    free(w->kq);
+    free(w->kl_j);
+    free(w->kl_c);
 }
 
 /* Predicted positions of a first-order implicit step: gravity on the linear
@@ -1045,7 +1058,10 @@ static void pcr_solve(const snake_ctx* c, scratch_t* W, int n_it)
  * solves, else solve eq. schur_system for the multiplier increment with
  * n_pcr inner iterations and apply lambda += dl, x += W J^T dl (rotations
  * as in the Jacobi update; in linearised mode into the accumulated
- * displacement, as there).  Returns the inner iterations run. */
+ * displacement, as there).  With newton_keep_best the substep ends at the
+ * evaluated iterate with the smallest residual (the earliest of equals),
+ * which a fixed budget otherwise leaves to chance where the iterates cycle.
+ * Returns the inner iterations run. */
 static int newton_pcr(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* x, double* q,
                       double* lam_j, double* lam_c, int n_newton, int n_pcr, double tol, double* res,
                       int* status)
@@ -1054,6 +1070,9 @@ static int newton_pcr(const orc_batch* b, const snake_ctx* c, scratch_t* W, doub
     int B = c->B;
     int its = 0;
     double r = 0.0;
+    double best = INFINITY;
+    size_t nj6 = sizeof(double) * 6 * (size_t)(c->nj > 0 ? c->nj : 1);
+    size_t nc3 = sizeof(double) * 3 * (size_t)B;
     if (c->linear) {
         memcpy(W->xt, x, sizeof(double) * 3 * (size_t)B);
         memcpy(W->qt, q, sizeof(double) * 4 * (size_t)B);
@@ -1070,6 +1089,17 @@ static int newton_pcr(const orc_batch* b, const snake_ctx* c, scratch_t* W, doub
         }
         double rf = friction_residual(c, W, lam_c);
         if (rf > r || rf != rf) r = rf;
+        if (b->newton_keep_best && r < best) {
+            best = r;
+            if (c->linear) {
+                memcpy(W->kx, W->acc, sizeof(double) * 6 * (size_t)B);
+            } else {
+                memcpy(W->kx, x, sizeof(double) * 3 * (size_t)B);
+                memcpy(W->kq, q, sizeof(double) * 4 * (size_t)B);
+            }
+            memcpy(W->kl_j, lam_j, nj6);
+            memcpy(W->kl_c, lam_c, nc3);
+        }
         if (!isfinite(r)) {
             *status |= ORC_STATUS_NONFINITE;
             break;
@@ -1098,6 +1128,20 @@ static int newton_pcr(const orc_batch* b, const snake_ctx* c, scratch_t* W, doub
                 if (!is_fixed(c, i)) q_apply_rotvec(q + 4 * i, dth);
             }
         }
+    }
+    /* with keep_best, end at the best evaluated iterate instead */
+    if (b->newton_keep_best && !(r <= best) && isfinite(best)) {
+        r = best;
+        if (c->linear) {
+            memcpy(W->acc, W->kx, sizeof(double) * 6 * (size_t)B);
+        } else {
+            memcpy(x, W->kx, sizeof(double) * 3 * (size_t)B);
+            memcpy(q, W->kq, sizeof(double) * 4 * (size_t)B);
+        }
+        memcpy(lam_j, W->kl_j, nj6);
+        memcpy(lam_c, W->kl_c, nc3);
+        /* no status change: an iterate at or below tol ends the loop
+         * itself, so the best one here is above tol whenever tol > 0 */
     }
     if (c->linear) {
         for (int i = 0; i < B; ++i) {

@@ -88,6 +88,8 @@ typedef struct {
                           /* warm start, GS the zero one                      */
     int32_t newton_iters; /* NEWTON: outer iterations per substep            */
     int32_t pcr_iters;    /* NEWTON: inner iterations per outer iteration     */
+    int32_t newton_keep_best; /* NEWTON: end at the evaluated iterate with the
+                               * smallest residual (the earliest of equals)  */
 } orc_batch;
 
 /* Batch state, owned by the caller.  Offsets: body_off / module_off /

@@ -71,7 +71,7 @@ class Desc(C.Structure):
         ("autotune", C.c_int32), ("map_waves", C.c_int32), ("map_min_seg", C.c_int32),
         ("map_grid", C.c_int32), ("mlp_fallback", C.c_int32), ("map_rows", C.c_int32),
         ("mlp_fallback_k", C.c_int32), ("solver", C.c_int32), ("newton_iters", C.c_int32),
-        ("pcr_iters", C.c_int32),
+        ("pcr_iters", C.c_int32), ("newton_keep_best", C.c_int32),
     ]
 
 
@@ -163,6 +163,7 @@ def make_desc(wl, **over):
     d.solver = int(over.get("solver", getattr(wl, "solver", SOLVER_JACOBI)))
     d.newton_iters = int(over.get("newton_iters", getattr(wl, "newton_iters", 4)))
     d.pcr_iters = int(over.get("pcr_iters", getattr(wl, "pcr_iters", 20)))
+    d.newton_keep_best = int(over.get("newton_keep_best", 0))
     return d, keep
 
 

@@ -123,6 +123,8 @@ int validate(const sim_desc_t* d, Sizes* z)
         if (d->newton_iters < 0 || d->newton_iters > 10000)
             return fail(SIM_EINVAL, "newton_iters must be in [0, 10000]");
         if (d->pcr_iters < 1 || d->pcr_iters > 100000) return fail(SIM_EINVAL, "pcr_iters must be in [1, 100000]");
+        if (d->newton_keep_best != 0 && d->newton_keep_best != 1)
+            return fail(SIM_EINVAL, "newton_keep_best must be 0 or 1");
     }
     z->newton = d->solver == SIM_SOLVER_NEWTON;
     if (mw != 0 && !d->autotune) {
@@ -643,6 +645,7 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     np.T_p = d->T_p;
     np.kappa_max = d->kappa_max;
     np.newton_iters = d->newton_iters;
+    np.keep_best = d->newton_keep_best;
     np.pcr_iters = d->pcr_iters;
 
     IParams& ip = w.ip;

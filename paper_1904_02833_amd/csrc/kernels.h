@@ -77,6 +77,7 @@ struct NParams {
     double lag_in, lag_de;  // exp(-h / tau)
     double amp, p_s, k_i, k_d, T_p, kappa_max;
     int newton_iters, pcr_iters;
+    int keep_best;          // end at the evaluated iterate of smallest residual
 };
 
 // Index-work parameters.

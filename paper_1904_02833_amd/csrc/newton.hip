@@ -215,6 +215,9 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
     constexpr int NWV = SEG > 64 ? SEG / 64 : 1;
     __shared__ double xbuf[2 * NWV * 8];   // two buffers used in turn
     __shared__ double red[2 * NWV];
+    // the kept (best) iterate of each lane: x, q, stretch, bend-twist and
+    // contact multipliers (each lane reads and writes only its own row)
+    __shared__ double kept[WG][16];
     int xph = 0, rph = 0;   // which buffer the next exchange / reduction takes
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int idx = blockIdx.x * (WG / SEG) + t / SEG;
@@ -418,7 +421,7 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
                 lc = zero;
             }
 
-            double r = 0.0;
+            double r = 0.0, best = INFINITY;
             int its = 0;
             for (int k = 0;; ++k) {
                 // blocks at the current iterate
@@ -452,6 +455,15 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
                 }
                 if (!(rl <= INFINITY)) rl = INFINITY;   // NaN
                 r = seg_reduce<SEG, true>(rl, lane, wv, red, rph);
+                if (Q.keep_best && r < best) {
+                    best = r;
+                    double* kp = kept[t];
+                    kp[0] = x.x; kp[1] = x.y; kp[2] = x.z;
+                    kp[3] = q.w; kp[4] = q.x; kp[5] = q.y; kp[6] = q.z;
+                    kp[7] = ls.x; kp[8] = ls.y; kp[9] = ls.z;
+                    kp[10] = lb.x; kp[11] = lb.y; kp[12] = lb.z;
+                    kp[13] = lc.x; kp[14] = lc.y; kp[15] = lc.z;
+                }
                 if (!(r < INFINITY)) {
                     status |= kStatusNonfinite;
                     break;
@@ -619,6 +631,18 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
                     x = x + uf;
                     q = qturn(q, ut);
                 }
+            }
+            if (Q.keep_best && !(r <= best) && best < INFINITY) {
+                // end at the best evaluated iterate instead of the last
+                r = best;
+                const double* kp = kept[t];
+                x = d3(kp[0], kp[1], kp[2]);
+                q = DQ{kp[3], kp[4], kp[5], kp[6]};
+                ls = d3(kp[7], kp[8], kp[9]);
+                lb = d3(kp[10], kp[11], kp[12]);
+                lc = d3(kp[13], kp[14], kp[15]);
+                // (no status change: an iterate at or below tol ends the loop
+                // itself, so the best one here is above tol whenever tol > 0)
             }
             itstep += its;
             rstep = fmaxf(rstep, (float)r);

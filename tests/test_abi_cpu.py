@@ -128,6 +128,7 @@ def test_descriptor_validation(L, field, value, msg):
     (dict(solver=1, newton_iters=-1), "newton_iters"),
     (dict(solver=1, newton_iters=10001), "newton_iters"),
     (dict(solver=1, pcr_iters=0), "pcr_iters"),
+    (dict(solver=1, newton_keep_best=2), "newton_keep_best"),
 ])
 def test_solver_descriptor_validation(L, over, msg):
     rc, _, err = ws_bytes(L, W.custom([2, 2], 8), **over)

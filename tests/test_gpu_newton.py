@@ -194,3 +194,16 @@ def test_newton_previous_multiplier_start_whole_step():
     assert np.array_equal(np.asarray(g["iters"]), o.iters)
     for k in keys:
         assert err[k].max() <= max(TOL, 2 * spread[k].max()), k
+
+
+def test_newton_keep_best_matches_oracle():
+    """newton_keep_best: each substep ends at its best evaluated Newton
+    iterate (kept per lane in LDS), as the oracle's does."""
+    wl = W.make("uneven", n_snakes=32)
+    st = state_after(wl, 10)
+    over = dict(solver=snk.SOLVER_NEWTON, newton_iters=8, pcr_iters=20, newton_keep_best=1)
+    o, g = advance_both(wl, st, **over)
+    plain, _ = advance_both(wl, st, solver=snk.SOLVER_NEWTON, newton_iters=8, pcr_iters=20)
+    assert np.all(o.residual <= plain.residual)
+    assert np.any(o.residual < plain.residual)
+    check(o, g, wl, "newton keep best")

@@ -151,3 +151,32 @@ def test_newton_previous_multipliers_start_as_jacobi_does():
     for k in ("x", "q", "lam_j", "lam_c"):
         ref = np.abs(getattr(b, k)).max()
         assert np.abs(getattr(a, k) - getattr(b, k)).max() <= 1e-9 * ref, k
+
+
+def test_newton_keep_best_ends_at_the_best_iterate():
+    """With newton_keep_best the substep ends at the Newton iterate of
+    smallest residual: the same state, bit for bit, as the plain solve
+    stopped after that many iterations (found by separate runs with 0..N
+    iterations); the inner iterations of all N still count."""
+    wl = W.make("short", n_snakes=8)
+    kw = dict(substeps=1, tol=0, pcr_iters=20)
+    st = moved_state(wl, substeps=1)
+    N = 8
+    runs = []
+    for k in range(N + 1):
+        o = load(newton(wl, newton_iters=k, **kw), st)
+        o.run(1)
+        runs.append(o)
+    kb = load(newton(wl, newton_iters=N, newton_keep_best=1, **kw), st)
+    kb.run(1)
+    assert np.all(kb.iters == N * 20)
+    cycled = 0
+    for s in range(wl.n_snakes):
+        r = np.array([o.residual[s] for o in runs])
+        best = int(np.argmin(r))          # the earliest of equal minima
+        cycled += best < N
+        assert kb.residual[s] == r[best]
+        d, ref = kb.snake(s), runs[best].snake(s)
+        for f in ("x", "q", "lam_j", "lam_c"):
+            assert np.array_equal(d[f], ref[f]), (s, f)
+    assert cycled > 0   # some snake's last iterate is not its best
