@@ -44,14 +44,14 @@ PEAK_FP32 = 157.3e12       # MI355X FP32 vector (published)
 # profiles/), keyed by workload, waves per workgroup and layout, with the digest of
 # the kernel sources they were taken on; a changed kernel reports null.
 MEASURED_TRAFFIC = {("uniform", 4, 1): 113.8e6, ("uneven", 4, 1): 696.3e6, ("stiff", 16, 1): 123.3e6}
-TRAFFIC_SOURCES_DIGEST = "6f9961ac0237831e:d9b1e61db4cc8d70:959545d7849e09a9:88568938c3414506"
+TRAFFIC_SOURCES_DIGEST = "6f9961ac0237831e:d9b1e61db4cc8d70:959545d7849e09a9:eddaaf41a8a0af4a"
 PEAK_HBM = 8.0e12
 # the same for the other solvers' kernels on the uniform batch (--solver),
 # with the digest of their sources
-SOLVER_TRAFFIC = {"newton": (323.9e6, ("newton.hip", "blocks.h", "device_math.h", "kernels.h"),
-                             "98730c19aa984fa0:d9b1e61db4cc8d70:959545d7849e09a9:88568938c3414506"),
+SOLVER_TRAFFIC = {"newton": (337.0e6, ("newton.hip", "blocks.h", "device_math.h", "kernels.h"),
+                             "4396631c732a5be7:d9b1e61db4cc8d70:959545d7849e09a9:eddaaf41a8a0af4a"),
                   "gs": (52.8e6, ("gs.hip", "blocks.h", "device_math.h", "kernels.h"),
-                         "a2a8923ebb111535:d9b1e61db4cc8d70:959545d7849e09a9:88568938c3414506")}
+                         "a2a8923ebb111535:d9b1e61db4cc8d70:959545d7849e09a9:eddaaf41a8a0af4a")}
 # Newton solver (FP64): operations per body per inner conjugate-residual
 # iteration and per Newton iteration outside it (block evaluation, residual,
 # rows, the two initial products, the update), counted from the compiled
@@ -74,6 +74,9 @@ FLOP_GS_SWEEP = 3 * FLOP_EVAL + 100
 # larger than the zero start's (both probes' iterations count in the totals)
 FALLBACK_K = 2
 CONVERGING_FALLBACK_K = 400
+# the same network on a batch of short snakes that fills the GPU
+SATURATED_SNAKES = 65536
+SATURATED_FALLBACK_K = 100
 STATE_BYTES = 4 * (13 + 13 + 9 + 9)   # per body: state in/out, multipliers in/out
 
 
@@ -157,11 +160,13 @@ def learned_comparison(n_steps):
 def learned_converging(n_steps=6):
     """Learned vs zero start where the solve converges within its budget:
     the short-snake batch (6 or 8 bodies), residual 1e-4 with at most 30 000
-    iterations.  The network learns the converged multipliers (tolerance
-    1e-7) at the states of a converged trajectory of training-seed snakes;
-    both starts then run from the same converged state of the evaluation
-    snakes, the learned one kept only where its residual after
-    CONVERGING_FALLBACK_K iterations is not larger than the zero start's."""
+    iterations, at its default size (4096 snakes: the step time follows the
+    slowest snake) and on a batch that fills the GPU (65 536 snakes).  The
+    network learns the converged multipliers (tolerance 1e-7) at the states
+    of a converged trajectory of training-seed snakes; both starts then run
+    from the same converged state of the evaluation snakes, the learned one
+    kept only where its residual after k iterations (CONVERGING_FALLBACK_K,
+    SATURATED_FALLBACK_K) is not larger than the zero start's."""
     import torch
 
     import paper_1904_02833_amd as snk
@@ -182,27 +187,44 @@ def learned_converging(n_steps=6):
     out = {"workload": f"short: {ev.n_snakes} snakes of 6 or 8 bodies, residual<=1e-4, max {ev.iters} iterations",
            "fallback_k": CONVERGING_FALLBACK_K,
            "train": {"rows": int(ds.features.shape[0]), "seconds": t_train, "loss_by_epoch": losses}}
-    for name in ("plain", "learned"):
-        sim = (snk.Sim(ev) if name == "plain"
-               else warmstart.learned_sim(ev, net, mlp_fallback_k=CONVERGING_FALLBACK_K))
-        sim.write(**state)
-        sim.step(1)
-        torch.cuda.synchronize()
-        r0 = sim.read("iters_total")["iters_total"].copy()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(sim.stream)
-        for _ in range(n_steps):
+
+    def compare(ev, state, k, n_steps):
+        res = {}
+        for name in ("plain", "learned"):
+            sim = snk.Sim(ev) if name == "plain" else warmstart.learned_sim(ev, net, mlp_fallback_k=k)
+            sim.write(**state)
             sim.step(1)
-        e1.record(sim.stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / n_steps
-        r = sim.read("iters_total", "residual", "status")
-        its = (r["iters_total"] - r0) / (n_steps * ev.substeps)
-        out[name] = {"snake_steps_per_s": ev.n_snakes / (ms / 1e3), "ms_per_step": ms,
-                     "mean_iters_per_substep": float(its.mean()), "median_iters_per_substep": float(np.median(its)),
-                     "not_converged_last_step": int(np.sum((r["status"] & 2) != 0)),
-                     "fell_back_last_step": int(np.sum((r["status"] & 4) != 0))}
-        sim.close()
+            torch.cuda.synchronize()
+            r0 = sim.read("iters_total")["iters_total"].copy()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(sim.stream)
+            for _ in range(n_steps):
+                sim.step(1)
+            e1.record(sim.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / n_steps
+            r = sim.read("iters_total", "residual", "status")
+            its = (r["iters_total"] - r0) / (n_steps * ev.substeps)
+            res[name] = {"snake_steps_per_s": ev.n_snakes / (ms / 1e3), "ms_per_step": ms,
+                         "mean_iters_per_substep": float(its.mean()),
+                         "median_iters_per_substep": float(np.median(its)),
+                         "not_converged_last_step": int(np.sum((r["status"] & 2) != 0)),
+                         "fell_back_last_step": int(np.sum((r["status"] & 4) != 0))}
+            sim.close()
+        return res
+
+    out.update(compare(ev, state, CONVERGING_FALLBACK_K, n_steps))
+    # A batch that fills the GPU (16 snakes per wave slot): the step time then
+    # follows the mean iteration count rather than the slowest snake's.
+    big = W.make("short", n_snakes=SATURATED_SNAKES)
+    big.tol, big.iters = 1e-4, 30000
+    lead = snk.Sim(big, tol=1e-7, iters=60000)
+    lead.step(6)
+    big_state = lead.read()
+    lead.close()
+    out["saturated"] = {"workload": f"short: {big.n_snakes} snakes, residual<=1e-4, max {big.iters} iterations",
+                        "fallback_k": SATURATED_FALLBACK_K,
+                        **compare(big, big_state, SATURATED_FALLBACK_K, 4)}
     return out
 
 
