@@ -8,7 +8,9 @@ library.  Inputs come from the shared seeded generator in ``workloads``.
 State arrays here are array-of-structures per body, float64:
 ``x[N,3]``, ``q[N,4]`` (w,x,y,z), ``v[N,3]``, ``w[N,3]``, ``p[Mtot,2]``,
 ``cmd[Mtot]``, ``lam_j[Jtot,6]`` (stretch xyz, twist, bend_y, bend_z) and
-``lam_c[N,3]`` (normal, tangential x, tangential y).
+``lam_c[N,3]`` (normal, tangential x, tangential y).  A wheel carriage
+(``FLAG_WHEELS``) adds ``wx[2N,3]``, ``wq[2N,4]``, ``wv``, ``ww`` (wheel 2i+k
+of body i) and ``lam_w[2N,9]`` (hinge position, hinge axis, contact).
 """
 from __future__ import annotations
 
@@ -28,6 +30,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 FLAG_FIXED_ROOT = 1
 FLAG_NO_GROUND = 2
 FLAG_LINEARISED = 8
+FLAG_WHEELS = 16
 WARM_ZERO, WARM_PREV, WARM_GIVEN = 0, 1, 2
 STATUS_NONFINITE, STATUS_NOT_CONVERGED = 1, 2
 SOLVER_JACOBI, SOLVER_NEWTON, SOLVER_GS = 0, 1, 2
@@ -89,7 +92,8 @@ class Batch(C.Structure):
 
 class State(C.Structure):
     _fields_ = [(n, _P) for n in ("x", "q", "v", "w", "p", "cmd", "lam_j", "lam_c",
-                                  "residual", "iters", "status", "iters_total", "step")]
+                                  "residual", "iters", "status", "iters_total", "step",
+                                  "wx", "wq", "wv", "ww", "lam_w")]
 
 
 def _declare(L):
@@ -101,6 +105,8 @@ def _declare(L):
     L.orc_run.restype = C.c_int
     L.orc_assemble.argtypes = [bp, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P]
     L.orc_assemble.restype = C.c_int
+    L.orc_assemble_wheels.argtypes = [bp, C.c_int32] + [_P] * 9
+    L.orc_assemble_wheels.restype = C.c_int
     L.orc_predict_snake.argtypes = [bp, C.c_int32, _P, _P, _P, _P, C.c_double]
     L.orc_index.argtypes = [bp] + [_P] * 7
     L.orc_pre_substep.argtypes = [bp, C.c_int32, C.c_int32] + [_P] * 7
@@ -193,6 +199,15 @@ class Oracle:
         self.status = np.zeros(n, np.int32)
         self.iters_total = np.zeros(n, np.int64)
         self.step = np.zeros(n, np.int64)
+        self.wheels = bool(b.flags & FLAG_WHEELS)
+        if self.wheels:
+            if b.solver != SOLVER_JACOBI or b.warm != WARM_ZERO:
+                raise ValueError("a wheel carriage takes the Jacobi solver from the zero start")
+            self.wx = np.zeros((2 * N, 3))
+            self.wq = np.zeros((2 * N, 4))
+            self.wv = np.zeros((2 * N, 3))
+            self.ww = np.zeros((2 * N, 3))
+            self.lam_w = np.zeros((2 * N, 9))
         self._state()
         self.L.orc_init_state(C.byref(self.batch), C.byref(self.st))
 
@@ -201,6 +216,9 @@ class Oracle:
         for f in ("x", "q", "v", "w", "p", "cmd", "lam_j", "lam_c", "residual", "iters",
                   "status", "iters_total", "step"):
             setattr(s, f, _ptr(getattr(self, f)))
+        if self.wheels:
+            for f in ("wx", "wq", "wv", "ww", "lam_w"):
+                setattr(s, f, _ptr(getattr(self, f)))
         self.st = s
 
     # -- stepping ---------------------------------------------------------
@@ -213,7 +231,8 @@ class Oracle:
         contiguous snake ranges run concurrently (ctypes releases the GIL)."""
         s0, s1 = (0, self.n) if snakes is None else snakes
         if threads <= 1 or s1 - s0 <= 1:
-            self.L.orc_run(C.byref(self.batch), C.byref(self.st), s0, s1, int(n_steps))
+            if self.L.orc_run(C.byref(self.batch), C.byref(self.st), s0, s1, int(n_steps)) != 0:
+                raise ValueError("orc_run refused the batch")
             return self
         cost = self.B[s0:s1].astype(np.float64)
         cuts = np.searchsorted(np.cumsum(cost), np.linspace(0, cost.sum(), threads + 1)[1:-1])
@@ -231,9 +250,13 @@ class Oracle:
         b0, b1 = self.body_off[s], self.body_off[s + 1]
         j0, j1 = self.joint_off[s], self.joint_off[s + 1]
         m0, m1 = self.module_off[s], self.module_off[s + 1]
-        return dict(x=self.x[b0:b1], q=self.q[b0:b1], v=self.v[b0:b1], w=self.w[b0:b1],
-                    p=self.p[m0:m1], cmd=self.cmd[m0:m1], lam_j=self.lam_j[j0:j1],
-                    lam_c=self.lam_c[b0:b1])
+        d = dict(x=self.x[b0:b1], q=self.q[b0:b1], v=self.v[b0:b1], w=self.w[b0:b1],
+                 p=self.p[m0:m1], cmd=self.cmd[m0:m1], lam_j=self.lam_j[j0:j1],
+                 lam_c=self.lam_c[b0:b1])
+        if self.wheels:
+            d.update(wx=self.wx[2 * b0:2 * b1], wq=self.wq[2 * b0:2 * b1], wv=self.wv[2 * b0:2 * b1],
+                     ww=self.ww[2 * b0:2 * b1], lam_w=self.lam_w[2 * b0:2 * b1])
+        return d
 
     def assemble(self, s, x, q, xp, p):
         """Dense C, J, W, comp of snake s at configuration (x, q)."""
@@ -248,6 +271,28 @@ class Oracle:
         self.L.orc_assemble(C.byref(self.batch), int(s), _ptr(x), _ptr(q), _ptr(xp), _ptr(p),
                             _ptr(Cv), _ptr(J), _ptr(W), _ptr(comp))
         return Cv, J, W, comp
+
+    def assemble_wheels(self, s, x, q, xp, qp, p):
+        """Dense C, J, W, comp of wheel-carriage snake s: x, q, xp, qp hold
+        its B segments then its 2B wheels; 3 rows per block (a hinge axis
+        block's spin row is all zero)."""
+        B = int(self.B[s])
+        ground = 0 if (self.batch.flags & FLAG_NO_GROUND) else 1
+        rows = 6 * (B - 1) + 3 * 2 * B * (2 + ground)
+        ncol = 6 * 3 * B
+        Cv, J, W, comp = np.zeros(rows), np.zeros((rows, ncol)), np.zeros((ncol, ncol)), np.zeros(rows)
+        x, q, xp, qp, p = (np.ascontiguousarray(a, np.float64) for a in (x, q, xp, qp, p))
+        got = self.L.orc_assemble_wheels(C.byref(self.batch), int(s), _ptr(x), _ptr(q), _ptr(xp), _ptr(qp),
+                                         _ptr(p), _ptr(Cv), _ptr(J), _ptr(W), _ptr(comp))
+        assert got == rows
+        return Cv, J, W, comp
+
+    def predict_bodies(self, s, x, q, v, w, h):
+        """The prediction stage on arrays holding all bodies of snake s (for
+        a wheel carriage: segments, then wheels); returns new arrays."""
+        arrs = [np.array(a, np.float64, order="C") for a in (x, q, v, w)]
+        self.L.orc_predict_snake(C.byref(self.batch), int(s), *[_ptr(a) for a in arrs], float(h))
+        return arrs
 
     def predict(self, s, h):
         """Apply the prediction stage to snake s in place (returns its views)."""

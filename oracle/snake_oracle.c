@@ -175,6 +175,14 @@ typedef struct {
     double Ib[3];               /* principal inertia in the body frame */
     double a_s, a_b, a_t;       /* joint compliance = per-length value * L */
     double mu, relax;
+    /* wheel carriage: bodies 0..B-1 are the segments, B + 2i + k the wheels
+     * of segment i; NB bodies in all */
+    int wheels, NB;
+    double mw, rw, dw, hw;      /* wheel mass, radius, lateral offset, drop */
+    double Iwh[3];              /* wheel inertia in its frame (axle e_y) */
+    const double* anchor;       /* [2B*6] per wheel: contact point at the
+                                 * start of the substep (world) and its arm
+                                 * in the wheel frame */
 } snake_ctx;
 
 static void make_ctx(const orc_batch* b, int s, snake_ctx* c)
@@ -200,11 +208,29 @@ static void make_ctx(const orc_batch* b, int s, snake_ctx* c)
     c->a_t = b->alpha_t[s] * c->L;
     c->mu = b->mu[s];
     c->relax = b->relax;
+    c->wheels = (b->flags & ORC_FLAG_WHEELS) ? 1 : 0;
+    c->NB = c->wheels ? 3 * c->B : c->B;
+    /* a thin disc: axial inertia m r^2 / 2, diametral m r^2 / 4 */
+    c->mw = c->m / 8.0;
+    c->rw = 0.5 * c->R;
+    c->dw = c->R;
+    c->hw = 0.5 * c->R;
+    c->Iwh[0] = 0.25 * c->mw * c->rw * c->rw;
+    c->Iwh[1] = 0.5 * c->mw * c->rw * c->rw;
+    c->Iwh[2] = c->Iwh[0];
+    c->anchor = NULL;
 }
 
 static int is_fixed(const snake_ctx* c, int i) { return c->fixed_root && i == 0; }
 
-static double inv_mass(const snake_ctx* c, int i) { return is_fixed(c, i) ? 0.0 : 1.0 / c->m; }
+static double inv_mass(const snake_ctx* c, int i)
+{
+    if (is_fixed(c, i)) return 0.0;
+    return i >= c->B ? 1.0 / c->mw : 1.0 / c->m;
+}
+
+/* principal inertia of body i in its own frame */
+static const double* body_inertia(const snake_ctx* c, int i) { return i >= c->B ? c->Iwh : c->Ib; }
 
 /* world inverse inertia R diag(1/I) R^T (zero for a fixed body) */
 static void inv_inertia_world(const snake_ctx* c, int i, const double* q, double* Iinv)
@@ -216,17 +242,17 @@ static void inv_inertia_world(const snake_ctx* c, int i, const double* q, double
     double R[9], RT[9], D[9] = {0}, T[9];
     q_to_matrix(q, R);
     m3_transpose(R, RT);
-    for (int k = 0; k < 3; ++k) D[4 * k] = 1.0 / c->Ib[k];
+    for (int k = 0; k < 3; ++k) D[4 * k] = 1.0 / body_inertia(c, i)[k];
     m3_mul(R, D, T);
     m3_mul(T, RT, Iinv);
 }
 
-static void inertia_world(const snake_ctx* c, const double* q, double* Iw)
+static void inertia_world(const snake_ctx* c, int i, const double* q, double* Iw)
 {
     double R[9], RT[9], D[9] = {0}, T[9];
     q_to_matrix(q, R);
     m3_transpose(R, RT);
-    for (int k = 0; k < 3; ++k) D[4 * k] = c->Ib[k];
+    for (int k = 0; k < 3; ++k) D[4 * k] = body_inertia(c, i)[k];
     m3_mul(R, D, T);
     m3_mul(T, RT, Iw);
 }
@@ -244,7 +270,21 @@ static int body_degree(int i, int B, int ground)
 /* constraint blocks                                                    */
 /* ------------------------------------------------------------------ */
 
-enum { BLK_STRETCH = 0, BLK_BEND = 1, BLK_CONTACT = 2 };
+enum { BLK_STRETCH = 0, BLK_BEND = 1, BLK_CONTACT = 2, BLK_HINGE = 3, BLK_AXLE = 4, BLK_WHEEL = 5 };
+
+/* number of blocks touching body i of a wheel carriage: two per joint on
+ * each side and two per wheel for a segment; hinge position, hinge axis and
+ * contact for a wheel */
+static int carriage_degree(const snake_ctx* c, int i)
+{
+    if (i >= c->B) return 2 + c->ground;
+    return (i > 0 ? 2 : 0) + (i < c->B - 1 ? 2 : 0) + 4;
+}
+
+static int degree(const snake_ctx* c, int i)
+{
+    return c->wheels ? carriage_degree(c, i) : body_degree(i, c->B, c->ground);
+}
 
 typedef struct {
     int type, a, b;         /* b < 0 for a contact */
@@ -342,6 +382,104 @@ static void eval_contact(const snake_ctx* c, const double* x, const double* xp, 
     k->comp[0] = k->comp[1] = k->comp[2] = 0.0;
 }
 
+/* Hinge position (wheel side k): the wheel centre coincides with the point
+ * r_h = (0, +-dw, -hw) of its segment, the attachment form of
+ * eq. rigid_to_particle with the wheel centre as the attached point. */
+static void eval_hinge(const snake_ctx* c, int k_side, const double* xa, const double* qa, const double* xw,
+                       block_t* k)
+{
+    double Ra[9], rh[3] = {0.0, k_side == 0 ? c->dw : -c->dw, -c->hw}, ra[3], Sa[9];
+    q_to_matrix(qa, Ra);
+    m3_vec(Ra, rh, ra);
+    for (int d = 0; d < 3; ++d) k->C[d] = (xa[d] + ra[d]) - xw[d];
+    skew3(ra, Sa);
+    for (int r = 0; r < 3; ++r)
+        for (int col = 0; col < 3; ++col) {
+            double id = (r == col) ? 1.0 : 0.0;
+            k->Ja[6 * r + col] = id;
+            k->Ja[6 * r + 3 + col] = -Sa[3 * r + col];
+            k->Jb[6 * r + col] = -id;
+            k->Jb[6 * r + 3 + col] = 0.0;
+        }
+    k->comp[0] = k->comp[1] = k->comp[2] = 0.0;
+}
+
+/* Hinge axis: the relative rotation of the wheel in its segment's frame is
+ * a turn about the common y axis.  With e = conj(qa) qw (e_w >= 0) that is
+ * e_x = e_z = 0: the twist and z-bend rows of the bend-twist form at rest
+ * angle 0, rigid; the y row (the wheel's spin) is free and left at zero. */
+static void eval_axle(const snake_ctx* c, const double* qa, const double* qw, block_t* k)
+{
+    eval_bend(c, qa, qw, 0.0, k);
+    k->C[1] = 0.0;
+    for (int col = 0; col < 6; ++col) {
+        k->Ja[6 + col] = 0.0;
+        k->Jb[6 + col] = 0.0;
+    }
+    k->comp[0] = k->comp[1] = k->comp[2] = 0.0;
+}
+
+/* Contact point of a wheel (disc of radius rw, axle a = R(q) e_y) with the
+ * ground plane z = 0: the rim point lowest in z, x + r with
+ * r = -rw (e_z - a_z a) / |e_z - a_z a| (r = 0 for a disc lying flat). */
+static void wheel_low_point(const snake_ctx* c, const double* q, double* r)
+{
+    double R[9];
+    q_to_matrix(q, R);
+    double a[3] = {R[1], R[4], R[7]};
+    double u[3] = {-a[2] * a[0], -a[2] * a[1], 1.0 - a[2] * a[2]};
+    double n = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    for (int d = 0; d < 3; ++d) r[d] = n > 0.0 ? -c->rw * u[d] / n : 0.0;
+}
+
+/* Wheel contact (the non-interpenetration form of section "Rigid Body
+ * Joints and Contact" with the ground plane): C_n = z of the wheel's lowest
+ * rim point >= 0, Jacobian (e_z, r x e_z).  Friction rows measure the
+ * tangential slip of the wheel's material point that was the contact point
+ * at the start of the substep (world point p0, arm s0 in the wheel frame):
+ * C_t = x + R(q) s0 - p0 along x and y, Jacobian (e_t, (R s0) x e_t), so a
+ * wheel rolls without slip at the cost of its spin inertia only and slides
+ * sideways against the full friction cone. */
+static void eval_wheel_contact(const snake_ctx* c, const double* x, const double* q, const double* anc,
+                               block_t* k)
+{
+    double r[3], R[9], s[3];
+    wheel_low_point(c, q, r);
+    q_to_matrix(q, R);
+    m3_vec(R, anc + 3, s);
+    memset(k->Ja, 0, sizeof k->Ja);
+    memset(k->Jb, 0, sizeof k->Jb);
+    k->C[0] = x[2] + r[2];
+    k->C[1] = x[0] + s[0] - anc[0];
+    k->C[2] = x[1] + s[1] - anc[1];
+    /* (r x e_z), (s x e_x), (s x e_y) */
+    k->Ja[0 * 6 + 2] = 1.0;
+    k->Ja[0 * 6 + 3] = r[1];
+    k->Ja[0 * 6 + 4] = -r[0];
+    k->Ja[1 * 6 + 0] = 1.0;
+    k->Ja[1 * 6 + 4] = s[2];
+    k->Ja[1 * 6 + 5] = -s[1];
+    k->Ja[2 * 6 + 1] = 1.0;
+    k->Ja[2 * 6 + 3] = -s[2];
+    k->Ja[2 * 6 + 5] = s[0];
+    k->comp[0] = k->comp[1] = k->comp[2] = 0.0;
+}
+
+/* anchors of the wheels' friction rows from the start-of-substep pose */
+static void wheel_anchors(const snake_ctx* c, const double* xp, const double* qp, double* anc)
+{
+    for (int wi = 0; wi < 2 * c->B; ++wi) {
+        const double* x = xp + 3 * (c->B + wi);
+        const double* q = qp + 4 * (c->B + wi);
+        double r[3], R[9], RT[9];
+        wheel_low_point(c, q, r);
+        q_to_matrix(q, R);
+        m3_transpose(R, RT);
+        for (int d = 0; d < 3; ++d) anc[6 * wi + d] = x[d] + r[d];
+        m3_vec(RT, r, anc + 6 * wi + 3);
+    }
+}
+
 /* rest angle of joint j: intra-module joints follow their module's
  * pressure difference, joints between modules are straight */
 static double rest_angle(const orc_batch* b, const snake_ctx* c, const double* p, int j)
@@ -395,9 +533,34 @@ static void eval_blocks(const orc_batch* b, const snake_ctx* c, const double* x,
         ks->b = kb->b = j + 1;
         eval_stretch(c, x + 3 * j, q + 4 * j, x + 3 * (j + 1), q + 4 * (j + 1), ks);
         eval_bend(c, q + 4 * j, q + 4 * (j + 1), theta0[j], kb);
-        int d = body_degree(j, c->B, c->ground);
-        int d1 = body_degree(j + 1, c->B, c->ground);
+        int d = degree(c, j);
+        int d1 = degree(c, j + 1);
         ks->scale = kb->scale = c->relax / (double)(d > d1 ? d : d1);
+    }
+    if (c->wheels) {
+        for (int i = 0; i < c->B; ++i)
+            for (int s = 0; s < 2; ++s) {
+                int wb = c->B + 2 * i + s;
+                int dd = degree(c, i) > degree(c, wb) ? degree(c, i) : degree(c, wb);
+                block_t* kh = &blk[n++];
+                block_t* ka = &blk[n++];
+                kh->type = BLK_HINGE;
+                ka->type = BLK_AXLE;
+                kh->a = ka->a = i;
+                kh->b = ka->b = wb;
+                eval_hinge(c, s, x + 3 * i, q + 4 * i, x + 3 * wb, kh);
+                eval_axle(c, q + 4 * i, q + 4 * wb, ka);
+                kh->scale = ka->scale = c->relax / (double)dd;
+                if (c->ground) {
+                    block_t* kc = &blk[n++];
+                    kc->type = BLK_WHEEL;
+                    kc->a = wb;
+                    kc->b = -1;
+                    eval_wheel_contact(c, x + 3 * wb, q + 4 * wb, c->anchor + 6 * (2 * i + s), kc);
+                    kc->scale = c->relax / (double)degree(c, wb);
+                }
+            }
+        return;
     }
     if (c->ground)
         for (int i = 0; i < c->B; ++i) {
@@ -411,15 +574,28 @@ static void eval_blocks(const orc_batch* b, const snake_ctx* c, const double* x,
     (void)b;
 }
 
-static int n_blocks(const snake_ctx* c) { return 2 * c->nj + (c->ground ? c->B : 0); }
+/* blocks of one wheel: hinge position, hinge axis, contact (if ground) */
+static int wheel_blocks(const snake_ctx* c) { return 2 + c->ground; }
 
-/* lambda of block k inside the state arrays */
+static int n_blocks(const snake_ctx* c)
+{
+    if (c->wheels) return 2 * c->nj + 2 * c->B * wheel_blocks(c);
+    return 2 * c->nj + (c->ground ? c->B : 0);
+}
+
+/* lambda of block k inside the state arrays (for a wheel carriage lam_c
+ * holds the wheels' multipliers, 9 per wheel) */
 static double* block_lambda(const snake_ctx* c, double* lam_j, double* lam_c, const block_t* k, int idx)
 {
     if (k->type == BLK_CONTACT) return lam_c + 3 * k->a;
-    (void)c;
+    if (k->type == BLK_HINGE) return lam_c + 9 * (k->b - c->B);
+    if (k->type == BLK_AXLE) return lam_c + 9 * (k->b - c->B) + 3;
+    if (k->type == BLK_WHEEL) return lam_c + 9 * (k->a - c->B) + 6;
     return lam_j + 6 * (idx / 2) + 3 * (idx % 2);
 }
+
+/* multipliers of the contact-side array: 3 per body, or 9 per wheel */
+static size_t contact_lambdas(const snake_ctx* c) { return (size_t)(c->wheels ? 18 * c->B : 3 * c->B); }
 
 /* Gather the increments dl[block] onto body i in the fixed order
  * stretch_{i-1}, bend_{i-1}, stretch_i, bend_i, contact_i. */
@@ -428,6 +604,15 @@ static void gather_body(const snake_ctx* c, int i, const block_t* blk, const dou
 {
     dx[0] = dx[1] = dx[2] = 0.0;
     dth[0] = dth[1] = dth[2] = 0.0;
+    if (c->wheels && i >= c->B) {
+        /* a wheel: hinge position, hinge axis, contact */
+        int wi = i - c->B;
+        int k = 2 * c->nj + wheel_blocks(c) * wi;
+        add_jt(blk[k].Jb, w, Iinv, dl + 3 * k, dx, dth);
+        add_jt(blk[k + 1].Jb, w, Iinv, dl + 3 * (k + 1), dx, dth);
+        if (c->ground) add_jt(blk[k + 2].Ja, w, Iinv, dl + 3 * (k + 2), dx, dth);
+        return;
+    }
     if (i > 0) {
         int k = 2 * (i - 1);
         add_jt(blk[k].Jb, w, Iinv, dl + 3 * k, dx, dth);
@@ -438,7 +623,14 @@ static void gather_body(const snake_ctx* c, int i, const block_t* blk, const dou
         add_jt(blk[k].Ja, w, Iinv, dl + 3 * k, dx, dth);
         add_jt(blk[k + 1].Ja, w, Iinv, dl + 3 * (k + 1), dx, dth);
     }
-    if (c->ground) {
+    if (c->wheels) {
+        /* then its wheels' hinge position and axis, side 0 then side 1 */
+        for (int s = 0; s < 2; ++s) {
+            int k = 2 * c->nj + wheel_blocks(c) * (2 * i + s);
+            add_jt(blk[k].Ja, w, Iinv, dl + 3 * k, dx, dth);
+            add_jt(blk[k + 1].Ja, w, Iinv, dl + 3 * (k + 1), dx, dth);
+        }
+    } else if (c->ground) {
         int k = 2 * c->nj + i;
         add_jt(blk[k].Ja, w, Iinv, dl + 3 * k, dx, dth);
     }
@@ -486,12 +678,15 @@ typedef struct {
     double* kq;         /* [B*4] */
     double* kl_j;       /* [B*6] */
     double* kl_c;       /* [B*3] */
+    double* anc;        /* [2B*6] wheel friction anchors */
 } scratch_t;
 
 static void scratch_alloc(scratch_t* w, const snake_ctx* c)
 {
     int nb = n_blocks(c) + 1;
-    int B = c->B;
+    int B = c->NB;
+    size_t nlc = contact_lambdas(c);
+    w->anc = (double*)calloc((size_t)c->B * 12, sizeof(double));
     w->blk = (block_t*)calloc((size_t)nb, sizeof(block_t));
     w->blk0 = (block_t*)calloc((size_t)nb, sizeof(block_t));
     w->dl = (double*)calloc((size_t)nb * 3, sizeof(double));
@@ -503,11 +698,11 @@ static void scratch_alloc(scratch_t* w, const snake_ctx* c)
     w->Iinv = (double*)calloc((size_t)B * 9, sizeof(double));
     w->theta0 = (double*)calloc((size_t)B, sizeof(double));
     w->lz_j = (double*)calloc((size_t)B * 6, sizeof(double));
-    w->lz_c = (double*)calloc((size_t)B * 3, sizeof(double));
+    w->lz_c = (double*)calloc(nlc, sizeof(double));
     w->xs = (double*)calloc((size_t)B * 3, sizeof(double));
     w->qs = (double*)calloc((size_t)B * 4, sizeof(double));
     w->l0_j = (double*)calloc((size_t)B * 6, sizeof(double));
-    w->l0_c = (double*)calloc((size_t)B * 3, sizeof(double));
+    w->l0_c = (double*)calloc(nlc, sizeof(double));
     w->xz = (double*)calloc((size_t)B * 3, sizeof(double));
     w->qz = (double*)calloc((size_t)B * 4, sizeof(double));
     size_t r3 = (size_t)(n_blocks(c) + 1) * 3;
@@ -526,11 +721,12 @@ static void scratch_alloc(scratch_t* w, const snake_ctx* c)
     w->kx = (double*)calloc((size_t)B * 6, sizeof(double));
     w->kq = (double*)calloc((size_t)B * 4, sizeof(double));
     w->kl_j = (double*)calloc((size_t)B * 6, sizeof(double));
-    w->kl_c = (double*)calloc((size_t)B * 3, sizeof(double));
+    w->kl_c = (double*)calloc(nlc, sizeof(double));
 }
 
 static void scratch_free(scratch_t* w)
 {
+    free(w->anc);
     free(w->blk);
     free(w->blk0);
     free(w->dl);
@@ -572,7 +768,7 @@ static void scratch_free(scratch_t* w)
  * position-level step of length h. */
 static void predict(const snake_ctx* c, double* x, double* q, double* v, double* w)
 {
-    for (int i = 0; i < c->B; ++i) {
+    for (int i = 0; i < c->NB; ++i) {
         if (is_fixed(c, i)) {
             v[3 * i] = v[3 * i + 1] = v[3 * i + 2] = 0.0;
             w[3 * i] = w[3 * i + 1] = w[3 * i + 2] = 0.0;
@@ -581,7 +777,7 @@ static void predict(const snake_ctx* c, double* x, double* q, double* v, double*
         v[3 * i + 2] -= c->h * c->g;
         for (int d = 0; d < 3; ++d) x[3 * i + d] += c->h * v[3 * i + d];
         double Iw[9], Iinv[9], Lw[3], tq[3], dw[3];
-        inertia_world(c, q + 4 * i, Iw);
+        inertia_world(c, i, q + 4 * i, Iw);
         inv_inertia_world(c, i, q + 4 * i, Iinv);
         m3_vec(Iw, w + 3 * i, Lw);
         cross3(w + 3 * i, Lw, tq);
@@ -632,6 +828,50 @@ static double local_solves(const snake_ctx* c, scratch_t* W, double* lam_j, doub
             dl[0] = ln - l[0];
             dl[1] = lt0 - l[1];
             dl[2] = lt1 - l[2];
+        } else if (kb->type == BLK_WHEEL) {
+            /* the contact rule above with the wheel's own effective masses:
+             * K = J W J^T of the block, the normal row by K_nn, the
+             * tangential pair by its 2x2 block, then the Coulomb disc */
+            double cn = kb->C[0];
+            double rc = (l[0] > 0.0) ? fabs(cn) : (cn < 0.0 ? -cn : 0.0);
+            rc /= c->L;
+            if (rc > r || rc != rc) r = rc;
+            double K[9] = {0};
+            add_jwjt(kb->Ja, inv_mass(c, kb->a), W->Iinv + 9 * kb->a, K);
+            double ln = l[0] + kb->scale * (-cn / K[0]);
+            if (ln < 0.0) ln = 0.0;
+            double det = K[4] * K[8] - K[5] * K[7];
+            double y0 = (K[8] * kb->C[1] - K[5] * kb->C[2]) / det;
+            double y1 = (K[4] * kb->C[2] - K[7] * kb->C[1]) / det;
+            double lt0 = l[1] - kb->scale * y0;
+            double lt1 = l[2] - kb->scale * y1;
+            double cap = c->mu * ln;
+            double nt = sqrt(lt0 * lt0 + lt1 * lt1);
+            if (ln <= 0.0) {
+                lt0 = lt1 = 0.0;
+            } else if (nt > cap) {
+                lt0 *= cap / nt;
+                lt1 *= cap / nt;
+            }
+            dl[0] = ln - l[0];
+            dl[1] = lt0 - l[1];
+            dl[2] = lt1 - l[2];
+        } else if (kb->type == BLK_AXLE) {
+            /* the two rigid rows (x, z) solved together; the spin row
+             * carries nothing */
+            double K[9] = {0};
+            add_jwjt(kb->Ja, inv_mass(c, kb->a), W->Iinv + 9 * kb->a, K);
+            add_jwjt(kb->Jb, inv_mass(c, kb->b), W->Iinv + 9 * kb->b, K);
+            double r0 = kb->C[0], r2 = kb->C[2];
+            double rb = fabs(r0) > fabs(r2) ? fabs(r0) : fabs(r2);
+            if (r0 != r0 || r2 != r2) rb = r0 + r2;
+            if (rb > r || rb != rb) r = rb;
+            double det = K[0] * K[8] - K[2] * K[6];
+            double d0 = (K[8] * r0 - K[2] * r2) / det;
+            double d2 = (K[0] * r2 - K[6] * r0) / det;
+            dl[0] = -kb->scale * d0;
+            dl[1] = 0.0;
+            dl[2] = -kb->scale * d2;
         } else {
             double rhs[3], K[9] = {0}, Iinva[9], Iinvb[9], dlam[3];
             for (int d = 0; d < 3; ++d) rhs[d] = kb->C[d] + kb->comp[d] * l[d];
@@ -640,7 +880,7 @@ static double local_solves(const snake_ctx* c, scratch_t* W, double* lam_j, doub
                 double t = fabs(rhs[d]);
                 if (t > rb || t != t) rb = t;
             }
-            if (kb->type == BLK_STRETCH) rb /= c->L;
+            if (kb->type == BLK_STRETCH || kb->type == BLK_HINGE) rb /= c->L;
             if (rb > r || rb != rb) r = rb;
             memcpy(Iinva, W->Iinv + 9 * kb->a, sizeof Iinva);
             memcpy(Iinvb, W->Iinv + 9 * kb->b, sizeof Iinvb);
@@ -659,7 +899,7 @@ static double residual_at(const orc_batch* b, const snake_ctx* c, scratch_t* W, 
                           const double* q, double* lam_j, double* lam_c)
 {
     eval_blocks(b, c, x, q, W->xp, W->theta0, W->blk);
-    for (int i = 0; i < c->B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
+    for (int i = 0; i < c->NB; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
     return local_solves(c, W, lam_j, lam_c);
 }
 
@@ -674,8 +914,8 @@ static void apply_start(const orc_batch* b, const snake_ctx* c, scratch_t* W, do
         double* l = block_lambda(c, lam_j, lam_c, &W->blk[k], k);
         for (int d = 0; d < 3; ++d) W->dl[3 * k + d] = l[d];
     }
-    for (int i = 0; i < c->B; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
-    for (int i = 0; i < c->B; ++i) {
+    for (int i = 0; i < c->NB; ++i) inv_inertia_world(c, i, q + 4 * i, W->Iinv + 9 * i);
+    for (int i = 0; i < c->NB; ++i) {
         double dx[3], dth[3];
         gather_body(c, i, W->blk, W->dl, inv_mass(c, i), W->Iinv + 9 * i, dx, dth);
         for (int d = 0; d < 3; ++d) x[3 * i + d] += dx[d];
@@ -712,7 +952,7 @@ static int jacobi(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* 
                   double* lam_c, int k0, int kmax, double tol, int probe, double* res, int* status)
 {
     int nb = n_blocks(c);
-    int B = c->B;
+    int B = c->NB;
     if (c->linear) {
         memcpy(W->xt, x, sizeof(double) * 3 * (size_t)B);
         memcpy(W->qt, q, sizeof(double) * 4 * (size_t)B);
@@ -1282,9 +1522,9 @@ static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, d
                          double* lam_j, double* lam_c, int warm, int kmax, double tol, double* res,
                          int* status)
 {
-    int B = c->B;
+    int B = c->NB;
     size_t nj6 = sizeof(double) * 6 * (size_t)(c->nj > 0 ? c->nj : 1);
-    size_t nc3 = sizeof(double) * 3 * (size_t)B;
+    size_t nc3 = sizeof(double) * contact_lambdas(c);
     int fallback = (warm == ORC_WARM_GIVEN && b->fallback);
 
     if (b->solver == ORC_SOLVER_NEWTON) {
@@ -1372,7 +1612,7 @@ static int solve_substep(const orc_batch* b, const snake_ctx* c, scratch_t* W, d
 static void finalize(const snake_ctx* c, const double* xp, const double* qp, const double* x,
                      const double* q, double* v, double* w)
 {
-    for (int i = 0; i < c->B; ++i) {
+    for (int i = 0; i < c->NB; ++i) {
         for (int d = 0; d < 3; ++d) v[3 * i + d] = (x[3 * i + d] - xp[3 * i + d]) / c->h;
         double qpc[4], dq[4];
         q_conj(qp + 4 * i, qpc);
@@ -1506,6 +1746,22 @@ void orc_init_state(const orc_batch* b, orc_state* st)
                 st->lam_c[3 * (bo + i) + d] = 0.0;
             }
         }
+        if (c.wheels && st->wx)
+            for (int wi = 0; wi < 2 * c.B; ++wi) {
+                int i = wi / 2;
+                double* x = st->wx + 3 * (2 * bo + wi);
+                double* q = st->wq + 4 * (2 * bo + wi);
+                x[0] = (i + 0.5) * c.L;
+                x[1] = (wi % 2 == 0) ? c.dw : -c.dw;
+                x[2] = c.R - c.hw;
+                q[0] = 1.0;
+                q[1] = q[2] = q[3] = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    st->wv[3 * (2 * bo + wi) + d] = 0.0;
+                    st->ww[3 * (2 * bo + wi) + d] = 0.0;
+                }
+                for (int d = 0; d < 9; ++d) st->lam_w[9 * (2 * bo + wi) + d] = 0.0;
+            }
         for (int j = 0; j < 6 * (c.B - 1); ++j) st->lam_j[6 * jo + j] = 0.0;
         for (int m = 0; m < c.M; ++m) {
             st->p[2 * (mo + m)] = st->p[2 * (mo + m) + 1] = 0.0;
@@ -1522,8 +1778,27 @@ void orc_init_state(const orc_batch* b, orc_state* st)
     }
 }
 
+/* a wheel carriage's bodies in one array: segments, then wheels */
+static double* join_bodies(const double* seg, const double* whl, int B, int k)
+{
+    double* o = (double*)malloc(sizeof(double) * (size_t)(3 * B * k));
+    memcpy(o, seg, sizeof(double) * (size_t)(B * k));
+    memcpy(o + (size_t)B * k, whl, sizeof(double) * (size_t)(2 * B * k));
+    return o;
+}
+
+static void split_bodies(double* o, double* seg, double* whl, int B, int k)
+{
+    memcpy(seg, o, sizeof(double) * (size_t)(B * k));
+    memcpy(whl, o + (size_t)B * k, sizeof(double) * (size_t)(2 * B * k));
+    free(o);
+}
+
 int orc_run(const orc_batch* b, orc_state* st, int32_t s0, int32_t s1, int32_t n_steps)
 {
+    if ((b->flags & ORC_FLAG_WHEELS) &&
+        (b->solver != ORC_SOLVER_JACOBI || b->warm != ORC_WARM_ZERO || !st->wx || !st->lam_w))
+        return -1;
     int64_t bo, jo, mo;
     offsets_of(b, s0, &bo, &jo, &mo);
     for (int s = s0; s < s1; ++s) {
@@ -1539,6 +1814,14 @@ int orc_run(const orc_batch* b, orc_state* st, int32_t s0, int32_t s1, int32_t n
         double* cmd = st->cmd + mo;
         double* lj = st->lam_j + 6 * jo;
         double* lc = st->lam_c + 3 * bo;
+        if (c.wheels) {
+            x = join_bodies(x, st->wx + 6 * bo, c.B, 3);
+            q = join_bodies(q, st->wq + 8 * bo, c.B, 4);
+            v = join_bodies(v, st->wv + 6 * bo, c.B, 3);
+            w = join_bodies(w, st->ww + 6 * bo, c.B, 3);
+            lc = st->lam_w + 18 * bo;
+            c.anchor = W.anc;
+        }
         for (int n = 0; n < n_steps; ++n) {
             snake_commands(b, s, mo, st->step[s], cmd);
             double rmax = 0.0;
@@ -1558,8 +1841,9 @@ int orc_run(const orc_batch* b, orc_state* st, int32_t s0, int32_t s1, int32_t n
                             lag_update(p[2 * m + 1], a < 0.0 ? -a : 0.0, c.h, b->tau_inf, b->tau_def);
                     }
                 for (int j = 0; j < c.nj; ++j) W.theta0[j] = rest_angle(b, &c, p, j);
-                memcpy(W.xp, x, sizeof(double) * 3 * (size_t)c.B);
-                memcpy(W.qp, q, sizeof(double) * 4 * (size_t)c.B);
+                memcpy(W.xp, x, sizeof(double) * 3 * (size_t)c.NB);
+                memcpy(W.qp, q, sizeof(double) * 4 * (size_t)c.NB);
+                if (c.wheels) wheel_anchors(&c, W.xp, W.qp, W.anc);
                 predict(&c, x, q, v, w);
                 double r;
                 it += solve_substep(b, &c, &W, x, q, lj, lc, b->warm, b->iters, b->tol, &r, &status);
@@ -1571,6 +1855,12 @@ int orc_run(const orc_batch* b, orc_state* st, int32_t s0, int32_t s1, int32_t n
             st->status[s] = status;
             st->iters_total[s] += it;
             st->step[s] += 1;
+        }
+        if (c.wheels) {
+            split_bodies(x, st->x + 3 * bo, st->wx + 6 * bo, c.B, 3);
+            split_bodies(q, st->q + 4 * bo, st->wq + 8 * bo, c.B, 4);
+            split_bodies(v, st->v + 3 * bo, st->wv + 6 * bo, c.B, 3);
+            split_bodies(w, st->w + 3 * bo, st->ww + 6 * bo, c.B, 3);
         }
         scratch_free(&W);
         bo += c.B;
@@ -1589,17 +1879,20 @@ void orc_predict_snake(const orc_batch* b, int32_t snake, double* x, double* q, 
     predict(&c, x, q, v, w);
 }
 
-int orc_assemble(const orc_batch* b, int32_t snake, const double* x, const double* q,
-                 const double* xp, const double* p, double* C, double* J, double* W, double* comp)
+static int assemble(const orc_batch* b, snake_ctx c, const double* x, const double* q, const double* xp,
+                    const double* qp, const double* p, double* C, double* J, double* W, double* comp)
 {
-    snake_ctx c;
-    make_ctx(b, snake, &c);
     int nb = n_blocks(&c);
-    int B = c.B;
+    int B = c.NB;
     int ncol = 6 * B;
     block_t* blk = (block_t*)calloc((size_t)nb + 1, sizeof(block_t));
     double* th = (double*)calloc((size_t)B, sizeof(double));
+    double* anc = (double*)calloc((size_t)c.B * 12 + 1, sizeof(double));
     for (int j = 0; j < c.nj; ++j) th[j] = rest_angle(b, &c, p, j);
+    if (c.wheels) {
+        wheel_anchors(&c, xp, qp, anc);
+        c.anchor = anc;
+    }
     eval_blocks(b, &c, x, q, xp, th, blk);
     int rows = 3 * nb;
     memset(J, 0, sizeof(double) * (size_t)rows * (size_t)ncol);
@@ -1625,7 +1918,28 @@ int orc_assemble(const orc_batch* b, int32_t snake, const double* x, const doubl
     }
     free(blk);
     free(th);
+    free(anc);
     return rows;
+}
+
+int orc_assemble(const orc_batch* b, int32_t snake, const double* x, const double* q,
+                 const double* xp, const double* p, double* C, double* J, double* W, double* comp)
+{
+    snake_ctx c;
+    make_ctx(b, snake, &c);
+    c.wheels = 0;
+    c.NB = c.B;
+    return assemble(b, c, x, q, xp, NULL, p, C, J, W, comp);
+}
+
+int orc_assemble_wheels(const orc_batch* b, int32_t snake, const double* x, const double* q,
+                        const double* xp, const double* qp, const double* p, double* C, double* J,
+                        double* W, double* comp)
+{
+    snake_ctx c;
+    make_ctx(b, snake, &c);
+    if (!c.wheels) return -1;
+    return assemble(b, c, x, q, xp, qp, p, C, J, W, comp);
 }
 
 /* ------------------------------------------------------------------ */

@@ -25,7 +25,15 @@
  *     Newton iterations, each solving eq. schur_system with a fixed number
  *     of preconditioned conjugate-residual iterations (diagonal
  *     preconditioner), contact by a Fischer-Burmeister reformulation; or
- *     block Gauss-Seidel sweeps over the greedy block colouring.
+ *     block Gauss-Seidel sweeps over the greedy block colouring;
+ *   - optionally the wheeled carriage (section "Rigid Body Joints and
+ *     Contact"): every segment carries two rigid wheels on hinge joints, and
+ *     the wheels, not the segments, touch the ground, with Coulomb friction
+ *     at the wheel's contact point.  The paper gives no wheel dimensions;
+ *     here a wheel is a thin disc of radius R/2 and mass m/8 whose centre
+ *     sits at (0, +-R, -R/2) in its segment's frame, axle along the
+ *     segment's y axis (so a segment at rest has its centre at height R,
+ *     as without wheels).
  * Every floating-point quantity is double.  No fast-math.
  *
  * Memory layout: array-of-structures per body (x[3*i+k], q[4*i+k] with
@@ -39,6 +47,9 @@
 #define ORC_FLAG_FIXED_ROOT 1   /* body 0 has infinite mass and inertia     */
 #define ORC_FLAG_NO_GROUND 2    /* no ground plane, no contact blocks       */
 #define ORC_FLAG_LINEARISED 8   /* Jacobians frozen at the predicted state  */
+#define ORC_FLAG_WHEELS 16      /* wheel carriage: two wheels per segment on */
+                                /* hinge joints carry the ground contact    */
+                                /* (block-Jacobi solver, zero start only)    */
 
 #define ORC_CTRL_EXTERNAL 0
 #define ORC_CTRL_SERPENOID 1
@@ -108,6 +119,14 @@ typedef struct {
     int32_t* status;    /* [n_snakes] */
     int64_t* iters_total; /* [n_snakes] cumulative iterations */
     int64_t* step;      /* [n_snakes] step counter */
+    /* wheel carriage only (NULL otherwise): wheel 2i+k of body i (k = 0 on
+     * the +y side), same per-body layouts as above */
+    double* wx;         /* [N*2*3] */
+    double* wq;         /* [N*2*4] */
+    double* wv;         /* [N*2*3] */
+    double* ww;         /* [N*2*3] */
+    double* lam_w;      /* [N*2*9] hinge position (3), hinge axis (x, unused
+                         * spin row, z), wheel contact (normal, tx, ty) */
 } orc_state;
 
 /* offsets: body_off, joint_off, module_off, block_off each [n_snakes+1] */
@@ -132,6 +151,15 @@ int orc_run(const orc_batch* b, orc_state* s, int32_t s0, int32_t s1, int32_t n_
 int orc_assemble(const orc_batch* b, int32_t snake, const double* x, const double* q,
                  const double* xp, const double* p, double* C, double* J, double* W,
                  double* comp);
+
+/* The same for a wheel-carriage batch: x, q, xp, qp hold the snake's B
+ * segments followed by its 2B wheels (start-of-substep pose xp, qp, which
+ * anchors the wheels' friction rows); columns 6 per body in that order;
+ * rows 3 per block in block order (joints, then per wheel: hinge position,
+ * hinge axis with its free spin row all zero, contact if ground). */
+int orc_assemble_wheels(const orc_batch* b, int32_t snake, const double* x, const double* q,
+                        const double* xp, const double* qp, const double* p, double* C, double* J,
+                        double* W, double* comp);
 
 /* stages of one substep of one snake, exposed for tests */
 void orc_predict_snake(const orc_batch* b, int32_t snake, double* x, double* q, double* v,
