@@ -48,8 +48,8 @@ TRAFFIC_SOURCES_DIGEST = "6f9961ac0237831e:d9b1e61db4cc8d70:959545d7849e09a9:edd
 PEAK_HBM = 8.0e12
 # the same for the other solvers' kernels on the uniform batch (--solver),
 # with the digest of their sources
-SOLVER_TRAFFIC = {"newton": (337.0e6, ("newton.hip", "blocks.h", "device_math.h", "kernels.h"),
-                             "4396631c732a5be7:d9b1e61db4cc8d70:959545d7849e09a9:eddaaf41a8a0af4a"),
+SOLVER_TRAFFIC = {"newton": (337.0e6, ("newton.hip", "lanes.h", "blocks.h", "device_math.h", "kernels.h"),
+                             "fcc37ef4a1894212:8e25130f7604f42f:d9b1e61db4cc8d70:959545d7849e09a9:eddaaf41a8a0af4a"),
                   "gs": (52.8e6, ("gs.hip", "blocks.h", "device_math.h", "kernels.h"),
                          "a2a8923ebb111535:d9b1e61db4cc8d70:959545d7849e09a9:eddaaf41a8a0af4a")}
 # Newton solver (FP64): operations per body per inner conjugate-residual

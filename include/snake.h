@@ -111,6 +111,29 @@ extern "C" {
 /* ---- flags ---- */
 #define SIM_FLAG_FIXED_ROOT 1u /* body 0 of every snake is immovable         */
 #define SIM_FLAG_NO_GROUND 2u  /* no ground plane: no contact blocks         */
+#define SIM_FLAG_WHEELS 16u    /* the wheeled carriage (section "Rigid Body */
+                               /* Joints and Contact"): every segment       */
+                               /* carries two rigid wheels on hinge joints  */
+                               /* and the wheels, not the segments, touch   */
+                               /* the ground, with Coulomb friction at the  */
+                               /* wheel's contact point (so a snake rolls   */
+                               /* along its wheels and grips sideways, the  */
+                               /* anisotropic friction of section "Soft     */
+                               /* robotic snake model").  A wheel is a thin */
+                               /* disc of radius R/2 and mass m/8 centred   */
+                               /* at (0, +-R, -R/2) in its segment's frame, */
+                               /* axle along the segment's y axis (the      */
+                               /* paper gives no wheel dimensions).  Blocks */
+                               /* per wheel: hinge position (attachment     */
+                               /* form of eq. rigid_to_particle), hinge     */
+                               /* axis (two rigid rows: the bend-twist form */
+                               /* at rest angle 0 without its spin row),    */
+                               /* contact (normal at the lowest rim point,  */
+                               /* friction on the material point that       */
+                               /* touched at the start of the substep).     */
+                               /* Needs SIM_SOLVER_JACOBI, SIM_WARM_ZERO;   */
+                               /* computes in double; no autotune and no    */
+                               /* split substeps.  State in SIM_F_WHEEL_*.  */
 
 /* ---- per-snake status bits (field SIM_F_STATUS) ---- */
 #define SIM_STATUS_NONFINITE 1     /* residual became NaN or inf             */
@@ -135,7 +158,16 @@ extern "C" {
 #define SIM_F_STATUS (1u << 10)        /* int32 [n_snakes] SIM_STATUS_* bits */
 #define SIM_F_STEP (1u << 11)          /* int64 [n_snakes] step counter      */
 #define SIM_F_ITERS_TOTAL (1u << 12)   /* int64 [n_snakes] all iterations    */
-#define SIM_F_COUNT 13
+#define SIM_F_WHEEL_POS (1u << 13)     /* float [3][2N] wheel centres; wheel */
+                                       /* 2 b + k of body b, k = 0 on +y    */
+                                       /* (SIM_FLAG_WHEELS batches only)    */
+#define SIM_F_WHEEL_QUAT (1u << 14)    /* float [4][2N]                     */
+#define SIM_F_WHEEL_VEL (1u << 15)     /* float [3][2N]                     */
+#define SIM_F_WHEEL_ANGVEL (1u << 16)  /* float [3][2N] world frame         */
+#define SIM_F_LAMBDA_WHEEL (1u << 17)  /* float [9][2N] hinge position (3), */
+                                       /* hinge axis (x, spin row = 0, z),  */
+                                       /* contact (normal, tangent x, y)    */
+#define SIM_F_COUNT 18
 
 /* ---- index arrays (sim_read_index), all int32 ---- */
 #define SIM_IDX_BODY_OFF 0    /* [n_snakes+1] exclusive prefix sum of B       */

@@ -21,7 +21,7 @@ LAW_LAG, LAW_PAPER = 0, 1
 CTRL_EXTERNAL, CTRL_SERPENOID, CTRL_SCHEDULE = 0, 1, 2
 WARM_ZERO, WARM_PREV, WARM_MLP = 0, 1, 2
 SOLVER_JACOBI, SOLVER_NEWTON, SOLVER_GS = 0, 1, 2
-FLAG_FIXED_ROOT, FLAG_NO_GROUND = 1, 2
+FLAG_FIXED_ROOT, FLAG_NO_GROUND, FLAG_WHEELS = 1, 2, 16
 STATUS_NONFINITE, STATUS_NOT_CONVERGED, STATUS_FELL_BACK = 1, 2, 4
 
 # state fields: bit -> (name, dtype, rows, length key)
@@ -39,7 +39,13 @@ FIELDS = [
     ("status", np.int32, 1, "n"),
     ("step", np.int64, 1, "n"),
     ("iters_total", np.int64, 1, "n"),
+    ("wheel_pos", np.float32, 3, "W2"),
+    ("wheel_quat", np.float32, 4, "W2"),
+    ("wheel_vel", np.float32, 3, "W2"),
+    ("wheel_angvel", np.float32, 3, "W2"),
+    ("lambda_wheel", np.float32, 9, "W2"),
 ]
+WHEEL_FIELDS = ("wheel_pos", "wheel_quat", "wheel_vel", "wheel_angvel", "lambda_wheel")
 FIELD_BIT = {f[0]: 1 << k for k, f in enumerate(FIELDS)}
 INDEX = ["body_off", "joint_off", "module_off", "block_off", "blk_type", "blk_a", "blk_b",
          "blk_color", "degree", "bucket", "order"]
@@ -220,7 +226,8 @@ class Sim:
         _check(self.L.sim_mapping(self.h, mp))
         self.mapping = dict(waves=mp[0], min_seg=mp[1], grid=mp[2], tiles=mp[3], rows=mp[4])
         self._substeps = d.substeps
-        self._len = dict(n=self.n, N=self.N, J=self.J, Mt=self.Mt)
+        self._len = dict(n=self.n, N=self.N, J=self.J, Mt=self.Mt, W2=2 * self.N)
+        self.wheels = bool(d.flags & FLAG_WHEELS)
         del keep
 
     def __del__(self):
@@ -253,7 +260,7 @@ class Sim:
 
     def read(self, *names) -> dict:
         """Host copies of the named fields (all if none), SoA as stored."""
-        names = names or tuple(f[0] for f in FIELDS)
+        names = names or tuple(f[0] for f in FIELDS if self.wheels or f[0] not in WHEEL_FIELDS)
         ptrs = (_P * len(FIELDS))()
         out, mask = {}, 0
         for name in names:

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "carriage.h"
 #include "kernels.h"
 #include "snake_mlp.h"
 
@@ -38,6 +39,7 @@ struct Sizes {
     bool mlp = false;
     bool newton = false;
     bool gs = false;
+    bool wheels = false;
 };
 
 // Carves 256-byte aligned sub-arrays out of the workspace (base == nullptr
@@ -83,7 +85,8 @@ int validate(const sim_desc_t* d, Sizes* z)
     if (!std::isfinite(d->kappa_max)) return fail(SIM_EINVAL, "kappa_max must be finite");
     if (d->warm_start != SIM_WARM_ZERO && d->warm_start != SIM_WARM_PREV && d->warm_start != SIM_WARM_MLP)
         return fail(SIM_EINVAL, "unknown warm start");
-    if (d->flags & ~(SIM_FLAG_FIXED_ROOT | SIM_FLAG_NO_GROUND)) return fail(SIM_EINVAL, "unknown flag bits");
+    if (d->flags & ~(SIM_FLAG_FIXED_ROOT | SIM_FLAG_NO_GROUND | SIM_FLAG_WHEELS))
+        return fail(SIM_EINVAL, "unknown flag bits");
     if (d->controller < SIM_CTRL_EXTERNAL || d->controller > SIM_CTRL_SCHEDULE)
         return fail(SIM_EINVAL, "unknown controller");
     const bool ground = !(d->flags & SIM_FLAG_NO_GROUND);
@@ -127,6 +130,9 @@ int validate(const sim_desc_t* d, Sizes* z)
             return fail(SIM_EINVAL, "newton_keep_best must be 0 or 1");
     }
     z->newton = d->solver == SIM_SOLVER_NEWTON;
+    z->wheels = (d->flags & SIM_FLAG_WHEELS) != 0;
+    if (z->wheels && (d->solver != SIM_SOLVER_JACOBI || d->warm_start != SIM_WARM_ZERO))
+        return fail(SIM_EINVAL, "the wheel carriage takes the Jacobi solver from zero multipliers");
     if (mw != 0 && !d->autotune) {
         int seg = 16;
         while (seg < z->max_B) seg <<= 1;
@@ -164,6 +170,7 @@ struct Views {
     size_t state_bytes;
     char* backup;           // copy of the state while autotuning
     NParams np;
+    WParams wp;
     int* newton_list;       // [n] snakes by lane class (Newton and Gauss-Seidel solvers)
     double* comp_d;         // [4][n] compliances / h^2 and mu in double
     float* feat;            // [2J][32] network inputs (learned warm start)
@@ -201,6 +208,12 @@ size_t carve(const Sizes& z, char* base, Views* v)
     k.status = c.take<int>(n);
     k.step = c.take<long long>(n);
     k.iters_total = c.take<long long>(n);
+    WParams& wp = v->wp;
+    wp.x = z.wheels ? c.take<float>(6 * N) : nullptr;
+    wp.q = z.wheels ? c.take<float>(8 * N) : nullptr;
+    wp.v = z.wheels ? c.take<float>(6 * N) : nullptr;
+    wp.w = z.wheels ? c.take<float>(6 * N) : nullptr;
+    wp.lam = z.wheels ? c.take<float>(18 * N) : nullptr;
     v->state_begin = reinterpret_cast<char*>(k.x);
     v->state_bytes = c.pos;
     v->Bn = c.take<int>(n);
@@ -231,8 +244,8 @@ size_t carve(const Sizes& z, char* base, Views* v)
     v->mlp_y = z.mlp ? c.take<float>(6 * J) : nullptr;
     v->mlp_params = z.mlp ? c.take<float>(8192) : nullptr;
     v->mlp_ms = z.mlp ? c.take<float>(64) : nullptr;
-    v->newton_list = (z.newton || z.gs) ? c.take<int>(n) : nullptr;
-    v->comp_d = z.newton ? c.take<double>(4 * n) : nullptr;
+    v->newton_list = (z.newton || z.gs || z.wheels) ? c.take<int>(n) : nullptr;
+    v->comp_d = (z.newton || z.wheels) ? c.take<double>(4 * n) : nullptr;
     v->hdr = c.take<int4>(n + 1);
     v->slots = c.take<int2>(n + 1);
     v->backup = z.autotune ? c.take<char>((int64_t)v->state_bytes) : nullptr;
@@ -391,6 +404,11 @@ int split_substep(sim* s, hipStream_t st, int sub, float* feat, float* tgt)
 
 int launch_steps(sim* s, hipStream_t st, int n_steps)
 {
+    if (s->z.wheels) {
+        hipError_t e = launch_carriage(s->v.kp, s->v.np, s->v.wp, s->v.newton_list, s->newton_off, n_steps, st);
+        if (e != hipSuccess) return hip_fail(e, "carriage step launch");
+        return SIM_OK;
+    }
     if (s->z.newton) {
         hipError_t e = launch_newton(s->v.kp, s->v.np, s->v.newton_list, s->newton_off, n_steps, st);
         if (e != hipSuccess) return hip_fail(e, "Newton step launch");
@@ -647,6 +665,16 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     np.newton_iters = d->newton_iters;
     np.keep_best = d->newton_keep_best;
     np.pcr_iters = d->pcr_iters;
+    // wheels: thin discs of radius R/2 and mass m/8 centred at (0, +-R, -R/2)
+    // in their segment's frame, axle along the segment's y axis
+    WParams& wp = w.wp;
+    wp.mw = m / 8.0;
+    wp.rw = 0.5 * R;
+    wp.dw = R;
+    wp.hw = 0.5 * R;
+    wp.Ip = 0.25 * wp.mw * wp.rw * wp.rw;
+    wp.Ia = 0.5 * wp.mw * wp.rw * wp.rw;
+    wp.relax = d->relax;
 
     IParams& ip = w.ip;
     ip.n_snakes = n;
@@ -676,7 +704,7 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     CK(hipMemcpyAsync(w.sched_off, soff.data(), soff.size() * sizeof(int), hipMemcpyHostToDevice, st), "upload schedule");
     CK(hipMemcpyAsync(w.sched_start, sstart.data(), sstart.size() * sizeof(int), hipMemcpyHostToDevice, st), "upload schedule");
     CK(hipMemcpyAsync(w.sched_val, sval.data(), sval.size() * sizeof(float), hipMemcpyHostToDevice, st), "upload schedule");
-    if (z.newton || z.gs) {
+    if (z.newton || z.gs || z.wheels) {
         // snakes grouped by lane class (power of two >= B, at least 16)
         std::vector<double> cd(4 * (size_t)n);
         std::vector<int> cls(n), list;
@@ -695,7 +723,7 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
                 if (cls[q] == c) list.push_back(q);
         }
         s->newton_off[7] = (int)list.size();
-        if (z.newton)
+        if (z.newton || z.wheels)
             CK(hipMemcpyAsync(w.comp_d, cd.data(), cd.size() * sizeof(double), hipMemcpyHostToDevice, st),
                "upload compliance");
         CK(hipMemcpyAsync(w.newton_list, list.data(), n * sizeof(int), hipMemcpyHostToDevice, st),
@@ -718,8 +746,9 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
         s->B_host = Bn;
     }
     CK(launch_init_state(k, st), "init state");
+    if (z.wheels) CK(launch_init_wheels(k, w.wp, st), "init wheels");
     CK(hipStreamSynchronize(st), "init state");
-    if (z.autotune && !z.newton && !z.gs) {
+    if (z.autotune && !z.newton && !z.gs && !z.wheels) {
         rc = autotune(s);
         if (rc) goto error;
     } else {
@@ -811,10 +840,12 @@ static void field_table(sim* s, void* ptr[SIM_F_COUNT], size_t bytes[SIM_F_COUNT
 {
     const KParams& k = s->v.kp;
     const size_t N = s->z.N, J = s->z.J, Mt = s->z.Mt, n = s->z.n;
+    const WParams& wp = s->v.wp;
     void* p[SIM_F_COUNT] = {k.x, k.q, k.v, k.w, k.p, k.lam_j, k.lam_c, k.cmd, k.residual,
-                            k.iters_out, k.status, k.step, k.iters_total};
+                            k.iters_out, k.status, k.step, k.iters_total, wp.x, wp.q, wp.v, wp.w, wp.lam};
     size_t b[SIM_F_COUNT] = {3 * N * 4, 4 * N * 4, 3 * N * 4, 3 * N * 4, 2 * Mt * 4, 6 * J * 4,
-                             3 * N * 4, Mt * 4, n * 4, n * 4, n * 4, n * 8, n * 8};
+                             3 * N * 4, Mt * 4, n * 4, n * 4, n * 4, n * 8, n * 8,
+                             6 * N * 4, 8 * N * 4, 6 * N * 4, 6 * N * 4, 18 * N * 4};
     for (int f = 0; f < SIM_F_COUNT; ++f) {
         ptr[f] = p[f];
         bytes[f] = b[f];
@@ -832,6 +863,7 @@ static int copy_fields(sim_t* s, uint32_t fields, void* const* user, int mem, bo
     for (int f = 0; f < SIM_F_COUNT; ++f) {
         if (!(fields & (1u << f))) continue;
         if (!user[f]) return fail(SIM_EINVAL, "pointer for a selected field is NULL");
+        if (!ptr[f]) return fail(SIM_EINVAL, "wheel fields need a batch with SIM_FLAG_WHEELS");
         hipMemcpyKind kind = mem == SIM_MEM_HOST ? (to_user ? hipMemcpyDeviceToHost : hipMemcpyHostToDevice)
                                                  : hipMemcpyDeviceToDevice;
         hipError_t e = to_user ? hipMemcpyAsync(user[f], ptr[f], bytes[f], kind, s->stream)
@@ -875,7 +907,8 @@ int sim_step_record(sim_t* s, int32_t n_steps, float* features, float* targets, 
     if (!s || !features || !targets) return fail(SIM_EINVAL, "sim, features or targets is NULL");
     if (n_steps < 0) return fail(SIM_EINVAL, "n_steps must be >= 0");
     if (s->z.mlp && !s->mlp_loaded) return fail(SIM_ESTATE, "learned warm start needs sim_set_mlp first");
-    if (s->z.newton || s->z.gs) return fail(SIM_EINVAL, "recording needs the Jacobi solver");
+    if (s->z.newton || s->z.gs || s->z.wheels)
+        return fail(SIM_EINVAL, "recording needs the Jacobi solver on the plain chain");
     const int64_t per_sub = 2 * s->z.J;
     const int64_t rows = per_sub * s->v.kp.substeps * (int64_t)n_steps;
     if (written) *written = rows;

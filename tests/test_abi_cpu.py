@@ -129,6 +129,10 @@ def test_descriptor_validation(L, field, value, msg):
     (dict(solver=1, newton_iters=10001), "newton_iters"),
     (dict(solver=1, pcr_iters=0), "pcr_iters"),
     (dict(solver=1, newton_keep_best=2), "newton_keep_best"),
+    (dict(flags=16, solver=1), "wheel carriage"),
+    (dict(flags=16, solver=2), "wheel carriage"),
+    (dict(flags=16, warm_start=1), "wheel carriage"),
+    (dict(flags=16, warm_start=2), "wheel carriage"),
 ])
 def test_solver_descriptor_validation(L, over, msg):
     rc, _, err = ws_bytes(L, W.custom([2, 2], 8), **over)
@@ -141,6 +145,16 @@ def test_newton_workspace_adds_its_arrays(L):
     rc0, b0, _ = ws_bytes(L, wl)
     rc1, b1, _ = ws_bytes(L, wl, solver=1, newton_iters=4, pcr_iters=20)
     assert rc0 == rc1 == 0 and b1 > b0
+
+
+def test_carriage_workspace_adds_the_wheels(L):
+    """Wheel state (segments x 2 wheels x 22 floats) and the lane-class list
+    and double compliances of the carriage kernel."""
+    wl = W.make("uneven", n_snakes=40)
+    rc0, b0, _ = ws_bytes(L, wl)
+    rc1, b1, _ = ws_bytes(L, wl, flags=16)
+    assert rc0 == rc1 == 0
+    assert b1 - b0 >= 2 * 22 * 4 * int(wl.bodies.sum())
 
 
 def test_schedule_validation(L):
