@@ -50,6 +50,8 @@ PEAK_HBM = 8.0e12
 # with the digest of their sources
 SOLVER_TRAFFIC = {"newton": (337.0e6, ("newton.hip", "lanes.h", "blocks.h", "device_math.h", "kernels.h"),
                              "fcc37ef4a1894212:8e25130f7604f42f:d9b1e61db4cc8d70:959545d7849e09a9:eddaaf41a8a0af4a"),
+                  "carriage": (118.0e6, ("carriage.hip", "carriage.h", "lanes.h", "blocks.h", "device_math.h",
+                                         "kernels.h"), "3e1aa58cf5a456d5:7bc9e2b6ca45b80b:8e25130f7604f42f:d9b1e61db4cc8d70:959545d7849e09a9:eddaaf41a8a0af4a"),
                   "gs": (52.8e6, ("gs.hip", "blocks.h", "device_math.h", "kernels.h"),
                          "a2a8923ebb111535:d9b1e61db4cc8d70:959545d7849e09a9:eddaaf41a8a0af4a")}
 # Newton solver (FP64): operations per body per inner conjugate-residual
@@ -61,6 +63,14 @@ SOLVER_TRAFFIC = {"newton": (337.0e6, ("newton.hip", "lanes.h", "blocks.h", "dev
 FLOP_PCR_ITER = 307
 FLOP_NEWTON_ITER = 1050
 FLOP_NEWTON_SUBSTEP = 450
+# Wheel carriage (FP64): operations per segment (its joint, two wheels and
+# their hinge and contact blocks) per Jacobi iteration, and per substep
+# outside the iterations (pressure, rest rotation, prediction of three
+# bodies, friction anchors, velocities), counted from the compiled loops as
+# for the Newton solver.
+FLOP_CARRIAGE_ITER = 1930
+FLOP_CARRIAGE_SUBSTEP = 750
+CARRIAGE_ITERS = 20
 PEAK_FP64 = 78.6e12        # MI355X FP64 vector (published)
 # the paper's budget (4 Newton iterations of 20 inner iterations) and two larger ones
 NEWTON_BUDGETS = ((4, 20), (8, 50), (16, 50))
@@ -97,6 +107,10 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
     ap.add_argument("--learned-steps", type=int, default=20)
     ap.add_argument("--no-newton", action="store_true", help="skip the Newton solver comparison")
+    ap.add_argument("--wheels", action="store_true",
+                    help="the wheeled carriage (two wheels per segment on hinge joints), "
+                         f"{CARRIAGE_ITERS} Jacobi iterations per substep")
+    ap.add_argument("--no-carriage", action="store_true", help="skip the wheeled-carriage line")
     ap.add_argument("--solver", default="jacobi", choices=("jacobi", "newton", "gs"),
                     help="solver of the timed loop (newton: the paper's budget, 4 x 20, FP64; "
                          "gs: block Gauss-Seidel, 40 sweeps)")
@@ -292,6 +306,46 @@ def newton_comparison(wl, n_steps=5):
             "rows": rows}
 
 
+def carriage_run(wl, n_steps=5, iters=CARRIAGE_ITERS):
+    """The batch on wheels (two per segment on hinge joints, FP64 Jacobi
+    iterations) from the state after 20 steps on wheels: time per step, the
+    residual reached and the kernel's FP64 throughput."""
+    import torch
+
+    import paper_1904_02833_amd as snk
+
+    cw = wl.take(np.arange(wl.n_snakes))
+    cw.flags = cw.flags | snk.FLAG_WHEELS
+    cw.tol, cw.iters = 0.0, iters
+    sim = snk.Sim(cw)
+    sim.step(20)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    for _ in range(n_steps):
+        sim.step(1)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n_steps
+    r = sim.read("residual", "status")
+    sim.close()
+    B = float(cw.bodies.sum())
+    ach = B * cw.substeps * (iters * FLOP_CARRIAGE_ITER + FLOP_CARRIAGE_SUBSTEP) / (ms / 1e3)
+    traffic = None
+    if wl.name == "uniform" and wl.n_snakes == 4096:
+        t, files, digest = SOLVER_TRAFFIC["carriage"]
+        traffic = t if kernel_digest(files) == digest else None
+    return {"workload": f"{wl.name} on wheels: {cw.n_snakes} snakes, {int(B)} segments, {int(2 * B)} wheels, "
+                        f"{cw.substeps} substeps, {iters} iterations",
+            "ms_per_step": ms, "snake_steps_per_s": cw.n_snakes / (ms / 1e3),
+            "residual_last_step": {"median": float(np.median(r["residual"])),
+                                   "max": float(np.max(r["residual"]))},
+            "nonfinite_snakes": int(np.sum((r["status"] & 1) != 0)),
+            "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                         "frac": ach / PEAK_FP64, "traffic": traffic, "kernel": "k_carriage<64>", "dtype": "f64",
+                         "flop_per_segment_iter": FLOP_CARRIAGE_ITER}}
+
+
 def cpu_baseline(wl, n_snakes, n_steps):
     import oracle
 
@@ -331,6 +385,18 @@ def main():
     import workloads as W
 
     wl = W.make(args.workload, n_snakes=args.snakes)
+    if args.wheels:
+        if args.solver != "jacobi":
+            raise SystemExit("--wheels takes the Jacobi solver")
+        row = carriage_run(wl, n_steps=args.steps)
+        out = {"metric": "wheel-carriage snake-steps/s", "value": row["snake_steps_per_s"],
+               "unit": "snake-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": 20,
+               "ms_per_step": row["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": row["workload"]}, "roofline": row["roofline"],
+               "residual_last_step": row["residual_last_step"]}
+        print(json.dumps(out), flush=True)
+        return
     if args.fixed:
         wl.tol, wl.iters = 0.0, 20
     else:
@@ -427,6 +493,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_snakes, args.cpu_steps)
     if not args.no_newton:
         out["newton_pcr"] = newton_comparison(wl)
+    if not args.no_carriage:
+        out["wheel_carriage"] = carriage_run(wl)
     if not args.no_learned:
         out["learned_warm_start"] = learned_comparison(args.learned_steps)
         out["learned_warm_start_converging"] = learned_converging()
