@@ -156,9 +156,11 @@ def test_carriage_stiff_1024_lanes():
 
 
 def test_carriage_odd_sizes_fixed_root_and_no_ground():
-    """B = 1 (one segment on two wheels), 2, 3, 17, 15, 63 bodies; the same
-    with a fixed root; and without the ground (hinges and joints only)."""
-    wl = with_wheels(W.custom([1, 1, 1, 1, 3, 1], [1, 2, 3, 17, 5, 63], mu=0.4, controller=W.CTRL_EXTERNAL))
+    """B = 1 (one segment on two wheels), 2, 3, 17, 15, 63 and 300 bodies
+    (lane classes 16 to 512); the same with a fixed root; and without the
+    ground (hinges and joints only)."""
+    wl = with_wheels(W.custom([1, 1, 1, 1, 3, 1, 3], [1, 2, 3, 17, 5, 63, 100], mu=0.4,
+                              controller=W.CTRL_EXTERNAL))
     rng = np.random.default_rng(3)
     for label, flags in (("odd sizes", wl.flags), ("fixed root", wl.flags | oracle.FLAG_FIXED_ROOT),
                          ("no ground", wl.flags | oracle.FLAG_NO_GROUND)):
