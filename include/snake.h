@@ -133,7 +133,9 @@ extern "C" {
                                /* touched at the start of the substep).     */
                                /* Needs SIM_SOLVER_JACOBI, SIM_WARM_ZERO;   */
                                /* computes in double; no autotune and no    */
-                               /* split substeps.  State in SIM_F_WHEEL_*.  */
+                               /* split substeps.  State in SIM_F_WHEEL_*;  */
+                               /* the index arrays (sim_read_index) keep    */
+                               /* describing the segment chain.             */
 
 /* ---- per-snake status bits (field SIM_F_STATUS) ---- */
 #define SIM_STATUS_NONFINITE 1     /* residual became NaN or inf             */

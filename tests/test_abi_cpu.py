@@ -45,6 +45,17 @@ def test_exports_every_declared_symbol(L):
         assert hasattr(L, n)
 
 
+def test_state_fields_match_the_header():
+    """The binding's field table names the header's SIM_F_* bits in order,
+    with SIM_F_COUNT entries."""
+    text = open(os.path.join(ROOT, "include", "snake.h")).read()
+    bits = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define SIM_F_(\w+) \(1u << (\d+)\)", text)}
+    count = int(re.search(r"#define SIM_F_COUNT (\d+)", text).group(1))
+    assert len(snk.FIELDS) == count == len(bits)
+    for k, f in enumerate(snk.FIELDS):
+        assert bits[f[0].upper()] == k, f[0]
+
+
 def test_descriptor_layout_matches_c(tmp_path):
     """Compile a probe against the header with gcc and compare sizeof and
     every field offset with the ctypes mirror."""
