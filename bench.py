@@ -44,16 +44,16 @@ PEAK_FP32 = 157.3e12       # MI355X FP32 vector (published)
 # profiles/), keyed by workload, waves per workgroup and layout, with the digest of
 # the kernel sources they were taken on; a changed kernel reports null.
 MEASURED_TRAFFIC = {("uniform", 4, 1): 113.8e6, ("uneven", 4, 1): 696.3e6, ("stiff", 16, 1): 123.3e6}
-TRAFFIC_SOURCES_DIGEST = "6f9961ac0237831e:d9b1e61db4cc8d70:959545d7849e09a9:eddaaf41a8a0af4a"
+TRAFFIC_SOURCES_DIGEST = "6f9961ac0237831e:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"
 PEAK_HBM = 8.0e12
 # the same for the other solvers' kernels on the uniform batch (--solver),
 # with the digest of their sources
 SOLVER_TRAFFIC = {"newton": (337.0e6, ("newton.hip", "lanes.h", "blocks.h", "device_math.h", "kernels.h"),
-                             "fcc37ef4a1894212:8e25130f7604f42f:d9b1e61db4cc8d70:959545d7849e09a9:eddaaf41a8a0af4a"),
+                             "03507154f969a960:7d1acb2a40eb1590:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"),
                   "carriage": (118.0e6, ("carriage.hip", "carriage.h", "lanes.h", "blocks.h", "device_math.h",
-                                         "kernels.h"), "3e1aa58cf5a456d5:7bc9e2b6ca45b80b:8e25130f7604f42f:d9b1e61db4cc8d70:959545d7849e09a9:eddaaf41a8a0af4a"),
+                                         "kernels.h"), "a89ffe76c52a146a:b17d334d03f00823:7d1acb2a40eb1590:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"),
                   "gs": (52.8e6, ("gs.hip", "blocks.h", "device_math.h", "kernels.h"),
-                         "a2a8923ebb111535:d9b1e61db4cc8d70:959545d7849e09a9:eddaaf41a8a0af4a")}
+                         "a845d97590629bbd:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726")}
 # Newton solver (FP64): operations per body per inner conjugate-residual
 # iteration and per Newton iteration outside it (block evaluation, residual,
 # rows, the two initial products, the update), counted from the compiled

@@ -348,7 +348,7 @@ struct sim {
     std::map<int, hipGraphExec_t> graphs;
     std::vector<int> order_host;
     std::vector<int> B_host;
-    int newton_off[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // lane classes 16 << c
+    int newton_off[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // lane classes 8 << c
 };
 
 namespace {
@@ -705,7 +705,7 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
     CK(hipMemcpyAsync(w.sched_start, sstart.data(), sstart.size() * sizeof(int), hipMemcpyHostToDevice, st), "upload schedule");
     CK(hipMemcpyAsync(w.sched_val, sval.data(), sval.size() * sizeof(float), hipMemcpyHostToDevice, st), "upload schedule");
     if (z.newton || z.gs || z.wheels) {
-        // snakes grouped by lane class (power of two >= B, at least 16)
+        // snakes grouped by lane class (power of two >= B, at least 8)
         std::vector<double> cd(4 * (size_t)n);
         std::vector<int> cls(n), list;
         for (int q = 0; q < n; ++q) {
@@ -714,15 +714,15 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
             cd[2 * (size_t)n + q] = d->alpha_twist[q] * d->seg_length / (h * h);
             cd[3 * (size_t)n + q] = d->mu[q];
             int c = 0;
-            while ((16 << c) < Bn[q]) ++c;
+            while ((8 << c) < Bn[q]) ++c;
             cls[q] = c;
         }
-        for (int c = 0; c < 7; ++c) {
+        for (int c = 0; c < 8; ++c) {
             s->newton_off[c] = (int)list.size();
             for (int q = 0; q < n; ++q)
                 if (cls[q] == c) list.push_back(q);
         }
-        s->newton_off[7] = (int)list.size();
+        s->newton_off[8] = (int)list.size();
         if (z.newton || z.wheels)
             CK(hipMemcpyAsync(w.comp_d, cd.data(), cd.size() * sizeof(double), hipMemcpyHostToDevice, st),
                "upload compliance");

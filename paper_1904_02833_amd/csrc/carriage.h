@@ -30,7 +30,7 @@ hipError_t launch_init_wheels(const KParams& P, const WParams& Wp, hipStream_t s
 
 // n_steps steps of every snake with block-Jacobi iterations on the chain's
 // joints and the wheels' hinge and contact blocks, in double; snakes grouped
-// by lane class as for the Newton solver (list, off[8]).
+// by lane class as for the Newton solver (list, off[9]).
 hipError_t launch_carriage(const KParams& P, const NParams& Q, const WParams& Wp, const int* list, const int* off,
                            int n_steps, hipStream_t stream);
 

@@ -524,13 +524,14 @@ hipError_t launch_carriage(const KParams& P, const NParams& Q, const WParams& Wp
         hipError_t e = hipGetLastError();                                                                 \
         if (e != hipSuccess) return e;                                                                    \
     }
-    CARRIAGE_CLASS(0, 16)
-    CARRIAGE_CLASS(1, 32)
-    CARRIAGE_CLASS(2, 64)
-    CARRIAGE_CLASS(3, 128)
-    CARRIAGE_CLASS(4, 256)
-    CARRIAGE_CLASS(5, 512)
-    CARRIAGE_CLASS(6, 1024)
+    CARRIAGE_CLASS(0, 8)
+    CARRIAGE_CLASS(1, 16)
+    CARRIAGE_CLASS(2, 32)
+    CARRIAGE_CLASS(3, 64)
+    CARRIAGE_CLASS(4, 128)
+    CARRIAGE_CLASS(5, 256)
+    CARRIAGE_CLASS(6, 512)
+    CARRIAGE_CLASS(7, 1024)
 #undef CARRIAGE_CLASS
     return hipSuccess;
 }

@@ -7,7 +7,7 @@
 // substep.
 //
 // Layout: one body per lane as in the Newton kernel (a snake takes SEG
-// lanes, a power of two >= B, at least 16; up to 64 lanes per snake several
+// lanes, a power of two >= B, at least 8; up to 64 lanes per snake several
 // snakes share a wave and exchange by lane shuffles; longer snakes take a
 // workgroup of SEG / 64 waves joined through LDS).  A sweep is the residual
 // pass of the iterate followed by five colour passes; each pass fetches the
@@ -366,13 +366,14 @@ hipError_t launch_gs(const KParams& P, const int* block_off, const int* blk_colo
         hipError_t e = hipGetLastError();                                                               \
         if (e != hipSuccess) return e;                                                                  \
     }
-    GS_CLASS(0, 16)
-    GS_CLASS(1, 32)
-    GS_CLASS(2, 64)
-    GS_CLASS(3, 128)
-    GS_CLASS(4, 256)
-    GS_CLASS(5, 512)
-    GS_CLASS(6, 1024)
+    GS_CLASS(0, 8)
+    GS_CLASS(1, 16)
+    GS_CLASS(2, 32)
+    GS_CLASS(3, 64)
+    GS_CLASS(4, 128)
+    GS_CLASS(5, 256)
+    GS_CLASS(6, 512)
+    GS_CLASS(7, 1024)
 #undef GS_CLASS
     return hipSuccess;
 }

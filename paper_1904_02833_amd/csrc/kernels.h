@@ -107,8 +107,8 @@ struct IParams {
 hipError_t launch_tiles(int nw, int rows, const KParams& P, const int4* hdr, const int2* slots,
                         int n_tiles, int grid, int n_steps, int phase, int sub, hipStream_t stream);
 // Newton solver: one launch per class of snakes whose lane count (the
-// power of two >= B, at least 16) is 16 << c; list holds the snakes class by
-// class, class c at [off[c], off[c+1]).  Runs n_steps whole steps.
+// power of two >= B, at least 8) is 8 << c; list holds the snakes class by
+// class, class c at [off[c], off[c+1]), c < 8.  Runs n_steps whole steps.
 hipError_t launch_newton(const KParams& P, const NParams& Q, const int* list, const int* off,
                          int n_steps, hipStream_t stream);
 // Block Gauss-Seidel solver, same lane classes and snake list as the Newton

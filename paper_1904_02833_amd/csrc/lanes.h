@@ -145,11 +145,12 @@ __device__ __forceinline__ void from_prev(double (&v)[K], int lane, int wv, doub
 }
 
 // Sum (MAX = false) or maximum over the snake's lanes, the same bits in
-// every lane: within rows of 16 lanes by DPP swaps (quad [1,0,3,2], quad
-// [2,3,0,1], then the half-row and row mirrors, which pair lanes already
-// holding equal values, so each stage combines disjoint sets and every lane
-// adds the same two operands), the rows of the snake read lane by lane and
-// joined in a fixed order, then the waves' partials in order.
+// every lane: within rows of 16 lanes (8 for an 8-lane snake) by DPP swaps
+// (quad [1,0,3,2], quad [2,3,0,1], then the half-row and row mirrors, which
+// pair lanes already holding equal values, so each stage combines disjoint
+// sets and every lane adds the same two operands), the rows of the snake
+// read lane by lane and joined in a fixed order, then the waves' partials
+// in order.
 template <int SEG, bool MAX>
 __device__ __forceinline__ double seg_reduce(double v, int lane, int wv, double* red, int& ph)
 {
@@ -158,7 +159,7 @@ __device__ __forceinline__ double seg_reduce(double v, int lane, int wv, double*
     v = join(v, dpp_move<0xB1>(v));
     v = join(v, dpp_move<0x4E>(v));
     v = join(v, dpp_move<0x141>(v));
-    v = join(v, dpp_move<0x140>(v));
+    if constexpr (W >= 16) v = join(v, dpp_move<0x140>(v));
     if constexpr (W >= 32) {
         // every lane of a row now holds its row's value: read the four rows
         // into scalar registers and join them in a fixed order

@@ -10,7 +10,7 @@
 // library's FP32 arrays between launches.
 //
 // Layout: a snake takes SEG lanes (a power of two >= its body count, at
-// least 16), lane i holding body i, joint i (bodies i, i+1: the stretch and
+// least 8), lane i holding body i, joint i (bodies i, i+1: the stretch and
 // bend-twist blocks) and contact i.  Snakes of up to 64 lanes share a wave
 // and exchange through lane shuffles only; longer ones take a workgroup of
 // SEG / 64 waves joined through LDS at the wave boundaries.  The matrix is
@@ -544,13 +544,14 @@ hipError_t launch_newton(const KParams& P, const NParams& Q, const int* list, co
         hipError_t e = hipGetLastError();                                                              \
         if (e != hipSuccess) return e;                                                                 \
     }
-    NEWTON_CLASS(0, 16)
-    NEWTON_CLASS(1, 32)
-    NEWTON_CLASS(2, 64)
-    NEWTON_CLASS(3, 128)
-    NEWTON_CLASS(4, 256)
-    NEWTON_CLASS(5, 512)
-    NEWTON_CLASS(6, 1024)
+    NEWTON_CLASS(0, 8)
+    NEWTON_CLASS(1, 16)
+    NEWTON_CLASS(2, 32)
+    NEWTON_CLASS(3, 64)
+    NEWTON_CLASS(4, 128)
+    NEWTON_CLASS(5, 256)
+    NEWTON_CLASS(6, 512)
+    NEWTON_CLASS(7, 1024)
 #undef NEWTON_CLASS
     return hipSuccess;
 }

@@ -9,7 +9,7 @@ the FP32 state arrays (relative 6e-8).  Bound: 1e-6 on segment and wheel
 positions and on every multiplier type, each relative to the largest of its
 type in the snake (floor: one segment's weight over a substep, m g h^2, and
 m g h^2 L for rotational rows); iteration counts and status bits equal.
-Lane classes 16 to 1024 (workgroups of 16 waves joined through LDS)."""
+Lane classes 8 to 1024 (workgroups of 16 waves joined through LDS)."""
 import numpy as np
 import pytest
 
@@ -157,7 +157,7 @@ def test_carriage_stiff_1024_lanes():
 
 def test_carriage_odd_sizes_fixed_root_and_no_ground():
     """B = 1 (one segment on two wheels), 2, 3, 17, 15, 63 and 300 bodies
-    (lane classes 16 to 512); the same with a fixed root; and without the
+    (lane classes 8 to 512); the same with a fixed root; and without the
     ground (hinges and joints only)."""
     wl = with_wheels(W.custom([1, 1, 1, 1, 3, 1, 3], [1, 2, 3, 17, 5, 63, 100], mu=0.4,
                               controller=W.CTRL_EXTERNAL))

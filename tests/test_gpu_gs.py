@@ -4,7 +4,7 @@ the substep protocol of tests/parity.py: positions to 1e-5, multipliers to
 1e-4 relative per block type or the oracle's own FP64 spread under a 1-ulp
 input nudge where that is larger, contacts whose active set or stick/slip
 branch differs between the precisions counted apart (at most 2 % of
-bodies).  Lane classes 16 to 1024."""
+bodies).  Lane classes 8 to 1024."""
 import numpy as np
 import pytest
 

@@ -6,7 +6,7 @@ Both sides compute in double from the same FP32-rounded state and differ
 by summation order only; the GPU then rounds its result to its FP32 state
 arrays (relative 6e-8).  The bound, 1e-6 on positions and multipliers (in
 the parity helpers' relative measures), leaves room for the inner solve to
-amplify the summation-order differences a few times.  Lane classes: 16 to
+amplify the summation-order differences a few times.  Lane classes: 8 to
 256 lanes (uneven and short batches), 1024 lanes (workgroups of 16 waves
 joined through LDS)."""
 import numpy as np
