@@ -44,7 +44,7 @@ PEAK_FP32 = 157.3e12       # MI355X FP32 vector (published)
 # profiles/), keyed by workload, waves per workgroup and layout, with the digest of
 # the kernel sources they were taken on; a changed kernel reports null.
 MEASURED_TRAFFIC = {("uniform", 4, 1): 113.8e6, ("uneven", 4, 1): 696.3e6, ("stiff", 16, 1): 123.3e6}
-TRAFFIC_SOURCES_DIGEST = "6f9961ac0237831e:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"
+TRAFFIC_SOURCES_DIGEST = "91c62fffee1bdbe0:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"
 PEAK_HBM = 8.0e12
 # the same for the other solvers' kernels on the uniform batch (--solver),
 # with the digest of their sources

@@ -222,7 +222,8 @@ typedef struct sim_desc {
      * tiles of snakes; each snake owns an aligned power-of-two lane segment
      * of at least map_min_seg lanes (16, 32 or 64), or with map_rows = 1 a
      * segment of its length rounded up to 16 lanes, placed without
-     * alignment; map_grid workgroups loop over the tiles (0: one workgroup
+     * alignment (map_rows = 2: the same, with snakes of up to 8 bodies in
+     * 8-lane half rows, two to a row); map_grid workgroups loop over the tiles (0: one workgroup
      * per tile).  0 selects the default.  autotune = 1 times the candidate
      * mappings on the real batch inside sim_create (the state is restored
      * afterwards) and keeps the fastest; explicit map_* values are then
@@ -234,7 +235,7 @@ typedef struct sim_desc {
     int32_t mlp_fallback;      /* 1: per snake and substep, keep the learned */
                                /* start only if its residual is not larger   */
                                /* than the zero start's ...                  */
-    int32_t map_rows;          /* 0 or 1, see the mapping above             */
+    int32_t map_rows;          /* 0, 1 or 2, see the mapping above          */
     int32_t mlp_fallback_k;    /* ... after this many iterations from each   */
                                /* start (0: the starts themselves; at most   */
                                /* iters).  For k > 0 the zero start runs k   */
@@ -326,7 +327,9 @@ int sim_sizes(const sim_t* s, int64_t* out5);
  * state): snakes in work order (longest first, ties by index) packed into
  * tiles of 64 * waves lanes, aligned power-of-two segments of at least
  * min_seg lanes (rows = 0) or segments of the length rounded up to 16 lanes,
- * best fit (rows = 1) -- the layout sim_create builds for that mapping.
+ * best fit (rows = 1; rows = 2: snakes of up to 8 bodies in 8-lane half
+ * rows, consecutive ones sharing a row) -- the layout sim_create builds for
+ * that mapping.
  * Outputs in caller host memory with room for n_snakes entries:
  *   hdr[tile][4] = {first slot, slot count, some segment crosses a wave
  *                   boundary, rows}

@@ -34,7 +34,7 @@ int hip_fail(hipError_t e, const char* what)
 
 struct Sizes {
     int64_t n = 0, N = 0, J = 0, Mt = 0, blocks = 0, pieces = 0;
-    int max_B = 0;
+    int max_B = 0, min_B = 1 << 30;
     bool autotune = false;
     bool mlp = false;
     bool newton = false;
@@ -104,6 +104,7 @@ int validate(const sim_desc_t* d, Sizes* z)
         z->Mt += M;
         z->blocks += 2 * (B - 1) + (ground ? B : 0);
         if (B > z->max_B) z->max_B = (int)B;
+        if (B < z->min_B) z->min_B = (int)B;
     }
     if (z->N > (int64_t)1 << 28) return fail(SIM_EINVAL, "too many bodies (limit 2^28)");
     const int mw = d->map_waves;
@@ -112,7 +113,7 @@ int validate(const sim_desc_t* d, Sizes* z)
     if (d->map_min_seg != 0 && d->map_min_seg != 16 && d->map_min_seg != 32 && d->map_min_seg != 64)
         return fail(SIM_EINVAL, "map_min_seg must be 0, 16, 32 or 64");
     if (d->map_grid < 0) return fail(SIM_EINVAL, "map_grid must be >= 0");
-    if (d->map_rows != 0 && d->map_rows != 1) return fail(SIM_EINVAL, "map_rows must be 0 or 1");
+    if (d->map_rows < 0 || d->map_rows > 2) return fail(SIM_EINVAL, "map_rows must be 0, 1 or 2");
     if (d->mlp_fallback_k < 0 || d->mlp_fallback_k > d->iters)
         return fail(SIM_EINVAL, "mlp_fallback_k must be in [0, iters]");
     if (d->solver != SIM_SOLVER_JACOBI && d->solver != SIM_SOLVER_NEWTON && d->solver != SIM_SOLVER_GS)
@@ -267,7 +268,8 @@ struct Mapping {
 // Aligned layout: each snake gets max(min_seg, 2^ceil(log2 B)) lanes;
 // segments arrive in non-increasing size, so placing them one after another
 // keeps every segment aligned to its own size.  Rows layout: each snake gets
-// B rounded up to 16 lanes, placed one after another.
+// B rounded up to 16 lanes (rows = 2: snakes of up to 8 bodies 8 lanes, two
+// to a row), placed one after another.
 // Tile header: first slot, slot count, some segment crosses a wave
 // boundary, rows layout.  Slot: snake, lane offset << 16 | lanes.
 void build_tiles(const std::vector<int>& order, const std::vector<int>& Bn, const Mapping& mp,
@@ -296,12 +298,31 @@ void build_tiles(const std::vector<int>& order, const std::vector<int>& Bn, cons
     // open tile with the least free room that still holds it (a new tile
     // if none does); tiles keep the order in which they were opened, so the
     // longest snakes come first.  Open tiles are bucketed by free rows.
+    // With half rows (rows = 2) snakes of up to 8 bodies take 8 lanes, two
+    // consecutive ones (in work order) sharing a row.
+    struct Item {
+        int need, s0, n0, s1;   // rows, first snake and its lanes, partner (-1: none)
+    };
+    std::vector<Item> items;
+    for (int sidx : order) {
+        if (mp.rows == 2 && Bn[sidx] <= 8) {
+            if (!items.empty() && items.back().n0 == 8 && items.back().s1 < 0) {
+                items.back().s1 = sidx;
+                continue;
+            }
+            items.push_back(Item{1, sidx, 8, -1});
+            continue;
+        }
+        const int need = (Bn[sidx] + 15) / 16;
+        items.push_back(Item{need, sidx, 16 * need, -1});
+    }
     const int nrow = cap / 16;
-    std::vector<std::vector<int>> slot_of_tile;
+    std::vector<std::vector<int>> item_of_tile;
     std::vector<int> fill;
     std::vector<std::vector<int>> free_rows(nrow + 1);   // tiles by free rows
-    for (int sidx : order) {
-        const int need = (Bn[sidx] + 15) / 16;
+    std::vector<int> at(items.size());
+    for (size_t k = 0; k < items.size(); ++k) {
+        const int need = items[k].need;
         int t = -1;
         for (int r = need; r <= nrow && t < 0; ++r)
             if (!free_rows[r].empty()) {
@@ -311,21 +332,25 @@ void build_tiles(const std::vector<int>& order, const std::vector<int>& Bn, cons
         if (t < 0) {
             t = (int)fill.size();
             fill.push_back(0);
-            slot_of_tile.emplace_back();
+            item_of_tile.emplace_back();
         }
-        slot_of_tile[t].push_back(sidx);
-        slot_of_tile[t].push_back(fill[t]);
+        item_of_tile[t].push_back((int)k);
+        at[k] = fill[t];
         fill[t] += need;
         free_rows[nrow - fill[t]].push_back(t);
     }
     for (size_t t = 0; t < fill.size(); ++t) {
-        int4 h = make_int4((int)slots.size(), 0, 0, 1);
-        const std::vector<int>& v = slot_of_tile[t];
-        for (size_t k = 0; k < v.size(); k += 2) {
-            const int sidx = v[k], pos = 16 * v[k + 1], seg = (Bn[sidx] + 15) / 16 * 16;
-            slots.push_back(make_int2(sidx, (pos << 16) | seg));
+        int4 h = make_int4((int)slots.size(), 0, 0, mp.rows);
+        for (int k : item_of_tile[t]) {
+            const Item& it = items[k];
+            const int pos = 16 * at[k];
+            slots.push_back(make_int2(it.s0, (pos << 16) | it.n0));
             h.y += 1;
-            if ((pos >> 6) != ((pos + seg - 1) >> 6)) h.z = 1;
+            if ((pos >> 6) != ((pos + it.n0 - 1) >> 6)) h.z = 1;
+            if (it.s1 >= 0) {
+                slots.push_back(make_int2(it.s1, ((pos + 8) << 16) | 8));
+                h.y += 1;
+            }
         }
         hdr.push_back(h);
     }
@@ -466,6 +491,13 @@ int autotune(sim* s)
             Mapping p = m;
             p.grid = cus * (16 / nw > 0 ? 16 / nw : 1);
             cand.push_back(p);
+            if (ms == 0 && s->z.min_B <= 8) {
+                // half rows for the snakes of up to 8 bodies
+                Mapping hr = m, hp = p;
+                hr.rows = hp.rows = 2;
+                cand.push_back(hr);
+                cand.push_back(hp);
+            }
         }
     hipError_t e = hipMemcpyAsync(s->v.backup, s->v.state_begin, s->v.state_bytes,
                                   hipMemcpyDeviceToDevice, s->stream);
@@ -757,7 +789,7 @@ int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_str
         mp.nw = d->map_waves ? d->map_waves : (max_seg > 64 ? max_seg / 64 : 1);
         mp.min_seg = d->map_min_seg ? d->map_min_seg : 16;
         mp.grid = d->map_grid;
-        mp.rows = d->map_rows ? 1 : 0;
+        mp.rows = d->map_rows;
         rc = upload_tiles(s, mp);
         if (rc) goto error;
     }
@@ -962,7 +994,7 @@ int sim_plan_tiles(const sim_desc_t* d, int32_t waves, int32_t min_seg, int32_t 
     if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
         return fail(SIM_EINVAL, "waves must be 1, 2, 4, 8 or 16");
     if (min_seg != 16 && min_seg != 32 && min_seg != 64) return fail(SIM_EINVAL, "min_seg must be 16, 32 or 64");
-    if (rows != 0 && rows != 1) return fail(SIM_EINVAL, "rows must be 0 or 1");
+    if (rows < 0 || rows > 2) return fail(SIM_EINVAL, "rows must be 0, 1 or 2");
     const int n = (int)z.n;
     std::vector<int> Bn(n), order(n);
     for (int k = 0; k < n; ++k) {

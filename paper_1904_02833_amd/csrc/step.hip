@@ -54,7 +54,8 @@ __device__ __forceinline__ void lds_row(const float* src, float* dst)
 // two layouts: power-of-two segments placed largest first, so each is
 // aligned to its size (segments of <= 64 lanes stay inside a wave), or
 // segments of the snake's length rounded up to 16 lanes, placed one after
-// another (fewer idle lanes, and a segment may cross a wave boundary).  A
+// another (fewer idle lanes, and a segment may cross a wave boundary);
+// ROWS = 2 is the latter with 8-lane half rows for snakes of up to 8 bodies.  A
 // segment that crosses a wave boundary exchanges the boundary body and the
 // residual through LDS (two workgroup barriers per iteration, only in tiles
 // that have such a snake).
@@ -178,7 +179,13 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                 b = max(b, __builtin_amdgcn_update_dpp(0, b, 0xB1, 0xf, 0xf, false));   // quad [1,0,3,2]
                 b = max(b, __builtin_amdgcn_update_dpp(0, b, 0x4E, 0xf, 0xf, false));   // quad [2,3,0,1]
                 b = max(b, __builtin_amdgcn_update_dpp(0, b, 0x141, 0xf, 0xf, false));  // half-row mirror
-                b = max(b, __builtin_amdgcn_update_dpp(0, b, 0x140, 0xf, 0xf, false));  // row mirror
+                if constexpr (ROWS == 2) {
+                    // an 8-lane segment shares its row with another snake
+                    const int t = __builtin_amdgcn_update_dpp(0, b, 0x140, 0xf, 0xf, false);
+                    if (seg > 8) b = max(b, t);
+                } else {
+                    b = max(b, __builtin_amdgcn_update_dpp(0, b, 0x140, 0xf, 0xf, false));  // row mirror
+                }
             } else {
 #pragma unroll
                 for (int o = 8; o >= 1; o >>= 1) b = max(b, __shfl_xor(b, o, 64));
@@ -854,8 +861,9 @@ hipError_t launch_tiles(int nw, int rows, const KParams& P, const int4* hdr, con
     if (phase == kPhaseFull) SNAKE_LAUNCH(NWV, kPhaseFull, RW);     \
     else if (phase == kPhasePre) SNAKE_LAUNCH(NWV, kPhasePre, RW);  \
     else SNAKE_LAUNCH(NWV, kPhaseSolve, RW);
-#define SNAKE_LAYOUTS(NWV)                \
-    if (rows) { SNAKE_PHASES(NWV, 1) }     \
+#define SNAKE_LAYOUTS(NWV)                   \
+    if (rows == 2) { SNAKE_PHASES(NWV, 2) }     \
+    else if (rows) { SNAKE_PHASES(NWV, 1) }   \
     else { SNAKE_PHASES(NWV, 0) }
     switch (nw) {
         case 1: SNAKE_LAYOUTS(1) break;

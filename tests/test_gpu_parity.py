@@ -474,14 +474,35 @@ def test_full_stiff_batch_sampled_parity():
 
 def test_rows_layout_on_tiny_and_odd_sizes_bit_identical():
     """Snakes of 1, 2, 3, 15, 17, 63 and 64 bodies in the rows layout (segments
-    rounded to 16 lanes, unaligned, crossing waves) give the same bits as
-    the aligned layout."""
+    rounded to 16 lanes, unaligned, crossing waves; with half rows the
+    snakes of up to 8 bodies two to a row) give the same bits as the
+    aligned layout."""
     wl = W.custom([1, 1, 1, 1, 1, 3, 1, 4] * 20, [1, 2, 3, 15, 17, 5, 63, 16] * 20, mu=0.4)
     ref = None
     for mp in (dict(map_waves=1), dict(map_waves=1, map_rows=1), dict(map_waves=2, map_rows=1),
-               dict(map_waves=4, map_rows=1, map_grid=8)):
+               dict(map_waves=4, map_rows=1, map_grid=8), dict(map_waves=1, map_rows=2),
+               dict(map_waves=2, map_rows=2), dict(map_waves=4, map_rows=2, map_grid=8)):
         sim = snk.Sim(wl, **mp)
         sim.step(6)
+        r = sim.read()
+        print(mp, sim.mapping)
+        if ref is None:
+            ref = r
+        else:
+            for k in r:
+                assert np.array_equal(r[k], ref[k]), (mp, k)
+        sim.close()
+
+
+def test_half_rows_on_the_short_batch_bit_identical():
+    """The short batch (6 to 8 bodies) with half rows, two snakes to a
+    16-lane row, gives the same bits as with whole rows."""
+    wl = W.make("short", n_snakes=300)
+    ref = None
+    for mp in (dict(map_waves=1, map_rows=1), dict(map_waves=1, map_rows=2), dict(map_waves=4, map_rows=2),
+               dict(map_waves=2, map_rows=2, map_grid=16)):
+        sim = snk.Sim(wl, **mp)
+        sim.step(5)
         r = sim.read()
         print(mp, sim.mapping)
         if ref is None:
