@@ -202,10 +202,11 @@ def learned_converging(n_steps=6):
            "fallback_k": CONVERGING_FALLBACK_K,
            "train": {"rows": int(ds.features.shape[0]), "seconds": t_train, "loss_by_epoch": losses}}
 
-    def compare(ev, state, k, n_steps):
+    def compare(ev, state, k, n_steps, **mapping):
         res = {}
         for name in ("plain", "learned"):
-            sim = snk.Sim(ev) if name == "plain" else warmstart.learned_sim(ev, net, mlp_fallback_k=k)
+            sim = (snk.Sim(ev, **mapping) if name == "plain"
+                   else warmstart.learned_sim(ev, net, mlp_fallback_k=k, **mapping))
             sim.write(**state)
             sim.step(1)
             torch.cuda.synchronize()
@@ -228,17 +229,20 @@ def learned_converging(n_steps=6):
         return res
 
     out.update(compare(ev, state, CONVERGING_FALLBACK_K, n_steps))
-    # A batch that fills the GPU (16 snakes per wave slot): the step time then
-    # follows the mean iteration count rather than the slowest snake's.
+    # A batch that fills the GPU (half rows: two snakes per 16-lane row, 8
+    # waves per SIMD slot): the step time then follows the mean iteration
+    # count rather than the slowest snake's.  Both forms take the same mapping.
     big = W.make("short", n_snakes=SATURATED_SNAKES)
     big.tol, big.iters = 1e-4, 30000
-    lead = snk.Sim(big, tol=1e-7, iters=60000)
+    half_rows = dict(map_waves=4, map_rows=2)
+    lead = snk.Sim(big, tol=1e-7, iters=60000, **half_rows)
     lead.step(6)
     big_state = lead.read()
     lead.close()
-    out["saturated"] = {"workload": f"short: {big.n_snakes} snakes, residual<=1e-4, max {big.iters} iterations",
+    out["saturated"] = {"workload": f"short: {big.n_snakes} snakes, residual<=1e-4, max {big.iters} iterations, "
+                                    "half rows",
                         "fallback_k": SATURATED_FALLBACK_K,
-                        **compare(big, big_state, SATURATED_FALLBACK_K, 4)}
+                        **compare(big, big_state, SATURATED_FALLBACK_K, 4, **half_rows)}
     return out
 
 
