@@ -80,6 +80,26 @@ def constant_net(c):
     return snk.Net(p, ms)
 
 
+def test_learned_start_in_half_rows_bit_identical():
+    """The split substeps around the network (prediction, then the
+    warm-started solve with the fallback after a few iterations) give the
+    same bits in half rows, two short snakes to a 16-lane row, as in whole
+    rows."""
+    wl = W.make("short", n_snakes=200)
+    net = constant_net(np.array([0.5, -0.2, 0.1], np.float32))
+    out = []
+    for mp in (dict(map_waves=1, map_rows=1), dict(map_waves=1, map_rows=2), dict(map_waves=4, map_rows=2)):
+        sim = snk.Sim(wl, warm_start=snk.WARM_MLP, mlp_fallback=1, mlp_fallback_k=3, **mp)
+        sim.set_mlp(net.params, net.mean_std)
+        sim.step(3)
+        out.append(sim.read())
+        print(mp, sim.mapping)
+        sim.close()
+    for r in out[1:]:
+        for k in out[0]:
+            assert np.array_equal(out[0][k], r[k]), k
+
+
 @pytest.mark.parametrize("fallback,fallback_k", [(0, 0), (1, 0), (1, 3)])
 def test_warm_start_from_network_outputs_matches_oracle(fallback, fallback_k):
     """A network that outputs the constant c gives lambda0 = m g h^2 R(qA) c
