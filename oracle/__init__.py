@@ -294,8 +294,13 @@ class Oracle:
         self.L.orc_predict_snake(C.byref(self.batch), int(s), *[_ptr(a) for a in arrs], float(h))
         return arrs
 
+    def _plain_chain_only(self):
+        if self.wheels:
+            raise ValueError("this stage takes the plain chain; for a wheel carriage use predict_bodies / run")
+
     def predict(self, s, h):
         """Apply the prediction stage to snake s in place (returns its views)."""
+        self._plain_chain_only()
         d = self.snake(s)
         arrs = [np.ascontiguousarray(d[k]) for k in ("x", "q", "v", "w")]
         self.L.orc_predict_snake(C.byref(self.batch), int(s), *[_ptr(a) for a in arrs], float(h))
@@ -306,6 +311,7 @@ class Oracle:
     # -- split substep (learned warm start) ------------------------------------
     def pre_substep(self, s, sub):
         """First half of substep `sub` of snake s in place; returns q_pred."""
+        self._plain_chain_only()
         d = self.snake(s)
         arrs = {k: np.ascontiguousarray(d[k]) for k in ("x", "q", "v", "w", "p", "cmd")}
         qp = np.zeros_like(arrs["q"])
@@ -318,6 +324,7 @@ class Oracle:
     def solve_substep(self, s, q_pred):
         """Second half for snake s (lam_* hold lambda0 for a GIVEN warm
         start); returns (residual, iterations, status)."""
+        self._plain_chain_only()
         d = self.snake(s)
         arrs = {k: np.ascontiguousarray(d[k]) for k in ("x", "q", "v", "w", "p", "lam_j", "lam_c")}
         qp = np.ascontiguousarray(q_pred, np.float64)

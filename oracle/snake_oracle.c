@@ -1953,6 +1953,7 @@ int orc_assemble_wheels(const orc_batch* b, int32_t snake, const double* x, cons
 void orc_pre_substep(const orc_batch* b, int32_t snake, int32_t sub, const double* x, const double* q,
                      double* v, double* w, double* p, const double* cmd, double* q_pred)
 {
+    if (b->flags & ORC_FLAG_WHEELS) return;   /* the split substep is the plain chain's */
     snake_ctx c;
     make_ctx(b, snake, &c);
     if (b->law == ORC_LAW_PAPER && sub == 0)
@@ -1980,6 +1981,7 @@ void orc_solve_substep(const orc_batch* b, int32_t snake, double* x, double* q, 
                        double* v, double* w, const double* p, double* lam_j, double* lam_c,
                        double* residual, int32_t* iters, int32_t* status)
 {
+    if (b->flags & ORC_FLAG_WHEELS) return;   /* the split substep is the plain chain's */
     snake_ctx c;
     make_ctx(b, snake, &c);
     scratch_t W;

@@ -161,11 +161,13 @@ int orc_assemble_wheels(const orc_batch* b, int32_t snake, const double* x, cons
                         const double* xp, const double* qp, const double* p, double* C, double* J,
                         double* W, double* comp);
 
-/* stages of one substep of one snake, exposed for tests */
+/* stages of one substep of one snake, exposed for tests (for a wheel-carriage
+ * batch the arrays hold the snake's B segments followed by its 2B wheels) */
 void orc_predict_snake(const orc_batch* b, int32_t snake, double* x, double* q, double* v,
                        double* w, double h);
 
-/* split substep: command effects on pressure and prediction, then the solve */
+/* split substep: command effects on pressure and prediction, then the solve
+ * (the plain chain only: both return at once for a wheel-carriage batch) */
 void orc_pre_substep(const orc_batch* b, int32_t snake, int32_t sub, const double* x, const double* q,
                      double* v, double* w, double* p, const double* cmd, double* q_pred);
 void orc_solve_substep(const orc_batch* b, int32_t snake, double* x, double* q, const double* q_pred,

@@ -156,8 +156,12 @@ def test_linearised_solve_meets_the_dense_solve_without_ground():
     assert np.abs(got - dl).max() <= 1e-8 * np.abs(dl).max()
 
 
-def test_carriage_refuses_other_solvers_and_starts():
+def test_carriage_refuses_other_solvers_starts_and_split_stages():
     wl = carriage()
     for over in (dict(solver=oracle.SOLVER_NEWTON), dict(solver=oracle.SOLVER_GS), dict(warm=oracle.WARM_PREV)):
         with pytest.raises(ValueError):
             oracle.Oracle(wl, **over)
+    o = oracle.Oracle(wl)
+    for stage in (lambda: o.predict(0, 0.01), lambda: o.pre_substep(0, 0), lambda: o.solve_substep(0, o.q)):
+        with pytest.raises(ValueError):
+            stage()
