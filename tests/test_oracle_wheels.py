@@ -165,3 +165,59 @@ def test_carriage_refuses_other_solvers_starts_and_split_stages():
     for stage in (lambda: o.predict(0, 0.01), lambda: o.pre_substep(0, 0), lambda: o.solve_substep(0, o.q)):
         with pytest.raises(ValueError):
             stage()
+
+
+def test_first_iteration_is_the_scaled_block_solve():
+    """From zero multipliers one iteration gives every block
+    dl = -(relax / d) K^-1 C, K = J_blk W J_blk^T + diag(alpha~), at the
+    predicted state, d the largest block count of its bodies (counted here
+    from the nonzero columns of the assembled J: a segment carries its
+    joints and its wheels' hinge blocks, a wheel its hinge blocks and its
+    contact); the hinge axis block uses its two rigid rows; a contact block
+    takes the normal row by K_nn and the tangential pair by its 2x2 block,
+    then the Coulomb disc of radius mu lambda_n."""
+    wl = carriage(n_modules=(1,), segs=(3,), substeps=1, relax=0.8)
+    o = oracle.Oracle(wl)
+    o.cmd[...] = 0.5
+    o.v[:, 0] = 0.01
+    o.wv[:, 0] = 0.01
+    o.run(3)
+    st = {k: getattr(o, k).copy() for k in ("x", "q", "v", "w", "wx", "wq", "wv", "ww")}
+    one = oracle.Oracle(wl, iters=1, tol=0.0)
+    for k, v in st.items():
+        getattr(one, k)[...] = v
+    one.p[...] = o.p
+    one.cmd[...] = o.cmd
+    one.run(1)
+    B = int(one.B[0])
+    xs, qs = np.r_[st["x"], st["wx"]], np.r_[st["q"], st["wq"]]
+    xt, qt, _, _ = one.predict_bodies(0, xs, qs, np.r_[st["v"], st["wv"]], np.r_[st["w"], st["ww"]], wl.dt)
+    Cv, J, Wm, comp = one.assemble_wheels(0, xt, qt, xs, qs, one.p)
+    nblk = len(Cv) // 3
+    touches = [sorted({c // 6 for c in np.nonzero(np.abs(J[3 * n:3 * n + 3]).sum(axis=0))[0]}) for n in range(nblk)]
+    deg = np.zeros(3 * B, int)
+    for t in touches:
+        deg[t] += 1
+    assert list(deg[:B]) == [6, 8, 6] and np.all(deg[B:] == 3)
+    nj = 2 * (B - 1)
+    expect = np.zeros(3 * nblk)
+    mu = float(wl.mu[0])
+    for n in range(nblk):
+        sc = 0.8 / max(deg[b] for b in touches[n])
+        rows = np.arange(3 * n, 3 * n + 3)
+        kind = None if n < nj else (n - nj) % 3
+        if kind == 1:
+            rows = rows[[0, 2]]
+        if kind == 2:
+            K = J[rows] @ Wm @ J[rows].T
+            ln = max(0.0, -sc * Cv[rows[0]] / K[0, 0])
+            lt = -sc * np.linalg.solve(K[1:, 1:], Cv[rows[1:]])
+            if np.linalg.norm(lt) > mu * ln:
+                lt *= mu * ln / np.linalg.norm(lt)
+            expect[rows] = [ln, *lt]
+            continue
+        K = J[rows] @ Wm @ J[rows].T + np.diag(comp[rows])
+        expect[rows] = -sc * np.linalg.solve(K, Cv[rows])
+    got = np.r_[one.lam_j.reshape(-1), one.lam_w.reshape(-1)]
+    assert np.abs(expect).max() > 0 and np.any(expect[3 * nj + 6::9] > 0)
+    assert np.abs(got - expect).max() <= 1e-9 * np.abs(expect).max()
