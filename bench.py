@@ -370,7 +370,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 "
-                          "(snakes are independent, see DESIGN.md for the multi-GPU split)"}))
+                          "(snakes are independent: several GPUs would each take a share of the snakes, "
+                          "one process per GPU, with no exchange during a step)"}))
         sys.exit(2)
     import torch
 
