@@ -51,7 +51,7 @@ PEAK_HBM = 8.0e12
 SOLVER_TRAFFIC = {"newton": (337.0e6, ("newton.hip", "lanes.h", "blocks.h", "device_math.h", "kernels.h"),
                              "03507154f969a960:7d1acb2a40eb1590:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"),
                   "carriage": (118.0e6, ("carriage.hip", "carriage.h", "lanes.h", "blocks.h", "device_math.h",
-                                         "kernels.h"), "a89ffe76c52a146a:b17d334d03f00823:7d1acb2a40eb1590:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"),
+                                         "kernels.h"), "720f771d897fa22f:b17d334d03f00823:7d1acb2a40eb1590:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"),
                   "gs": (52.8e6, ("gs.hip", "blocks.h", "device_math.h", "kernels.h"),
                          "a845d97590629bbd:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726")}
 # Newton solver (FP64): operations per body per inner conjugate-residual

@@ -65,6 +65,15 @@ __device__ __forceinline__ double iform(D3 s, D3 t, D3 a, double c1, double c2)
     return c1 * dot(s, t) + c2 * dot(a, s) * dot(a, t);
 }
 
+// q <- normalize(q + 1/2 [0, dth] (x) q), one reciprocal of the norm
+__device__ __forceinline__ DQ qturn1(DQ q, D3 dth)
+{
+    const DQ t = qmul(DQ{0.0, dth.x, dth.y, dth.z}, q);
+    const DQ r{q.w + 0.5 * t.w, q.x + 0.5 * t.x, q.y + 0.5 * t.y, q.z + 0.5 * t.z};
+    const double in = 1.0 / sqrt(r.w * r.w + r.x * r.x + r.y * r.y + r.z * r.z);
+    return DQ{r.w * in, r.x * in, r.y * in, r.z * in};
+}
+
 // larger of a and b, NaN kept
 __device__ __forceinline__ double rmax(double a, double b) { return (b > a || b != b) ? b : a; }
 
@@ -327,9 +336,9 @@ k_carriage(KParams P, NParams Q, WParams Wp, const int* __restrict__ list, int c
                         const double k22 = wW + iform(j1, j1, aW, c1W, c2W);
                         double ln = lc[k].x + scc * (-cn / knn);
                         if (ln < 0.0) ln = 0.0;
-                        const double det = k11 * k22 - k12 * k12;
-                        const double y0 = (k22 * c0 - k12 * c1t) / det;
-                        const double y1 = (k11 * c1t - k12 * c0) / det;
+                        const double idet = 1.0 / (k11 * k22 - k12 * k12);
+                        const double y0 = (k22 * c0 - k12 * c1t) * idet;
+                        const double y1 = (k11 * c1t - k12 * c0) * idet;
                         double lt0 = lc[k].y - scc * y0, lt1 = lc[k].z - scc * y1;
                         const double cap = mu * ln;
                         const double nt = sqrt(lt0 * lt0 + lt1 * lt1);
@@ -396,11 +405,11 @@ k_carriage(KParams P, NParams Q, WParams Wp, const int* __restrict__ list, int c
                                  dlc[k].z * cross(sarm[k], d3(0.0, 1.0, 0.0));
                         }
                         xw[k] = xw[k] + wW * fw;
-                        qw[k] = qturn(qw[k], inv_inertia(tw, qcol1(qw[k]), c1W, c2W));
+                        qw[k] = qturn1(qw[k], inv_inertia(tw, qcol1(qw[k]), c1W, c2W));
                     }
                     if (!fixed) {
                         x = x + wA * f;
-                        q = qturn(q, inv_inertia(tq, aA, c1A, c2A));
+                        q = qturn1(q, inv_inertia(tq, aA, c1A, c2A));
                     }
                 }
             }
