@@ -50,8 +50,8 @@ PEAK_HBM = 8.0e12
 # with the digest of their sources
 SOLVER_TRAFFIC = {"newton": (337.0e6, ("newton.hip", "lanes.h", "blocks.h", "device_math.h", "kernels.h"),
                              "03507154f969a960:7d1acb2a40eb1590:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"),
-                  "carriage": (118.0e6, ("carriage.hip", "carriage.h", "lanes.h", "blocks.h", "device_math.h",
-                                         "kernels.h"), "720f771d897fa22f:b17d334d03f00823:7d1acb2a40eb1590:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"),
+                  "carriage": (126.1e6, ("carriage.hip", "carriage.h", "lanes.h", "blocks.h", "device_math.h",
+                                         "kernels.h"), "de6cffb718471c85:b17d334d03f00823:7d1acb2a40eb1590:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"),
                   "gs": (52.8e6, ("gs.hip", "blocks.h", "device_math.h", "kernels.h"),
                          "a845d97590629bbd:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726")}
 # Newton solver (FP64): operations per body per inner conjugate-residual
@@ -68,7 +68,7 @@ FLOP_NEWTON_SUBSTEP = 450
 # outside the iterations (pressure, rest rotation, prediction of three
 # bodies, friction anchors, velocities), counted from the compiled loops as
 # for the Newton solver.
-FLOP_CARRIAGE_ITER = 1930
+FLOP_CARRIAGE_ITER = 1780
 FLOP_CARRIAGE_SUBSTEP = 750
 CARRIAGE_ITERS = 20
 PEAK_FP64 = 78.6e12        # MI355X FP64 vector (published)

@@ -59,6 +59,21 @@ __device__ __forceinline__ D3 solve_sym3(const S3& K, D3 b)
               (c02 * b.x + c12 * b.y + c22 * b.z) * id};
 }
 
+// (alpha I + d0 u0 u0^T + d1 u1 u1^T)^-1 b through the 2x2 capacitance
+// system (Woodbury): z = (I + D U^T U / alpha)^-1 D U^T b / alpha,
+// u = (b - U z) / alpha, U = [u0 u1], D = diag(d0, d1).
+__device__ __forceinline__ D3 solve_rank2(double alpha, D3 u0, double d0, D3 u1, double d1, D3 b)
+{
+    const double ia = 1.0 / alpha;
+    const double g00 = dot(u0, u0), g01 = dot(u0, u1), g11 = dot(u1, u1);
+    const double y0 = d0 * dot(u0, b) * ia, y1 = d1 * dot(u1, b) * ia;
+    const double m00 = 1.0 + d0 * g00 * ia, m01 = d0 * g01 * ia;
+    const double m10 = d1 * g01 * ia, m11 = 1.0 + d1 * g11 * ia;
+    const double idet = 1.0 / (m00 * m11 - m01 * m10);
+    const double z0 = (m11 * y0 - m01 * y1) * idet, z1 = (m00 * y1 - m10 * y0) * idet;
+    return ia * (b - (z0 * u0 + z1 * u1));
+}
+
 // s^T M t for the inverse inertia M of a body with symmetry axis a
 __device__ __forceinline__ double iform(D3 s, D3 t, D3 a, double c1, double c2)
 {
@@ -264,18 +279,12 @@ k_carriage(KParams P, NParams Q, WParams Wp, const int* __restrict__ list, int c
                     A0 = G0.x * F0 + G0.y * F1 + G0.z * F2;
                     A1 = G1.x * F0 + G1.y * F1 + G1.z * F2;
                     A2 = G2.x * F0 + G2.y * F1 + G2.z * F2;
-                    // stretch block: K = (wA + wB) I + [ra]x IA [ra]x^T + [rb]x IB [rb]x^T + comp
-                    const D3 sa0 = skew_row(ra, 0), sa1 = skew_row(ra, 1), sa2 = skew_row(ra, 2);
-                    const D3 sb0 = skew_row(rb, 0), sb1 = skew_row(rb, 1), sb2 = skew_row(rb, 2);
-                    auto ks = [&](D3 u, D3 vv, D3 p, D3 pp) {
-                        return iform(u, vv, aA, c1A, c2A) + iform(p, pp, aB, c1, c2);
-                    };
-                    const double wab = wA + wB + comp_s;
-                    const S3 Ks{wab + ks(sa0, sa0, sb0, sb0), ks(sa0, sa1, sb0, sb1), ks(sa0, sa2, sb0, sb2),
-                                wab + ks(sa1, sa1, sb1, sb1), ks(sa1, sa2, sb1, sb2), wab + ks(sa2, sa2, sb2, sb2)};
+                    // stretch block: K = (wA + wB + comp) I + [ra]x IA [ra]x^T + [rb]x IB [rb]x^T;
+                    // each arm lies on its body's axis, so [r]x I^-1 [r]x^T = c1 (|r|^2 I - r r^T)
                     const D3 rs = Cs + comp_s * ls;
                     rl = rmax(rl, rmax(rmax(fabs(rs.x), fabs(rs.y)), fabs(rs.z)) * inv_L);
-                    dls = -scj * solve_sym3(Ks, rs);
+                    dls = -scj * solve_rank2(wA + wB + comp_s + c1A * dot(ra, ra) + c1 * dot(rb, rb), ra, -c1A, rb,
+                                             -c1, rs);
                     // bend-twist block: K = A (IA + IB) A^T + comp
                     auto kb = [&](D3 u, D3 vv) { return iform(u, vv, aA, c1A, c2A) + iform(u, vv, aB, c1, c2); };
                     const S3 Kb{kb(A0, A0) + comp_t, kb(A0, A1), kb(A0, A2), kb(A1, A1) + comp_b, kb(A1, A2),
@@ -294,13 +303,11 @@ k_carriage(KParams P, NParams Q, WParams Wp, const int* __restrict__ list, int c
                     rh[k] = (k == 0 ? Wp.dw : -Wp.dw) * qcol1(q) - Wp.hw * qcol2(q);
                     const D3 Ch = (x + rh[k]) - xw[k];
                     {
-                        const D3 s0 = skew_row(rh[k], 0), s1 = skew_row(rh[k], 1), s2 = skew_row(rh[k], 2);
-                        const double wsum = wA + wW;
-                        const S3 Kh{wsum + iform(s0, s0, aA, c1A, c2A), iform(s0, s1, aA, c1A, c2A),
-                                    iform(s0, s2, aA, c1A, c2A), wsum + iform(s1, s1, aA, c1A, c2A),
-                                    iform(s1, s2, aA, c1A, c2A), wsum + iform(s2, s2, aA, c1A, c2A)};
+                        // K = (wA + wW) I + [rh]x IA [rh]x^T
+                        //   = (wA + wW + c1 |rh|^2) I - c1 rh rh^T + c2 (rh x a)(rh x a)^T
                         rl = rmax(rl, rmax(rmax(fabs(Ch.x), fabs(Ch.y)), fabs(Ch.z)) * inv_L);
-                        dlh[k] = -sch * solve_sym3(Kh, Ch);
+                        dlh[k] = -sch * solve_rank2(wA + wW + c1A * dot(rh[k], rh[k]), rh[k], -c1A, cross(rh[k], aA),
+                                                    c2A, Ch);
                     }
                     // hinge axis: e = conj(q) q_wheel, rows x and z rigid
                     {
