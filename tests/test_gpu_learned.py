@@ -85,7 +85,7 @@ def test_learned_start_in_half_rows_bit_identical():
     warm-started solve with the fallback after a few iterations) give the
     same bits in half rows, two short snakes to a 16-lane row, as in whole
     rows."""
-    wl = W.make("short", n_snakes=200)
+    wl = W.make("short", n_snakes=201)
     net = constant_net(np.array([0.5, -0.2, 0.1], np.float32))
     out = []
     for mp in (dict(map_waves=1, map_rows=1), dict(map_waves=1, map_rows=2), dict(map_waves=4, map_rows=2)):
