@@ -24,7 +24,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "snake_oracle.c")
-SRCS = [SRC, os.path.join(HERE, "mlp_oracle.c")]
+SRCS = [SRC, os.path.join(HERE, "mlp_oracle.c"), os.path.join(HERE, "fem_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 FLAG_FIXED_ROOT = 1
@@ -113,6 +113,17 @@ def _declare(L):
     L.orc_solve_substep.argtypes = [bp, C.c_int32] + [_P] * 11
     L.orc_features.argtypes = [bp, C.c_int32] + [_P] * 9
     L.orc_targets.argtypes = [bp, C.c_int32, _P, _P, _P]
+    L.fem_tet_rest.argtypes = [_P, _P, _P]
+    L.fem_tet_rest.restype = C.c_int
+    L.fem_polar.argtypes = [_P, _P]
+    L.fem_polar.restype = C.c_int
+    L.fem_tet_eval.argtypes = [_P, _P, _P, C.c_int, _P, _P]
+    L.fem_tet_eval.restype = C.c_int
+    L.fem_tet_compliance.argtypes = [C.c_double, C.c_double, C.c_double, _P]
+    L.fem_expansion.argtypes = [C.c_double, C.c_double]
+    L.fem_expansion.restype = C.c_double
+    L.fem_dist_eval.argtypes = [_P, _P, C.c_double, C.c_double, C.c_double, _P]
+    L.fem_dist_eval.restype = C.c_double
     L.mlo_param_count.restype = C.c_int
     L.mlo_norm_stats.argtypes = [_P, C.c_int64, _P, _P]
     L.mlo_forward.argtypes = [_P, _P, _P, _P, C.c_int64, _P]
@@ -406,3 +417,50 @@ def mlp_loss_grad(params, mean, std, x, t, with_grad=True):
 def mlp_adam(params, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     """One Adam step in place on float64 arrays."""
     lib().mlo_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(_d(g)), params.size, int(t), lr, b1, b2, eps)
+
+
+# ---------------------------------------------------------------- link elements
+
+def fem_tet_rest(X):
+    """Rest tetrahedron X[4][3] -> (Dm^-1 [3][3], volume)."""
+    X = _d(X)
+    Dm_inv, V = np.zeros((3, 3)), C.c_double()
+    if lib().fem_tet_rest(_ptr(X), _ptr(Dm_inv), C.byref(V)) != 0:
+        raise ValueError("degenerate tetrahedron")
+    return Dm_inv, V.value
+
+
+def fem_polar(F):
+    F, R = _d(F), np.zeros((3, 3))
+    if lib().fem_polar(_ptr(F), _ptr(R)) != 0:
+        raise ValueError("det F <= 0")
+    return R
+
+
+def fem_tet_eval(Dm_inv, x, R=None):
+    """Corotational strain C[6] (xx, yy, zz, yz, xz, xy), Jacobian J[6][12]
+    with the rotation held fixed, and the rotation R (given, or the polar
+    one of F)."""
+    Dm_inv, x = _d(Dm_inv), _d(x)
+    Rm = np.zeros((3, 3)) if R is None else _d(R).copy()
+    Cv, J = np.zeros(6), np.zeros((6, 12))
+    if lib().fem_tet_eval(_ptr(Dm_inv), _ptr(x), _ptr(Rm), 0 if R is None else 1, _ptr(Cv), _ptr(J)) != 0:
+        raise ValueError("inverted tetrahedron")
+    return Cv, J, Rm
+
+
+def fem_tet_compliance(V, Y, nu):
+    E = np.zeros((6, 6))
+    lib().fem_tet_compliance(float(V), float(Y), float(nu), _ptr(E))
+    return E
+
+
+def fem_expansion(p, Y):
+    return lib().fem_expansion(float(p), float(Y))
+
+
+def fem_dist(xi, xj, r, p, Y):
+    """Actuation distance constraint value and Jacobian J[6] (xi, xj)."""
+    xi, xj, J = _d(xi), _d(xj), np.zeros(6)
+    c = lib().fem_dist_eval(_ptr(xi), _ptr(xj), float(r), float(p), float(Y), _ptr(J))
+    return c, J
