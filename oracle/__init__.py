@@ -124,6 +124,7 @@ def _declare(L):
     L.fem_expansion.restype = C.c_double
     L.fem_dist_eval.argtypes = [_P, _P, C.c_double, C.c_double, C.c_double, _P]
     L.fem_dist_eval.restype = C.c_double
+    L.fem_attach_eval.argtypes = [_P] * 6
     L.mlo_param_count.restype = C.c_int
     L.mlo_norm_stats.argtypes = [_P, C.c_int64, _P, _P]
     L.mlo_forward.argtypes = [_P, _P, _P, _P, C.c_int64, _P]
@@ -464,3 +465,12 @@ def fem_dist(xi, xj, r, p, Y):
     xi, xj, J = _d(xi), _d(xj), np.zeros(6)
     c = lib().fem_dist_eval(_ptr(xi), _ptr(xj), float(r), float(p), float(Y), _ptr(J))
     return c, J
+
+
+def fem_attach(x, q, r, xp):
+    """Attachment constraint C[3] and Jacobian J[3][9] (body x, body
+    rotation, particle)."""
+    x, q, r, xp = _d(x), _d(q), _d(r), _d(xp)
+    Cv, J = np.zeros(3), np.zeros((3, 9))
+    lib().fem_attach_eval(_ptr(x), _ptr(q), _ptr(r), _ptr(xp), _ptr(Cv), _ptr(J))
+    return Cv, J

@@ -13,7 +13,9 @@
  *   - the element compliance E_tetra = M / (V Y) of the same section;
  *   - the actuation distance constraint |x_i - x_j| - r eps(p) with the
  *     strain eps(p) = 1 + p / Y of eq. expansion (section "Actuation
- *     Constraints"), and its Jacobian.
+ *     Constraints"), and its Jacobian;
+ *   - the attachment of a particle to a point of a rigid body,
+ *     eq. rigid_to_particle, and its Jacobian.
  * Every quantity is double.
  */
 #include <math.h>
@@ -155,4 +157,27 @@ double fem_dist_eval(const double* xi, const double* xj, double r, double p, dou
         J[3 + k] = -n;
     }
     return L - r * fem_expansion(p, Y);
+}
+
+/* Attachment of particle xp to the point r (body frame) of a rigid body
+ * (centre x, unit quaternion q = (w, x, y, z)), eq. rigid_to_particle:
+ * C = x + R(q) r - xp (3 rows); J[3][9] = d C / d (x, theta, xp) with theta
+ * a world rotation vector: (I, -[R r]x, -I). */
+void fem_attach_eval(const double* x, const double* q, const double* r, const double* xp, double* C, double* J)
+{
+    const double w = q[0], a = q[1], b = q[2], c = q[3];
+    const double R[9] = {1 - 2 * (b * b + c * c), 2 * (a * b - w * c), 2 * (a * c + w * b),
+                         2 * (a * b + w * c), 1 - 2 * (a * a + c * c), 2 * (b * c - w * a),
+                         2 * (a * c - w * b), 2 * (b * c + w * a), 1 - 2 * (a * a + b * b)};
+    double u[3];
+    for (int i = 0; i < 3; ++i) u[i] = R[3 * i] * r[0] + R[3 * i + 1] * r[1] + R[3 * i + 2] * r[2];
+    for (int i = 0; i < 3; ++i) C[i] = x[i] + u[i] - xp[i];
+    /* rows of -[u]x: d (theta x u) = -u x d theta */
+    const double S[9] = {0, u[2], -u[1], -u[2], 0, u[0], u[1], -u[0], 0};
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) {
+            J[9 * i + k] = i == k ? 1.0 : 0.0;
+            J[9 * i + 3 + k] = S[3 * i + k];
+            J[9 * i + 6 + k] = i == k ? -1.0 : 0.0;
+        }
 }

@@ -112,3 +112,31 @@ def test_degenerate_and_inverted_elements_refused():
     Dm_inv, _ = oracle.fem_tet_rest(REST)
     with pytest.raises(ValueError):
         oracle.fem_tet_eval(Dm_inv, REST * [-1.0, 1.0, 1.0])
+
+
+def test_attachment_constraint():
+    """eq. rigid_to_particle: zero when the particle sits at the body point
+    (rotation applied by an independent matrix), Jacobian against finite
+    differences (world rotation vectors for the body)."""
+    Q = rot([0.3, -1.0, 0.5], 0.9)
+    ang, ax = 0.9, np.array([0.3, -1.0, 0.5]) / np.linalg.norm([0.3, -1.0, 0.5])
+    q = np.r_[np.cos(ang / 2), np.sin(ang / 2) * ax]
+    x, r = np.array([0.1, -0.2, 0.3]), np.array([0.005, 0.0, -0.002])
+    c, J = oracle.fem_attach(x, q, r, x + Q @ r)
+    assert np.abs(c).max() <= 1e-15
+    xp = x + Q @ r + np.array([1e-3, -2e-3, 5e-4])
+    c, J = oracle.fem_attach(x, q, r, xp)
+    eps = 1e-7
+    for k in range(9):
+        d = np.zeros(9)
+        d[k] = eps
+
+        def at(d):
+            dq = rot(d[3:6], np.linalg.norm(d[3:6])) if np.linalg.norm(d[3:6]) > 0 else np.eye(3)
+            # rotate the body by the world rotation dq: R' = dq R, i.e. the point R r -> dq R r
+            Rn = dq @ Q
+            w = np.sqrt(max(0.0, 1 + np.trace(Rn))) / 2
+            qn = np.array([w, (Rn[2, 1] - Rn[1, 2]) / (4 * w), (Rn[0, 2] - Rn[2, 0]) / (4 * w), (Rn[1, 0] - Rn[0, 1]) / (4 * w)])
+            return oracle.fem_attach(x + d[:3], qn, r, xp + d[6:])[0]
+        fd = (at(d) - at(-d)) / (2 * eps)
+        assert np.abs(fd - J[:, k]).max() <= 1e-7, k
