@@ -140,3 +140,40 @@ def test_attachment_constraint():
             return oracle.fem_attach(x + d[:3], qn, r, xp + d[6:])[0]
         fd = (at(d) - at(-d)) / (2 * eps)
         assert np.abs(fd - J[:, k]).max() <= 1e-7, k
+
+
+def test_procedural_link_mesh():
+    """The stand-in link mesh: volume exactly that of the polygonal prism
+    (sections - 1 gaps x regular ring-gon area), every element positively
+    oriented with the oracle's rest volume, a conforming mesh (interior
+    triangles in two elements, the two caps and the outer surface in one),
+    and symmetric under a turn of 2 pi / ring about the link axis."""
+    import workloads as W
+
+    S, K, L, R = 13, 8, 0.01, 0.01
+    pts, tets = W.link_mesh(S, K, L, R)
+    assert pts.shape == (S * (K + 1), 3) and tets.shape == (3 * K * (S - 1), 4)
+    vols = []
+    for t in tets:
+        p = pts[t]
+        v = np.linalg.det((p[1:] - p[0]).T) / 6
+        assert v > 0
+        vols.append(v)
+        assert np.isclose(oracle.fem_tet_rest(p)[1], v, rtol=1e-12)
+    assert np.isclose(sum(vols), L * 0.5 * K * R * R * np.sin(2 * np.pi / K), rtol=1e-12)
+    faces = {}
+    for t in tets:
+        for f in ((0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)):
+            key = tuple(sorted(int(t[i]) for i in f))
+            faces[key] = faces.get(key, 0) + 1
+    assert set(faces.values()) == {1, 2}
+    assert sum(1 for c in faces.values() if c == 1) == 2 * K + 2 * K * (S - 1)
+    per = K + 1
+
+    def turn(i):
+        s, j = divmod(int(i), per)
+        return i if j == 0 else s * per + 1 + j % K
+
+    Q = rot([1, 0, 0], 2 * np.pi / K)
+    assert np.abs(pts @ Q.T - pts[[turn(i) for i in range(len(pts))]]).max() <= 1e-15
+    assert {tuple(sorted(turn(i) for i in t)) for t in tets} == {tuple(sorted(int(i) for i in t)) for t in tets}

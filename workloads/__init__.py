@@ -257,3 +257,35 @@ def custom(n_modules, segs_per_module, *, alpha=(1e-5, 1e-5, 1e-5), mu=0.5,
                     alpha_stretch=col(alpha[0]), alpha_bend=col(alpha[1]),
                     alpha_twist=col(alpha[2]), mu=col(mu), controller=controller,
                     ctrl_freq=col(freq), ctrl_phase0=col(phase0), **kw)
+
+
+def link_mesh(sections: int = 13, ring: int = 8, length: float = 0.01, radius: float = 0.01):
+    """Procedural tetrahedral mesh of one soft link, a stand-in for the
+    paper's TetGen mesh (not distributed): `sections` cross-sections evenly
+    along x in [0, length], each a centre particle and `ring` particles on a
+    circle of `radius` (radially symmetric); between consecutive sections
+    every wedge (centre, k, k+1) is split into three tetrahedra with the
+    diagonals centre -> next section's ring on its radial faces and ring k ->
+    next section's ring k+1 on its outer face, so neighbouring wedges share
+    whole triangles.  Returns particles [n][3] (section-major: centre, then
+    the ring) and positively oriented tetrahedra [m][4] (particle indices)."""
+    per = ring + 1
+    xs = np.linspace(0.0, length, sections)
+    th = 2.0 * np.pi * np.arange(ring) / ring
+    pts = []
+    for x in xs:
+        pts.append([x, 0.0, 0.0])
+        for t in th:
+            pts.append([x, radius * np.cos(t), radius * np.sin(t)])
+    pts = np.array(pts)
+    tets = []
+    for s in range(sections - 1):
+        for k in range(ring):
+            a0, a1, a2 = s * per, s * per + 1 + k, s * per + 1 + (k + 1) % ring
+            b0, b1, b2 = a0 + per, a1 + per, a2 + per
+            for t in ((a0, a1, a2, b2), (a0, a1, b1, b2), (a0, b0, b1, b2)):
+                p = pts[list(t)]
+                if np.linalg.det((p[1:] - p[0]).T) < 0:
+                    t = (t[0], t[2], t[1], t[3])
+                tets.append(t)
+    return pts, np.array(tets, np.int64)
