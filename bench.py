@@ -5,16 +5,21 @@ evaluation, chamber pressures, rest shape, prediction, the block-Jacobi
 solve of every substep (to residual <= 1e-4, at most 200 iterations, by
 default) and the velocity update.  The state lives in HBM between steps.
 
-Prints one JSON line: snake-steps/s (value), constraint-iterations/s, the
-dominant kernel's roofline position (measured with HIP events on the
-solver's stream) and the FP64 CPU oracle timed on a bounded sample of the
-same workload on this machine's host cores.  Comparisons ride along: the
+Prints one JSON line.  The headline is the uneven batch (16 384 snakes of
+16 to 256 bodies, the batch the plain-versus-learned comparison is defined
+on): snake-steps/s (value) and constraint-iterations/s at residual 1e-4 with
+at most 200 iterations per substep, with the fraction of snakes that reach
+1e-4 and the distribution of iterations per substep; no snake of this batch
+reaches 1e-4 within 200 block-Jacobi iterations, and the line says so
+("fixed budget, not converged").  Beside it: the dominant kernel's roofline
+position (measured with HIP events on the solver's stream), the FP64 CPU
+oracle timed on a bounded sample on this machine's host cores together with
+the FP64 error of every GPU result on that sample, the rate at which the
+uniform batch's 64-body snakes actually reach 1e-4 when the iteration cap
+is lifted, the learned warm start against the zero start on its batch, the
 paper's own solver (Newton with a preconditioned conjugate-residual inner
-solve, FP64) and block Gauss-Seidel against block Jacobi at fixed budgets on
-the same batch, and the
-learned warm start against the zero start on the uneven batch at the
-headline setting (at most 200 iterations, which no snake's solve reaches
-1e-4 within) and on short snakes whose solve converges within its budget.
+solve, FP64) and block Gauss-Seidel against block Jacobi at fixed budgets,
+and the wheel carriage.
 """
 from __future__ import annotations
 
@@ -95,15 +100,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="uniform")
+    ap.add_argument("--workload", default="uneven")
     ap.add_argument("--snakes", type=int, default=None)
     ap.add_argument("--fixed", action="store_true", help="fixed 20 iterations per substep")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--mapping", default=None,
                     help="force a mapping instead of autotuning: waves,min_seg,rows (e.g. 4,16,1)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-snakes", type=int, default=1024)
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-snakes", type=int, default=256,
+                    help="snakes of the CPU-baseline sample (evenly spaced over the batch)")
+    ap.add_argument("--cpu-steps", type=int, default=50, help="first steps of the CPU-baseline sample")
+    ap.add_argument("--no-converged", action="store_true",
+                    help="skip the leg that lifts the iteration cap until the uniform batch reaches 1e-4")
+    ap.add_argument("--converged-cap", type=int, default=400000)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
     ap.add_argument("--learned-steps", type=int, default=20)
     ap.add_argument("--no-newton", action="store_true", help="skip the Newton solver comparison")
@@ -162,12 +171,19 @@ def learned_comparison(n_steps):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         r = sim.read("iters_total", "residual", "status")
-        its = (r["iters_total"] - r0).sum() / (ev.n_snakes * n_steps * ev.substeps)
+        its = (r["iters_total"] - r0).astype(np.float64)
+        B = ev.bodies.astype(np.float64)
         out[name] = {"snake_steps_per_s": ev.n_snakes * n_steps / (ms / 1e3),
-                     "ms_per_step": ms / n_steps, "mean_iters_per_substep": float(its),
-                     "residual_median_last_step": float(np.median(r["residual"])),
+                     "constraint_iters_per_s": float(np.sum((9 * B - 6) * its)) / (ms / 1e3),
+                     "ms_per_step": ms / n_steps,
+                     "mean_iters_per_substep": float(its.sum() / (ev.n_snakes * n_steps * ev.substeps)),
+                     **iteration_stats(its, ev.substeps, n_steps, r["status"], r["residual"], ev.tol, ev.iters),
                      "fell_back_last_step": int(np.sum((r["status"] & 4) != 0))}
         sim.close()
+    out["workload"] = (f"learned: the uneven batch's shape and draws, evaluation seed, {ev.n_snakes} snakes, "
+                       f"residual<=1e-4 or at most {ev.iters} iterations per substep")
+    out["gain"] = {"fewer_iterations": out["learned"]["mean_iters_per_substep"] < out["plain"]["mean_iters_per_substep"],
+                   "more_snake_steps_per_s": out["learned"]["snake_steps_per_s"] > out["plain"]["snake_steps_per_s"]}
     return out
 
 
@@ -350,20 +366,123 @@ def carriage_run(wl, n_steps=5, iters=CARRIAGE_ITERS):
                          "flop_per_segment_iter": FLOP_CARRIAGE_ITER}}
 
 
-def cpu_baseline(wl, n_snakes, n_steps):
-    import oracle
+def host_cores():
+    """Threads the oracle runs on: the CPUs this process may use, at most 16
+    (the host share of one GPU on the benchmark machines)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail)), avail
 
-    sub = wl.take(np.arange(min(n_snakes, wl.n_snakes)))
-    threads = max(1, min(16, os.cpu_count() or 1))
+
+def cpu_baseline(wl, n_snakes, n_steps, gpu_kw):
+    """The FP64 oracle as it stands, timed on this machine's host cores:
+    (1) the single-snake workload in full (600 steps, 4 substeps x 20
+    iterations), one thread; (2) the first n_steps steps of n_snakes snakes
+    spread evenly over the timed batch, its settings, snakes split over the
+    host cores.  The value is (2)'s snake-steps/s.  Then both sides take one
+    more substep of that sample from the oracle's state rounded to FP32, and
+    the GPU's results are compared with the oracle's (the FP64 error of
+    every result: positions, velocities, angular velocities, multipliers)."""
+    import oracle
+    import workloads as W
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import advance_both, compare, rounded_state
+
+    threads, avail = host_cores()
+    single = W.make("single")
+    o1 = oracle.Oracle(single)
+    t0 = time.perf_counter()
+    o1.run(single.steps, threads=1)
+    t_single = time.perf_counter() - t0
+
+    pick = np.unique(np.linspace(0, wl.n_snakes - 1, min(n_snakes, wl.n_snakes)).round().astype(np.int64))
+    sub = wl.take(pick)
     o = oracle.Oracle(sub)
     t0 = time.perf_counter()
     o.run(n_steps, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": sub.n_snakes * n_steps / dt, "unit": "snake-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"first {n_steps} steps of {sub.n_snakes} of the {wl.n_snakes} snakes, "
-                      f"FP64 C oracle, {dt:.1f} s wall",
-            "constraint_iters_per_s": float(np.sum((9 * sub.bodies - 6) * o.iters_total) / dt)}
+    out = {"value": sub.n_snakes * n_steps / dt, "unit": "snake-steps/s", "cores": threads,
+           "host_cpus_available": avail, "kind": "oracle",
+           "sample": f"first {n_steps} steps of {sub.n_snakes} of the {wl.n_snakes} snakes (evenly spaced "
+                     f"by index, {int(sub.bodies.sum())} bodies), the timed batch's settings, FP64 C oracle "
+                     f"on {threads} threads, {dt:.1f} s wall",
+           "constraint_iters_per_s": float(np.sum((9 * sub.bodies - 6) * o.iters_total) / dt),
+           "single_snake_full": {"workload": f"single: 1 snake of 64 bodies, {single.steps} steps, "
+                                             f"{single.substeps} substeps x {single.iters} iterations",
+                                 "snake_steps_per_s": single.steps / t_single, "seconds": t_single,
+                                 "cores": 1}}
+    o.commands()
+    oo, g = advance_both(sub, rounded_state(o), threads=threads, **gpu_kw)
+    err = compare(oo, g, np.asarray(sub.mu, np.float64))
+    out["fp64_error"] = {
+        "protocol": "one substep of the sample from the oracle's state rounded to FP32, GPU (FP32) "
+                    "against the FP64 oracle; positions relative to the snake's extent, velocities "
+                    "to max(|v|, g h) and max(|w|, g h / L), multipliers per block type to their "
+                    "largest magnitude (floor m g h^2, bend m g h^2 L)",
+        **{k: {"max": float(np.max(v)), "p99": float(np.percentile(v, 99))}
+           for k, v in err.items() if k != "branch"},
+        "contact_branch_mismatches": int(err["branch"].sum()),
+        "bodies": int(sub.bodies.sum())}
+    return out
+
+
+def iteration_stats(its, substeps, n_steps, status, residual, tol, cap):
+    """Per-snake iterations per substep over the timed steps, the fraction
+    of snakes whose last step reached the tolerance in every substep, and
+    the last step's residuals."""
+    per = its / (substeps * n_steps)
+    conv = (status & 2) == 0
+    st = {"tol": tol, "max_iters": cap,
+          "converged_frac_last_step": float(conv.mean()),
+          "iters_per_substep": {"mean": float(per.mean()), "median": float(np.median(per)),
+                                "p99": float(np.percentile(per, 99)), "max": float(per.max())},
+          "residual_last_step": {"median": float(np.median(residual)),
+                                 "p99": float(np.percentile(residual, 99)), "max": float(np.max(residual))}}
+    st["label"] = ("converged" if conv.all() else
+                   "fixed budget, not converged" if not conv.any() else "partly converged")
+    return st
+
+
+def converged_run(name="uniform", n_steps=2, cap=400000):
+    """The batch from rest with the iteration cap lifted until its snakes
+    reach residual 1e-4 (or stall at FP32's floor): snake-steps/s and
+    constraint-iterations/s at the tolerance, with the iterations it took."""
+    import torch
+
+    import paper_1904_02833_amd as snk
+    import workloads as W
+
+    wl = W.make(name)
+    wl.tol, wl.iters = 1e-4, cap
+    sim = snk.Sim(wl, use_graph=1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res, ms_steps, its_all = [], [], []
+    for n in range(n_steps):
+        before = sim.read("iters_total")["iters_total"].copy()
+        e0.record(sim.stream)
+        sim.step(1)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        ms_steps.append(e0.elapsed_time(e1))
+        r = sim.read("iters_total", "residual", "status")
+        its_all.append((r["iters_total"] - before).astype(np.float64))
+        res.append(r)
+        print(f"[converged {name}] step {n}: {ms_steps[-1]:.0f} ms, "
+              f"converged {float(np.mean((r['status'] & 2) == 0)):.3f}", file=sys.stderr, flush=True)
+    sim.close()
+    its = np.sum(its_all, axis=0)
+    ms = float(np.sum(ms_steps))
+    B = wl.bodies.astype(np.float64)
+    last = res[-1]
+    return {"workload": f"{name}: {wl.n_snakes} snakes, {int(B.sum())} bodies, {wl.substeps} substeps, "
+                        f"from rest, residual<=1e-4 with at most {cap} iterations per substep",
+            "steps": n_steps, "ms_per_step": ms / n_steps, "ms_each_step": ms_steps,
+            "snake_steps_per_s": wl.n_snakes * n_steps / (ms / 1e3),
+            "constraint_iters_per_s": float(np.sum((9 * B - 6) * its)) / (ms / 1e3),
+            **iteration_stats(its, wl.substeps, n_steps, last["status"], last["residual"], 1e-4, cap)}
 
 
 def main():
@@ -408,13 +527,16 @@ def main():
         wl.tol, wl.iters = 1e-4, 200
     newton = args.solver == "newton"
     gs = args.solver == "gs"
+    gpu_kw = {}
     if gs:
         wl.tol, wl.iters = 0.0, GS_BUDGETS[0]
-        sim = snk.Sim(wl, use_graph=1, solver=snk.SOLVER_GS)
+        gpu_kw = dict(solver=snk.SOLVER_GS)
+        sim = snk.Sim(wl, use_graph=1, **gpu_kw)
     elif newton:
         wl.tol = 0.0
         ni, npc = NEWTON_BUDGETS[0]
-        sim = snk.Sim(wl, use_graph=1, solver=snk.SOLVER_NEWTON, newton_iters=ni, pcr_iters=npc)
+        gpu_kw = dict(solver=snk.SOLVER_NEWTON, newton_iters=ni, pcr_iters=npc)
+        sim = snk.Sim(wl, use_graph=1, **gpu_kw)
     elif args.mapping:
         mw, ms, mr = (int(v) for v in args.mapping.split(","))
         sim = snk.Sim(wl, use_graph=1, autotune=0, map_waves=mw, map_min_seg=ms, map_rows=mr)
@@ -427,7 +549,6 @@ def main():
     before = sim.read("iters_total")["iters_total"].copy()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    res_hist = []
     torch.cuda.synchronize()
     ev0.record(stream)
     for _ in range(args.steps):
@@ -459,6 +580,12 @@ def main():
             traffic = t if kernel_digest(files) == digest else None
     elif traffic is not None and kernel_digest() != TRAFFIC_SOURCES_DIGEST:
         traffic = None
+    conv = iteration_stats(its, wl.substeps, args.steps, r["status"], r["residual"], wl.tol, wl.iters)
+    budget = (f"Newton {ni} x {npc} inner iterations" if newton
+              else f"Gauss-Seidel {wl.iters} sweeps" if gs
+              else "20 iterations" if args.fixed
+              else f"residual<=1e-4 or at most 200 iterations per substep ({conv['label']}: "
+                   f"{conv['converged_frac_last_step']:.3f} of the snakes reach 1e-4)")
     out = {
         "metric": METRIC,
         "value": snake_steps,
@@ -472,38 +599,39 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if newton else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {wl.n_snakes} snakes, {int(B.sum())} bodies, "
-                               f"{wl.substeps} substeps, "
-                               + (f"Newton {ni} x {npc} inner iterations" if newton
-                                  else f"Gauss-Seidel {wl.iters} sweeps" if gs
-                                  else "20 iterations" if args.fixed else "residual<=1e-4, max 200 iterations")
-                               + ", plain (zero warm start)",
+        "config": {"workload": f"{wl.name}: {wl.n_snakes} snakes of {int(B.min())}..{int(B.max())} bodies, "
+                               f"{int(B.sum())} bodies, {wl.substeps} substeps, {budget}, plain (zero warm start)",
                    "snakes": wl.n_snakes, "bodies": int(B.sum()), "substeps": wl.substeps,
                    "tol": wl.tol, "max_iters": wl.iters},
         "constraint_iters_per_s": citers,
-        "mean_iters_per_substep": float(its.sum() / (wl.n_snakes * args.steps * wl.substeps)),
-        "not_converged_snakes_last_step": int(np.sum((r["status"] & 2) != 0)),
-        "residual_last_step": {"median": float(np.median(r["residual"])),
-                               "p99": float(np.percentile(r["residual"], 99)),
-                               "max": float(np.max(r["residual"]))},
+        "convergence": conv,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": (PEAK_FP64 if newton else PEAK_FP32) / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64 if newton else PEAK_FP32), "traffic": traffic,
                      "kernel": "k_newton<64>" if newton else "k_gs<64>" if gs
                      else f"k_tile<{sim.mapping['waves']}, 0, {sim.mapping['rows']}>",
                      "mapping": sim.mapping,
                      "flop_per_body_iter": FLOP_PCR_ITER if newton else FLOP_GS_SWEEP if gs else FLOP_ITER,
+                     "hbm_bytes_algorithmic": hbm_bytes,
                      "hbm_frac_algorithmic": hbm_bytes / (per_launch_ms / 1e3) / PEAK_HBM},
     }
+    sim.close()
+    print(f"[bench] headline {snake_steps:.4g} snake-steps/s, {per_launch_ms:.3f} ms per step",
+          file=sys.stderr, flush=True)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_snakes, args.cpu_steps)
-    if not args.no_newton:
-        out["newton_pcr"] = newton_comparison(wl)
-    if not args.no_carriage:
-        out["wheel_carriage"] = carriage_run(wl)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_snakes, args.cpu_steps, gpu_kw)
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+    if not args.no_converged:
+        out["converged_at_tolerance"] = converged_run("uniform", cap=args.converged_cap)
     if not args.no_learned:
         out["learned_warm_start"] = learned_comparison(args.learned_steps)
+        print("[bench] learned comparison done", file=sys.stderr, flush=True)
         out["learned_warm_start_converging"] = learned_converging()
-    sim.close()
+        print("[bench] learned converging done", file=sys.stderr, flush=True)
+    if not args.no_newton:
+        out["newton_pcr"] = newton_comparison(wl)
+        print("[bench] solver comparison done", file=sys.stderr, flush=True)
+    if not args.no_carriage:
+        out["wheel_carriage"] = carriage_run(wl)
     print(json.dumps(out), flush=True)
 
 

@@ -257,11 +257,17 @@ typedef struct sim_desc {
 
 typedef struct sim sim_t;
 
-/* Workspace size for a descriptor.  Pure host computation.
- * Returns SIM_EINVAL for an invalid descriptor. */
+/* Workspace size for a descriptor.  Pure host computation: the state of the
+ * system described in section "Simulator" (generalized coordinates of every
+ * body, section "Rigid Bodies"; one multiplier per constraint row) plus the
+ * index work and the tile plan.  Returns SIM_EINVAL for an invalid
+ * descriptor. */
 int sim_workspace_bytes(const sim_desc_t* d, size_t* bytes);
 
-/* Build a solver in caller-owned device memory `workspace` (at least
+/* Build a solver (the bodies of sections "Particles" / "Rigid Bodies" with
+ * lumped mass, the compliant joint constraints with block-diagonal
+ * compliance E and the ground contacts of section "Simulator") in
+ * caller-owned device memory `workspace` (at least
  * sim_workspace_bytes, 256-byte aligned, kept alive until sim_destroy) on
  * stream `hip_stream` (borrowed).  Runs the index work on the device,
  * uploads the parameters and sets every snake straight at rest on the
@@ -270,23 +276,35 @@ int sim_workspace_bytes(const sim_desc_t* d, size_t* bytes);
 int sim_create(const sim_desc_t* d, void* workspace, size_t bytes, void* hip_stream,
                sim_t** out);
 
-/* Set one command per module (n == Mtot), in [-1, 1] (clamped): a > 0
+/* The target pressures p of section "Simulator" (parameters of the
+ * actuation constraints), as the commands a_i of eq. snake_control that
+ * eq. delta_p_i and eq. deflation turn into chamber pressures.
+ * Set one command per module (n == Mtot), in [-1, 1] (clamped): a > 0
  * drives chamber 0 (bends toward positive rotation about body z), a < 0
  * chamber 1.  Used by SIM_CTRL_EXTERNAL and held until the next call.
  * Host memory: NaN gives SIM_EINVAL.  Device memory: NaN is read as 0.
  * Stream-ordered. */
 int sim_set_pressures(sim_t* s, const float* cmd, int64_t n, int mem);
 
-/* Advance every snake by n_steps steps, asynchronously.  Launch failures
+/* Advance every snake by n_steps steps of the first-order implicit
+ * discretisation of section "Time-Stepping" (each step = `substeps`
+ * substeps; each substep solves the compliant system whose linearisation is
+ * eq. schur_system with the descriptor's solver), asynchronously.  Launch failures
  * return SIM_EDEVICE; numerical failures are per-snake status bits. */
 int sim_step(sim_t* s, int32_t n_steps);
 
-/* Copy the selected fields (SIM_F_*) to dst[k] for each selected bit k.
+/* Read the state of section "Simulator": body centres and orientations
+ * (maximal coordinates, section "Rigid Bodies"), their velocities, the
+ * chamber pressures, and the multipliers lambda_b (joints) and lambda_n,
+ * lambda_f (contact normal and friction) of the equations of motion.
+ * Copy the selected fields (SIM_F_*) to dst[k] for each selected bit k.
  * Host memory: the call synchronises the stream.  Layouts as listed with
  * the field bits. */
 int sim_read_state(sim_t* s, uint32_t fields, void* const* dst, int mem);
 
-/* Overwrite the selected fields from src[k] (checkpoint restore and state
+/* Write the same state (section "Simulator" quantities, as read by
+ * sim_read_state).
+ * Overwrite the selected fields from src[k] (checkpoint restore and state
  * injection).  A round trip through sim_read_state is bitwise.  Host
  * memory: the call synchronises the stream. */
 int sim_write_state(sim_t* s, uint32_t fields, const void* const* src, int mem);

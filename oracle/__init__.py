@@ -130,6 +130,7 @@ def _declare(L):
     L.mlo_forward.argtypes = [_P, _P, _P, _P, C.c_int64, _P]
     L.mlo_loss_grad.argtypes = [_P, _P, _P, _P, _P, C.c_int64, _P]
     L.mlo_loss_grad.restype = C.c_double
+    L.mlo_grad_abs.argtypes = [_P, _P, _P, _P, _P, C.c_int64, _P]
     L.mlo_adam.argtypes = [_P, _P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                            C.c_double]
 
@@ -413,6 +414,15 @@ def mlp_loss_grad(params, mean, std, x, t, with_grad=True):
     loss = lib().mlo_loss_grad(_ptr(params), _ptr(mean), _ptr(std), _ptr(x), _ptr(t), x.shape[0],
                                _ptr(g))
     return loss, g
+
+
+def mlp_grad_abs(params, mean, std, x, t):
+    """Per-entry scale of the gradient's rounding error: the sum over samples
+    of |delta| |activation|, deltas carried back through absolute values."""
+    params, mean, std, x, t = _d(params), _d(mean), _d(std), _d(x), _d(t)
+    A = np.zeros(params.size)
+    lib().mlo_grad_abs(_ptr(params), _ptr(mean), _ptr(std), _ptr(x), _ptr(t), x.shape[0], _ptr(A))
+    return A
 
 
 def mlp_adam(params, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

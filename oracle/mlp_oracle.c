@@ -127,6 +127,48 @@ double mlo_loss_grad(const double* p, const double* mean, const double* stdv, co
     return loss;
 }
 
+/* Scale of the rounding error of each gradient entry when the products of
+ * the backward pass take operands rounded to a short mantissa: every entry
+ * is a sum over samples of (delta * activation) products, so its error is
+ * bounded by a small multiple of the unit roundoff times
+ *   A = sum over samples of |delta| * |activation|,
+ * with |delta| carried backward through the absolute values of the weights
+ * and of the activation derivatives (no cancellation inside a dot product
+ * can hide an operand's error).  A has the layout of the gradient. */
+void mlo_grad_abs(const double* p, const double* mean, const double* stdv, const double* x,
+                  const double* t, int64_t n, double* A)
+{
+    double xn[NI], z1[NH], h1[NH], z2[NH], h2[NH], y[NO], dy[NO], dz2[NH], dz1[NH];
+    const double scale = 1.0 / ((double)n * NO);
+    memset(A, 0, sizeof(double) * P_COUNT);
+    for (int64_t r = 0; r < n; ++r) {
+        forward1(p, mean, stdv, x + r * NI, xn, z1, h1, z2, h2, y);
+        for (int o = 0; o < NO; ++o) dy[o] = fabs(2.0 * (y[o] - t[r * NO + o]) * scale);
+        for (int o = 0; o < NO; ++o) {
+            A[P_B3 + o] += dy[o];
+            for (int i = 0; i < NH; ++i) A[P_W3 + o * NH + i] += dy[o] * fabs(h2[i]);
+        }
+        for (int i = 0; i < NH; ++i) {
+            double s = 0.0;
+            for (int o = 0; o < NO; ++o) s += fabs(p[P_W3 + o * NH + i]) * dy[o];
+            dz2[i] = s * fabs(gelu_grad(z2[i]));
+        }
+        for (int o = 0; o < NH; ++o) {
+            A[P_B2 + o] += dz2[o];
+            for (int i = 0; i < NH; ++i) A[P_W2 + o * NH + i] += dz2[o] * fabs(h1[i]);
+        }
+        for (int i = 0; i < NH; ++i) {
+            double s = 0.0;
+            for (int o = 0; o < NH; ++o) s += fabs(p[P_W2 + o * NH + i]) * dz2[o];
+            dz1[i] = s * fabs(gelu_grad(z1[i]));
+        }
+        for (int o = 0; o < NH; ++o) {
+            A[P_B1 + o] += dz1[o];
+            for (int i = 0; i < NI; ++i) A[P_W1 + o * NI + i] += dz1[o] * fabs(xn[i]);
+        }
+    }
+}
+
 /* Adam (Kingma and Ba): m <- b1 m + (1-b1) g; v <- b2 v + (1-b2) g^2;
  * p <- p - lr * m/(1-b1^t) / (sqrt(v/(1-b2^t)) + eps); t counts from 1 */
 void mlo_adam(double* p, double* m, double* v, const double* g, int n, int t, double lr, double b1,

@@ -134,6 +134,10 @@ int validate(const sim_desc_t* d, Sizes* z)
     z->wheels = (d->flags & SIM_FLAG_WHEELS) != 0;
     if (z->wheels && (d->solver != SIM_SOLVER_JACOBI || d->warm_start != SIM_WARM_ZERO))
         return fail(SIM_EINVAL, "the wheel carriage takes the Jacobi solver from zero multipliers");
+    // the carriage kernels index wheel multipliers as int: component c < 9
+    // of wheel w < 2N sits at c * 2N + w, so 18 N must stay below 2^31
+    if (z->wheels && z->N > ((int64_t)1 << 31) / 18 - 1)
+        return fail(SIM_EINVAL, "too many bodies for a wheel carriage (limit 2^31 / 18)");
     if (mw != 0 && !d->autotune) {
         int seg = 16;
         while (seg < z->max_B) seg <<= 1;

@@ -5,7 +5,12 @@ substep (or one step) with the same command, and compare.
 
 Errors reported per snake:
   pos     max |x_gpu - x_orc| / max(max |x_orc|, L)
+  vel     max |v_gpu - v_orc| / max(max |v_orc|, g h)        (finalize)
+  angvel  max |w_gpu - w_orc| / max(max |w_orc|, g h / L)    (finalize)
   lam_*   max |l_gpu - l_orc| / max(max |l_orc|, l_ref), per block type
+The velocity floors are what gravity adds in one substep (g h, and g h / L
+for a segment end turning about its centre); they only matter for snakes at
+rest.
 The floor l_ref is the multiplier scale of one segment's weight over one
 substep: m g h^2 (stretch, contact; g = 9.81) and m g h^2 L (bend-twist).
 It only matters for snakes whose joints carry almost no load, where the
@@ -22,6 +27,9 @@ import workloads as W
 
 POS_TOL = 1e-5
 LAM_TOL = 1e-4
+# velocities come out of the solve like the multipliers (differences of
+# positions over one substep), so they take the multipliers' tolerance
+VEL_TOL = 1e-4
 
 
 def f32(a):
@@ -57,7 +65,10 @@ def gpu_state(sim):
 def compare(o: oracle.Oracle, g: dict, mu):
     """Per-snake error table (dict of arrays) between oracle o and GPU state g."""
     n = o.n
-    out = {k: np.zeros(n) for k in ("pos", "lam_s", "lam_b", "lam_n", "lam_t")}
+    vel = "v" in g and "w" in g
+    keys = ("pos", "vel", "angvel", "lam_s", "lam_b", "lam_n", "lam_t") if vel else \
+        ("pos", "lam_s", "lam_b", "lam_n", "lam_t")
+    out = {k: np.zeros(n) for k in keys}
     out["branch"] = np.zeros(n, np.int64)
     L = o.batch.length
     h = o.batch.dt / o.batch.substeps
@@ -68,6 +79,11 @@ def compare(o: oracle.Oracle, g: dict, mu):
         j0, j1 = o.joint_off[s], o.joint_off[s + 1]
         xo, xg = o.x[b0:b1], g["x"][b0:b1]
         out["pos"][s] = np.abs(xg - xo).max() / max(np.abs(xo).max(), L)
+        if vel:
+            vo, vg = o.v[b0:b1], g["v"][b0:b1]
+            out["vel"][s] = np.abs(vg - vo).max() / max(np.abs(vo).max(), 9.81 * h)
+            wo, wg = o.w[b0:b1], g["w"][b0:b1]
+            out["angvel"][s] = np.abs(wg - wo).max() / max(np.abs(wo).max(), 9.81 * h / L)
         for key, sl in (("lam_s", slice(0, 3)), ("lam_b", slice(3, 6))):
             lo, lg = o.lam_j[j0:j1, sl], g["lam_j"][j0:j1, sl]
             if lo.size:

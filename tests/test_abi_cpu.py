@@ -285,3 +285,21 @@ def test_empty_and_oversized_batches_rejected(L):
     edge = W.custom([8], 128)            # exactly 1024 bodies
     rc, b, _ = ws_bytes(L, edge)
     assert rc == 0 and b > 0
+
+
+def test_wheel_batch_size_limit(L):
+    """The carriage indexes its wheel multipliers (9 components of 2N wheels)
+    with 32-bit offsets, so a wheel batch stops below 2^31 / 18 bodies; the
+    same batch without wheels is accepted (its limit is 2^28)."""
+    limit = (1 << 31) // 18 - 1
+    n = limit // 1024 + 1                      # snakes of 1024 bodies
+    big = W.custom(np.full(n, 8, np.int32), 128)
+    assert int(big.bodies.sum()) > limit
+    rc, _, err = ws_bytes(L, big, flags=16)
+    assert rc == snk.SIM_EINVAL and "wheel carriage" in err
+    rc, b, _ = ws_bytes(L, big)
+    assert rc == 0 and b > 0
+    ok = W.custom(np.full(n - 1, 8, np.int32), 128)
+    assert int(ok.bodies.sum()) <= limit
+    rc, b, _ = ws_bytes(L, ok, flags=16)
+    assert rc == 0 and b > 0

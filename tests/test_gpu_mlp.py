@@ -58,7 +58,18 @@ def test_forward_matches_oracle(n):
     assert err <= 8 * U * scale
 
 
+GRAD_K = 12
+
+
 def test_gradient_matches_oracle():
+    """Every gradient entry against the FP64 oracle (BF16-rounded weights),
+    within GRAD_K unit roundoffs of its own error scale A (the oracle's sum
+    over samples of |delta| |activation| for that entry, deltas carried back
+    through absolute values): the kernel rounds each activation and each
+    delta to BF16 before it enters a product (u each) and the forward and
+    backward errors of those operands are a few u of the same scale.  A
+    sign error in the largest entry of any parameter group would exceed the
+    bound (checked), so the gate is element-wise, not a norm."""
     n = 2000
     p, x, t = setup(n, 3)
     xd, td = torch.as_tensor(x, device="cuda"), torch.as_tensor(t, device="cuda")
@@ -67,13 +78,21 @@ def test_gradient_matches_oracle():
     net = snk.Net(p, ms)
     g, loss = net.grad(xd, td)
     g = g.cpu().numpy().astype(np.float64)
-    lo, go = oracle.mlp_loss_grad(bf16_weights(p), msh[:32], msh[32:], x, t)
+    pb = bf16_weights(p)
+    lo, go = oracle.mlp_loss_grad(pb, msh[:32], msh[32:], x, t)
+    A = oracle.mlp_grad_abs(pb, msh[:32], msh[32:], x, t)
     assert abs(float(loss.cpu()) - lo) <= 1e-2 * lo
+    floor = 1e-12 * A.max()
     for name, a, b in (("W1", 0, 2048), ("b1", 2048, 2112), ("W2", 2112, 6208), ("b2", 6208, 6272),
                        ("W3", 6272, 6464), ("b3", 6464, 6467)):
+        err = np.abs(g[a:b] - go[a:b])
+        ratio = err / (U * A[a:b] + floor)
         rel = np.linalg.norm(g[a:b] - go[a:b]) / np.linalg.norm(go[a:b])
-        print(f"[mlp grad] {name}: relative error {rel:.3g} ({rel / U:.2f} u)")
-        assert rel <= 10 * U, name
+        k = int(np.argmax(np.abs(go[a:b])))
+        print(f"[mlp grad] {name}: worst entry {ratio.max():.3g} u of its scale "
+              f"(entry {int(np.argmax(ratio))}), norm-relative {rel:.3g}", flush=True)
+        assert ratio.max() <= GRAD_K, name
+        assert 2 * abs(go[a + k]) > GRAD_K * U * A[a + k], name
     # deterministic: the same call twice gives the same bits
     g2, _ = net.grad(xd, td)
     assert np.array_equal(g2.cpu().numpy().astype(np.float64), g)
