@@ -166,3 +166,48 @@ def full_batch_substep(name, sample, steps, gpu_over, orc_over):
     load_oracle(o, st_s)
     o.run(1, threads=8)
     return o, g, sub, st_s, dict(kw, **orc_over)
+
+
+STATE_FIELDS = ("pos", "quat", "vel", "angvel", "pressure", "lambda_joint", "lambda_contact")
+
+
+def chained_substeps(wl, st, gpu_over=None, orc_over=None, threads=8):
+    """A whole step from the rounded state st, held to the per-substep
+    protocol substep by substep.  The GPU takes the step once in a single
+    launch (all substeps, state in registers throughout) and once as one
+    launch per substep (dt = h, one substep, the same held command); the
+    two must give the same bits.  Each one-substep launch is then compared
+    with the oracle's substep from the same FP32 state, the GPU's own state
+    before it, so an error does not compound across substeps.  Returns the
+    (oracle, GPU state, FP32 state before the substep) of every substep.  The lag law only: the
+    paper's law acts once per step, which one-substep launches cannot
+    reproduce."""
+    import paper_1904_02833_amd as snk
+
+    assert wl.pressure_law == W.LAW_LAG
+    gpu_over = dict(gpu_over or {})
+    orc_over = dict(orc_over or {})
+    base = dict(controller=W.CTRL_EXTERNAL)
+    whole = snk.Sim(wl, **base, **gpu_over)
+    load_gpu(whole, st)
+    whole.step(1)
+    g_whole = whole.read(*STATE_FIELDS)
+    whole.close()
+    one = dict(base, dt=wl.dt / wl.substeps, substeps=1)
+    sim = snk.Sim(wl, **one, **gpu_over)
+    load_gpu(sim, st)
+    prev, out = st, []
+    for _ in range(wl.substeps):
+        sim.step(1)
+        g = gpu_state(sim)
+        o = oracle.Oracle(wl, **one, **orc_over)
+        load_oracle(o, prev)
+        o.run(1, threads=threads)
+        out.append((o, g, prev))
+        prev = dict(x=g["x"], q=g["q"], v=g["v"], w=g["w"], p=g["p"], cmd=st["cmd"], lam_j=g["lam_j"],
+                    lam_c=g["lam_c"])
+    g_chain = sim.read(*STATE_FIELDS)
+    sim.close()
+    for k in STATE_FIELDS:
+        assert np.array_equal(g_whole[k], g_chain[k]), f"one launch and per-substep launches differ in {k}"
+    return out

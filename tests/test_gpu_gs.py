@@ -1,16 +1,17 @@
 """GPU block Gauss-Seidel (FP32, colour by colour over the index work's
 greedy block colouring) against the FP64 oracle's Gauss-Seidel solver, per
-the substep protocol of tests/parity.py: positions to 1e-5, multipliers to
-1e-4 relative per block type or the oracle's own FP64 spread under a 1-ulp
-input nudge where that is larger, contacts whose active set or stick/slip
-branch differs between the precisions counted apart (at most 2 % of
-bodies).  Lane classes 8 to 1024."""
+the substep protocol of tests/parity.py: positions to 1e-5, velocities and
+multipliers to 1e-4 relative per block type (the friction multipliers to
+twice the oracle's own spread under a one-ulp input nudge, 1e-4 to 0.28 by
+case: the sequential sweep's friction is that sensitive), contacts whose active set or stick/slip branch differs
+between the precisions counted apart (at most 2 % of bodies).  Whole steps
+are checked substep by substep.  Lane classes 8 to 1024."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads as W
-from parity import LAM_TOL, POS_TOL, advance_both, compare, load_oracle, rounded_state
+from parity import LAM_TOL, POS_TOL, VEL_TOL, advance_both, compare, load_oracle, rounded_state
 
 pytestmark = pytest.mark.gpu
 snk = pytest.importorskip("paper_1904_02833_amd")
@@ -25,17 +26,21 @@ def state_after(wl, steps, **over):
     return rounded_state(o)
 
 
-def gs_parity(tag, wl, st, one_substep=True, **over):
-    """Advance the rounded state st on both sides; multipliers are held per
-    type to the larger of 1e-4 and twice the spread of the FP64 oracle's own
-    result when its input positions move by one FP32 ulp (the conditioning
-    floor of the substep protocol: a Gauss-Seidel solve converges further
-    than Jacobi at the same budget, and its converged friction multipliers
-    are that sensitive); positions keep 1e-5, sweep counts are equal."""
-    o, g = advance_both(wl, st, one_substep=one_substep, **GS, **over)
-    kw = dict(controller=W.CTRL_EXTERNAL, solver=oracle.SOLVER_GS, **over)
-    if one_substep:
-        kw.update(dt=wl.dt / wl.substeps, substeps=1)
+def gs_parity(tag, wl, st, cond_gate=("lam_t",), **over):
+    """Advance the rounded state st one substep on both sides: positions to
+    1e-5, velocities and multipliers to 1e-4 per type, sweep counts equal.
+    The spread of the FP64 oracle's own result when its input positions
+    move by one FP32 ulp (the conditioning of the substep) is printed beside
+    the errors; the block types named in cond_gate (the friction
+    multipliers) are gated at twice that spread where it exceeds 1e-4.  A
+    Gauss-Seidel sweep carries every contact's friction update into the
+    next block's state at once, and the sticking contacts' friction of one
+    substep moves by 1e-4 to 6.6e-3 of its scale under a one-ulp input
+    nudge (0.28 on the near-rigid stiff chains, where compliances of 1e-8
+    decide the split of the friction among sticking contacts); the GPU's
+    errors sit at 4e-5 to 4e-4, inside that."""
+    o, g = advance_both(wl, st, **GS, **over)
+    kw = dict(controller=W.CTRL_EXTERNAL, solver=oracle.SOLVER_GS, dt=wl.dt / wl.substeps, substeps=1, **over)
     o2 = oracle.Oracle(wl, **kw)
     nudged = dict(st)
     nudged["x"] = np.nextafter(st["x"].astype(np.float32), np.float32(np.inf)).astype(np.float64)
@@ -45,13 +50,16 @@ def gs_parity(tag, wl, st, one_substep=True, **over):
     spread = compare(o, dict(x=o2.x, lam_j=o2.lam_j, lam_c=o2.lam_c), mu)
     err = compare(o, g, mu)
     keys = ("lam_s", "lam_b", "lam_n", "lam_t")
-    print(f"\n[{tag}] worst", {k: float(err[k].max()) for k in ("pos",) + keys},
-          "FP64 spread", {k: float(spread[k].max()) for k in keys},
+    print(f"\n[{tag}] worst", {k: float(err[k].max()) for k in err if k != "branch"},
+          "FP64 1-ulp spread", {k: float(spread[k].max()) for k in keys},
           "branch mismatches", int(err["branch"].sum()), flush=True)
     assert np.array_equal(np.asarray(g["iters"]), o.iters)
     assert err["pos"].max() <= POS_TOL
+    for k in ("vel", "angvel"):
+        assert err[k].max() <= VEL_TOL, k
     for k in keys:
-        assert err[k].max() <= max(LAM_TOL, 2 * spread[k].max()), k
+        gate = max(LAM_TOL, 2 * spread[k].max()) if k in cond_gate else LAM_TOL
+        assert err[k].max() <= gate, (k, float(err[k].max()), gate)
     assert err["branch"].sum() <= 0.02 * int(wl.bodies.sum())
     return o, g
 
@@ -69,10 +77,32 @@ def test_gs_substep_parity(name):
 
 
 def test_gs_step_parity_uneven():
-    """A whole step (four substeps, the GPU's state rounded to FP32 between
-    them)."""
+    """A whole step (four substeps), substep by substep: the one-launch
+    step equals four one-substep launches bit for bit, and each of those is
+    held to the per-substep gates against the oracle from the GPU's own
+    state before it (friction multipliers at twice the oracle's one-ulp
+    spread, as in every Gauss-Seidel case)."""
+    from parity import chained_substeps
+
     wl = W.make("uneven", n_snakes=24)
-    gs_parity("gs step uneven", wl, state_after(wl, 10), one_substep=False)
+    orc = dict(solver=oracle.SOLVER_GS)
+    steps = chained_substeps(wl, state_after(wl, 10), gpu_over=GS, orc_over=orc)
+    mu = np.asarray(wl.mu, np.float64)
+    for k, (o, g, st) in enumerate(steps):
+        o2 = oracle.Oracle(wl, controller=W.CTRL_EXTERNAL, dt=wl.dt / wl.substeps, substeps=1, **orc)
+        load_oracle(o2, dict(st, x=np.nextafter(st["x"].astype(np.float32), np.float32(np.inf)).astype(np.float64)))
+        o2.run(1, threads=8)
+        spread = compare(o, dict(x=o2.x, lam_j=o2.lam_j, lam_c=o2.lam_c), mu)
+        err = compare(o, g, mu)
+        print(f"\n[gs step uneven, substep {k}] worst", {q: float(err[q].max()) for q in err if q != "branch"},
+              "FP64 1-ulp spread", {q: float(spread[q].max()) for q in ("lam_s", "lam_b", "lam_n", "lam_t")},
+              "branch mismatches", int(err["branch"].sum()), flush=True)
+        assert np.array_equal(np.asarray(g["iters"]), o.iters)
+        assert err["pos"].max() <= POS_TOL
+        for q in ("vel", "angvel", "lam_s", "lam_b", "lam_n"):
+            assert err[q].max() <= LAM_TOL, (k, q, float(err[q].max()))
+        assert err["lam_t"].max() <= max(LAM_TOL, 2 * spread["lam_t"].max()), (k, float(err["lam_t"].max()))
+        assert err["branch"].sum() <= 0.02 * int(wl.bodies.sum())
 
 
 def test_gs_stiff_1024_lanes():
@@ -119,12 +149,11 @@ def test_gs_graph_equals_direct_and_is_deterministic():
 
 
 def test_gs_serpenoid_and_paper_law_whole_step():
-    """A whole step with the command computed on the device (serpenoid) and
-    the paper's pressure law.  The GPU carries its state in FP32 through the
-    four substeps; the multiplier gate is twice the difference between the
-    FP64 oracle's step and the same step with its state rounded to FP32
-    after every substep (split substeps), or 1e-4 where larger."""
-    from parity import f32, gpu_state, load_gpu
+    """The command computed on the device (serpenoid) and the paper's
+    pressure law: a whole step gives the oracle's commands and pressures to
+    1e-6; the first substep of the step (the law applied once to the held
+    command, then one substep) is held to the per-substep gates."""
+    from parity import gpu_state, load_gpu
 
     wl = W.make("uniform", n_snakes=8)
     wl.pressure_law = W.LAW_PAPER
@@ -136,15 +165,6 @@ def test_gs_serpenoid_and_paper_law_whole_step():
     load_oracle(o, st)
     o.step[...] = base.step
     o.run(1, threads=8)
-    r = oracle.Oracle(wl, solver=oracle.SOLVER_GS)
-    load_oracle(r, st)
-    r.step[...] = base.step
-    r.commands()
-    for sub in range(wl.substeps):
-        for s_ in range(r.n):
-            r.solve_substep(s_, r.pre_substep(s_, sub))
-        for k in ("x", "q", "v", "w", "lam_j", "lam_c"):
-            getattr(r, k)[...] = f32(getattr(r, k))
     sim = snk.Sim(wl, **GS)
     load_gpu(sim, st)
     sim.write(step=base.step.copy())
@@ -152,23 +172,16 @@ def test_gs_serpenoid_and_paper_law_whole_step():
     g = gpu_state(sim)
     cmd = sim.read("cmd")["cmd"]
     sim.close()
-    mu = np.asarray(wl.mu, np.float64)
-    spread = compare(o, dict(x=r.x, lam_j=r.lam_j, lam_c=r.lam_c), mu)
-    err = compare(o, g, mu)
-    print("\n[gs serpenoid paper law] worst", {k: float(err[k].max()) for k in err if k != "branch"},
-          "FP32-trajectory spread", {k: float(spread[k].max()) for k in ("lam_s", "lam_b", "lam_n", "lam_t")})
     assert np.abs(cmd - o.cmd).max() <= 1e-6
     assert np.abs(g["p"] - o.p).max() <= 1e-6
-    assert np.array_equal(np.asarray(g["iters"]), o.iters)
-    assert err["pos"].max() <= POS_TOL
-    for k in ("lam_s", "lam_b", "lam_n", "lam_t"):
-        assert err[k].max() <= max(LAM_TOL, 2 * spread[k].max()), k
+    oo, g1 = gs_parity("gs paper law first substep", wl, dict(st, cmd=o.cmd.copy()))
+    assert np.abs(g1["p"] - oo.p).max() <= 1e-6
 
 
 def test_gs_full_uniform_batch_sampled():
     """The whole uniform batch in the benchmark's Gauss-Seidel configuration
-    (40 sweeps), sampled snakes against the oracle, with the 1-ulp spread
-    gate of the other Gauss-Seidel tests."""
+    (40 sweeps), sampled snakes against the oracle at the per-substep gates
+    (the oracle's 1-ulp spread printed as context)."""
     from parity import full_batch_substep
 
     rng = np.random.default_rng(22)
@@ -185,5 +198,5 @@ def test_gs_full_uniform_batch_sampled():
           "spread", {k: float(spread[k].max()) for k in ("lam_s", "lam_b", "lam_n", "lam_t")})
     assert np.array_equal(np.asarray(g["iters"]), o.iters)
     assert err["pos"].max() <= POS_TOL
-    for k in ("lam_s", "lam_b", "lam_n", "lam_t"):
-        assert err[k].max() <= max(LAM_TOL, 2 * spread[k].max()), k
+    for k in ("vel", "angvel", "lam_s", "lam_b", "lam_n", "lam_t"):
+        assert err[k].max() <= LAM_TOL, k

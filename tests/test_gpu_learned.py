@@ -220,3 +220,44 @@ def test_learned_start_saves_iterations_where_the_solve_converges():
         sim.close()
     print(f"\n[learned-short] mean iterations per substep: plain {its['plain']:.0f}, learned {its['learned']:.0f}")
     assert its["learned"] < its["plain"]
+
+
+@pytest.mark.xfail(strict=False, reason="block Jacobi leaves every snake of the uneven batch at the 200-iteration "
+                   "cap, so neither start reaches 1e-4, and the fallback rejects the network's starts: on the full "
+                   "16 384-snake batch 202 against 200 iterations per substep, 1.09 M against 1.32 M snake-steps/s, "
+                   "every snake falling back")
+def test_learned_start_gains_on_the_uneven_batch():
+    """The comparison the learned start is specified by: on the learned
+    workload (the uneven batch's shapes and draws, its own seed; 2048
+    snakes here), with the fallback judged after 2 iterations, the learned
+    start must reach residual 1e-4 (at most 200 iterations per substep) in
+    fewer iterations per substep and at more snake-steps/s than the zero
+    start, the network trained on the solver's converged multipliers at the
+    states the plain solver visits on training-seed snakes."""
+    import torch
+
+    train_wl = W.make("uneven", n_snakes=512, seed=2004)
+    ds = warmstart.record_on_policy(train_wl, 8, stride=3, warmup_steps=6, tol=1e-6, iters=1500)
+    net = warmstart.train(ds, epochs=4, batch=4096, lr=2e-3)
+    ev = W.make("learned", n_snakes=2048)
+    ev.tol, ev.iters = 1e-4, 200
+    out = {}
+    for name in ("plain", "learned"):
+        sim = snk.Sim(ev) if name == "plain" else warmstart.learned_sim(ev, net, mlp_fallback_k=2)
+        sim.step(3)
+        torch.cuda.synchronize()
+        r0 = sim.read("iters_total")["iters_total"].copy()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.step(5)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        r = sim.read("iters_total", "status")
+        its = float((r["iters_total"] - r0).sum()) / (ev.n_snakes * 5 * ev.substeps)
+        conv = float(np.mean((r["status"] & snk.STATUS_NOT_CONVERGED) == 0))
+        out[name] = dict(iters=its, rate=ev.n_snakes * 5 / (e0.elapsed_time(e1) / 1e3), converged=conv,
+                         fell_back=int(np.sum((r["status"] & snk.STATUS_FELL_BACK) != 0)))
+        sim.close()
+    print(f"\n[learned uneven] plain {out['plain']} learned {out['learned']}")
+    assert out["learned"]["iters"] < out["plain"]["iters"]
+    assert out["learned"]["rate"] > out["plain"]["rate"]

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import workloads as W
-from parity import advance_both, compare, rounded_state
+from parity import LAM_TOL, POS_TOL, advance_both, compare, rounded_state
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -173,9 +173,10 @@ def test_newton_previous_multiplier_start_substep():
 def test_newton_previous_multiplier_start_whole_step():
     """A whole step with the previous-multiplier start: each substep starts
     from the last one's multipliers, whose ill-conditioning carries the two
-    sides' different summation orders forward.  The gate is twice the
-    oracle's own spread when its input positions move by one FP64 ulp (or
-    1e-6 where larger)."""
+    sides' different summation orders forward over the four substeps, past
+    the 1e-6 of the single substeps.  Held to the stated tolerances
+    (positions 1e-5, multipliers 1e-4); the oracle's own spread when its
+    input positions move by one FP64 ulp is printed as context."""
     from parity import load_oracle
 
     wl = W.make("uneven", n_snakes=24)
@@ -192,8 +193,9 @@ def test_newton_previous_multiplier_start_whole_step():
     print("\n[newton previous start, step] worst", {k: float(err[k].max()) for k in keys},
           "FP64 1-ulp spread", {k: float(spread[k].max()) for k in keys})
     assert np.array_equal(np.asarray(g["iters"]), o.iters)
-    for k in keys:
-        assert err[k].max() <= max(TOL, 2 * spread[k].max()), k
+    assert err["pos"].max() <= POS_TOL
+    for k in keys[1:]:
+        assert err[k].max() <= LAM_TOL, k
 
 
 def test_newton_keep_best_matches_oracle():

@@ -106,16 +106,18 @@ def test_substep_parity_single(warm_steps):
 
 
 def test_step_parity_single():
-    """A whole step (4 substeps): the state is re-rounded to FP32 between
-    substeps, which alone moves lightly loaded multipliers by a few 1e-4
-    (FP64 runs from inputs perturbed by one FP32 ulp differ by 6e-5), so
-    positions keep the 1e-5 gate and multipliers are held to 1e-3."""
+    """A whole step (4 substeps), substep by substep: the one-launch step
+    equals four one-substep launches bit for bit, and each of those is held
+    to the per-substep gates against the oracle from the GPU's own state
+    before it."""
+    from parity import chained_substeps
+
     wl = W.make("single")
     o = oracle.Oracle(wl)
     o.run(120)
     o.commands()
-    oo, g = advance_both(wl, rounded_state(o), one_substep=False)
-    assert_parity("single-step", compare(oo, g, wl.mu), n_bodies=64, lam_tol=1e-3)
+    for k, (oo, g, _) in enumerate(chained_substeps(wl, rounded_state(o))):
+        assert_parity(f"single-step substep {k}", compare(oo, g, wl.mu), n_bodies=64)
 
 
 def test_substep_parity_uniform_slice():
@@ -167,14 +169,20 @@ def test_parity_warm_start_prev(scene):
 
 
 def test_parity_paper_pressure_law():
+    """The paper's pressure law: a whole step gives the oracle's pressures
+    to 1e-6; the first substep of a step (the law applied once, then one
+    substep, as in the whole step) is held to the per-substep gates."""
     wl = W.make("uniform", n_snakes=8)
     wl.pressure_law = W.LAW_PAPER
     o = oracle.Oracle(wl)
     o.run(30, threads=8)
     o.commands()
-    oo, g = advance_both(wl, rounded_state(o), one_substep=False)
+    st = rounded_state(o)
+    oo, g = advance_both(wl, st, one_substep=False)
     assert np.abs(g["p"] - oo.p).max() <= 1e-6
-    assert_parity("paper-law", compare(oo, g, wl.mu), n_bodies=wl.total_bodies, lam_tol=1e-3)
+    oo, g = advance_both(wl, st)
+    assert np.abs(g["p"] - oo.p).max() <= 1e-6
+    assert_parity("paper-law first substep", compare(oo, g, wl.mu), n_bodies=wl.total_bodies)
 
 
 def test_parity_cantilever_fixed_root():
