@@ -24,7 +24,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "snake_oracle.c")
-SRCS = [SRC, os.path.join(HERE, "mlp_oracle.c"), os.path.join(HERE, "fem_oracle.c")]
+SRCS = [SRC, os.path.join(HERE, "mlp_oracle.c"), os.path.join(HERE, "fem_oracle.c"),
+        os.path.join(HERE, "link_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 FLAG_FIXED_ROOT = 1

@@ -1,0 +1,418 @@
+"""Pins of the oracle's full-resolution link solve (survey row "FEM link":
+particles with lumped masses, corotational tetrahedra with the element
+compliance of section "Tetrahedral Finite-Elements", distance constraints
+with the actuation rest length of eq. expansion, attachments of
+eq. rigid_to_particle, ground contact), on the procedural link mesh.
+
+Pinned by: the patch test (a uniform stretch or shear of the whole mesh
+gives the same exact strain in every element); zero constraint values under
+any rigid motion of links and frames; a batch at rest without gravity
+staying at rest (to round-off); the lumped masses adding up to the mesh's mass;
+free fall without ground leaving every constraint satisfied; linear
+momentum conserved by every iteration; the topology and degrees counted
+here from the mesh; the linearised block-Jacobi iteration converging to
+the dense solve of eq. schur_system (with and without pressed-in
+contacts), and its first iterations equal to the closed-form scaled block
+Jacobi step built here from the dense matrix; and the compliance -> 0
+limit (multipliers tend to the rigid solution, strains fall as 1 / Y)."""
+import numpy as np
+import pytest
+
+import oracle.link as OL
+import workloads as W
+
+
+def small(n_snakes=1, n_links=1, sections=3, ring=4, **kw):
+    wl = W.make_link(n_snakes, n_links=n_links, sections=sections, ring=ring)
+    X, tets = W.link_mesh(sections, ring, length=wl.link_length * (sections - 1) / 12, radius=wl.radius)
+    wl.X, wl.tets = X, tets.astype(np.int32)
+    wl.link_length = float(X[:, 0].max())
+    for k, v in kw.items():
+        setattr(wl, k, v)
+    return wl
+
+
+def rot(axis, ang):
+    a = np.asarray(axis, float) / np.linalg.norm(axis)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + np.sin(ang) * K + (1 - np.cos(ang)) * K @ K
+
+
+def quat_of(Q):
+    w = np.sqrt(max(0.0, 1 + np.trace(Q))) / 2
+    return np.array([w, (Q[2, 1] - Q[1, 2]) / (4 * w), (Q[0, 2] - Q[2, 0]) / (4 * w), (Q[1, 0] - Q[0, 1]) / (4 * w)])
+
+
+# ---------------------------------------------------------------- topology
+
+def test_topology_and_degrees_counted_from_the_mesh():
+    """Counts of the constraint kinds, and every particle's and frame's
+    degree counted here by incidence over the mesh arrays."""
+    wl = W.make_link(1, n_links=3)
+    o = OL.LinkOracle(wl)
+    S, R = wl.sections, wl.ring
+    per = S * (R + 1)
+    assert (o.P, o.F, o.T) == (3 * per, 4, 3 * wl.n_tets)
+    pi, pj, kind, rest = o.link_dists()
+    assert len(pi) == (S - 1) * (R + 1) + (S - 2) * R
+    # the plane y = 0 holds the centre and the ring particles at 90 and 270 degrees
+    th = 2 * np.pi * np.arange(R) / R
+    slot_kind = [OL.KIND_CENTRE] + [OL.KIND_CENTRE if abs(np.cos(t)) < 1e-12 else
+                                    OL.KIND_CHAMBER0 if np.cos(t) > 0 else OL.KIND_CHAMBER1 for t in th]
+    want = []
+    for g in range(S - 1):
+        want += [(g * (R + 1) + s, (g + 1) * (R + 1) + s, slot_kind[s]) for s in range(R + 1)]
+    for g in range(1, S - 1):     # the attached end sections carry no spokes
+        want += [(g * (R + 1), g * (R + 1) + 1 + k, OL.KIND_RADIAL) for k in range(R)]
+    assert [tuple(t) for t in np.stack([pi, pj, kind], 1).tolist()] == want
+    assert np.allclose(rest, np.linalg.norm(wl.X[pi] - wl.X[pj], axis=1), rtol=0, atol=1e-15)
+    part, side = o.link_atts()
+    assert part.tolist() == list(range(R + 1)) + list(range((S - 1) * (R + 1), S * (R + 1)))
+    assert side.tolist() == [0] * (R + 1) + [1] * (R + 1)
+    idx = o.index()
+    deg = np.ones(3 * per, np.int64)     # contact
+    for l in range(3):
+        for t in wl.tets:
+            deg[l * per + t] += 1
+        for a, b in zip(pi, pj):
+            deg[l * per + a] += 1
+            deg[l * per + b] += 1
+        deg[l * per + part] += 1
+    assert np.array_equal(idx["degree_particle"], deg)
+    assert idx["degree_frame"].tolist() == [R + 1, 2 * (R + 1), 2 * (R + 1), R + 1]
+    assert np.array_equal(idx["dist_i"], np.concatenate([l * per + pi for l in range(3)]))
+    assert np.array_equal(idx["dist_kind"], np.tile(kind, 3))
+
+
+def test_lumped_masses_add_up_to_the_mesh_mass():
+    """Each element's mass split in four: the total is the density times the
+    polygonal prism's volume."""
+    wl = W.make_link(1)
+    m = OL.LinkOracle(wl).link_masses()
+    R, r, L = wl.ring, wl.radius, wl.link_length
+    vol = R * 0.5 * r * r * np.sin(2 * np.pi / R) * L
+    assert abs(m.sum() - wl.density * vol) <= 1e-12 * wl.density * vol
+    assert np.all(m > 0)
+
+
+# ---------------------------------------------------------------- constraint values
+
+def test_patch_test_uniform_strains():
+    """A uniform axial stretch, a uniform lateral stretch and a simple shear
+    of the whole link give every element the same exact corotational strain
+    (the patch test of constant-strain elements); the axial distance
+    constraints at zero pressure read the stretched rest length."""
+    wl = W.make_link(1, n_links=1)
+    o = OL.LinkOracle(wl)
+    X = o.x.copy()
+    ctr = np.array([0.0, 0.0, wl.radius])
+    p0 = np.zeros((1, 2))
+    for F, want in ((np.diag([1.07, 1, 1]), [0.07, 0, 0, 0, 0, 0]),
+                    (np.diag([1, 0.96, 0.96]), [0, -0.04, -0.04, 0, 0, 0])):
+        x = ctr + (X - ctr) @ F.T
+        Cv, _, _, _ = o.assemble(x, o.fx, o.fq, p0)
+        tet = Cv[:6 * o.T].reshape(-1, 6)
+        assert np.abs(tet - want).max() <= 1e-12
+    g = 0.3
+    x = X.copy()
+    x[:, 0] += g * (X[:, 1] - ctr[1])
+    Cv, _, _, _ = o.assemble(x, o.fx, o.fq, p0)
+    w = np.sqrt(4 + g * g)
+    tet = Cv[:6 * o.T].reshape(-1, 6)
+    assert np.abs(tet - [2 / w - 1, (2 + g * g) / w - 1, 0, 0, 0, g / w]).max() <= 1e-12
+    # axial edges under the axial stretch
+    pi, pj, kind, rest = o.link_dists()
+    x = ctr + (X - ctr) @ np.diag([1.07, 1, 1]).T
+    Cv, _, _, _ = o.assemble(x, o.fx, o.fq, p0)
+    dist = Cv[6 * o.T:6 * o.T + o.D]
+    axial = kind != OL.KIND_RADIAL
+    assert np.abs(dist[axial] - 0.07 * rest[axial]).max() <= 1e-15
+    assert np.abs(dist[~axial]).max() <= 1e-15
+
+
+def test_rigid_motions_satisfy_every_constraint():
+    """Any rotation and translation of a whole snake (particles and frames
+    together) leaves every element strain, distance and attachment at zero."""
+    wl = W.make_link(1, n_links=2)
+    o = OL.LinkOracle(wl)
+    rng = np.random.default_rng(4)
+    for _ in range(8):
+        Q = rot(rng.normal(size=3), rng.uniform(0, np.pi))
+        t = rng.normal(size=3)
+        x = o.x @ Q.T + t
+        fx = o.fx @ Q.T + t
+        fq = np.tile(quat_of(Q), (o.F, 1))
+        Cv, _, _, _ = o.assemble(x, fx, fq, np.zeros((2, 2)))
+        assert np.abs(Cv).max() <= 1e-13
+
+
+def test_actuation_rest_length_follows_eq_expansion():
+    """The chamber rows read |x_i - x_j| - r (1 + P / Y) with P the chamber's
+    pressure in pascal; the other rows do not see the pressure."""
+    wl = W.make_link(1, n_links=1)
+    o = OL.LinkOracle(wl)
+    pi, pj, kind, rest = o.link_dists()
+    p = np.array([[0.6, 0.25]])
+    Cv, _, _, _ = o.assemble(o.x, o.fx, o.fq, p)
+    dist = Cv[6 * o.T:6 * o.T + o.D]
+    eps = {OL.KIND_CHAMBER0: 1 + 0.6 * wl.p_max / wl.young, OL.KIND_CHAMBER1: 1 + 0.25 * wl.p_max / wl.young}
+    for k in range(o.D):
+        want = rest[k] - rest[k] * eps.get(int(kind[k]), 1.0)
+        assert abs(dist[k] - want) <= 1e-16
+
+
+# ---------------------------------------------------------------- dynamics invariants
+
+def test_rest_without_gravity_stays_at_rest():
+    wl = W.make_link(2, n_links=2)
+    o = OL.LinkOracle(wl, gravity=0.0, flags=OL.NO_GROUND)
+    x0, fx0 = o.x.copy(), o.fx.copy()
+    o.run(20)
+    # the mesh's rest coordinates carry round-off (cos of the ring angles),
+    # so "at rest" holds to round-off
+    assert np.abs(o.x - x0).max() <= 1e-15 and np.abs(o.fx - fx0).max() <= 1e-15
+    assert np.abs(o.v).max() <= 1e-12 and np.abs(o.lam_tet).max() <= 1e-15
+    assert np.all(o.residual <= 1e-13)
+
+
+def test_free_fall_leaves_every_constraint_satisfied():
+    """Without ground every body falls by the same discrete gravity step, so
+    the constraints stay satisfied and the multipliers stay (round-off) zero."""
+    wl = W.make_link(1, n_links=2)
+    o = OL.LinkOracle(wl, flags=OL.NO_GROUND)
+    x0 = o.x.copy()
+    n, sub = 6, wl.substeps
+    h = wl.dt / sub
+    o.run(n)
+    k = n * sub
+    drop = wl.gravity * h * h * k * (k + 1) / 2
+    assert np.abs(o.x - (x0 - [0, 0, drop])).max() <= 1e-12
+    assert np.abs(o.v[:, 2] + wl.gravity * h * k).max() <= 1e-10
+    assert np.abs(o.lam_tet).max() <= 1e-12 and np.abs(o.lam_att).max() <= 1e-15
+    assert o.residual[0] <= 1e-9
+
+
+def test_linear_momentum_is_conserved_by_every_iteration():
+    """No gravity, no ground, pressurised chamber and random velocities: the
+    internal blocks' impulses sum to zero, so the total momentum of
+    particles and frames is kept to round-off after every step (also with
+    a budget that leaves the solve far from converged)."""
+    wl = W.make_link(1, n_links=2)
+    o = OL.LinkOracle(wl, gravity=0.0, flags=OL.NO_GROUND, iters=7)
+    rng = np.random.default_rng(6)
+    o.v[:] = rng.normal(scale=0.05, size=o.v.shape)
+    o.fv[:] = rng.normal(scale=0.05, size=o.fv.shape)
+    o.fw[:] = rng.normal(scale=0.5, size=o.fw.shape)
+    o.cmd[:] = [0.8, -0.5]
+    m = np.tile(o.link_masses(), 2)
+
+    def momentum():
+        return (m[:, None] * o.v).sum(0) + wl.frame_mass * o.fv.sum(0)
+
+    p0 = momentum()
+    for _ in range(5):
+        o.run(1)
+        assert np.abs(momentum() - p0).max() <= 1e-13 * max(1.0, np.abs(p0).max())
+    assert o.residual[0] > 1e-3      # far from converged
+
+
+# ---------------------------------------------------------------- the linear system
+
+def perturbed(o, rng, amp=2e-4, vel=0.02, rot=0.01, spin=0.3):
+    x = o.x + rng.normal(scale=amp, size=o.x.shape)
+    v = rng.normal(scale=vel, size=o.v.shape)
+    fx = o.fx + rng.normal(scale=amp, size=o.fx.shape)
+    fq = o.fq + np.concatenate([np.zeros((o.F, 1)), rng.normal(scale=rot, size=(o.F, 3))], 1)
+    fq /= np.linalg.norm(fq, axis=1, keepdims=True)
+    fw = rng.normal(scale=spin, size=o.fw.shape)
+    return x, v, fx, fq, fw
+
+
+def dense_system(o, st, pred, cmd, ground):
+    """The compliant system of eq. schur_system at the predicted state: rows of
+    the active blocks (the commanded chamber's actuation only), and with
+    ground one normal and two tangential rows per particle predicted below
+    the plane (slip measured from the start of the substep).  Returns C, J,
+    W, E, the kept bilateral rows and the contact particles."""
+    p = o.p.copy()
+    Cv, J, Wm, E = o.assemble(pred["x"], pred["fx"], pred["fq"], p)
+    pi, pj, kind, rest = o.link_dists()
+    keep = np.ones(len(Cv), bool)
+    kinds = np.tile(kind, o.batch.n_links)
+    off = 6 * o.T
+    for d in range(o.D):
+        c = o.cmd[d // len(kind)]
+        if (kinds[d] == OL.KIND_CHAMBER0 and not c > 0) or (kinds[d] == OL.KIND_CHAMBER1 and not c < 0):
+            keep[off + d] = False
+    Cv, J, E = Cv[keep], J[keep], E[np.ix_(keep, keep)]
+    touching = np.nonzero(pred["x"][:, 2] < 0)[0] if ground else np.zeros(0, np.int64)
+    if ground:
+        n = J.shape[1]
+        rows, cs = [], []
+        for i in touching:
+            for r, c in ((2, pred["x"][i, 2]), (0, pred["x"][i, 0] - st["x"][i, 0]),
+                         (1, pred["x"][i, 1] - st["x"][i, 1])):
+                row = np.zeros(n)
+                row[3 * i + r] = 1.0
+                rows.append(row)
+                cs.append(c)
+        J = np.vstack([J, rows])
+        Cv = np.concatenate([Cv, cs])
+        E = np.block([[E, np.zeros((E.shape[0], len(cs)))], [np.zeros((len(cs), E.shape[0])), np.zeros((len(cs),) * 2)]])
+    return Cv, J, Wm, E, keep, touching
+
+
+def lam_vector(o, keep, touching):
+    lam = np.concatenate([o.lam_tet.reshape(-1), o.lam_dist, o.lam_att.reshape(-1)])[keep]
+    return np.concatenate([lam, o.lam_c[touching].reshape(-1)])
+
+
+def sink(x, fx, v, fv, depth=1e-3, speed=0.3):
+    """Lower the mesh and its frames until the lowest ring particles are
+    `depth` below the plane, all sinking at `speed`."""
+    drop = x[:, 2].min() + depth
+    x[:, 2] -= drop
+    fx[:, 2] -= drop
+    v[:, 2] = -speed
+    fv[:, 2] = -speed
+
+
+# A link with the paper's near-incompressible material (nu = 0.4999) and
+# almost rigid distance rows is so ill-conditioned that block Jacobi needs
+# millions of iterations per e-fold; the pins of the linear system take a
+# compressible material and softer rows, which leave every block type in
+# play and converge in thousands.
+WELL_POSED = dict(poisson=0.3, rigid_compliance=1e-3)
+# small enough that every particle of the sunken mesh stays pressed in
+GROUND_PERTURBATION = dict(amp=2e-5, vel=0.002, rot=1e-3, spin=0.03)
+
+
+@pytest.mark.parametrize("ground", [False, True])
+def test_linearised_jacobi_matches_dense_solve(ground):
+    """A small mesh (three sections of four ring particles, the middle one
+    free, its two frames, the commanded chamber active): the linearised
+    block-Jacobi iteration (values and Jacobians frozen at the predicted
+    state) converges to the solution of (J W J^T + E/h^2) lambda = -C(x~),
+    solved densely.  With ground the lowest particle of every section is
+    pressed in and mu is large, so those contact rows are active equalities
+    and every other particle stays clear of the plane."""
+    rng = np.random.default_rng(30 + ground)
+    wl = small(mu=np.array([1e6]), substeps=1, dt=1 / 240, **WELL_POSED)
+    flags = OL.LINEARISED | (0 if ground else OL.NO_GROUND)
+    o = OL.LinkOracle(wl, flags=flags, tol=1e-14, iters=2_000_000)
+    x, v, fx, fq, fw = perturbed(o, rng, **(GROUND_PERTURBATION if ground else {}))
+    if ground:
+        sink(x, fx, v, o.fv)
+    o.x[:], o.v[:], o.fx[:], o.fq[:], o.fw[:] = x, v, fx, fq, fw
+    o.cmd[:] = 0.7
+    o.p[:] = [[0.4, 0.1]]
+    # pressures after the substep's lag, then the prediction, by the oracle's own stages on copies
+    h = 1 / 240
+    p_after = np.array([[0.7 + (0.4 - 0.7) * np.exp(-h / wl.tau_inflate), 0.1 * np.exp(-h / wl.tau_deflate)]])
+    probe = OL.LinkOracle(wl, flags=flags)
+    pred = probe.predict(x, v, fx, fq, o.fv, fw)
+    o2p = OL.LinkOracle(wl, flags=flags)
+    o2p.p[:] = p_after
+    o2p.cmd[:] = 0.7
+    Cv, J, Wm, E, keep, touching = dense_system(o2p, dict(x=x), pred, o2p.cmd, ground)
+    lam_dense = np.linalg.solve(J @ Wm @ J.T + E, -Cv)
+    if ground:   # premise: the pressed-in contacts push
+        assert len(touching) == wl.sections and np.all(lam_dense[-3 * len(touching)::3] > 0)
+    o.run(1)
+    assert abs(o.p[0, 0] - p_after[0, 0]) <= 1e-15
+    assert o.status[0] == 0, o.residual
+    lam = lam_vector(o, keep, touching)
+    assert np.abs(lam - lam_dense).max() <= 1e-9 * np.abs(lam_dense).max()
+    if ground:   # premise: the rest stay clear
+        clear = np.setdiff1d(np.arange(o.P), touching)
+        assert np.all(o.lam_c[clear] == 0) and np.all(o.x[clear, 2] > 0)
+
+
+@pytest.mark.parametrize("ground", [False, True])
+def test_first_jacobi_iterations_in_closed_form(ground):
+    """The linearised iteration is scaled block Jacobi on A lambda = -C
+    (A = J W J^T + E/h^2): lambda_{k+1} = lambda_k - S D^-1 (C + A lambda_k),
+    D the diagonal blocks of A (6 per element, 1 per distance, 3 per
+    attachment, the particle's inverse mass per contact row) and S the
+    per-block factor 1 / (most blocks on one of its bodies), the degrees
+    counted here from the mesh.  Checked for the first three iterations."""
+    rng = np.random.default_rng(40 + ground)
+    wl = small(mu=np.array([1e6]), substeps=1, dt=1 / 240, **WELL_POSED)
+    flags = OL.LINEARISED | (0 if ground else OL.NO_GROUND)
+    base = OL.LinkOracle(wl, flags=flags)
+    x, v, fx, fq, fw = perturbed(base, rng, **(GROUND_PERTURBATION if ground else {}))
+    if ground:
+        sink(x, fx, v, base.fv)
+    pred = base.predict(x, v, fx, fq, base.fv, fw)
+    h = 1 / 240
+    ref = OL.LinkOracle(wl, flags=flags)
+    ref.cmd[:] = -0.6
+    ref.p[:] = [[0.0, 0.6 * (1 - np.exp(-h / wl.tau_inflate))]]
+    Cv, J, Wm, E, keep, touching = dense_system(ref, dict(x=x), pred, ref.cmd, ground)
+    A = J @ Wm @ J.T + E
+    # blocks and their scale from the mesh
+    pi, pj, kind, _ = base.link_dists()
+    part, side = base.link_atts()
+    deg_p = np.full(base.P, 1 if ground else 0)
+    for t in wl.tets:
+        deg_p[t] += 1
+    for a, b in zip(pi, pj):
+        deg_p[a] += 1
+        deg_p[b] += 1
+    deg_p[part] += 1
+    deg_f = np.array([np.sum(side == 0), np.sum(side == 1)])
+    blocks = [(6, max(deg_p[t])) for t in wl.tets]
+    active = [d for d in range(base.D) if keep[6 * base.T + d]]
+    blocks += [(1, max(deg_p[pi[d]], deg_p[pj[d]])) for d in active]
+    blocks += [(3, max(deg_p[part[a]], deg_f[side[a]])) for a in range(base.A)]
+    blocks += [(3, deg_p[i]) for i in touching]
+    lam = np.zeros(len(Cv))
+    for k in range(1, 4):
+        r = Cv + A @ lam
+        step = np.zeros_like(lam)
+        at = 0
+        for size, dg in blocks:
+            sl = slice(at, at + size)
+            step[sl] = -np.linalg.solve(A[sl, sl], r[sl]) / dg
+            at += size
+        lam = lam + step
+        o = OL.LinkOracle(wl, flags=flags, iters=k)
+        o.x[:], o.v[:], o.fx[:], o.fq[:], o.fv[:], o.fw[:] = x, v, fx, fq, base.fv, fw
+        o.cmd[:] = -0.6
+        o.run(1)
+        got = lam_vector(o, keep, touching)
+        assert np.abs(got - lam).max() <= 1e-11 * np.abs(lam).max(), k
+        if ground:
+            assert np.all(o.lam_c[np.setdiff1d(np.arange(o.P), touching)] == 0)
+
+
+def test_compliance_to_zero_limit():
+    """One converged substep of a link hanging from a fixed frame, no
+    ground, as the material stiffens (the distance rows and attachments
+    made soft enough that the elements carry the load): the element
+    multipliers approach the rigid solution (each decade of Y past 1e5 moves
+    them less than half as much as the one before) and the strains fall as
+    1 / Y (their product with Y approaches a constant), so the constraint
+    values vanish in the limit."""
+    wl = small(n_links=1, substeps=1, dt=1 / 240, poisson=0.3, rigid_compliance=0.1)
+    lams, strain_y = [], []
+    rest = OL.LinkOracle(wl)
+    for Y in (1e3, 1e4, 1e5, 1e6):
+        o = OL.LinkOracle(wl, young=Y, flags=OL.NO_GROUND | OL.FIXED_FRAME0 | OL.LINEARISED, tol=1e-14,
+                          iters=2_000_000)
+        o.run(1)
+        assert o.status[0] == 0, (Y, o.residual)
+        lams.append(o.lam_tet.copy())
+        pred = o.predict(rest.x, np.zeros((o.P, 3)), rest.fx, rest.fq, np.zeros((o.F, 3)), np.zeros((o.F, 3)))
+        Cv, J, Wm, E = o.assemble(pred["x"], pred["fx"], pred["fq"], o.p)
+        dx = np.concatenate([(o.x - pred["x"]).reshape(-1), np.zeros(6 * o.F)])
+        strain = Cv[:6 * o.T] + J[:6 * o.T] @ dx
+        strain_y.append(np.abs(strain).max() * Y)
+    d = [np.abs(lams[k + 1] - lams[k]).max() for k in range(3)]
+    print("\n[link compliance limit] multiplier steps", d, "strain * Y", strain_y)
+    # from Y = 1e5 on (the elements stiffer than the distance rows) the
+    # approach is geometric
+    assert d[2] <= 0.5 * d[1], d
+    sy = np.array(strain_y)
+    assert abs(sy[3] - sy[2]) <= 0.5 * abs(sy[2] - sy[1]), sy
+    assert abs(sy[3] - sy[2]) <= 0.2 * sy[3], sy

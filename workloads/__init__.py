@@ -289,3 +289,86 @@ def link_mesh(sections: int = 13, ring: int = 8, length: float = 0.01, radius: f
                     t = (t[0], t[2], t[1], t[3])
                 tets.append(t)
     return pts, np.array(tets, np.int64)
+
+
+@dataclasses.dataclass
+class LinkWorkload:
+    """A batch of snakes built from full-resolution soft links (a
+    tetrahedral particle mesh per link, rigid frames at the junctions).
+    Every snake has the same links; friction differs per snake.  Commands
+    are external: `link_commands` draws them."""
+    name: str
+    seed: int
+    n_links: int
+    sections: int
+    ring: int
+    X: np.ndarray                # float64 [per_link][3] link mesh, link frame
+    tets: np.ndarray             # int32 [n_tets][4]
+    mu: np.ndarray               # float64 [n_snakes]
+    link_length: float = 0.16    # 16 cm: four 1 cm segments' modules of the chain workloads
+    radius: float = 0.01
+    young: float = 66243.0       # Pa, Ecoflex 00-30 (section "Soft robotic snake model")
+    poisson: float = 0.4999
+    density: float = 1070.0      # kg/m^3 (not given in the paper)
+    p_max: float = 5333.0        # Pa at full chamber pressure: eq. expansion then bends a link to 10 1/m
+    frame_mass: float = 0.02
+    frame_length: float = 0.01
+    gravity: float = 9.81
+    dt: float = 1.0 / 60.0
+    substeps: int = 4
+    iters: int = 20
+    tol: float = 0.0
+    relax: float = 1.0
+    tau_inflate: float = 0.1
+    tau_deflate: float = 0.2
+    rigid_compliance: float = 1e-7   # m/N on the non-deformable distance rows and the attachments
+    flags: int = 0
+
+    @property
+    def n_snakes(self) -> int:
+        return int(self.mu.shape[0])
+
+    @property
+    def per_link(self) -> int:
+        return self.sections * (self.ring + 1)
+
+    @property
+    def particles(self) -> int:
+        """particles per snake"""
+        return self.n_links * self.per_link
+
+    @property
+    def n_tets(self) -> int:
+        """tetrahedra per link"""
+        return int(self.tets.shape[0])
+
+    def take(self, idx) -> "LinkWorkload":
+        w = dataclasses.replace(self)
+        w.mu = np.ascontiguousarray(self.mu[np.asarray(idx, np.int64)])
+        return w
+
+
+def make_link(n_snakes: int = 2048, n_links: int = 4, seed: int = 1006, sections: int = 13,
+              ring: int = 8) -> LinkWorkload:
+    """The link batch: `n_snakes` snakes of `n_links` links on the procedural
+    13-section mesh (the paper's snake has four links), friction U[0.2, 0.8]
+    per snake."""
+    rng = SplitMix64(seed)
+    mu = np.array([rng.uniform(0.2, 0.8) for _ in range(n_snakes)], np.float64)
+    X, tets = link_mesh(sections, ring, length=0.16, radius=0.01)
+    return LinkWorkload("link", seed, n_links, sections, ring, X, tets.astype(np.int32), mu)
+
+
+def link_commands(wl: LinkWorkload, n_steps: int, seed: int | None = None) -> np.ndarray:
+    """Piecewise-constant signed commands per link, U[-1, 1] held for
+    U{6..60} steps: float64 [n_steps][n_snakes * n_links]."""
+    rng = SplitMix64(wl.seed + 17 if seed is None else seed)
+    n = wl.n_snakes * wl.n_links
+    out = np.empty((n_steps, n), np.float64)
+    for c in range(n):
+        t = 0
+        while t < n_steps:
+            k = rng.integer(6, 60)
+            out[t:t + k, c] = rng.uniform(-1.0, 1.0)
+            t += k
+    return out
