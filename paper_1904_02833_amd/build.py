@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsnake.so")
-SOURCES = ["step.hip", "newton.hip", "gs.hip", "carriage.hip", "index.hip", "api.hip", "mlp.hip"]
+SOURCES = ["step.hip", "newton.hip", "gs.hip", "carriage.hip", "index.hip", "api.hip", "mlp.hip", "link.hip"]
 
 # Packed FP32 instructions are kept out of the generated code; contraction
 # follows source expressions only, so one device function compiles to the
