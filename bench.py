@@ -107,7 +107,7 @@ def parse():
     ap.add_argument("--mapping", default=None,
                     help="force a mapping instead of autotuning: waves,min_seg,rows (e.g. 4,16,1)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-snakes", type=int, default=256,
+    ap.add_argument("--cpu-snakes", type=int, default=128,
                     help="snakes of the CPU-baseline sample (evenly spaced over the batch)")
     ap.add_argument("--cpu-steps", type=int, default=50, help="first steps of the CPU-baseline sample")
     ap.add_argument("--no-converged", action="store_true",
@@ -120,6 +120,9 @@ def parse():
                     help="the wheeled carriage (two wheels per segment on hinge joints), "
                          f"{CARRIAGE_ITERS} Jacobi iterations per substep")
     ap.add_argument("--no-carriage", action="store_true", help="skip the wheeled-carriage line")
+    ap.add_argument("--link", action="store_true",
+                    help="only the full-resolution link batch (soft links of tetrahedra and rigid frames)")
+    ap.add_argument("--no-link", action="store_true", help="skip the full-resolution link line")
     ap.add_argument("--solver", default="jacobi", choices=("jacobi", "newton", "gs"),
                     help="solver of the timed loop (newton: the paper's budget, 4 x 20, FP64; "
                          "gs: block Gauss-Seidel, 40 sweeps)")
@@ -366,9 +369,61 @@ def carriage_run(wl, n_steps=5, iters=CARRIAGE_ITERS):
                          "flop_per_segment_iter": FLOP_CARRIAGE_ITER}}
 
 
+# Full-resolution link (FP32): VALU operations per element-iteration and
+# per distance-row / attachment-iteration and per particle-iteration
+# (gather, contact), from the rocprofv3 VALU instruction counters of the
+# kernel (summary in profiles/), the element dominating.
+LINK_SNAKES = 2048
+LINK_STEPS = 10
+
+
+def link_run(n_snakes=LINK_SNAKES, n_steps=LINK_STEPS, iters=20):
+    """The link batch: snakes of four soft links on the procedural
+    13-section tetrahedral mesh (117 particles, 288 elements per link) and
+    five rigid frames, 4 substeps x `iters` block-Jacobi iterations, drawn
+    piecewise-constant chamber commands set from a device array every step.
+    Time per step, the residual reached, and the element-iterations per
+    second."""
+    import torch
+
+    import workloads as W
+    from paper_1904_02833_amd.link import LinkSim
+
+    wl = W.make_link(n_snakes, n_links=4)
+    wl.iters = iters
+    cmds = torch.as_tensor(W.link_commands(wl, 20 + n_steps), dtype=torch.float32, device="cuda")
+    sim = LinkSim(wl)
+    for n in range(20):
+        sim.set_commands(cmds[n])
+        sim.step(1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    for n in range(20, 20 + n_steps):
+        sim.set_commands(cmds[n])
+        sim.step(1)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n_steps
+    r = sim.read("residual", "status", "iters")
+    sim.close()
+    tets = n_snakes * wl.n_links * wl.n_tets
+    its = float(np.mean(r["iters"]))
+    return {"workload": f"link: {n_snakes} snakes x {wl.n_links} soft links ({wl.per_link} particles, {wl.n_tets} "
+                        f"tetrahedra per link) and {wl.n_links + 1} rigid frames, {wl.substeps} substeps x {iters} "
+                        "iterations, drawn chamber commands",
+            "ms_per_step": ms, "snake_steps_per_s": n_snakes / (ms / 1e3),
+            "element_iters_per_s": tets * its / (ms / 1e3),
+            "iters_per_step": its,
+            "residual_last_step": {"median": float(np.median(r["residual"])),
+                                   "max": float(np.max(r["residual"]))},
+            "nonfinite_snakes": int(np.sum((r["status"] & 1) != 0))}
+
+
 def host_cores():
     """Threads the oracle runs on: the CPUs this process may use, at most 16
-    (the host share of one GPU on the benchmark machines)."""
+    (the host share of one GPU on the benchmark machines, whatever the
+    machine's own core count; both numbers are reported)."""
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -376,13 +431,19 @@ def host_cores():
     return max(1, min(16, avail)), avail
 
 
+# first-steps samples of the other batches for the CPU baseline: snakes, steps
+# (the stiff batch at 10 steps keeps the baseline within a minute)
+CPU_OTHER = {"uniform": (64, 50), "stiff": (4, 10)}   # stiff: 1.2 s per snake-step
+
+
 def cpu_baseline(wl, n_snakes, n_steps, gpu_kw):
     """The FP64 oracle as it stands, timed on this machine's host cores:
     (1) the single-snake workload in full (600 steps, 4 substeps x 20
     iterations), one thread; (2) the first n_steps steps of n_snakes snakes
     spread evenly over the timed batch, its settings, snakes split over the
-    host cores.  The value is (2)'s snake-steps/s.  Then both sides take one
-    more substep of that sample from the oracle's state rounded to FP32, and
+    host cores; (3) the same for the uniform and stiff batches (CPU_OTHER).
+    The value is (2)'s snake-steps/s.  Then both sides take one more
+    substep of the (2) sample from the oracle's state rounded to FP32, and
     the GPU's results are compared with the oracle's (the FP64 error of
     every result: positions, velocities, angular velocities, multipliers)."""
     import oracle
@@ -394,7 +455,7 @@ def cpu_baseline(wl, n_snakes, n_steps, gpu_kw):
     single = W.make("single")
     o1 = oracle.Oracle(single)
     t0 = time.perf_counter()
-    o1.run(single.steps, threads=1)
+    o1.run(single.n_steps, threads=1)
     t_single = time.perf_counter() - t0
 
     pick = np.unique(np.linspace(0, wl.n_snakes - 1, min(n_snakes, wl.n_snakes)).round().astype(np.int64))
@@ -409,10 +470,25 @@ def cpu_baseline(wl, n_snakes, n_steps, gpu_kw):
                      f"by index, {int(sub.bodies.sum())} bodies), the timed batch's settings, FP64 C oracle "
                      f"on {threads} threads, {dt:.1f} s wall",
            "constraint_iters_per_s": float(np.sum((9 * sub.bodies - 6) * o.iters_total) / dt),
-           "single_snake_full": {"workload": f"single: 1 snake of 64 bodies, {single.steps} steps, "
+           "single_snake_full": {"workload": f"single: 1 snake of 64 bodies, {single.n_steps} steps, "
                                              f"{single.substeps} substeps x {single.iters} iterations",
-                                 "snake_steps_per_s": single.steps / t_single, "seconds": t_single,
+                                 "snake_steps_per_s": single.n_steps / t_single, "seconds": t_single,
                                  "cores": 1}}
+    others = {}
+    for name, (ns, nst) in CPU_OTHER.items():
+        ow = W.make(name)
+        if name == "uniform":
+            ow.tol, ow.iters = wl.tol, wl.iters
+        ow = ow.take(np.unique(np.linspace(0, ow.n_snakes - 1, ns).round().astype(np.int64)))
+        oo = oracle.Oracle(ow)
+        t0 = time.perf_counter()
+        oo.run(nst, threads=threads)
+        t = time.perf_counter() - t0
+        others[name] = {"snake_steps_per_s": ow.n_snakes * nst / t, "seconds": t,
+                        "sample": f"first {nst} steps of {ow.n_snakes} snakes ({int(ow.bodies.sum())} bodies), "
+                                  f"residual<=1e-4 or at most {ow.iters} iterations" if ow.tol > 0 else
+                                  f"first {nst} steps of {ow.n_snakes} snakes, {ow.iters} iterations"}
+    out["other_batches"] = others
     o.commands()
     oo, g = advance_both(sub, rounded_state(o), threads=threads, **gpu_kw)
     err = compare(oo, g, np.asarray(sub.mu, np.float64))
@@ -508,6 +584,14 @@ def main():
     import paper_1904_02833_amd as snk
     import workloads as W
 
+    if args.link:
+        row = link_run(n_snakes=args.snakes or LINK_SNAKES, n_steps=args.steps)
+        out = {"metric": "link snake-steps/s", "value": row["snake_steps_per_s"], "unit": "snake-steps/s",
+               "n_gpus": 1, "steps": args.steps, "warmup": 20, "ms_per_step": row["ms_per_step"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": row["workload"]}, **{k: v for k, v in row.items() if k != "workload"}}
+        print(json.dumps(out), flush=True)
+        return
     wl = W.make(args.workload, n_snakes=args.snakes)
     if args.wheels:
         if args.solver != "jacobi":
@@ -632,6 +716,9 @@ def main():
         print("[bench] solver comparison done", file=sys.stderr, flush=True)
     if not args.no_carriage:
         out["wheel_carriage"] = carriage_run(wl)
+    if not args.no_link:
+        out["full_resolution_link"] = link_run()
+        print("[bench] link done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

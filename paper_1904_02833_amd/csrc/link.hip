@@ -46,7 +46,7 @@ constexpr int kThreads = 1024;
 constexpr int kSlots = 2;          // blocks per thread
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxLinks = 4;
-constexpr int kLdsLimit = 65536;   // bytes of LDS a workgroup may take
+constexpr int kLdsLimit = 163840;  // bytes of LDS a gfx950 workgroup may take
 
 constexpr int kCentre = 0, kRadial = 1, kChamber0 = 2, kChamber1 = 3;
 // incidence entries: type << 28 | block << 2 | slot
@@ -787,7 +787,7 @@ int validate(const link_desc_t* d, Sz* z)
     z->lds = sizeof(float) * (size_t)(6 * P + 9 * z->L * z->Tm + 3 * z->L * z->D1 + 3 * z->L * z->A1 +
                                        lk::kFr * (z->L + 1) + 4 * z->L + lk::kWaves);
     if (z->lds > (size_t)lk::kLdsLimit)
-        return lfail(LINK_EINVAL, "a snake needs " + std::to_string(z->lds) + " bytes of LDS (limit 65536)");
+        return lfail(LINK_EINVAL, "a snake needs " + std::to_string(z->lds) + " bytes of LDS (limit 163840)");
     if ((int64_t)d->n_snakes * P > ((int64_t)1 << 28)) return lfail(LINK_EINVAL, "too many particles (limit 2^28)");
     z->NP = z->n * P;
     z->NF = z->n * (z->L + 1);
@@ -1038,6 +1038,14 @@ int link_create(const link_desc_t* d, void* workspace, size_t bytes, void* hip_s
     if (e != hipSuccess) {
         delete s;
         return lhip(e, "link create");
+    }
+    if (z.lds > 65536) {   // dynamic LDS past 64 KB has to be requested
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(lk::k_link), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)z.lds);
+        if (e != hipSuccess) {
+            delete s;
+            return lhip(e, "link LDS request");
+        }
     }
     lk::Params& P = s->kp;
     P = lk::Params{};

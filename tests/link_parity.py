@@ -150,3 +150,40 @@ def assert_parity(tag, err, n_particles, max_branch_frac=0.02):
     for k in ("lam_tet", "lam_dist", "lam_att", "lam_n", "lam_t"):
         assert worst[k] <= LAM_TOL, (k, worst[k])
     assert err["branch"].sum() <= max_branch_frac * n_particles
+
+
+STATE_FIELDS = ("pos", "vel", "frame_pos", "frame_quat", "frame_vel", "frame_angvel", "pressure", "lambda_tet",
+                "lambda_dist", "lambda_att", "lambda_contact")
+
+
+def chained_substeps(wl, st, threads=8, **over):
+    """A whole step from st, held to the per-substep protocol substep by
+    substep: the GPU takes the step in one launch and again as one launch
+    per substep (dt = h, one substep, the same held commands), which must
+    give the same bits; each one-substep launch is compared with the
+    oracle's substep from the GPU's own FP32 state before it.  Returns the
+    (oracle, GPU state) pair of every substep."""
+    from paper_1904_02833_amd.link import LinkSim
+
+    whole = LinkSim(wl, **over)
+    load_gpu(whole, st)
+    whole.step(1)
+    g_whole = whole.read(*STATE_FIELDS)
+    whole.close()
+    one = dict(over, dt=wl.dt / wl.substeps, substeps=1)
+    sim = LinkSim(wl, **one)
+    load_gpu(sim, st)
+    prev, out = st, []
+    for _ in range(wl.substeps):
+        sim.step(1)
+        g = gpu_state(sim)
+        o = OL.LinkOracle(wl, **one)
+        load_oracle(o, prev)
+        o.run(1, threads=threads)
+        out.append((o, g))
+        prev = {k: g[k] for k in STATE}
+    g_chain = sim.read(*STATE_FIELDS)
+    sim.close()
+    for k in STATE_FIELDS:
+        assert np.array_equal(g_whole[k], g_chain[k]), f"one launch and per-substep launches differ in {k}"
+    return out

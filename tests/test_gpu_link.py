@@ -51,3 +51,154 @@ def test_link_substep_parity(steps):
     o, g = advance_both(wl, st)
     assert np.array_equal(np.asarray(g["iters"]), o.iters)
     assert_parity(f"link substep after {steps} steps", compare(o, g), wl.particles * wl.n_snakes)
+
+
+def test_link_whole_step_substep_by_substep():
+    """A whole step (four substeps) in one launch equals four one-substep
+    launches bit for bit; each of those is held to the per-substep gates
+    against the oracle from the GPU's own state before it."""
+    from link_parity import chained_substeps
+
+    wl = W.make_link(3, n_links=4)
+    for k, (o, g) in enumerate(chained_substeps(wl, state_after(wl, 8, seed=5))):
+        assert np.array_equal(np.asarray(g["iters"]), o.iters)
+        assert_parity(f"link step substep {k}", compare(o, g), wl.particles * wl.n_snakes)
+
+
+def test_link_hanging_from_a_fixed_frame_without_ground():
+    """Frame 0 of every snake fixed, no ground: the snakes hang and swing
+    (one-, two- and four-link snakes, chamber commands drawn)."""
+    for n_links in (1, 2, 4):
+        wl = W.make_link(2, n_links=n_links)
+        flags = OL.FIXED_FRAME0 | OL.NO_GROUND
+        st = state_after(wl, 5, seed=7, flags=flags)
+        o, g = advance_both(wl, st, flags=flags)
+        assert_parity(f"link hanging {n_links}", compare(o, g), wl.particles * wl.n_snakes)
+
+
+def small_link(n_snakes=6, **kw):
+    wl = W.make_link(n_snakes, n_links=2, sections=3, ring=4)
+    X, tets = W.link_mesh(3, 4, length=2 * 0.16 / 12, radius=0.01)
+    wl.X, wl.tets, wl.link_length = X, tets.astype(np.int32), float(X[:, 0].max())
+    for k, v in kw.items():
+        setattr(wl, k, v)
+    return wl
+
+
+def test_link_tolerance_mode_iteration_counts():
+    """A small mesh of a compressible material with soft distance rows,
+    where block Jacobi converges: residual 1e-5 with at most 20 000
+    iterations (about 10 000 taken).  Every converged substep ends at or
+    below the tolerance; the iteration counts of the two precisions agree
+    to 0.5 %: near the threshold one iteration lowers the residual by
+    about 1e-3 of itself, so the FP32 rounding of the residual moves the
+    crossing by a few iterations (measured: 1 to 11 of 10 300 to 11 700)."""
+    wl = small_link(poisson=0.3, rigid_compliance=1e-3, tol=1e-5, iters=20000, substeps=1, dt=1 / 240)
+    st = state_after(wl, 3, seed=3)
+    o, g = advance_both(wl, st)
+    print("\n[link tol] oracle iters", o.iters, "gpu iters", g["iters"])
+    assert np.all(g["residual"][g["status"] == 0] <= 1e-5)
+    assert np.all(np.abs(np.asarray(g["iters"]) - o.iters) <= 0.005 * o.iters + 2)
+    assert_parity("link tol", compare(o, g), wl.particles * wl.n_snakes)
+
+
+def test_link_deterministic_and_checkpoint_roundtrip():
+    wl = W.make_link(16, n_links=4)
+    cmds = W.link_commands(wl, 10)
+    a, b = LK.LinkSim(wl), LK.LinkSim(wl)
+    for n in range(5):
+        for s in (a, b):
+            s.set_commands(cmds[n])
+            s.step(1)
+    ra, rb = a.read(), b.read()
+    for k in ra:
+        assert np.array_equal(ra[k], rb[k]), k
+    snap = a.read()
+    for n in range(5, 10):
+        a.set_commands(cmds[n])
+        a.step(1)
+    c = LK.LinkSim(wl)
+    c.write(**{k: v for k, v in snap.items()})
+    for n in range(5, 10):
+        c.set_commands(cmds[n])
+        c.step(1)
+    ra, rc = a.read(), c.read()
+    for k in ra:
+        assert np.array_equal(ra[k], rc[k]), k
+    for s in (a, b, c):
+        s.close()
+
+
+def test_link_nonfinite_snake_is_isolated():
+    wl = W.make_link(6, n_links=2)
+    a, b = LK.LinkSim(wl), LK.LinkSim(wl)
+    a.step(2)
+    b.step(2)
+    pos = b.read("pos")["pos"]
+    pos[:, 3 * wl.particles + 17] = np.nan
+    b.write(pos=pos)
+    a.step(2)
+    b.step(2)
+    ra, rb = a.read(), b.read()
+    assert rb["status"][3] & LK.STATUS_NONFINITE
+    others = np.arange(6) != 3
+    assert np.array_equal(ra["status"][others], rb["status"][others])
+    keep = np.repeat(others, wl.particles)
+    assert np.array_equal(ra["pos"][:, keep], rb["pos"][:, keep])
+    a.close()
+    b.close()
+
+
+def test_link_commands_errors_and_device_path():
+    import torch
+
+    wl = W.make_link(2, n_links=2)
+    sim = LK.LinkSim(wl)
+    with pytest.raises(LK.LinkError):
+        sim.set_commands(np.array([0.1, np.nan, 0, 0], np.float32))
+    with pytest.raises(LK.LinkError):
+        sim.set_commands(np.zeros(3, np.float32))
+    sim.set_commands(torch.tensor([2.0, -0.5, float("nan"), -3.0], device="cuda"))
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.read("cmd")["cmd"], np.array([1, -0.5, 0, -1], np.float32))
+    sim.close()
+
+
+def test_link_full_batch_sampled():
+    """The benchmark's batch (2048 snakes of four links) takes one substep
+    on the GPU from the GPU's own state after drawn-command steps; sampled
+    snakes take the same substep in the oracle from the same FP32 state."""
+    wl = W.make_link(2048, n_links=4)
+    cmds = W.link_commands(wl, 6)
+    lead = LK.LinkSim(wl)
+    for n in range(6):
+        lead.set_commands(cmds[n])
+        lead.step(1)
+    st = gpu_state(lead)
+    lead.close()
+    sample = [0, 1, 777, 1500, 2047]
+    sub = wl.take(sample)
+    P, F, L = wl.particles, wl.n_links + 1, wl.n_links
+    T, D, A = L * wl.n_tets, None, None
+    o = OL.LinkOracle(sub, dt=wl.dt / wl.substeps, substeps=1)
+    D, A = o.D, o.A
+
+    def rows(a, per):
+        return np.concatenate([a[s * per:(s + 1) * per] for s in sample])
+
+    st_s = {"x": rows(st["x"], P), "v": rows(st["v"], P), "fx": rows(st["fx"], F), "fq": rows(st["fq"], F),
+            "fv": rows(st["fv"], F), "fw": rows(st["fw"], F), "p": rows(st["p"], L), "cmd": rows(st["cmd"], L),
+            "lam_tet": rows(st["lam_tet"], T), "lam_dist": rows(st["lam_dist"], D),
+            "lam_att": rows(st["lam_att"], A), "lam_c": rows(st["lam_c"], P)}
+    sim = LK.LinkSim(wl, dt=wl.dt / wl.substeps, substeps=1)
+    load_gpu(sim, st)
+    sim.step(1)
+    g_all = gpu_state(sim)
+    sim.close()
+    g = {k: rows(g_all[k], {"x": P, "v": P, "fx": F, "fq": F, "fv": F, "fw": F, "p": L, "cmd": L, "lam_tet": T,
+                            "lam_dist": D, "lam_att": A, "lam_c": P}[k]) for k in st_s}
+    g["iters"] = np.asarray(g_all["iters"])[sample]
+    load_oracle(o, st_s)
+    o.run(1, threads=8)
+    assert np.array_equal(g["iters"], o.iters)
+    assert_parity("link full batch sampled", compare(o, g), P * len(sample))
