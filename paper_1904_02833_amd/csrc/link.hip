@@ -130,11 +130,27 @@ __device__ __forceinline__ V3 frame_inv_inertia(const Params& P, Q4 q, V3 t)
     return P.I_pe_inv * t + ((P.I_ax_inv - P.I_pe_inv) * dot(a, t)) * a;
 }
 
-// LDS of one snake's workgroup
+// LDS of one snake's workgroup: the per-mesh constants (copied once per
+// launch) and the snake's working arrays
 struct Lds {
+    // per-mesh constants
+    float* g;     // [12][Tm] element gradients g_0..g_3
+    float* ldl;   // [21][Tm] unit-lower L (15) and 1/D (6) of K + E/h^2
+    float* alpha; // [3][Tm] E/h^2 normal diagonal, off-diagonal, shear
+    float* tsc;   // [Tm] element scale
+    int* tv;      // [Tm] packed vertices
+    float* dc;    // [4][D1] rest, w_i, w_j, scale
+    int* dij;     // [D1]
+    int* dk;      // [D1]
+    float* ac;    // [5][A1] r (3), w_p, particle degree
+    int* ap;      // [A1]
+    int* ioff;    // [P1 + 1]
+    int* inc;     // incidence entries
+    // working arrays
     float* xp;    // [3][P] particle positions at the substep start
     float* d;     // [3][P] particle displacement since then
     float* U;     // [9][T] element outputs R T
+    float* pt;    // [6][T] element increments awaiting the stop decision
     float* dd;    // [3][D] distance impulses on the first particle
     float* da;    // [3][A] attachment increments
     float* fr;    // [kFr][F] frames: xp (3), d (3), q (4), v (3), w (3), q at the substep start (4)
@@ -142,6 +158,14 @@ struct Lds {
     float* red;   // [kWaves] residual maxima of the waves
 };
 constexpr int kFr = 20;
+
+// words of LDS for a snake (the layout of Lds)
+__host__ __device__ inline int lds_words(int L, int P1, int Tm, int D1, int A1, int n_inc)
+{
+    const int P = L * P1, T = L * Tm, D = L * D1, A = L * A1;
+    return 38 * Tm + 6 * D1 + 6 * A1 + (P1 + 1) + n_inc + 6 * P + 15 * T + 3 * D + 3 * A + kFr * (L + 1) + 4 * L +
+           kWaves;
+}
 
 __device__ __forceinline__ V3 ld3(const float* a, int n, int i) { return mk(a[i], a[n + i], a[2 * n + i]); }
 __device__ __forceinline__ void st3(float* a, int n, int i, V3 v)
@@ -151,21 +175,57 @@ __device__ __forceinline__ void st3(float* a, int n, int i, V3 v)
     a[2 * n + i] = v.z;
 }
 
+template <class T>
+__device__ __forceinline__ void copy_lds(T* dst, const T* src, int n)
+{
+    for (int i = threadIdx.x; i < n; i += kThreads) dst[i] = src[i];
+}
+
 __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
 {
     extern __shared__ float smem[];
     const int s = blockIdx.x;
     const int tid = threadIdx.x;
-    const int L = P.L, NP = P.P, NF = P.F, T = L * P.Tm, D = L * P.D1, A = L * P.A1;
+    const int L = P.L, NP = P.P, NF = P.F, Tm = P.Tm, D1 = P.D1, A1 = P.A1, P1 = P.P1;
+    const int T = L * Tm, D = L * D1, A = L * A1;
+    const int n_inc = 4 * Tm + 2 * D1 + A1;
     Lds S;
-    S.xp = smem;
-    S.d = S.xp + 3 * NP;
-    S.U = S.d + 3 * NP;
-    S.dd = S.U + 9 * T;
-    S.da = S.dd + 3 * D;
-    S.fr = S.da + 3 * A;
-    S.lk = S.fr + kFr * NF;
-    S.red = S.lk + 4 * L;
+    {
+        float* w = smem;
+        S.g = w, w += 12 * Tm;
+        S.ldl = w, w += 21 * Tm;
+        S.alpha = w, w += 3 * Tm;
+        S.tsc = w, w += Tm;
+        S.tv = reinterpret_cast<int*>(w), w += Tm;
+        S.dc = w, w += 4 * D1;
+        S.dij = reinterpret_cast<int*>(w), w += D1;
+        S.dk = reinterpret_cast<int*>(w), w += D1;
+        S.ac = w, w += 5 * A1;
+        S.ap = reinterpret_cast<int*>(w), w += A1;
+        S.ioff = reinterpret_cast<int*>(w), w += P1 + 1;
+        S.inc = reinterpret_cast<int*>(w), w += n_inc;
+        S.xp = w, w += 3 * NP;
+        S.d = w, w += 3 * NP;
+        S.U = w, w += 9 * T;
+        S.pt = w, w += 6 * T;
+        S.dd = w, w += 3 * D;
+        S.da = w, w += 3 * A;
+        S.fr = w, w += kFr * NF;
+        S.lk = w, w += 4 * L;
+        S.red = w;
+    }
+    copy_lds(S.g, P.tet_g, 12 * Tm);
+    copy_lds(S.ldl, P.tet_ldl, 21 * Tm);
+    copy_lds(S.alpha, P.tet_alpha, 3 * Tm);
+    copy_lds(S.tsc, P.tet_scale, Tm);
+    copy_lds(S.tv, P.tet_v, Tm);
+    copy_lds(S.dc, P.dist_c, 4 * D1);
+    copy_lds(S.dij, P.dist_ij, D1);
+    copy_lds(S.dk, P.dist_kind, D1);
+    copy_lds(S.ac, P.att_c, 5 * A1);
+    copy_lds(S.ap, P.att_p, A1);
+    copy_lds(S.ioff, P.inc_off, P1 + 1);
+    copy_lds(S.inc, P.inc, n_inc);
 
     const int64_t gp = (int64_t)s * NP + tid;     // particle
     const int64_t gf = (int64_t)s * NF + tid;     // frame
@@ -176,18 +236,16 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
     // particle state in registers
     V3 x = mk(0.f, 0.f, 0.f), v = x, lc = x, d = x, dlc = x;
     float wp = 0.f, pmass = 0.f, cscale = 0.f;
-    int inc0 = 0, inc1 = 0, pl = 0;
+    int pl = 0, pk = 0;
     if (isp) {
         x = mk(P.x[gp], P.x[P.NP + gp], P.x[2 * P.NP + gp]);
         v = mk(P.v[gp], P.v[P.NP + gp], P.v[2 * P.NP + gp]);
         lc = mk(P.lam_c[gp], P.lam_c[P.NP + gp], P.lam_c[2 * P.NP + gp]);
-        pl = tid / P.P1;
-        const int pk = tid - pl * P.P1;
+        pl = tid / P1;
+        pk = tid - pl * P1;
         wp = P.part_w[pk];
         pmass = P.part_m[pk];
         cscale = P.relax / (float)P.part_deg[pk];
-        inc0 = P.inc_off[pk];
-        inc1 = P.inc_off[pk + 1];
     }
     const float mu = P.mu[s];
     // frame and link state in LDS
@@ -204,18 +262,22 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
     }
     // blocks: kind 0 element, 1 distance row, 2 attachment, 3 none
     int bkind[kSlots], bidx[kSlots], blink[kSlots];
-    float lam[kSlots][6], pend[kSlots][6];
+    float lam[kSlots][6], pend[kSlots][3];
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) {
         const int b = tid + k * kThreads;
         bkind[k] = b < T ? 0 : b < T + D ? 1 : b < T + D + A ? 2 : 3;
         const int loc = bkind[k] == 0 ? b : bkind[k] == 1 ? b - T : b - T - D;
-        const int per = bkind[k] == 0 ? P.Tm : bkind[k] == 1 ? P.D1 : P.A1;
+        const int per = bkind[k] == 0 ? Tm : bkind[k] == 1 ? D1 : A1;
         blink[k] = bkind[k] < 3 ? loc / per : 0;
         bidx[k] = bkind[k] < 3 ? loc - blink[k] * per : 0;
 #pragma unroll
-        for (int r = 0; r < 6; ++r) lam[k][r] = pend[k][r] = 0.f;
+        for (int r = 0; r < 6; ++r) lam[k][r] = 0.f;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) pend[k][r] = 0.f;
     }
+    __syncthreads();
+    const int inc0 = isp ? S.ioff[pk] : 0, inc1 = isp ? S.ioff[pk + 1] : 0;
 
     float rstep = 0.f;
     int itstep = 0, status = 0, itsum = 0;
@@ -280,7 +342,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                 for (int k = 0; k < kSlots; ++k) {
                     const int t = bidx[k];
                     if (bkind[k] == 0) {
-                        const int vv = P.tet_v[t], base = blink[k] * P.P1;
+                        const int vv = S.tv[t], base = blink[k] * P1;
                         const int i0 = base + (vv & 255);
                         float F[9];
                         {
@@ -296,8 +358,8 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                             // F = sum_m (x_m - x_0) g_m^T
 #pragma unroll
                             for (int j = 0; j < 3; ++j) {
-                                const float g1 = P.tet_g[(3 + j) * P.Tm + t], g2 = P.tet_g[(6 + j) * P.Tm + t],
-                                            g3 = P.tet_g[(9 + j) * P.Tm + t];
+                                const float g1 = S.g[(3 + j) * Tm + t], g2 = S.g[(6 + j) * Tm + t],
+                                            g3 = S.g[(9 + j) * Tm + t];
 #pragma unroll
                                 for (int i = 0; i < 3; ++i) F[3 * i + j] = E[i][0] * g1 + E[i][1] * g2 + E[i][2] * g3;
                             }
@@ -305,7 +367,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         float R[9];
                         const bool ok = polar(F, R);
                         // S = R^T F; strain sym(S) - I in Voigt order (xx yy zz yz xz xy)
-                        float C[6];
+                        float y[6];
                         {
                             float Sm[9];
 #pragma unroll
@@ -313,14 +375,15 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
 #pragma unroll
                                 for (int b = 0; b < 3; ++b)
                                     Sm[3 * a + b] = R[a] * F[b] + R[3 + a] * F[3 + b] + R[6 + a] * F[6 + b];
-                            C[0] = Sm[0] - 1.f, C[1] = Sm[4] - 1.f, C[2] = Sm[8] - 1.f;
-                            C[3] = 0.5f * (Sm[5] + Sm[7]), C[4] = 0.5f * (Sm[2] + Sm[6]), C[5] = 0.5f * (Sm[1] + Sm[3]);
+                            const float ad = S.alpha[t], ao = S.alpha[Tm + t], as = S.alpha[2 * Tm + t];
+                            const float* l = lam[k];
+                            y[0] = (Sm[0] - 1.f) + ad * l[0] + ao * (l[1] + l[2]);
+                            y[1] = (Sm[4] - 1.f) + ad * l[1] + ao * (l[0] + l[2]);
+                            y[2] = (Sm[8] - 1.f) + ad * l[2] + ao * (l[0] + l[1]);
+                            y[3] = 0.5f * (Sm[5] + Sm[7]) + as * l[3];
+                            y[4] = 0.5f * (Sm[2] + Sm[6]) + as * l[4];
+                            y[5] = 0.5f * (Sm[1] + Sm[3]) + as * l[5];
                         }
-                        const float ad = P.tet_alpha[t], ao = P.tet_alpha[P.Tm + t], as = P.tet_alpha[2 * P.Tm + t];
-                        const float* l = lam[k];
-                        float y[6] = {C[0] + ad * l[0] + ao * (l[1] + l[2]), C[1] + ad * l[1] + ao * (l[0] + l[2]),
-                                      C[2] + ad * l[2] + ao * (l[0] + l[1]), C[3] + as * l[3], C[4] + as * l[4],
-                                      C[5] + as * l[5]};
                         float rm = 0.f;
 #pragma unroll
                         for (int q = 0; q < 6; ++q) rm = fmaxf(rm, fabsf(y[q]));
@@ -329,60 +392,61 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
 #pragma unroll
                         for (int q = 1; q < 6; ++q)
 #pragma unroll
-                            for (int c = 0; c < q; ++c) y[q] -= P.tet_ldl[(q * (q - 1) / 2 + c) * P.Tm + t] * y[c];
+                            for (int c = 0; c < q; ++c) y[q] -= S.ldl[(q * (q - 1) / 2 + c) * Tm + t] * y[c];
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) y[q] *= P.tet_ldl[(15 + q) * P.Tm + t];
+                        for (int q = 0; q < 6; ++q) y[q] *= S.ldl[(15 + q) * Tm + t];
 #pragma unroll
                         for (int q = 4; q >= 0; --q)
 #pragma unroll
-                            for (int c = q + 1; c < 6; ++c) y[q] -= P.tet_ldl[(c * (c - 1) / 2 + q) * P.Tm + t] * y[c];
-                        const float sc = -P.tet_scale[t];
+                            for (int c = q + 1; c < 6; ++c) y[q] -= S.ldl[(c * (c - 1) / 2 + q) * Tm + t] * y[c];
+                        const float sc = -S.tsc[t];
+                        const int b = blink[k] * Tm + t;
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) pend[k][q] = sc * y[q];
+                        for (int q = 0; q < 6; ++q) {
+                            y[q] *= sc;
+                            S.pt[q * T + b] = y[q];
+                        }
                         // U = R T, T the increment as a symmetric tensor
-                        const float* e = pend[k];
-                        const float Tn[9] = {e[0], 0.5f * e[5], 0.5f * e[4], 0.5f * e[5], e[1], 0.5f * e[3],
-                                             0.5f * e[4], 0.5f * e[3], e[2]};
-                        const int b = blink[k] * P.Tm + t;
+                        const float Tn[9] = {y[0], 0.5f * y[5], 0.5f * y[4], 0.5f * y[5], y[1], 0.5f * y[3],
+                                             0.5f * y[4], 0.5f * y[3], y[2]};
 #pragma unroll
                         for (int i = 0; i < 3; ++i)
 #pragma unroll
                             for (int j = 0; j < 3; ++j)
                                 S.U[(3 * i + j) * T + b] = R[3 * i] * Tn[j] + R[3 * i + 1] * Tn[3 + j] + R[3 * i + 2] * Tn[6 + j];
                     } else if (bkind[k] == 1) {
-                        const int ij = P.dist_ij[t], base = blink[k] * P.P1;
+                        const int ij = S.dij[t], base = blink[k] * P1;
                         const int i = base + (ij & 0xffff), j = base + (ij >> 16);
-                        const int kind = P.dist_kind[t];
+                        const int kind = S.dk[t];
                         const float* lkp = S.lk + blink[k];
                         const bool on = kind < kChamber0 || (kind == kChamber0 ? lkp[2 * L] > 0.f : lkp[3 * L] > 0.f);
-                        const int b = blink[k] * P.D1 + t;
+                        const int b = blink[k] * D1 + t;
                         pend[k][0] = 0.f;
                         V3 im = mk(0.f, 0.f, 0.f);
                         if (on) {
                             const float press = kind == kChamber0 ? lkp[0] : kind == kChamber1 ? lkp[L] : 0.f;
                             const V3 df = (ld3(S.xp, NP, i) - ld3(S.xp, NP, j)) + (ld3(S.d, NP, i) - ld3(S.d, NP, j));
                             const float len = sqrtf(dot(df, df));
-                            const float rest = P.dist_c[t] * (1.f + press * P.young_inv_pmax);
+                            const float rest = S.dc[t] * (1.f + press * P.young_inv_pmax);
                             const float rr = (len - rest) + P.a_rigid * lam[k][0];
                             res = fmaxf(res, fabsf(rr) * P.Lref_inv);
-                            const float dl =
-                                -P.dist_c[3 * P.D1 + t] * rr / (P.dist_c[P.D1 + t] + P.dist_c[2 * P.D1 + t] + P.a_rigid);
+                            const float dl = -S.dc[3 * D1 + t] * rr / (S.dc[D1 + t] + S.dc[2 * D1 + t] + P.a_rigid);
                             pend[k][0] = dl;
                             im = (dl / len) * df;
                         }
                         st3(S.dd, D, b, im);
                     } else if (bkind[k] == 2) {
-                        const int a = t, i = blink[k] * P.P1 + P.att_p[a];
-                        const int f = blink[k] + (a < P.A1 / 2 ? 0 : 1);
+                        const int a = t, i = blink[k] * P1 + S.ap[a];
+                        const int f = blink[k] + (a < A1 / 2 ? 0 : 1);
                         const float* fr = S.fr + kFr * f;
                         const Q4 q{fr[6], fr[7], fr[8], fr[9]};
-                        const V3 u = qrot(q, mk(P.att_c[a], P.att_c[P.A1 + a], P.att_c[2 * P.A1 + a]));
+                        const V3 u = qrot(q, mk(S.ac[a], S.ac[A1 + a], S.ac[2 * A1 + a]));
                         const V3 gap = (mk(fr[0], fr[1], fr[2]) - ld3(S.xp, NP, i)) + (mk(fr[3], fr[4], fr[5]) - ld3(S.d, NP, i));
                         const V3 rr = gap + u + P.a_rigid * mk(lam[k][0], lam[k][1], lam[k][2]);
                         res = fmaxf(res, snake::amax3(rr) * P.Lref_inv);
                         // K = (w_f + w_p + a) I + [u]x I^-1 [u]x^T; row k of [u]x is -(e_k x u)
                         const bool fixedf = P.fixed0 && f == 0;
-                        const float wdiag = (fixedf ? 0.f : P.frame_w) + P.att_c[3 * P.A1 + a] + P.a_rigid;
+                        const float wdiag = (fixedf ? 0.f : P.frame_w) + S.ac[3 * A1 + a] + P.a_rigid;
                         const V3 cx = mk(0.f, -u.z, u.y), cy = mk(u.z, 0.f, -u.x), cz = mk(-u.y, u.x, 0.f);
                         const V3 z0 = mk(0.f, 0.f, 0.f);
                         const V3 ix = fixedf ? z0 : frame_inv_inertia(P, q, cx);
@@ -390,13 +454,13 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         const V3 iz = fixedf ? z0 : frame_inv_inertia(P, q, cz);
                         const V3 sol = snake::sym3_solve(wdiag + dot(cx, ix), dot(cx, iy), dot(cx, iz), wdiag + dot(cy, iy),
                                                          dot(cy, iz), wdiag + dot(cz, iz), rr);
-                        const int dfr = (f == 0 || f == L) ? P.A1 / 2 : P.A1;
-                        const int dpart = (int)P.att_c[4 * P.A1 + a];
+                        const int dfr = (f == 0 || f == L) ? A1 / 2 : A1;
+                        const int dpart = (int)S.ac[4 * A1 + a];
                         const float sc = -P.relax / (float)(dpart > dfr ? dpart : dfr);
                         pend[k][0] = sc * sol.x;
                         pend[k][1] = sc * sol.y;
                         pend[k][2] = sc * sol.z;
-                        st3(S.da, A, blink[k] * P.A1 + a, mk(pend[k][0], pend[k][1], pend[k][2]));
+                        st3(S.da, A, blink[k] * A1 + a, mk(pend[k][0], pend[k][1], pend[k][2]));
                     }
                 }
                 // the particle's ground contact: normal, then the slip since the
@@ -434,26 +498,33 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                 }
                 // ---- apply: multipliers, then every body's gather in its fixed order
 #pragma unroll
-                for (int k = 0; k < kSlots; ++k)
+                for (int k = 0; k < kSlots; ++k) {
+                    if (bkind[k] == 0) {
+                        const int b = blink[k] * Tm + bidx[k];
 #pragma unroll
-                    for (int q = 0; q < 6; ++q) lam[k][q] += pend[k][q];
+                        for (int q = 0; q < 6; ++q) lam[k][q] += S.pt[q * T + b];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) lam[k][q] += pend[k][q];
+                    }
+                }
                 if (isp) {
                     V3 fsum = mk(0.f, 0.f, 0.f);
                     for (int e = inc0; e < inc1; ++e) {
-                        const int ent = P.inc[e];
+                        const int ent = S.inc[e];
                         const int type = ent >> 28, blk = (ent >> 2) & 0x3ffffff, slot = ent & 3;
                         if (type == kIncTet) {
-                            const int b = pl * P.Tm + blk;
-                            const float g0 = P.tet_g[(3 * slot) * P.Tm + blk], g1 = P.tet_g[(3 * slot + 1) * P.Tm + blk],
-                                        g2 = P.tet_g[(3 * slot + 2) * P.Tm + blk];
+                            const int b = pl * Tm + blk;
+                            const float g0 = S.g[(3 * slot) * Tm + blk], g1 = S.g[(3 * slot + 1) * Tm + blk],
+                                        g2 = S.g[(3 * slot + 2) * Tm + blk];
                             fsum.x += S.U[0 * T + b] * g0 + S.U[1 * T + b] * g1 + S.U[2 * T + b] * g2;
                             fsum.y += S.U[3 * T + b] * g0 + S.U[4 * T + b] * g1 + S.U[5 * T + b] * g2;
                             fsum.z += S.U[6 * T + b] * g0 + S.U[7 * T + b] * g1 + S.U[8 * T + b] * g2;
                         } else if (type == kIncDist) {
-                            const V3 im = ld3(S.dd, D, pl * P.D1 + blk);
+                            const V3 im = ld3(S.dd, D, pl * D1 + blk);
                             fsum = slot == 0 ? fsum + im : fsum - im;
                         } else {
-                            fsum = fsum - ld3(S.da, A, pl * P.A1 + blk);
+                            fsum = fsum - ld3(S.da, A, pl * A1 + blk);
                         }
                     }
                     if (P.ground) {
@@ -471,10 +542,10 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                     for (int side = 0; side < 2; ++side) {
                         const int l = tid - 1 + side;
                         if (l < 0 || l >= L) continue;
-                        const int a0 = side == 0 ? P.A1 / 2 : 0, a1 = side == 0 ? P.A1 : P.A1 / 2;
+                        const int a0 = side == 0 ? A1 / 2 : 0, a1 = side == 0 ? A1 : A1 / 2;
                         for (int a = a0; a < a1; ++a) {
-                            const V3 dl = ld3(S.da, A, l * P.A1 + a);
-                            const V3 u = qrot(q, mk(P.att_c[a], P.att_c[P.A1 + a], P.att_c[2 * P.A1 + a]));
+                            const V3 dl = ld3(S.da, A, l * A1 + a);
+                            const V3 u = qrot(q, mk(S.ac[a], S.ac[A1 + a], S.ac[2 * A1 + a]));
                             F = F + dl;
                             tq = tq + cross(u, dl);
                         }
@@ -527,13 +598,13 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) {
         if (bkind[k] == 0) {
-            const int64_t b = (int64_t)s * T + blink[k] * P.Tm + bidx[k];
+            const int64_t b = (int64_t)s * T + blink[k] * Tm + bidx[k];
 #pragma unroll
             for (int q = 0; q < 6; ++q) P.lam_tet[q * P.NT + b] = lam[k][q];
         } else if (bkind[k] == 1) {
-            P.lam_dist[(int64_t)s * D + blink[k] * P.D1 + bidx[k]] = lam[k][0];
+            P.lam_dist[(int64_t)s * D + blink[k] * D1 + bidx[k]] = lam[k][0];
         } else if (bkind[k] == 2) {
-            const int64_t b = (int64_t)s * A + blink[k] * P.A1 + bidx[k];
+            const int64_t b = (int64_t)s * A + blink[k] * A1 + bidx[k];
 #pragma unroll
             for (int q = 0; q < 3; ++q) P.lam_att[q * P.NA + b] = lam[k][q];
         }
@@ -784,8 +855,8 @@ int validate(const link_desc_t* d, Sz* z)
     const int64_t P = z->L * z->P1, NB = z->L * (z->Tm + z->D1 + z->A1);
     if (P > lk::kThreads) return lfail(LINK_EINVAL, "a snake may hold at most 1024 particles");
     if (NB > (int64_t)lk::kThreads * lk::kSlots) return lfail(LINK_EINVAL, "a snake may hold at most 2048 blocks");
-    z->lds = sizeof(float) * (size_t)(6 * P + 9 * z->L * z->Tm + 3 * z->L * z->D1 + 3 * z->L * z->A1 +
-                                       lk::kFr * (z->L + 1) + 4 * z->L + lk::kWaves);
+    z->lds = sizeof(float) * (size_t)lk::lds_words((int)z->L, (int)z->P1, (int)z->Tm, (int)z->D1, (int)z->A1,
+                                                   (int)(4 * z->Tm + 2 * z->D1 + z->A1));
     if (z->lds > (size_t)lk::kLdsLimit)
         return lfail(LINK_EINVAL, "a snake needs " + std::to_string(z->lds) + " bytes of LDS (limit 163840)");
     if ((int64_t)d->n_snakes * P > ((int64_t)1 << 28)) return lfail(LINK_EINVAL, "too many particles (limit 2^28)");

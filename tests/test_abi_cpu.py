@@ -303,3 +303,79 @@ def test_wheel_batch_size_limit(L):
     assert int(ok.bodies.sum()) <= limit
     rc, b, _ = ws_bytes(L, ok, flags=16)
     assert rc == 0 and b > 0
+
+
+# ---------------------------------------------------------------- full-resolution link (include/link.h)
+
+LINK_HEADER = os.path.join(ROOT, "include", "link.h")
+
+
+def test_link_exports_every_declared_symbol(L):
+    from paper_1904_02833_amd import link as LK
+
+    names = declared_functions(LINK_HEADER, "link_")
+    assert set(names) == set(LK.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", snk.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (link_\w+)$", out, re.M))
+    for n in names:
+        assert n in exported, n
+        assert hasattr(LK.lib(), n)
+
+
+def test_link_fields_and_index_match_the_header():
+    from paper_1904_02833_amd import link as LK
+
+    text = open(LINK_HEADER).read()
+    bits = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define LINK_F_(\w+) \(1u << (\d+)\)", text)}
+    count = int(re.search(r"#define LINK_F_COUNT (\d+)", text).group(1))
+    assert len(LK.FIELDS) == count == len(bits)
+    for k, f in enumerate(LK.FIELDS):
+        assert bits[f[0].upper()] == k, f[0]
+    idx = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define LINK_IDX_(\w+) (\d+)", text)}
+    names = {"DIST_I": "dist_i", "DIST_J": "dist_j", "DIST_KIND": "dist_kind", "DEG_PARTICLE": "degree_particle",
+             "DEG_FRAME": "degree_frame"}
+    for key, name in names.items():
+        assert LK.INDEX.index(name) == idx[key]
+
+
+def test_link_descriptor_layout_matches_c(tmp_path):
+    from paper_1904_02833_amd import link as LK
+
+    fields = [f[0] for f in LK.LinkDesc._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "link.h"', 'int main(void){',
+           'printf("%zu\\n", sizeof(link_desc_t));']
+    src += [f'printf("%zu\\n", offsetof(link_desc_t, {f}));' for f in fields]
+    src += ["return 0;}"]
+    c = tmp_path / "probe.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals[0] == C.sizeof(LK.LinkDesc)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(LK.LinkDesc, f).offset == off, f
+
+
+def test_link_validation_and_workspace(L):
+    """Descriptor checks run on the host: sizes grow with the batch, bad
+    input is refused with a message, nothing touches a device."""
+    from paper_1904_02833_amd import link as LK
+
+    wl = W.make_link(4, n_links=4)
+    b4 = LK.workspace_bytes(wl)
+    b8 = LK.workspace_bytes(W.make_link(8, n_links=4))
+    assert b8 > b4 > 0
+    for over, msg in ((dict(n_links=5), "n_links"), (dict(ring=6), "ring"), (dict(poisson=0.5), "material"),
+                      (dict(relax=0.0), "relax"), (dict(iters=-1), "iters"), (dict(flags=64), "flag"),
+                      (dict(rigid_compliance=-1.0), "rigid_compliance"), (dict(sections=2), "sections")):
+        with pytest.raises(LK.LinkError) as e:
+            LK.workspace_bytes(wl, **over)
+        assert e.value.code == -1 and msg in str(e.value), (over, str(e.value))
+    bad = wl.tets.copy()
+    bad[3, 2] = 999
+    with pytest.raises(LK.LinkError):
+        LK.workspace_bytes(wl, tets=bad)
+    big = W.make_link(1, n_links=4, sections=30)
+    with pytest.raises(LK.LinkError):
+        LK.workspace_bytes(big)
