@@ -51,6 +51,17 @@ int mlp_forward(const float* params, const float* mean_std, const float* x, floa
 int mlp_grad(const float* params, const float* mean_std, const float* x, const float* t, int64_t n,
              float* grad, float* loss, float* scratch, int64_t scratch_floats, void* stream);
 
+/* For callers that cannot allocate (code under graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): mlp_grad without the
+ * scratch argument.  The partial gradient rows live in a fixed device array
+ * of the library sized for at most 4096 samples (3.3 MB per device, held
+ * until the process ends); larger n gives SIM_EINVAL.  Allocates nothing.
+ * Every call on one device uses the same array: calls that overlap on one
+ * device (two streams, two threads) race and must be serialised by the
+ * caller.  Same kernels, same results as mlp_grad. */
+int mlp_grad_noalloc(const float* params, const float* mean_std, const float* x, const float* t, int64_t n,
+                     float* grad, float* loss, void* stream);
+
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected; t >= 1). */
 int mlp_adam(float* params, float* m, float* v, const float* grad, int32_t t, float lr, void* stream);
 

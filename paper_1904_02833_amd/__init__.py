@@ -324,7 +324,7 @@ class Sim:
 # ---------------------------------------------------------------- network
 
 MLP_EXPORTS = ["mlp_param_count", "mlp_train_scratch_floats", "mlp_norm_stats", "mlp_forward",
-               "mlp_grad", "mlp_adam", "mlp_last_error"]
+               "mlp_grad", "mlp_grad_noalloc", "mlp_adam", "mlp_last_error"]
 
 
 def _mlp_lib():
@@ -336,6 +336,7 @@ def _mlp_lib():
         L.mlp_norm_stats.argtypes = [_P, C.c_int64, _P, _P]
         L.mlp_forward.argtypes = [_P, _P, _P, _P, C.c_int64, _P]
         L.mlp_grad.argtypes = [_P, _P, _P, _P, C.c_int64, _P, _P, _P, C.c_int64, _P]
+        L.mlp_grad_noalloc.argtypes = [_P, _P, _P, _P, C.c_int64, _P, _P, _P]
         L.mlp_adam.argtypes = [_P, _P, _P, _P, C.c_int32, C.c_float, _P]
         L.mlp_last_error.restype = C.c_char_p
         L._mlp_declared = True
@@ -396,6 +397,15 @@ class Net:
         loss = self.torch.empty(1, dtype=self.torch.float32, device=x.device)
         _mcheck(L.mlp_grad(_dp(self.params), _dp(self.mean_std), _dp(x), _dp(t), x.shape[0], _dp(g),
                            _dp(loss), _dp(self._scratch), self._scratch.numel(), _stream(x)))
+        return g, loss
+
+    def grad_noalloc(self, x, t):
+        """mlp_grad through the entry point that allocates nothing (fixed
+        library scratch, batches of at most 4096 samples)."""
+        g = self.torch.empty_like(self.params)
+        loss = self.torch.empty(1, dtype=self.torch.float32, device=x.device)
+        _mcheck(_mlp_lib().mlp_grad_noalloc(_dp(self.params), _dp(self.mean_std), _dp(x), _dp(t), x.shape[0],
+                                            _dp(g), _dp(loss), _stream(x)))
         return g, loss
 
     def adam(self, g, lr=1e-3):

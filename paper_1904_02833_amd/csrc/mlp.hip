@@ -13,6 +13,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 
 namespace {
@@ -419,6 +420,58 @@ __global__ void __launch_bounds__(256) k_mlp_stats(const float* __restrict__ x, 
     }
 }
 
+// Fixed scratch of mlp_grad_noalloc: the gradient rows and loss partials of
+// a batch of up to kNoAllocSamples samples (3.3 MB).  Every device the
+// library runs on holds its own copy until the process ends.  In host code
+// the array's name is only a stand-in: its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr int64_t kNoAllocSamples = 4096;
+constexpr int64_t kNoAllocChunks = (kNoAllocSamples + CH - 1) / CH;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) float scratch[kNoAllocChunks * (P_COUNT + 1)];
+
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (nullptr on failure,
+// with the message set)
+float* scratch_on_current_device()
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        mfail(SIM_EDEVICE, std::string("mlp_grad_noalloc: hipGetDevice: ") + hipGetErrorString(e));
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        mfail(SIM_EINVAL, "mlp_grad_noalloc: device index beyond 63");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            mfail(SIM_EDEVICE, std::string("mlp_grad_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<float*>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
+int launch_grad(const float* params, const float* mean_std, const float* x, const float* t, int64_t n,
+                float* grad, float* loss, float* buf, hipStream_t st)
+{
+    const int64_t chunks = (n + CH - 1) / CH;
+    float* gpart = buf;
+    float* lpart = buf + chunks * P_COUNT;
+    hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)chunks), dim3(64), 0, st, params, mean_std, x, t, n, gpart, lpart);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((P_COUNT + 255) / 256), dim3(256), 0, st, gpart, lpart, chunks, n, grad, loss);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SIM_OK : mfail(SIM_EDEVICE, hipGetErrorString(e));
+}
+
 }  // namespace
 
 extern "C" {
@@ -461,13 +514,20 @@ int mlp_grad(const float* params, const float* mean_std, const float* x, const f
     if (scratch_floats < mlp_train_scratch_floats(n)) return mfail(SIM_ENOMEM, "mlp_grad: scratch too small");
     const int64_t chunks = (n + CH - 1) / CH;
     if (chunks > (1 << 30)) return mfail(SIM_EINVAL, "mlp_grad: batch too large");
-    hipStream_t st = (hipStream_t)stream;
-    float* gpart = scratch;
-    float* lpart = scratch + chunks * P_COUNT;
-    hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)chunks), dim3(64), 0, st, params, mean_std, x, t, n, gpart, lpart);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((P_COUNT + 255) / 256), dim3(256), 0, st, gpart, lpart, chunks, n, grad, loss);
-    hipError_t e = hipGetLastError();
-    return e == hipSuccess ? SIM_OK : mfail(SIM_EDEVICE, hipGetErrorString(e));
+    return launch_grad(params, mean_std, x, t, n, grad, loss, scratch, (hipStream_t)stream);
+}
+
+int mlp_grad_noalloc(const float* params, const float* mean_std, const float* x, const float* t, int64_t n,
+                     float* grad, float* loss, void* stream)
+{
+    if (!params || !mean_std || !x || !t || !grad || !loss || n < 1)
+        return mfail(SIM_EINVAL, "mlp_grad_noalloc: bad arguments");
+    if (n > kNoAllocSamples)
+        return mfail(SIM_EINVAL, "mlp_grad_noalloc: batch of " + std::to_string(n) + " samples exceeds the fixed "
+                                 "scratch (at most " + std::to_string(kNoAllocSamples) + ")");
+    float* buf = scratch_on_current_device();
+    if (!buf) return SIM_EDEVICE;
+    return launch_grad(params, mean_std, x, t, n, grad, loss, buf, (hipStream_t)stream);
 }
 
 int mlp_adam(float* params, float* m, float* v, const float* grad, int32_t t, float lr, void* stream)
