@@ -99,6 +99,7 @@ __device__ __forceinline__ bool polar(const float* F, float* R)
 #pragma unroll
     for (int k = 0; k < 9; ++k) R[k] = F[k];
     bool ok = true;
+#pragma unroll 1
     for (int it = 0; it < 12; ++it) {
         const float c00 = R[4] * R[8] - R[5] * R[7], c01 = R[5] * R[6] - R[3] * R[8], c02 = R[3] * R[7] - R[4] * R[6];
         const float c10 = R[2] * R[7] - R[1] * R[8], c11 = R[0] * R[8] - R[2] * R[6], c12 = R[1] * R[6] - R[0] * R[7];
@@ -130,55 +131,48 @@ __device__ __forceinline__ V3 frame_inv_inertia(const Params& P, Q4 q, V3 t)
     return P.I_pe_inv * t + ((P.I_ax_inv - P.I_pe_inv) * dot(a, t)) * a;
 }
 
-// LDS of one snake's workgroup: the per-mesh constants (copied once per
-// launch) and the snake's working arrays
+// LDS of one snake's workgroup.  Per-block and per-particle data are
+// records (array of structures with odd strides, free of bank conflicts for
+// consecutive blocks), so one address per record serves all its fields
+// through the instructions' immediate offsets.
+constexpr int kTR = 39;   // element record: g_0..g_3 (12), L (15), 1/D (6), E/h^2 (3), scale, vertices, pad
+constexpr int kDR = 7;    // distance row: rest, w_i, w_j, scale, i | j << 16, kind, pad
+constexpr int kAR = 7;    // attachment: r (3), w_p, particle degree, particle, pad
+constexpr int kPR = 7;    // particle: start-of-substep position (3), displacement (3), pad
+constexpr int kUR = 9;    // element output R T
+constexpr int kQR = 7;    // element increment awaiting the stop decision (6), pad
+constexpr int kFr = 20;   // frame: xp (3), d (3), q (4), v (3), w (3), q at the substep start (4)
+
 struct Lds {
-    // per-mesh constants
-    float* g;     // [12][Tm] element gradients g_0..g_3
-    float* ldl;   // [21][Tm] unit-lower L (15) and 1/D (6) of K + E/h^2
-    float* alpha; // [3][Tm] E/h^2 normal diagonal, off-diagonal, shear
-    float* tsc;   // [Tm] element scale
-    int* tv;      // [Tm] packed vertices
-    float* dc;    // [4][D1] rest, w_i, w_j, scale
-    int* dij;     // [D1]
-    int* dk;      // [D1]
-    float* ac;    // [5][A1] r (3), w_p, particle degree
-    int* ap;      // [A1]
+    float* tr;    // [Tm][kTR]
+    float* dr;    // [D1][kDR]
+    float* ar;    // [A1][kAR]
     int* ioff;    // [P1 + 1]
     int* inc;     // incidence entries
-    // working arrays
-    float* xp;    // [3][P] particle positions at the substep start
-    float* d;     // [3][P] particle displacement since then
-    float* U;     // [9][T] element outputs R T
-    float* pt;    // [6][T] element increments awaiting the stop decision
-    float* dd;    // [3][D] distance impulses on the first particle
-    float* da;    // [3][A] attachment increments
-    float* fr;    // [kFr][F] frames: xp (3), d (3), q (4), v (3), w (3), q at the substep start (4)
+    float* pr;    // [P][kPR]
+    float* U;     // [T][kUR]
+    float* pt;    // [T][kQR]
+    float* dd;    // [D][3] distance impulses on the first particle
+    float* da;    // [A][3] attachment increments
+    float* fr;    // [F][kFr]
     float* lk;    // [4][L] p0, p1, chamber 0 commanded, chamber 1 commanded
     float* red;   // [kWaves] residual maxima of the waves
 };
-constexpr int kFr = 20;
 
 // words of LDS for a snake (the layout of Lds)
 __host__ __device__ inline int lds_words(int L, int P1, int Tm, int D1, int A1, int n_inc)
 {
     const int P = L * P1, T = L * Tm, D = L * D1, A = L * A1;
-    return 38 * Tm + 6 * D1 + 6 * A1 + (P1 + 1) + n_inc + 6 * P + 15 * T + 3 * D + 3 * A + kFr * (L + 1) + 4 * L +
-           kWaves;
+    return kTR * Tm + kDR * D1 + kAR * A1 + (P1 + 1) + n_inc + kPR * P + (kUR + kQR) * T + 3 * D + 3 * A +
+           kFr * (L + 1) + 4 * L + kWaves;
 }
 
-__device__ __forceinline__ V3 ld3(const float* a, int n, int i) { return mk(a[i], a[n + i], a[2 * n + i]); }
-__device__ __forceinline__ void st3(float* a, int n, int i, V3 v)
+__device__ __forceinline__ V3 ld3(const float* a) { return mk(a[0], a[1], a[2]); }
+__device__ __forceinline__ void st3(float* a, V3 v)
 {
-    a[i] = v.x;
-    a[n + i] = v.y;
-    a[2 * n + i] = v.z;
-}
-
-template <class T>
-__device__ __forceinline__ void copy_lds(T* dst, const T* src, int n)
-{
-    for (int i = threadIdx.x; i < n; i += kThreads) dst[i] = src[i];
+    a[0] = v.x;
+    a[1] = v.y;
+    a[2] = v.z;
 }
 
 __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
@@ -192,40 +186,47 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
     Lds S;
     {
         float* w = smem;
-        S.g = w, w += 12 * Tm;
-        S.ldl = w, w += 21 * Tm;
-        S.alpha = w, w += 3 * Tm;
-        S.tsc = w, w += Tm;
-        S.tv = reinterpret_cast<int*>(w), w += Tm;
-        S.dc = w, w += 4 * D1;
-        S.dij = reinterpret_cast<int*>(w), w += D1;
-        S.dk = reinterpret_cast<int*>(w), w += D1;
-        S.ac = w, w += 5 * A1;
-        S.ap = reinterpret_cast<int*>(w), w += A1;
+        S.tr = w, w += kTR * Tm;
+        S.dr = w, w += kDR * D1;
+        S.ar = w, w += kAR * A1;
         S.ioff = reinterpret_cast<int*>(w), w += P1 + 1;
         S.inc = reinterpret_cast<int*>(w), w += n_inc;
-        S.xp = w, w += 3 * NP;
-        S.d = w, w += 3 * NP;
-        S.U = w, w += 9 * T;
-        S.pt = w, w += 6 * T;
+        S.pr = w, w += kPR * NP;
+        S.U = w, w += kUR * T;
+        S.pt = w, w += kQR * T;
         S.dd = w, w += 3 * D;
         S.da = w, w += 3 * A;
         S.fr = w, w += kFr * NF;
         S.lk = w, w += 4 * L;
         S.red = w;
     }
-    copy_lds(S.g, P.tet_g, 12 * Tm);
-    copy_lds(S.ldl, P.tet_ldl, 21 * Tm);
-    copy_lds(S.alpha, P.tet_alpha, 3 * Tm);
-    copy_lds(S.tsc, P.tet_scale, Tm);
-    copy_lds(S.tv, P.tet_v, Tm);
-    copy_lds(S.dc, P.dist_c, 4 * D1);
-    copy_lds(S.dij, P.dist_ij, D1);
-    copy_lds(S.dk, P.dist_kind, D1);
-    copy_lds(S.ac, P.att_c, 5 * A1);
-    copy_lds(S.ap, P.att_p, A1);
-    copy_lds(S.ioff, P.inc_off, P1 + 1);
-    copy_lds(S.inc, P.inc, n_inc);
+    // per-mesh constants into records
+    for (int i = tid; i < kTR * Tm; i += kThreads) {
+        const int t = i / kTR, f = i - t * kTR;
+        float val = 0.f;
+        if (f < 12)
+            val = P.tet_g[f * Tm + t];
+        else if (f < 33)
+            val = P.tet_ldl[(f - 12) * Tm + t];
+        else if (f < 36)
+            val = P.tet_alpha[(f - 33) * Tm + t];
+        else if (f == 36)
+            val = P.tet_scale[t];
+        else if (f == 37)
+            val = __int_as_float(P.tet_v[t]);
+        S.tr[i] = val;
+    }
+    for (int i = tid; i < kDR * D1; i += kThreads) {
+        const int e = i / kDR, f = i - e * kDR;
+        S.dr[i] = f < 4 ? P.dist_c[f * D1 + e] : f == 4 ? __int_as_float(P.dist_ij[e])
+                                                : f == 5 ? __int_as_float(P.dist_kind[e]) : 0.f;
+    }
+    for (int i = tid; i < kAR * A1; i += kThreads) {
+        const int e = i / kAR, f = i - e * kAR;
+        S.ar[i] = f < 5 ? P.att_c[f * A1 + e] : f == 5 ? __int_as_float(P.att_p[e]) : 0.f;
+    }
+    for (int i = tid; i < P1 + 1; i += kThreads) S.ioff[i] = P.inc_off[i];
+    for (int i = tid; i < n_inc; i += kThreads) S.inc[i] = P.inc[i];
 
     const int64_t gp = (int64_t)s * NP + tid;     // particle
     const int64_t gf = (int64_t)s * NF + tid;     // frame
@@ -247,6 +248,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
         pmass = P.part_m[pk];
         cscale = P.relax / (float)P.part_deg[pk];
     }
+    float* const my = S.pr + kPR * tid;   // this thread's particle record
     const float mu = P.mu[s];
     // frame and link state in LDS
     if (isf) {
@@ -303,8 +305,8 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                 v.z -= P.h * P.g;
                 d = P.h * v;
                 lc = mk(0.f, 0.f, 0.f);
-                st3(S.xp, NP, tid, x);
-                st3(S.d, NP, tid, d);
+                st3(my, x);
+                st3(my + 3, d);
             }
             if (isf) {
                 float* f = S.fr + kFr * tid;
@@ -342,27 +344,24 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                 for (int k = 0; k < kSlots; ++k) {
                     const int t = bidx[k];
                     if (bkind[k] == 0) {
-                        const int vv = S.tv[t], base = blink[k] * P1;
-                        const int i0 = base + (vv & 255);
+                        const float* c = S.tr + kTR * t;
+                        const int vv = __float_as_int(c[37]), base = blink[k] * P1;
+                        const float* p0 = S.pr + kPR * (base + (vv & 255));
                         float F[9];
                         {
                             float E[3][3];   // edges x_m - x_0, m = 1..3, as columns
 #pragma unroll
                             for (int m = 1; m < 4; ++m) {
-                                const int im = base + ((vv >> (8 * m)) & 255);
+                                const float* pm = S.pr + kPR * (base + ((vv >> (8 * m)) & 255));
 #pragma unroll
-                                for (int c = 0; c < 3; ++c)
-                                    E[c][m - 1] = (S.xp[c * NP + im] - S.xp[c * NP + i0]) +
-                                                  (S.d[c * NP + im] - S.d[c * NP + i0]);
+                                for (int q = 0; q < 3; ++q) E[q][m - 1] = (pm[q] - p0[q]) + (pm[3 + q] - p0[3 + q]);
                             }
                             // F = sum_m (x_m - x_0) g_m^T
 #pragma unroll
-                            for (int j = 0; j < 3; ++j) {
-                                const float g1 = S.g[(3 + j) * Tm + t], g2 = S.g[(6 + j) * Tm + t],
-                                            g3 = S.g[(9 + j) * Tm + t];
+                            for (int j = 0; j < 3; ++j)
 #pragma unroll
-                                for (int i = 0; i < 3; ++i) F[3 * i + j] = E[i][0] * g1 + E[i][1] * g2 + E[i][2] * g3;
-                            }
+                                for (int i = 0; i < 3; ++i)
+                                    F[3 * i + j] = E[i][0] * c[3 + j] + E[i][1] * c[6 + j] + E[i][2] * c[9 + j];
                         }
                         float R[9];
                         const bool ok = polar(F, R);
@@ -375,7 +374,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
 #pragma unroll
                                 for (int b = 0; b < 3; ++b)
                                     Sm[3 * a + b] = R[a] * F[b] + R[3 + a] * F[3 + b] + R[6 + a] * F[6 + b];
-                            const float ad = S.alpha[t], ao = S.alpha[Tm + t], as = S.alpha[2 * Tm + t];
+                            const float ad = c[33], ao = c[34], as = c[35];
                             const float* l = lam[k];
                             y[0] = (Sm[0] - 1.f) + ad * l[0] + ao * (l[1] + l[2]);
                             y[1] = (Sm[4] - 1.f) + ad * l[1] + ao * (l[0] + l[2]);
@@ -392,61 +391,67 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
 #pragma unroll
                         for (int q = 1; q < 6; ++q)
 #pragma unroll
-                            for (int c = 0; c < q; ++c) y[q] -= S.ldl[(q * (q - 1) / 2 + c) * Tm + t] * y[c];
+                            for (int cc = 0; cc < q; ++cc) y[q] -= c[12 + q * (q - 1) / 2 + cc] * y[cc];
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) y[q] *= S.ldl[(15 + q) * Tm + t];
+                        for (int q = 0; q < 6; ++q) y[q] *= c[27 + q];
 #pragma unroll
                         for (int q = 4; q >= 0; --q)
 #pragma unroll
-                            for (int c = q + 1; c < 6; ++c) y[q] -= S.ldl[(c * (c - 1) / 2 + q) * Tm + t] * y[c];
-                        const float sc = -S.tsc[t];
+                            for (int cc = q + 1; cc < 6; ++cc) y[q] -= c[12 + cc * (cc - 1) / 2 + q] * y[cc];
+                        const float sc = -c[36];
                         const int b = blink[k] * Tm + t;
+                        float* qp = S.pt + kQR * b;
 #pragma unroll
                         for (int q = 0; q < 6; ++q) {
                             y[q] *= sc;
-                            S.pt[q * T + b] = y[q];
+                            qp[q] = y[q];
                         }
                         // U = R T, T the increment as a symmetric tensor
                         const float Tn[9] = {y[0], 0.5f * y[5], 0.5f * y[4], 0.5f * y[5], y[1], 0.5f * y[3],
                                              0.5f * y[4], 0.5f * y[3], y[2]};
+                        float* up = S.U + kUR * b;
 #pragma unroll
                         for (int i = 0; i < 3; ++i)
 #pragma unroll
                             for (int j = 0; j < 3; ++j)
-                                S.U[(3 * i + j) * T + b] = R[3 * i] * Tn[j] + R[3 * i + 1] * Tn[3 + j] + R[3 * i + 2] * Tn[6 + j];
+                                up[3 * i + j] = R[3 * i] * Tn[j] + R[3 * i + 1] * Tn[3 + j] + R[3 * i + 2] * Tn[6 + j];
                     } else if (bkind[k] == 1) {
-                        const int ij = S.dij[t], base = blink[k] * P1;
-                        const int i = base + (ij & 0xffff), j = base + (ij >> 16);
-                        const int kind = S.dk[t];
+                        const float* c = S.dr + kDR * t;
+                        const int ij = __float_as_int(c[4]), base = blink[k] * P1;
+                        const float* pi = S.pr + kPR * (base + (ij & 0xffff));
+                        const float* pj = S.pr + kPR * (base + (ij >> 16));
+                        const int kind = __float_as_int(c[5]);
                         const float* lkp = S.lk + blink[k];
                         const bool on = kind < kChamber0 || (kind == kChamber0 ? lkp[2 * L] > 0.f : lkp[3 * L] > 0.f);
-                        const int b = blink[k] * D1 + t;
+                        float* out = S.dd + 3 * (blink[k] * D1 + t);
                         pend[k][0] = 0.f;
                         V3 im = mk(0.f, 0.f, 0.f);
                         if (on) {
                             const float press = kind == kChamber0 ? lkp[0] : kind == kChamber1 ? lkp[L] : 0.f;
-                            const V3 df = (ld3(S.xp, NP, i) - ld3(S.xp, NP, j)) + (ld3(S.d, NP, i) - ld3(S.d, NP, j));
+                            const V3 df = (ld3(pi) - ld3(pj)) + (ld3(pi + 3) - ld3(pj + 3));
                             const float len = sqrtf(dot(df, df));
-                            const float rest = S.dc[t] * (1.f + press * P.young_inv_pmax);
+                            const float rest = c[0] * (1.f + press * P.young_inv_pmax);
                             const float rr = (len - rest) + P.a_rigid * lam[k][0];
                             res = fmaxf(res, fabsf(rr) * P.Lref_inv);
-                            const float dl = -S.dc[3 * D1 + t] * rr / (S.dc[D1 + t] + S.dc[2 * D1 + t] + P.a_rigid);
+                            const float dl = -c[3] * rr / (c[1] + c[2] + P.a_rigid);
                             pend[k][0] = dl;
                             im = (dl / len) * df;
                         }
-                        st3(S.dd, D, b, im);
+                        st3(out, im);
                     } else if (bkind[k] == 2) {
-                        const int a = t, i = blink[k] * P1 + S.ap[a];
+                        const float* c = S.ar + kAR * t;
+                        const int a = t;
+                        const float* pi = S.pr + kPR * (blink[k] * P1 + __float_as_int(c[5]));
                         const int f = blink[k] + (a < A1 / 2 ? 0 : 1);
                         const float* fr = S.fr + kFr * f;
                         const Q4 q{fr[6], fr[7], fr[8], fr[9]};
-                        const V3 u = qrot(q, mk(S.ac[a], S.ac[A1 + a], S.ac[2 * A1 + a]));
-                        const V3 gap = (mk(fr[0], fr[1], fr[2]) - ld3(S.xp, NP, i)) + (mk(fr[3], fr[4], fr[5]) - ld3(S.d, NP, i));
+                        const V3 u = qrot(q, ld3(c));
+                        const V3 gap = (ld3(fr) - ld3(pi)) + (ld3(fr + 3) - ld3(pi + 3));
                         const V3 rr = gap + u + P.a_rigid * mk(lam[k][0], lam[k][1], lam[k][2]);
                         res = fmaxf(res, snake::amax3(rr) * P.Lref_inv);
                         // K = (w_f + w_p + a) I + [u]x I^-1 [u]x^T; row k of [u]x is -(e_k x u)
                         const bool fixedf = P.fixed0 && f == 0;
-                        const float wdiag = (fixedf ? 0.f : P.frame_w) + S.ac[3 * A1 + a] + P.a_rigid;
+                        const float wdiag = (fixedf ? 0.f : P.frame_w) + c[3] + P.a_rigid;
                         const V3 cx = mk(0.f, -u.z, u.y), cy = mk(u.z, 0.f, -u.x), cz = mk(-u.y, u.x, 0.f);
                         const V3 z0 = mk(0.f, 0.f, 0.f);
                         const V3 ix = fixedf ? z0 : frame_inv_inertia(P, q, cx);
@@ -455,12 +460,12 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         const V3 sol = snake::sym3_solve(wdiag + dot(cx, ix), dot(cx, iy), dot(cx, iz), wdiag + dot(cy, iy),
                                                          dot(cy, iz), wdiag + dot(cz, iz), rr);
                         const int dfr = (f == 0 || f == L) ? A1 / 2 : A1;
-                        const int dpart = (int)S.ac[4 * A1 + a];
+                        const int dpart = (int)c[4];
                         const float sc = -P.relax / (float)(dpart > dfr ? dpart : dfr);
                         pend[k][0] = sc * sol.x;
                         pend[k][1] = sc * sol.y;
                         pend[k][2] = sc * sol.z;
-                        st3(S.da, A, blink[k] * A1 + a, mk(pend[k][0], pend[k][1], pend[k][2]));
+                        st3(S.da + 3 * (blink[k] * A1 + a), mk(pend[k][0], pend[k][1], pend[k][2]));
                     }
                 }
                 // the particle's ground contact: normal, then the slip since the
@@ -500,9 +505,9 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
 #pragma unroll
                 for (int k = 0; k < kSlots; ++k) {
                     if (bkind[k] == 0) {
-                        const int b = blink[k] * Tm + bidx[k];
+                        const float* qp = S.pt + kQR * (blink[k] * Tm + bidx[k]);
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) lam[k][q] += S.pt[q * T + b];
+                        for (int q = 0; q < 6; ++q) lam[k][q] += qp[q];
                     } else {
 #pragma unroll
                         for (int q = 0; q < 3; ++q) lam[k][q] += pend[k][q];
@@ -514,17 +519,17 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         const int ent = S.inc[e];
                         const int type = ent >> 28, blk = (ent >> 2) & 0x3ffffff, slot = ent & 3;
                         if (type == kIncTet) {
-                            const int b = pl * Tm + blk;
-                            const float g0 = S.g[(3 * slot) * Tm + blk], g1 = S.g[(3 * slot + 1) * Tm + blk],
-                                        g2 = S.g[(3 * slot + 2) * Tm + blk];
-                            fsum.x += S.U[0 * T + b] * g0 + S.U[1 * T + b] * g1 + S.U[2 * T + b] * g2;
-                            fsum.y += S.U[3 * T + b] * g0 + S.U[4 * T + b] * g1 + S.U[5 * T + b] * g2;
-                            fsum.z += S.U[6 * T + b] * g0 + S.U[7 * T + b] * g1 + S.U[8 * T + b] * g2;
+                            const float* gm = S.tr + kTR * blk + 3 * slot;
+                            const float* up = S.U + kUR * (pl * Tm + blk);
+                            const float g0 = gm[0], g1 = gm[1], g2 = gm[2];
+                            fsum.x += up[0] * g0 + up[1] * g1 + up[2] * g2;
+                            fsum.y += up[3] * g0 + up[4] * g1 + up[5] * g2;
+                            fsum.z += up[6] * g0 + up[7] * g1 + up[8] * g2;
                         } else if (type == kIncDist) {
-                            const V3 im = ld3(S.dd, D, pl * D1 + blk);
+                            const V3 im = ld3(S.dd + 3 * (pl * D1 + blk));
                             fsum = slot == 0 ? fsum + im : fsum - im;
                         } else {
-                            fsum = fsum - ld3(S.da, A, pl * A1 + blk);
+                            fsum = fsum - ld3(S.da + 3 * (pl * A1 + blk));
                         }
                     }
                     if (P.ground) {
@@ -532,7 +537,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         fsum = fsum + mk(dlc.y, dlc.z, dlc.x);
                     }
                     d = d + wp * fsum;
-                    st3(S.d, NP, tid, d);
+                    st3(my + 3, d);
                 }
                 if (isf && !ffix) {
                     float* f = S.fr + kFr * tid;
@@ -544,8 +549,8 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         if (l < 0 || l >= L) continue;
                         const int a0 = side == 0 ? A1 / 2 : 0, a1 = side == 0 ? A1 : A1 / 2;
                         for (int a = a0; a < a1; ++a) {
-                            const V3 dl = ld3(S.da, A, l * A1 + a);
-                            const V3 u = qrot(q, mk(S.ac[a], S.ac[A1 + a], S.ac[2 * A1 + a]));
+                            const V3 dl = ld3(S.da + 3 * (l * A1 + a));
+                            const V3 u = qrot(q, ld3(S.ar + kAR * a));
                             F = F + dl;
                             tq = tq + cross(u, dl);
                         }
