@@ -100,6 +100,8 @@ class State(C.Structure):
 def _declare(L):
     bp, sp = C.POINTER(Batch), C.POINTER(State)
     L.orc_offsets.argtypes = [bp, _P, _P, _P, _P]
+    L.orc_set_friction_trial.argtypes = [C.c_double]
+    L.orc_set_friction_trial.restype = C.c_double
     L.orc_init_state.argtypes = [bp, sp]
     L.orc_commands.argtypes = [bp, sp, C.c_int32, C.c_int32]
     L.orc_run.argtypes = [bp, sp, C.c_int32, C.c_int32, C.c_int32]

@@ -1023,10 +1023,22 @@ static int jacobi(const orc_batch* b, const snake_ctx* c, scratch_t* W, double* 
  * with respect to the constraint value counts as zero. */
 #define NEWTON_EPS 1e-6
 /* Scale of the friction natural map's trial, in units of the body mass:
- * every positive scale has the same roots; this one keeps the Newton
- * iterates of the workloads' contacts from cycling between stick and slip
- * (a measured choice). */
-#define FRICTION_TRIAL 10.0
+ * every positive scale has the same roots, but the scale decides how the
+ * semismooth iterates behave.  One body mass lets the contacts of the short
+ * batch cycle between stick and slip at a few iterations; large scales make
+ * full solves cycle; ten masses is the measured compromise (swept in the
+ * tests). */
+#define FRICTION_TRIAL_DEFAULT 10.0
+static double FRICTION_TRIAL = FRICTION_TRIAL_DEFAULT;
+
+/* Set the friction trial scale (the reading's sweep); returns the previous
+ * value.  Not thread-safe against a running solve. */
+double orc_set_friction_trial(double scale)
+{
+    double old = FRICTION_TRIAL;
+    FRICTION_TRIAL = scale;
+    return old;
+}
 
 /* Rows of contact block k at multipliers l (normal, tangential x, y) for
  * eq. schur_system.  Each row is a semismooth Newton step on F(C, l) = 0,

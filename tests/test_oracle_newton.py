@@ -180,3 +180,59 @@ def test_newton_keep_best_ends_at_the_best_iterate():
         for f in ("x", "q", "lam_j", "lam_c"):
             assert np.array_equal(d[f], ref[f]), (s, f)
     assert cycled > 0   # some snake's last iterate is not its best
+
+
+def test_friction_trial_scale_sweep():
+    """Reading of the friction natural map's trial scale m' (the paper names
+    no reformulation for the cone).  Every positive m' has the same roots,
+    but the scale decides how the semismooth iterates behave, and the two
+    ends pull apart.  Measured (largest-residual medians / maxima after
+    4 x 20 Newton x PCR iterations on 64 snakes six steps in; full solves:
+    snakes of the linearised problem below reaching 1e-12 in 60 Newton
+    iterations):
+
+        m'      short        uniform      uneven       full solves
+        1       0.37 / 6.1   0.13 / 0.61  0.20 / 0.66  7 / 8
+        3       0.019 / 1.1  0.056 / 0.32 0.085 / 0.21 6 / 8
+        10      0.011 / 1.5  0.055 / 0.42 0.061 / 0.16 6 / 8
+        30      0.0065/ 0.12 0.055 / 0.16 0.055 / 0.16 3 / 8
+        100     0.0061/ 0.085 0.055/ 0.17 0.055 / 0.12 1 / 8
+        1000    0.0070/ 0.045 0.055/ 0.30 0.056 / 0.12 0 / 8
+
+    One body mass leaves the short snakes' contacts cycling at the paper's
+    budget; from thirty masses up the full solves cycle instead.  Ten masses
+    (the oracle's and the kernel's value) is the compromise; the test holds
+    the three corners of that trade."""
+    from parity import load_oracle, rounded_state
+
+    L = oracle.lib()
+    assert L.orc_set_friction_trial(10.0) == 10.0      # the default
+    try:
+        wl8 = W.make("short", n_snakes=8)
+        kw = dict(substeps=1, flags=wl8.flags | oracle.FLAG_LINEARISED)
+        lin = oracle.Oracle(wl8, **kw)
+        lin.run(20)
+        st8 = {k: getattr(lin, k).copy() for k in ("x", "q", "v", "w", "p", "cmd", "lam_j", "lam_c", "step")}
+        wl = W.make("short", n_snakes=64)
+        base = oracle.Oracle(wl)
+        base.run(6, threads=8)
+        base.commands()
+        st = rounded_state(base)
+        full, budget = {}, {}
+        for scale in (1.0, 10.0, 100.0):
+            L.orc_set_friction_trial(scale)
+            n = load(newton(wl8, newton_iters=60, pcr_iters=300, tol=0, **kw), st8)
+            n.run(1)
+            full[scale] = int((n.residual < 1e-12).sum())
+            o = oracle.Oracle(wl, solver=oracle.SOLVER_NEWTON, newton_iters=4, pcr_iters=20, tol=0.0,
+                              controller=W.CTRL_EXTERNAL)
+            load_oracle(o, st)
+            o.step[:] = base.step
+            o.run(1, threads=8)
+            budget[scale] = (float(np.median(o.residual)), float(o.residual.max()))
+        print("\n[friction trial] full solves", full, "budget median/max", budget)
+        assert budget[1.0][0] > 0.1 and budget[1.0][1] > 1.0        # cycles at the budget
+        assert full[10.0] >= 6 and budget[10.0][0] < 0.05            # the compromise
+        assert full[100.0] <= 2                                      # full solves cycle
+    finally:
+        L.orc_set_friction_trial(10.0)
