@@ -26,7 +26,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "snake_oracle.c")
 SRCS = [SRC, os.path.join(HERE, "mlp_oracle.c"), os.path.join(HERE, "fem_oracle.c"),
         os.path.join(HERE, "link_oracle.c")]
-LIB = os.path.join(HERE, "liboracle.so")
+# SNAKE_SANITIZE=1 selects the sanitizer build (AddressSanitizer and
+# UndefinedBehaviorSanitizer with the shared runtime, which the process must
+# preload), made by tests/run_sanitizers.py.  CPU only.
+SANITIZE = os.environ.get("SNAKE_SANITIZE") == "1"
+LIB = os.path.join(HERE, "liboracle_san.so" if SANITIZE else "liboracle.so")
 
 FLAG_FIXED_ROOT = 1
 FLAG_NO_GROUND = 2
@@ -40,11 +44,14 @@ _lock = threading.Lock()
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no fast-math)."""
+def build(force: bool = True, cc=("gcc",)) -> str:
+    """Compile the oracle (gcc -O2, no fast-math; ``cc`` replaces the
+    compiler and adds flags, as the sanitizer build does)."""
     if force or _stale():
+        if SANITIZE and tuple(cc) == ("gcc",):
+            raise RuntimeError("the sanitizer build of the oracle is made by tests/run_sanitizers.py")
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, *SRCS, "-lm"])
+        subprocess.check_call([*cc, "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, *SRCS, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsnake.so")
+# SNAKE_SANITIZE=1 loads the host-sanitized build (CPU checks of the host
+# paths only; its process preloads the sanitizer runtime)
+LIB_PATH = os.path.join(HERE, "libsnake_san.so" if os.environ.get("SNAKE_SANITIZE") == "1" else "libsnake.so")
 
 SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE = 0, -1, -2, -3, -4
 MEM_HOST, MEM_DEVICE = 0, 1

@@ -10,6 +10,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsnake.so")
 SOURCES = ["step.hip", "newton.hip", "gs.hip", "carriage.hip", "index.hip", "api.hip", "mlp.hip", "link.hip"]
+# host-sanitized variant for CPU checks of the host paths (descriptor
+# validation, workspace sizing, tile planning); its flags are the caller's
+SAN_LIB = os.path.join(HERE, "libsnake_san.so")
 
 # Packed FP32 instructions are kept out of the generated code; contraction
 # follows source expressions only, so one device function compiles to the
@@ -21,18 +24,20 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, extra_flags=()) -> str:
+    """Compile every source into ``out``; ``extra_flags`` follow the standard
+    ones (a later -O wins)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-o", tmp,
+    tmp = out + ".tmp"
+    cmd = [hipcc, *HIPCC_FLAGS, *extra_flags, "-I", INCLUDE, "-I", CSRC, "-o", tmp,
            *[os.path.join(CSRC, s) for s in SOURCES]]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stderr)
     if verbose:
         print(" ".join(cmd))
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
