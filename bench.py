@@ -115,6 +115,8 @@ def parse():
     ap.add_argument("--converged-cap", type=int, default=400000)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
     ap.add_argument("--learned-steps", type=int, default=20)
+    ap.add_argument("--no-learned-converging", action="store_true",
+                    help="skip the learned-start comparison on the converging short-snake batch")
     ap.add_argument("--no-newton", action="store_true", help="skip the Newton solver comparison")
     ap.add_argument("--wheels", action="store_true",
                     help="the wheeled carriage (two wheels per segment on hinge joints), "
@@ -159,7 +161,8 @@ def learned_comparison(n_steps):
     out = {"fallback_k": FALLBACK_K,
            "train": {"rows": int(ds.features.shape[0]), "seconds": t_train, "loss_by_epoch": losses,
                      "teacher": "tolerance 1e-6 (at most 1500 iterations), first substep of states "
-                                "visited by the plain solver"}}
+                                "visited by the plain solver",
+                     "step": training_step_rate(net, ds)}}
     for name in ("plain", "learned"):
         sim = (snk.Sim(ev, autotune=1) if name == "plain"
                else warmstart.learned_sim(ev, net, autotune=1, mlp_fallback_k=FALLBACK_K))
@@ -188,6 +191,41 @@ def learned_comparison(n_steps):
     out["gain"] = {"fewer_iterations": out["learned"]["mean_iters_per_substep"] < out["plain"]["mean_iters_per_substep"],
                    "more_snake_steps_per_s": out["learned"]["snake_steps_per_s"] > out["plain"]["snake_steps_per_s"]}
     return out
+
+
+# network arithmetic per sample: forward 2 (32*64 + 64*64 + 64*3) flop;
+# backward the weight gradients of all three layers and the input gradients
+# of layers 3 and 2, 2 (32*64 + 2*64*64 + 2*64*3) flop
+NET_FWD_FLOP = 2 * (32 * 64 + 64 * 64 + 64 * 3)
+NET_BWD_FLOP = 2 * (32 * 64 + 2 * 64 * 64 + 2 * 64 * 3)
+PEAK_BF16 = 2.5e15        # MI355X dense BF16 MFMA (published)
+
+
+def training_step_rate(net, ds, batch=4096, n=50):
+    """One training step of the network (gradient of a 4096-sample batch,
+    the ordered reduction of its chunk rows, Adam) timed with HIP events on
+    the stream the library launches on, against the BF16 MFMA peak."""
+    import torch
+
+    x, t = ds.features[:batch], ds.targets[:batch]
+    lr = 0.0   # parameters unchanged: the timed steps leave the trained network as it is
+    for _ in range(5):
+        g, _ = net.grad(x, t)
+        net.adam(g, lr=lr)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(n):
+        g, _ = net.grad(x, t)
+        net.adam(g, lr=lr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / n
+    flop = x.shape[0] * (NET_FWD_FLOP + NET_BWD_FLOP)
+    return {"batch": int(x.shape[0]), "us_per_step": us, "samples_per_s": x.shape[0] / (us * 1e-6),
+            "roofline": {"bound": "mfma", "achieved": flop / (us * 1e-6) / 1e12, "peak": PEAK_BF16 / 1e12,
+                         "unit": "TFLOP/s", "frac": flop / (us * 1e-6) / PEAK_BF16,
+                         "flop_per_sample": NET_FWD_FLOP + NET_BWD_FLOP}}
 
 
 def learned_converging(n_steps=6):
@@ -709,8 +747,9 @@ def main():
     if not args.no_learned:
         out["learned_warm_start"] = learned_comparison(args.learned_steps)
         print("[bench] learned comparison done", file=sys.stderr, flush=True)
-        out["learned_warm_start_converging"] = learned_converging()
-        print("[bench] learned converging done", file=sys.stderr, flush=True)
+        if not args.no_learned_converging:
+            out["learned_warm_start_converging"] = learned_converging()
+            print("[bench] learned converging done", file=sys.stderr, flush=True)
     if not args.no_newton:
         out["newton_pcr"] = newton_comparison(wl)
         print("[bench] solver comparison done", file=sys.stderr, flush=True)

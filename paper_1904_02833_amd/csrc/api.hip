@@ -178,7 +178,6 @@ struct Views {
     WParams wp;
     int* newton_list;       // [n] snakes by lane class (Newton and Gauss-Seidel solvers)
     double* comp_d;         // [4][n] compliances / h^2 and mu in double
-    float* feat;            // [2J][32] network inputs (learned warm start)
     float* mlp_y;           // [2J][3] network outputs
     float* mlp_params;      // [6467]
     float* mlp_ms;          // [64]
@@ -245,7 +244,6 @@ size_t carve(const Sizes& z, char* base, Views* v)
     ip.color_scratch = c.take<int>(N);
     k.q_pred = c.take<float>(4 * N);
     k.probe = z.mlp ? c.take<float>(16 * N) : nullptr;
-    v->feat = z.mlp ? c.take<float>(64 * J) : nullptr;
     v->mlp_y = z.mlp ? c.take<float>(6 * J) : nullptr;
     v->mlp_params = z.mlp ? c.take<float>(8192) : nullptr;
     v->mlp_ms = z.mlp ? c.take<float>(64) : nullptr;
@@ -413,14 +411,17 @@ int split_substep(sim* s, hipStream_t st, int sub, float* feat, float* tgt)
     const KParams& k = s->v.kp;
     int rc = tiles(s, st, 1, kPhasePre, sub);
     if (rc) return rc;
-    float* f = feat ? feat : s->v.feat;
-    if (f) {
-        hipError_t e = launch_features(k, f, st);
+    if (feat) {
+        // recording: the inputs go to the caller's rows, the network reads them there
+        hipError_t e = launch_features(k, feat, st);
         if (e != hipSuccess) return hip_fail(e, "features");
-    }
-    if (s->z.mlp) {
-        rc = mlp_forward(s->v.mlp_params, s->v.mlp_ms, f, s->v.mlp_y, 2 * (int64_t)s->z.J, st);
-        if (rc) return fail(rc, std::string("network: ") + mlp_last_error());
+        if (s->z.mlp) {
+            rc = mlp_forward(s->v.mlp_params, s->v.mlp_ms, feat, s->v.mlp_y, 2 * (int64_t)s->z.J, st);
+            if (rc) return fail(rc, std::string("network: ") + mlp_last_error());
+        }
+    } else if (s->z.mlp) {
+        hipError_t e = launch_warm_net(k, s->v.mlp_params, s->v.mlp_ms, s->v.mlp_y, st);
+        if (e != hipSuccess) return hip_fail(e, "network");
     }
     rc = tiles(s, st, 1, kPhaseSolve, sub);
     if (rc) return rc;

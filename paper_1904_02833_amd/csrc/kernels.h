@@ -117,6 +117,10 @@ hipError_t launch_gs(const KParams& P, const int* block_off, const int* blk_colo
                      const int* off, int n_steps, hipStream_t stream);
 hipError_t launch_features(const KParams& P, float* feat, hipStream_t stream);
 hipError_t launch_targets(const KParams& P, float* tgt, hipStream_t stream);
+// network outputs of the learned start from the predicted state, inputs
+// computed in the kernel (mlp.hip)
+hipError_t launch_warm_net(const KParams& P, const float* params, const float* mean_std, float* y,
+                           hipStream_t stream);
 hipError_t launch_index(const IParams& P, hipStream_t stream);
 hipError_t launch_init_state(const KParams& P, hipStream_t stream);
 hipError_t launch_set_cmd(float* dst, const float* src, int n, hipStream_t stream);

@@ -1,14 +1,19 @@
 // Warm-start network kernels (gfx950): a 32 -> 64 -> 64 -> 3 perceptron with
-// exact-erf GELU, evaluated and trained with BF16 MFMA (v_mfma_f32_16x16x32_bf16)
-// accumulating in FP32.
+// GELU (mlp_device.h), evaluated and trained with BF16 MFMA
+// (v_mfma_f32_16x16x32_bf16) accumulating in FP32.
 //
-// Training: one wave takes a chunk of 32 samples.  Weights, activations and
-// pre-activations of the chunk sit in LDS; every product is a small GEMM
-// computed tile by tile (16 x 16 output tiles, K in steps of 32).  Operands
-// are rounded to BF16 (round to nearest even) when they enter an MFMA; biases,
+// Training: a workgroup of four waves takes a chunk of 32 samples.  Weights,
+// activations and pre-activations of the chunk sit in LDS; every product is
+// a small GEMM computed tile by tile (16 x 16 output tiles, K in steps of
+// 32), the tiles of one product spread over the four waves.  Operands are
+// rounded to BF16 (round to nearest even) when they enter an MFMA; biases,
 // GELU and the loss are FP32.  Training writes one gradient row per chunk;
 // a second kernel sums the rows in chunk order (deterministic) and a third
 // applies Adam.
+//
+// Inference for the solver's learned start (k_warm_net) computes each
+// joint's inputs in registers (net_inputs.h) and feeds them to the network
+// through LDS, so the inputs never travel through HBM.
 #include "snake_mlp.h"
 
 #include <hip/hip_runtime.h>
@@ -16,16 +21,17 @@
 #include <mutex>
 #include <string>
 
+#include "net_inputs.h"
+#include "kernels.h"
+#include "mlp_device.h"
+
 namespace {
 
-constexpr int NI = 32, NH = 64, NO = 3;
-constexpr int P_W1 = 0, P_B1 = P_W1 + NH * NI, P_W2 = P_B1 + NH, P_B2 = P_W2 + NH * NH;
-constexpr int P_W3 = P_B2 + NH, P_B3 = P_W3 + NO * NH, P_COUNT = P_B3 + NO;
-constexpr int CH = 32;  // samples per training chunk (one wave)
-constexpr int MT = CH / 16, KS = CH / 32;   // sample row tiles; sample K steps
+using namespace snake::mlp;
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int CH = 32;  // samples per training chunk
+constexpr int MT = CH / 16, KS = CH / 32;   // sample row tiles; sample K steps
+constexpr int GW = 4;   // waves per training workgroup
 
 thread_local std::string g_mlp_err;
 
@@ -35,57 +41,30 @@ int mfail(int code, const std::string& m)
     return code;
 }
 
-// erf(x) by Abramowitz and Stegun, Handbook of Mathematical Functions,
-// formula 7.1.26: 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p |x|),
-// odd in x; absolute error at most 1.5e-7 (far below the BF16 rounding of
-// the activations).  exp(-x^2) also serves GELU's derivative.
-__device__ __forceinline__ float erf_as(float x, float& e)
-{
-    const float ax = fabsf(x);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.f));
-    const float poly =
-        t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
-                 0.254829592f);
-    e = __builtin_amdgcn_exp2f(-1.4426950408889634f * (x * x));   // exp(-x^2)
-    return copysignf(fmaf(-poly, e, 1.f), x);
-}
-
-__device__ __forceinline__ float gelu(float z)
-{
-    float e;
-    return 0.5f * z * (1.f + erf_as(z * 0.70710678118654752f, e));
-}
-
-// d GELU / dz = Phi(z) + z phi(z), phi(z) = exp(-z^2 / 2) / sqrt(2 pi)
-__device__ __forceinline__ float gelu_grad(float z)
-{
-    float e;
-    const float phi = 0.5f * (1.f + erf_as(z * 0.70710678118654752f, e));
-    return phi + z * 0.39894228040143268f * e;
-}
-
-// C[M x N] = A[M x K] B[K x N] for M, N multiples of 16 and K of 32, on one
-// wave.  Lane l supplies A rows l % 16 and B columns l % 16 for the k-slice
-// 8 (l / 16) .. +8 and receives D rows 4 (l / 16) .. +4 of column l % 16.
+// C[M x N] = A[M x K] B[K x N] for M, N multiples of 16 and K of 32.  The
+// 16 x 16 output tiles (row-major over tiles) go to the waves of the
+// workgroup in turn; each tile is computed by one wave.  Lane l supplies A
+// rows l % 16 and B columns l % 16 for the k-slice 8 (l / 16) .. +8 and
+// receives D rows 4 (l / 16) .. +4 of column l % 16.
 template <class FA, class FB, class FS>
 __device__ __forceinline__ void wave_gemm(int mtiles, int ntiles, int ktiles, FA A, FB Bm, FS store)
 {
-    const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
-    for (int mt = 0; mt < mtiles; ++mt)
-        for (int nt = 0; nt < ntiles; ++nt) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            for (int kt = 0; kt < ktiles; ++kt) {
-                bf16x8 a, b;
+    const int l = threadIdx.x & 63, r = l & 15, g = l >> 4, wv = threadIdx.x >> 6;
+    for (int tile = wv; tile < mtiles * ntiles; tile += GW) {
+        const int mt = tile / ntiles, nt = tile % ntiles;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int kt = 0; kt < ktiles; ++kt) {
+            bf16x8 a, b;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    a[j] = A(mt * 16 + r, kt * 32 + 8 * g + j);
-                    b[j] = Bm(kt * 32 + 8 * g + j, nt * 16 + r);
-                }
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+            for (int j = 0; j < 8; ++j) {
+                a[j] = A(mt * 16 + r, kt * 32 + 8 * g + j);
+                b[j] = Bm(kt * 32 + 8 * g + j, nt * 16 + r);
             }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) store(mt * 16 + 4 * g + v, nt * 16 + r, acc[v]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
         }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) store(mt * 16 + 4 * g + v, nt * 16 + r, acc[v]);
+    }
 }
 
 struct Lds {
@@ -103,24 +82,25 @@ struct Lds {
     float red[64];
 };
 
-// Weight matrices to LDS as BF16.  Each lane loads its float4 groups before
-// converting any, so the loads are in flight together.
+// Weight matrices to LDS as BF16.  Each thread loads its float4 groups
+// before converting any, so the loads are in flight together.
 template <int ROWS, int COLS, int PROWS>
 __device__ __forceinline__ void load_matrix(__bf16 (*dst)[COLS], const float* __restrict__ src)
 {
+    constexpr int T = 64 * GW;
     constexpr int G = ROWS * COLS / 4;   // float4 groups of the stored rows
-    constexpr int PER = (G + 63) / 64;
+    constexpr int PER = (G + T - 1) / T;
     const int l = threadIdx.x;
     float4 v[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int gi = l + 64 * k;
+        const int gi = l + T * k;
         v[k] = (gi < G && 4 * gi < PROWS * COLS) ? reinterpret_cast<const float4*>(src)[gi]
                                                   : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int gi = l + 64 * k;
+        const int gi = l + T * k;
         if (gi < G) {
             const int e = 4 * gi;
             __bf16* d = &dst[e / COLS][e % COLS];
@@ -144,7 +124,7 @@ __device__ void chunk_forward(Lds& S, const float* __restrict__ p, const float* 
                               const float* __restrict__ x, int64_t base, int64_t n, float* y_out)
 {
     const int l = threadIdx.x;
-    for (int e = l; e < CH * NI; e += 64) {
+    for (int e = l; e < CH * NI; e += 64 * GW) {
         const int s = e / NI, k = e % NI;
         const int64_t row = base + s;
         const float v = row < n ? (x[row * NI + k] - ms[k]) / ms[NI + k] : 0.f;
@@ -174,47 +154,25 @@ __device__ void chunk_forward(Lds& S, const float* __restrict__ p, const float* 
 
 // Inference: four waves per workgroup, each taking tiles of 16 samples in a
 // grid-stride loop.  The weights stay in registers as MFMA B operands for
-// the whole launch; a 16 x 64 BF16 buffer per wave in LDS turns each layer's
-// output (D layout: lane l holds rows 4 (l / 16) .. +4 of column l % 16) into
-// the next layer's A operand (row l % 16, columns 8 (l / 16) .. +8).  Same
-// arithmetic as the training pass: BF16 operands, FP32 accumulation, bias
-// and GELU.
-constexpr int FW_WAVES = 4, FW_ROW = NH + 8;   // padded row (144 bytes)
+// the whole launch; a 16 x 64 BF16 buffer per wave in LDS carries each
+// layer's output to the next (forward_tile).  Same arithmetic as the
+// training pass: BF16 operands, FP32 accumulation, bias and GELU.
+constexpr int FW_WAVES = 4;
 
-__global__ void __launch_bounds__(64 * FW_WAVES) __attribute__((amdgpu_waves_per_eu(4))) k_mlp_forward(const float* __restrict__ p,
-                                                               const float* __restrict__ ms,
-                                                               const float* __restrict__ x,
-                                                               float* __restrict__ y, int64_t n)
+__global__ void __launch_bounds__(64 * FW_WAVES) __attribute__((amdgpu_waves_per_eu(4)))
+k_mlp_forward(const float* __restrict__ p, const float* __restrict__ ms, const float* __restrict__ x,
+              float* __restrict__ y, int64_t n)
 {
     __shared__ __align__(16) __bf16 Hs[FW_WAVES][16][FW_ROW];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, r = l & 15, g = l >> 4;
-    __bf16 (*H)[FW_ROW] = Hs[w];
-    bf16x8 B1[4], B2[4][2], B3[2];
-    float bb1[4], bb2[4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const int o = nt * 16 + r;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            B1[nt][j] = (__bf16)p[P_W1 + o * NI + 8 * g + j];
-            B2[nt][0][j] = (__bf16)p[P_W2 + o * NH + 8 * g + j];
-            B2[nt][1][j] = (__bf16)p[P_W2 + o * NH + 32 + 8 * g + j];
-        }
-        bb1[nt] = p[P_B1 + o];
-        bb2[nt] = p[P_B2 + o];
-    }
-#pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) B3[kt][j] = r < NO ? (__bf16)p[P_W3 + r * NH + kt * 32 + 8 * g + j] : (__bf16)0.f;
-    const float bb3 = r < NO ? p[P_B3 + r] : 0.f;
+    FwdWeights W;
+    load_fwd_weights(p, W);
     float mu[8], is[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         mu[j] = ms[8 * g + j];
         is[j] = 1.f / ms[NI + 8 * g + j];
     }
-    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
     const int64_t tiles = (n + 15) / 16;
     for (int64_t t = (int64_t)blockIdx.x * FW_WAVES + w; t < tiles; t += (int64_t)gridDim.x * FW_WAVES) {
         const int64_t row = t * 16 + r;
@@ -229,46 +187,82 @@ __global__ void __launch_bounds__(64 * FW_WAVES) __attribute__((amdgpu_waves_per
 #pragma unroll
             for (int j = 0; j < 8; ++j) a[j] = (__bf16)0.f;
         }
-        // layer 1: h1 = GELU(W1 x + b1)
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B1[nt], zero, 0, 0, 0);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) H[4 * g + v][nt * 16 + r] = (__bf16)gelu(acc[v] + bb1[nt]);
-        }
-        // (memcpy: the vector read may not be reordered with the element stores)
-        bf16x8 a2[2];
-#pragma unroll
-        for (int kt = 0; kt < 2; ++kt) __builtin_memcpy(&a2[kt], &H[r][kt * 32 + 8 * g], sizeof(bf16x8));
-        // layer 2: h2 = GELU(W2 h1 + b2)
-        f32x4 acc2[4];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            acc2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[0], B2[nt][0], zero, 0, 0, 0);
-            acc2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[1], B2[nt][1], acc2[nt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) H[4 * g + v][nt * 16 + r] = (__bf16)gelu(acc2[nt][v] + bb2[nt]);
-        bf16x8 a3[2];
-#pragma unroll
-        for (int kt = 0; kt < 2; ++kt) __builtin_memcpy(&a3[kt], &H[r][kt * 32 + 8 * g], sizeof(bf16x8));
-        // layer 3: y = W3 h2 + b3 (columns >= 3 are padding)
-        f32x4 acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[0], B3[0], zero, 0, 0, 0);
-        acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[1], B3[1], acc3, 0, 0, 0);
+        const f32x4 out = forward_tile(W, a, Hs[w]);
         if (r < NO) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t rr = t * 16 + 4 * g + v;
-                if (rr < n) y[rr * NO + r] = acc3[v] + bb3;
+                if (rr < n) y[rr * NO + r] = out[v];
+            }
+        }
+    }
+}
+
+// The solver's learned start: network outputs of every joint's two rows at
+// the predicted state of the current substep, y[2 J][3] (row 2 j stretch,
+// 2 j + 1 bend-twist).  A wave takes 64 joints at a time: each lane computes
+// one joint's inputs (joint_features), normalises them and writes both rows
+// as BF16 to the wave's 128-row buffer in LDS; then the wave runs the
+// network over the buffer in eight 16-sample tiles.  The inputs, their
+// normalisation and the network's arithmetic are those of k_features
+// followed by k_mlp_forward, so the outputs are the same bits.
+constexpr int WN_ROW = NI + 8;   // padded input row (80 bytes)
+
+__global__ void __launch_bounds__(64 * FW_WAVES) __attribute__((amdgpu_waves_per_eu(3)))
+k_warm_net(snake::KParams P, const float* __restrict__ p, const float* __restrict__ ms, float* __restrict__ y)
+{
+    __shared__ __align__(16) __bf16 Xs[FW_WAVES][128][WN_ROW];
+    __shared__ __align__(16) __bf16 Hs[FW_WAVES][16][FW_ROW];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, r = l & 15, g = l >> 4;
+    FwdWeights W;
+    load_fwd_weights(p, W);
+    const int J = P.J;
+    const int64_t rows = 2 * (int64_t)J;
+    for (int64_t j0 = ((int64_t)blockIdx.x * FW_WAVES + w) * 64; j0 < J; j0 += (int64_t)gridDim.x * FW_WAVES * 64) {
+        const int64_t gj = j0 + l;
+        __bf16* xs = Xs[w][2 * l];
+        __bf16* xb = Xs[w][2 * l + 1];
+        // the wave's 64 joints lie in snakes s0..s1 (searched once per wave)
+        const int s0 = snake::snake_of_joint(P, __builtin_amdgcn_readfirstlane((int)j0), 0, P.n_snakes - 1);
+        const int jl = (int)(j0 + 63 < J ? j0 + 63 : J - 1);
+        const int s1 = snake::snake_of_joint(P, __builtin_amdgcn_readfirstlane(jl), s0, P.n_snakes - 1);
+        if (gj < J) {
+            float f[32];
+            snake::V3 lbn;
+            snake::joint_features(P, (int)gj, s0, s1, f, lbn);
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                const float mu = ms[k], is = 1.f / ms[NI + k];
+                xs[k] = (__bf16)((f[k] - mu) * is);
+                const float fb = k == 19 ? lbn.x : k == 20 ? lbn.y : k == 21 ? lbn.z : k == 30 ? 1.f : f[k];
+                xb[k] = (__bf16)((fb - mu) * is);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                xs[k] = (__bf16)0.f;
+                xb[k] = (__bf16)0.f;
+            }
+        }
+#pragma unroll 1
+        for (int tt = 0; tt < 8; ++tt) {
+            // (memcpy: the vector read may not be reordered with the element stores)
+            bf16x8 a;
+            __builtin_memcpy(&a, &Xs[w][16 * tt + r][8 * g], sizeof(bf16x8));
+            const f32x4 out = forward_tile(W, a, Hs[w]);
+            if (r < NO) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t rr = 2 * j0 + 16 * tt + 4 * g + v;
+                    if (rr < rows) y[rr * NO + r] = out[v];
+                }
             }
         }
     }
 }
 
 // forward + backward of one chunk per workgroup; one gradient row per chunk
-__global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ p, const float* __restrict__ ms,
+__global__ void __launch_bounds__(64 * GW) k_mlp_grad(const float* __restrict__ p, const float* __restrict__ ms,
                                                  const float* __restrict__ x, const float* __restrict__ t,
                                                  int64_t n, float* __restrict__ gpart,
                                                  float* __restrict__ lpart)
@@ -283,20 +277,22 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ p, co
     chunk_forward(S, p, ms, x, base, n, Y);
     // d loss / d y for loss = mean over samples and outputs of (y - t)^2
     const float scale = 2.f / (float)(n * NO);
-    float lsum = 0.f;
-    for (int e = l; e < CH * 16; e += 64) {
-        const int s = e / 16, o = e % 16;
-        const int64_t row = base + s;
-        float d = 0.f;
-        if (o < NO && row < n) {
-            const float err = Y[s * NO + o] - t[row * NO + o];
-            lsum += err * err;
-            d = scale * err;
+    if (l < 64) {   // the first wave: 64 partial sums of the loss, as in chunk order
+        float lsum = 0.f;
+        for (int e = l; e < CH * 16; e += 64) {
+            const int s = e / 16, o = e % 16;
+            const int64_t row = base + s;
+            float d = 0.f;
+            if (o < NO && row < n) {
+                const float err = Y[s * NO + o] - t[row * NO + o];
+                lsum += err * err;
+                d = scale * err;
+            }
+            if (o < NO) S.dYf[s][o] = d;
+            S.dY[s][o] = (__bf16)d;
         }
-        if (o < NO) S.dYf[s][o] = d;
-        S.dY[s][o] = (__bf16)d;
+        S.red[l] = lsum;
     }
-    S.red[l] = lsum;
     __syncthreads();
     if (l == 0) {
         float acc = 0.f;
@@ -333,7 +329,7 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ p, co
     wave_gemm(MT, 4, 2, [&](int s, int o) { return S.dZ[s][o]; }, [&](int o, int k) { return S.W2[o][k]; },
               [&](int s, int k, float a) { S.Z1[s][k] = a * gelu_grad(S.Z1[s][k]); });
     __syncthreads();
-    for (int e = l; e < CH * NH; e += 64) S.dZ[e / NH][e % NH] = (__bf16)S.Z1[e / NH][e % NH];
+    for (int e = l; e < CH * NH; e += 64 * GW) S.dZ[e / NH][e % NH] = (__bf16)S.Z1[e / NH][e % NH];
     if (l < NH) {
         float acc = 0.f;
         for (int s = 0; s < CH; ++s) acc += S.Z1[s][l];
@@ -346,29 +342,38 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ p, co
 }
 
 // grad[k] = sum over chunks, loss likewise, in a fixed order: eight partial
-// sums over chunks c = j mod 8 (loads in flight together), then combined
-// pairwise.  The same inputs give the same bits on every call.
-__device__ __forceinline__ float ordered_sum(const float* __restrict__ a, int64_t stride, int64_t count)
-{
-    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int64_t c = 0;
-    for (; c + 8 <= count; c += 8) {
-        float v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = a[(c + j) * stride];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) acc[j] += v[j];
-    }
-    for (int j = 0; c < count; ++c, ++j) acc[j] += a[c * stride];
-    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-}
+// sums over chunks c = j mod 8, each in increasing c, then combined pairwise
+// ((0 + 1) + (2 + 3)) + ((4 + 5) + (6 + 7)).  Eight lanes share a parameter,
+// one partial sum each, and combine by lane swaps; the same inputs give the
+// same bits on every call.
+constexpr int RED_PARAMS = 32;   // parameters per 256-thread block
 
-__global__ void k_mlp_reduce(const float* __restrict__ gpart, const float* __restrict__ lpart, int64_t chunks,
-                             int64_t n, float* __restrict__ grad, float* __restrict__ loss)
+__global__ void __launch_bounds__(256) k_mlp_reduce(const float* __restrict__ gpart, const float* __restrict__ lpart,
+                                                    int64_t chunks, int64_t n, float* __restrict__ grad,
+                                                    float* __restrict__ loss)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < P_COUNT) grad[k] = ordered_sum(gpart + k, P_COUNT, chunks);
-    if (k == 0) *loss = ordered_sum(lpart, 1, chunks) / (float)(n * NO);
+    const int j = threadIdx.x & 7;
+    const int k = blockIdx.x * RED_PARAMS + (threadIdx.x >> 3);   // k == P_COUNT: the loss
+    const float* a = k < P_COUNT ? gpart + k : lpart;
+    const int64_t stride = k < P_COUNT ? P_COUNT : 1;
+    float acc = 0.f;
+    if (k <= P_COUNT) {
+        int64_t c = j;
+        for (; c + 24 < chunks; c += 32) {
+            const float v0 = a[c * stride], v1 = a[(c + 8) * stride], v2 = a[(c + 16) * stride],
+                        v3 = a[(c + 24) * stride];
+            acc += v0;
+            acc += v1;
+            acc += v2;
+            acc += v3;
+        }
+        for (; c < chunks; c += 8) acc += a[c * stride];
+    }
+    acc += __shfl_xor(acc, 1, 8);
+    acc += __shfl_xor(acc, 2, 8);
+    acc += __shfl_xor(acc, 4, 8);
+    if (j == 0 && k < P_COUNT) grad[k] = acc;
+    if (j == 0 && k == P_COUNT) *loss = acc / (float)(n * NO);
 }
 
 // Adam with bias correction (Kingma and Ba), step t counts from 1
@@ -466,13 +471,28 @@ int launch_grad(const float* params, const float* mean_std, const float* x, cons
     const int64_t chunks = (n + CH - 1) / CH;
     float* gpart = buf;
     float* lpart = buf + chunks * P_COUNT;
-    hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)chunks), dim3(64), 0, st, params, mean_std, x, t, n, gpart, lpart);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((P_COUNT + 255) / 256), dim3(256), 0, st, gpart, lpart, chunks, n, grad, loss);
+    hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)chunks), dim3(64 * GW), 0, st, params, mean_std, x, t, n, gpart, lpart);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((P_COUNT + 1 + RED_PARAMS - 1) / RED_PARAMS), dim3(256), 0, st, gpart, lpart,
+                       chunks, n, grad, loss);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SIM_OK : mfail(SIM_EDEVICE, hipGetErrorString(e));
 }
 
 }  // namespace
+
+namespace snake {
+
+hipError_t launch_warm_net(const KParams& P, const float* params, const float* mean_std, float* y,
+                           hipStream_t stream)
+{
+    if (P.J <= 0) return hipSuccess;
+    const int64_t blocks = ((int64_t)P.J + 64 * FW_WAVES - 1) / (64 * FW_WAVES);
+    const int grid = (int)(blocks < 1024 ? blocks : 1024);
+    hipLaunchKernelGGL(k_warm_net, dim3(grid), dim3(64 * FW_WAVES), 0, stream, P, params, mean_std, y);
+    return hipGetLastError();
+}
+
+}  // namespace snake
 
 extern "C" {
 

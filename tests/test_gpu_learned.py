@@ -80,6 +80,37 @@ def constant_net(c):
     return snk.Net(p, ms)
 
 
+def test_fused_network_start_equals_the_recorded_path():
+    """Without recording, the learned start computes each joint's network
+    inputs inside the network kernel (k_warm_net); recording writes them to
+    the caller's rows and runs the network over those rows (k_features, then
+    k_mlp_forward).  Same inputs, normalisation and arithmetic: with the
+    learned start always kept (no fallback) the two give the same bits, for
+    a network with random weights and input statistics."""
+    wl = W.make("uneven", n_snakes=150, seed=2024)
+    rng = np.random.default_rng(11)
+    p = rng.normal(scale=0.2, size=6467).astype(np.float32)
+    ms = torch.as_tensor(np.concatenate([rng.normal(scale=0.1, size=32), rng.uniform(0.5, 2.0, 32)]),
+                         dtype=torch.float32, device="cuda")
+    net = snk.Net(p, ms)
+    out = []
+    for record in (False, True):
+        sim = snk.Sim(wl, warm_start=snk.WARM_MLP, mlp_fallback=0)
+        sim.set_mlp(net.params, net.mean_std)
+        sim.step(2)
+        if record:
+            rows = sim.record_rows(2)
+            f = torch.empty((rows, 32), device="cuda")
+            t = torch.empty((rows, 3), device="cuda")
+            assert sim.step_record(2, f, t) == rows
+        else:
+            sim.step(2)
+        out.append(sim.read())
+        sim.close()
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
 def test_learned_start_in_half_rows_bit_identical():
     """The split substeps around the network (prediction, then the
     warm-started solve with the fallback after a few iterations) give the

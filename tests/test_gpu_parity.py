@@ -168,6 +168,22 @@ def test_parity_warm_start_prev(scene):
     assert_parity(f"warm-prev-{scene}", compare(oo, g, wl.mu), n_bodies=16)
 
 
+def test_parity_warm_start_prev_actuated():
+    """The previous-multiplier start on the actuated single snake, where it
+    is unstable (its velocities grow about tenfold every ten steps): three
+    steps in, while the state is still well scaled, a whole step held to the
+    per-substep gates substep by substep from the GPU's own state."""
+    from parity import chained_substeps
+
+    wl = W.make("single")
+    o = oracle.Oracle(wl, warm=oracle.WARM_PREV)
+    o.run(3)
+    o.commands()
+    for k, (oo, g, _) in enumerate(chained_substeps(wl, rounded_state(o), gpu_over=dict(warm_start=snk.WARM_PREV),
+                                                    orc_over=dict(warm=oracle.WARM_PREV))):
+        assert_parity(f"warm-prev-actuated substep {k}", compare(oo, g, wl.mu), n_bodies=64)
+
+
 def test_parity_paper_pressure_law():
     """The paper's pressure law: a whole step gives the oracle's pressures
     to 1e-6; the first substep of a step (the law applied once, then one
