@@ -42,11 +42,11 @@ __device__ __forceinline__ void joint_eval(V3 dxp, V3 dA, V3 dB, Q4 qA, Q4 qB, V
 {
     g.aA = aA;   // body x axes R(q) e_x of A and B
     g.aB = aB;
-    const V3 rA = hl * aA, rB = (-hl) * aB;
 
-    // stretch: end point of A minus start point of B (eq. rigid_to_particle form)
-    const V3 C = (dxp + (dA - dB)) + (rA - rB);
-    const V3 rhs = C + comp_s * ls;
+    // stretch: end point of A minus start point of B (eq. rigid_to_particle
+    // form), the attachment offsets rA = hl aA and rB = -hl aB
+    const V3 C = fma3(hl, aA + aB, dxp + (dA - dB));
+    const V3 rhs = fma3(comp_s, ls, C);
     // K + alpha~ = (wA + wB + comp_s) I + kA (I - a a^T) + kB (I - b b^T) with the unit
     // axes a, b and kX = c1X hl^2, i.e. dg I - U diag(kA, kB) U^T with U = [a b].
     // Woodbury: (K + alpha~)^-1 r = (r + U M^-1 diag(kA, kB) U^T r) / dg with the
@@ -62,7 +62,7 @@ __device__ __forceinline__ void joint_eval(V3 dxp, V3 dA, V3 dB, Q4 qA, Q4 qB, V
     const float y1 = (pB * u1 + (kA * gab) * u2) * f;
     const float y2 = ((kB * gab) * u1 + pA * u2) * f;
     const float inv_dg = __builtin_amdgcn_rcpf(dg);
-    Dls = -((inv_dg * rhs + y1 * a) + y2 * b);
+    Dls = fma3(-y2, b, fma3(-y1, a, (-inv_dg) * rhs));
     rs = amax3(rhs) * inv_L;
 
     // bend-twist: e = conj(qA q0) qB with q0 = (c0h, 0, 0, s0h)
@@ -73,14 +73,13 @@ __device__ __forceinline__ void joint_eval(V3 dxp, V3 dA, V3 dB, Q4 qA, Q4 qB, V
     if (e.w < 0.f) e = Q4{-e.w, -e.x, -e.y, -e.z};
     g.e = e;
     const V3 ev{e.x, e.y, e.z};
-    const V3 rhsb = 2.f * ev + mk(comp_t * lb.x, comp_b * lb.y, comp_b * lb.z);
+    const V3 rhsb = fma3(2.f, ev, mk(comp_t * lb.x, comp_b * lb.y, comp_b * lb.z));
     // K = G F^T (IA^-1 + IB^-1) F G^T, G = e_w I - [e]x, F = R(qA q0):
     //   (c1A + c1B)(|e|^2 I - e e^T) + c2A gA gA^T + c2B gB gB^T
-    // with gX = G uX and uA = R(q0)^T e_x, uB = R(e) e_x
-    const V3 ua{ct, -st, 0.f};
+    // with gX = G uX and uA = R(q0)^T e_x = (ct, -st, 0), uB = R(e) e_x
+    const V3 ga{fmaf(e.w, ct, -(ev.z * st)), fmaf(-e.w, st, -(ev.z * ct)), fmaf(ev.x, st, ev.y * ct)};
     const V3 ub = qaxis(e);
-    const V3 ga = e.w * ua - cross(ev, ua);
-    const V3 gb = e.w * ub - cross(ev, ub);
+    const V3 gb = fma3(e.w, ub, -cross(ev, ub));
     const float M1 = c1A + c1B;
     const float n2 = e.w * e.w + dot(ev, ev);
     Dlb = -sym3_solve(M1 * (n2 - ev.x * ev.x) + c2A * ga.x * ga.x + c2B * gb.x * gb.x + comp_t,
@@ -100,15 +99,15 @@ __device__ __forceinline__ void joint_eval(V3 dxp, V3 dA, V3 dB, Q4 qA, Q4 qB, V
 __device__ __forceinline__ void joint_torques(const Geo& g, V3 dls, V3 dlb, float hl, V3& tA, V3& tB)
 {
     const V3 ev{g.e.x, g.e.y, g.e.z};
-    const V3 z = qrot(g.qA0, g.e.w * dlb + cross(ev, dlb));
-    tA = hl * cross(g.aA, dls) - z;
-    tB = hl * cross(g.aB, dls) + z;
+    const V3 z = qrot(g.qA0, fma3(g.e.w, dlb, cross(ev, dlb)));
+    tA = fma3(hl, cross(g.aA, dls), -z);
+    tB = fma3(hl, cross(g.aB, dls), z);
 }
 
 // I^-1 t = c1 t + c2 (a . t) a for a body with axis a (c1 = c2 = 0: fixed)
 __device__ __forceinline__ V3 inv_inertia(V3 t, V3 a, float c1, float c2)
 {
-    return c1 * t + (c2 * dot(a, t)) * a;
+    return fma3(c2 * dot(a, t), a, c1 * t);
 }
 
 // increments of the contact block of a body (normal, tangent x, tangent y)

@@ -24,6 +24,11 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b)
 }
 __device__ __forceinline__ float amax3(V3 a) { return fmaxf(fabsf(a.x), fmaxf(fabsf(a.y), fabsf(a.z))); }
 __device__ __forceinline__ V3 sel(bool c, V3 a, V3 b) { return c ? a : b; }
+// s a + b with one rounding per component (fused multiply-add)
+__device__ __forceinline__ V3 fma3(float s, V3 a, V3 b)
+{
+    return V3{fmaf(s, a.x, b.x), fmaf(s, a.y, b.y), fmaf(s, a.z, b.z)};
+}
 
 __device__ __forceinline__ Q4 qmul(Q4 a, Q4 b)
 {
@@ -44,19 +49,21 @@ __device__ __forceinline__ V3 qaxis(Q4 q)
     return V3{1.f - 2.f * (q.y * q.y + q.z * q.z), 2.f * (q.x * q.y + q.w * q.z),
               2.f * (q.x * q.z - q.w * q.y)};
 }
-// R(q) v
+// R(q) v = v + 2 (w (u x v) + u x (u x v)), u = (q.x, q.y, q.z)
 __device__ __forceinline__ V3 qrot(Q4 q, V3 v)
 {
-    V3 u{q.x, q.y, q.z};
-    V3 t = 2.f * cross(u, v);
-    return v + q.w * t + cross(u, t);
+    const V3 u{q.x, q.y, q.z};
+    const V3 t = cross(u, v);
+    return fma3(2.f, fma3(q.w, t, cross(u, t)), v);
 }
-// q <- normalize(q + 1/2 [0, dth] (x) q)
+// q <- normalize(q + 1/2 [0, dth] (x) q); the product [0, dth] (x) q is
+// (-dth . u, w dth + dth x u)
 __device__ __forceinline__ Q4 qturn(Q4 q, V3 dth)
 {
-    Q4 p{0.f, dth.x, dth.y, dth.z};
-    Q4 t = qmul(p, q);
-    return qnormalize(Q4{q.w + 0.5f * t.w, q.x + 0.5f * t.x, q.y + 0.5f * t.y, q.z + 0.5f * t.z});
+    const V3 u{q.x, q.y, q.z};
+    const float tw = -dot(dth, u);
+    const V3 tv = fma3(q.w, dth, cross(dth, u));
+    return qnormalize(Q4{fmaf(0.5f, tw, q.w), fmaf(0.5f, tv.x, q.x), fmaf(0.5f, tv.y, q.y), fmaf(0.5f, tv.z, q.z)});
 }
 
 // x = K^{-1} b for a symmetric 3x3 K = [[a,b,c],[b,d,e],[c,e,f]] (adjugate)

@@ -418,7 +418,7 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                             const V3 tsum = sel(recv, intq, zero) + sel(hasj, tA, zero);
                             const V3 dxc = (gnd && !fixed) ? P.inv_m * mk(lc.y, lc.z, lc.x) : zero;
                             if (hasb && !fixed) {
-                                d = d + (wA * fsum + dxc);
+                                d = d + fma3(wA, fsum, dxc);
                                 q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
                             }
                         }
@@ -469,7 +469,7 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                             const V3 tsum = sel(recv, intq, zero) + sel(hasj, tA, zero);
                             const V3 dxc = (gnd && !fixed) ? P.inv_m * mk(lc.y, lc.z, lc.x) : zero;
                             if (hasb && !fixed) {
-                                d = d + (wA * fsum + dxc);
+                                d = d + fma3(wA, fsum, dxc);
                                 q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
                             }
                         };
@@ -522,7 +522,7 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                         }
                         if (hasb && gnd) lc = lc + dlc;
                         if (hasb && !fixed) {
-                            d = d + wA * (fsum + mk(dlc.y, dlc.z, dlc.x));
+                            d = fma3(wA, fsum + mk(dlc.y, dlc.z, dlc.x), d);
                             q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
                         }
                     }
@@ -627,7 +627,7 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                         }
                         if (hasb && gnd) lc = lc + dlc;
                         if (hasb && !fixed) {
-                            d = d + wA * (fsum + mk(dlc.y, dlc.z, dlc.x));
+                            d = fma3(wA, fsum + mk(dlc.y, dlc.z, dlc.x), d);
                             q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
                         }
                     }
