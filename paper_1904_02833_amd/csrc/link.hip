@@ -109,7 +109,9 @@ __device__ __forceinline__ bool polar(const float* F, float* R)
             ok = false;
             break;
         }
-        const float id = 1.f / det;
+        // hardware reciprocal (1 ulp): the iteration's fixed point is the
+        // rotation either way, within the convergence test
+        const float id = __builtin_amdgcn_rcpf(det);
         // R^-T = cofactor matrix / det
         const float c[9] = {c00, c01, c02, c10, c11, c12, c20, c21, c22};
         float diff = 0.f;
@@ -148,6 +150,7 @@ struct Lds {
     float* dr;    // [D1][kDR]
     float* ar;    // [A1][kAR]
     int* ioff;    // [P1 + 1]
+    int* ikind;   // [P1] first distance entry | first attachment entry << 16
     int* inc;     // incidence entries
     float* pr;    // [P][kPR]
     float* U;     // [T][kUR]
@@ -163,7 +166,7 @@ struct Lds {
 __host__ __device__ inline int lds_words(int L, int P1, int Tm, int D1, int A1, int n_inc)
 {
     const int P = L * P1, T = L * Tm, D = L * D1, A = L * A1;
-    return kTR * Tm + kDR * D1 + kAR * A1 + (P1 + 1) + n_inc + kPR * P + (kUR + kQR) * T + 3 * D + 3 * A +
+    return kTR * Tm + kDR * D1 + kAR * A1 + (P1 + 1) + P1 + n_inc + kPR * P + (kUR + kQR) * T + 3 * D + 3 * A +
            kFr * (L + 1) + 4 * L + kWaves;
 }
 
@@ -190,6 +193,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
         S.dr = w, w += kDR * D1;
         S.ar = w, w += kAR * A1;
         S.ioff = reinterpret_cast<int*>(w), w += P1 + 1;
+        S.ikind = reinterpret_cast<int*>(w), w += P1;
         S.inc = reinterpret_cast<int*>(w), w += n_inc;
         S.pr = w, w += kPR * NP;
         S.U = w, w += kUR * T;
@@ -226,6 +230,16 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
         S.ar[i] = f < 5 ? P.att_c[f * A1 + e] : f == 5 ? __int_as_float(P.att_p[e]) : 0.f;
     }
     for (int i = tid; i < P1 + 1; i += kThreads) S.ioff[i] = P.inc_off[i];
+    // a particle's list holds its elements, then its distance rows, then its
+    // attachment: where each kind begins
+    for (int i = tid; i < P1; i += kThreads) {
+        const int e1 = P.inc_off[i + 1];
+        int d = P.inc_off[i];
+        while (d < e1 && (P.inc[d] >> 28) == kIncTet) ++d;
+        int a = d;
+        while (a < e1 && (P.inc[a] >> 28) == kIncDist) ++a;
+        S.ikind[i] = d | a << 16;
+    }
     for (int i = tid; i < n_inc; i += kThreads) S.inc[i] = P.inc[i];
 
     const int64_t gp = (int64_t)s * NP + tid;     // particle
@@ -421,13 +435,15 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         const float* pi = S.pr + kPR * (base + (ij & 0xffff));
                         const float* pj = S.pr + kPR * (base + (ij >> 16));
                         const int kind = __float_as_int(c[5]);
-                        const float* lkp = S.lk + blink[k];
-                        const bool on = kind < kChamber0 || (kind == kChamber0 ? lkp[2 * L] > 0.f : lkp[3 * L] > 0.f);
+                        // a chamber row acts while its chamber is commanded (S.lk rows
+                        // 2 and 3), at that chamber's pressure (rows 0 and 1)
+                        const int ch = kind - kChamber0;
+                        const bool on = ch < 0 || S.lk[(2 + ch) * L + blink[k]] > 0.f;
                         float* out = S.dd + 3 * (blink[k] * D1 + t);
                         pend[k][0] = 0.f;
                         V3 im = mk(0.f, 0.f, 0.f);
                         if (on) {
-                            const float press = kind == kChamber0 ? lkp[0] : kind == kChamber1 ? lkp[L] : 0.f;
+                            const float press = ch < 0 ? 0.f : S.lk[ch * L + blink[k]];
                             const V3 df = (ld3(pi) - ld3(pj)) + (ld3(pi + 3) - ld3(pj + 3));
                             const float len = sqrtf(dot(df, df));
                             const float rest = c[0] * (1.f + press * P.young_inv_pmax);
@@ -515,23 +531,33 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                 }
                 if (isp) {
                     V3 fsum = mk(0.f, 0.f, 0.f);
-                    for (int e = inc0; e < inc1; ++e) {
-                        const int ent = S.inc[e];
-                        const int type = ent >> 28, blk = (ent >> 2) & 0x3ffffff, slot = ent & 3;
-                        if (type == kIncTet) {
-                            const float* gm = S.tr + kTR * blk + 3 * slot;
-                            const float* up = S.U + kUR * (pl * Tm + blk);
-                            const float g0 = gm[0], g1 = gm[1], g2 = gm[2];
-                            fsum.x += up[0] * g0 + up[1] * g1 + up[2] * g2;
-                            fsum.y += up[3] * g0 + up[4] * g1 + up[5] * g2;
-                            fsum.z += up[6] * g0 + up[7] * g1 + up[8] * g2;
-                        } else if (type == kIncDist) {
-                            const V3 im = ld3(S.dd + 3 * (pl * D1 + blk));
-                            fsum = slot == 0 ? fsum + im : fsum - im;
-                        } else {
-                            fsum = fsum - ld3(S.da + 3 * (pl * A1 + blk));
-                        }
+                    const int kb = S.ikind[pk], incd = kb & 0xffff, inca = kb >> 16;
+                    // elements: U g of the particle's vertex slot, in list
+                    // order; the next entry is read while this one's data
+                    // arrive
+                    int ent = incd > inc0 ? S.inc[inc0] : 0;
+                    for (int e = inc0; e < incd; ++e) {
+                        const int blk = (ent >> 2) & 0x3ffffff, slot = ent & 3;
+                        const float* gm = S.tr + kTR * blk + 3 * slot;
+                        const float* up = S.U + kUR * (pl * Tm + blk);
+                        const float g0 = gm[0], g1 = gm[1], g2 = gm[2];
+                        float u[9];
+#pragma unroll
+                        for (int q = 0; q < 9; ++q) u[q] = up[q];
+                        if (e + 1 < incd) ent = S.inc[e + 1];
+                        fsum.x += u[0] * g0 + u[1] * g1 + u[2] * g2;
+                        fsum.y += u[3] * g0 + u[4] * g1 + u[5] * g2;
+                        fsum.z += u[6] * g0 + u[7] * g1 + u[8] * g2;
                     }
+                    // distance rows (+ on the first particle, - on the second)
+                    for (int e = incd; e < inca; ++e) {
+                        const int de = S.inc[e];
+                        const V3 im = ld3(S.dd + 3 * (pl * D1 + ((de >> 2) & 0x3ffffff)));
+                        fsum = (de & 3) == 0 ? fsum + im : fsum - im;
+                    }
+                    // attachment
+                    for (int e = inca; e < inc1; ++e)
+                        fsum = fsum - ld3(S.da + 3 * (pl * A1 + ((S.inc[e] >> 2) & 0x3ffffff)));
                     if (P.ground) {
                         lc = lc + dlc;
                         fsum = fsum + mk(dlc.y, dlc.z, dlc.x);
