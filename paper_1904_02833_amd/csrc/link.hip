@@ -137,12 +137,12 @@ __device__ __forceinline__ V3 frame_inv_inertia(const Params& P, Q4 q, V3 t)
 // records (array of structures with odd strides, free of bank conflicts for
 // consecutive blocks), so one address per record serves all its fields
 // through the instructions' immediate offsets.
-constexpr int kTR = 39;   // element record: g_0..g_3 (12), L (15), 1/D (6), E/h^2 (3), scale, vertices, pad
-constexpr int kDR = 7;    // distance row: rest, w_i, w_j, scale, i | j << 16, kind, pad
-constexpr int kAR = 7;    // attachment: r (3), w_p, particle degree, particle, pad
+// element record: g_0..g_3 (12), L (15), 1/D (6), E/h^2 (3), scale, vertices,
+// the gather slots of its four vertices (4), pad
+constexpr int kTR = 43;
+constexpr int kDR = 9;    // distance row: rest, w_i, w_j, scale, i | j << 16, kind, slots of i and j, pad
+constexpr int kAR = 7;    // attachment: r (3), w_p, particle degree, particle, slot
 constexpr int kPR = 7;    // particle: start-of-substep position (3), displacement (3), pad
-constexpr int kUR = 9;    // element output R T
-constexpr int kQR = 7;    // element increment awaiting the stop decision (6), pad
 constexpr int kFr = 20;   // frame: xp (3), d (3), q (4), v (3), w (3), q at the substep start (4)
 
 struct Lds {
@@ -150,13 +150,11 @@ struct Lds {
     float* dr;    // [D1][kDR]
     float* ar;    // [A1][kAR]
     int* ioff;    // [P1 + 1]
-    int* ikind;   // [P1] first distance entry | first attachment entry << 16
     int* inc;     // incidence entries
     float* pr;    // [P][kPR]
-    float* U;     // [T][kUR]
-    float* pt;    // [T][kQR]
-    float* dd;    // [D][3] distance impulses on the first particle
-    float* da;    // [A][3] attachment increments
+    float* V;     // [L][n_inc][3] what each block sends each of its particles, in the
+                  // particles' gather order (slot = incidence entry)
+    float* da;    // [A][6] attachment increments and their torques about the frame (the frames' side)
     float* fr;    // [F][kFr]
     float* lk;    // [4][L] p0, p1, chamber 0 commanded, chamber 1 commanded
     float* red;   // [kWaves] residual maxima of the waves
@@ -166,7 +164,7 @@ struct Lds {
 __host__ __device__ inline int lds_words(int L, int P1, int Tm, int D1, int A1, int n_inc)
 {
     const int P = L * P1, T = L * Tm, D = L * D1, A = L * A1;
-    return kTR * Tm + kDR * D1 + kAR * A1 + (P1 + 1) + P1 + n_inc + kPR * P + (kUR + kQR) * T + 3 * D + 3 * A +
+    return kTR * Tm + kDR * D1 + kAR * A1 + (P1 + 1) + n_inc + kPR * P + 3 * L * n_inc + 6 * A +
            kFr * (L + 1) + 4 * L + kWaves;
 }
 
@@ -193,20 +191,18 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
         S.dr = w, w += kDR * D1;
         S.ar = w, w += kAR * A1;
         S.ioff = reinterpret_cast<int*>(w), w += P1 + 1;
-        S.ikind = reinterpret_cast<int*>(w), w += P1;
         S.inc = reinterpret_cast<int*>(w), w += n_inc;
         S.pr = w, w += kPR * NP;
-        S.U = w, w += kUR * T;
-        S.pt = w, w += kQR * T;
-        S.dd = w, w += 3 * D;
-        S.da = w, w += 3 * A;
+        S.V = w, w += 3 * L * n_inc;
+        S.da = w, w += 6 * A;
         S.fr = w, w += kFr * NF;
         S.lk = w, w += 4 * L;
         S.red = w;
     }
-    // per-mesh constants into records
+    // per-mesh constants into records (the slot fields are filled below)
     for (int i = tid; i < kTR * Tm; i += kThreads) {
         const int t = i / kTR, f = i - t * kTR;
+        if (f >= 38 && f < 42) continue;
         float val = 0.f;
         if (f < 12)
             val = P.tet_g[f * Tm + t];
@@ -222,25 +218,29 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
     }
     for (int i = tid; i < kDR * D1; i += kThreads) {
         const int e = i / kDR, f = i - e * kDR;
+        if (f == 6 || f == 7) continue;
         S.dr[i] = f < 4 ? P.dist_c[f * D1 + e] : f == 4 ? __int_as_float(P.dist_ij[e])
                                                 : f == 5 ? __int_as_float(P.dist_kind[e]) : 0.f;
     }
     for (int i = tid; i < kAR * A1; i += kThreads) {
         const int e = i / kAR, f = i - e * kAR;
-        S.ar[i] = f < 5 ? P.att_c[f * A1 + e] : f == 5 ? __int_as_float(P.att_p[e]) : 0.f;
+        if (f == 6) continue;
+        S.ar[i] = f < 5 ? P.att_c[f * A1 + e] : __int_as_float(P.att_p[e]);
     }
     for (int i = tid; i < P1 + 1; i += kThreads) S.ioff[i] = P.inc_off[i];
-    // a particle's list holds its elements, then its distance rows, then its
-    // attachment: where each kind begins
-    for (int i = tid; i < P1; i += kThreads) {
-        const int e1 = P.inc_off[i + 1];
-        int d = P.inc_off[i];
-        while (d < e1 && (P.inc[d] >> 28) == kIncTet) ++d;
-        int a = d;
-        while (a < e1 && (P.inc[a] >> 28) == kIncDist) ++a;
-        S.ikind[i] = d | a << 16;
+    // incidence entry i is gather slot i: each block records the slots of
+    // its particles (one entry per block and particle)
+    for (int i = tid; i < n_inc; i += kThreads) {
+        const int ent = P.inc[i];
+        S.inc[i] = ent;
+        const int type = ent >> 28, blk = (ent >> 2) & 0x3ffffff, slot = ent & 3;
+        if (type == kIncTet)
+            S.tr[kTR * blk + 38 + slot] = __int_as_float(i);
+        else if (type == kIncDist)
+            S.dr[kDR * blk + 6 + slot] = __int_as_float(i);
+        else
+            S.ar[kAR * blk + 6] = __int_as_float(i);
     }
-    for (int i = tid; i < n_inc; i += kThreads) S.inc[i] = P.inc[i];
 
     const int64_t gp = (int64_t)s * NP + tid;     // particle
     const int64_t gf = (int64_t)s * NF + tid;     // frame
@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
     }
     // blocks: kind 0 element, 1 distance row, 2 attachment, 3 none
     int bkind[kSlots], bidx[kSlots], blink[kSlots];
-    float lam[kSlots][6], pend[kSlots][3];
+    float lam[kSlots][6], pend[kSlots][6];
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) {
         const int b = tid + k * kThreads;
@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
 #pragma unroll
         for (int r = 0; r < 6; ++r) lam[k][r] = 0.f;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) pend[k][r] = 0.f;
+        for (int r = 0; r < 6; ++r) pend[k][r] = 0.f;
     }
     __syncthreads();
     const int inc0 = isp ? S.ioff[pk] : 0, inc1 = isp ? S.ioff[pk + 1] : 0;
@@ -413,22 +413,30 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
 #pragma unroll
                             for (int cc = q + 1; cc < 6; ++cc) y[q] -= c[12 + cc * (cc - 1) / 2 + q] * y[cc];
                         const float sc = -c[36];
-                        const int b = blink[k] * Tm + t;
-                        float* qp = S.pt + kQR * b;
 #pragma unroll
                         for (int q = 0; q < 6; ++q) {
                             y[q] *= sc;
-                            qp[q] = y[q];
+                            pend[k][q] = y[q];
                         }
-                        // U = R T, T the increment as a symmetric tensor
+                        // U = R T, T the increment as a symmetric tensor; vertex m
+                        // receives U g_m, written to its gather slot
                         const float Tn[9] = {y[0], 0.5f * y[5], 0.5f * y[4], 0.5f * y[5], y[1], 0.5f * y[3],
                                              0.5f * y[4], 0.5f * y[3], y[2]};
-                        float* up = S.U + kUR * b;
+                        float u[9];
 #pragma unroll
                         for (int i = 0; i < 3; ++i)
 #pragma unroll
                             for (int j = 0; j < 3; ++j)
-                                up[3 * i + j] = R[3 * i] * Tn[j] + R[3 * i + 1] * Tn[3 + j] + R[3 * i + 2] * Tn[6 + j];
+                                u[3 * i + j] = R[3 * i] * Tn[j] + R[3 * i + 1] * Tn[3 + j] + R[3 * i + 2] * Tn[6 + j];
+                        float* vb = S.V + 3 * blink[k] * n_inc;
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            const float g0 = c[3 * m], g1 = c[3 * m + 1], g2 = c[3 * m + 2];
+                            float* o = vb + 3 * __float_as_int(c[38 + m]);
+                            o[0] = u[0] * g0 + u[1] * g1 + u[2] * g2;
+                            o[1] = u[3] * g0 + u[4] * g1 + u[5] * g2;
+                            o[2] = u[6] * g0 + u[7] * g1 + u[8] * g2;
+                        }
                     } else if (bkind[k] == 1) {
                         const float* c = S.dr + kDR * t;
                         const int ij = __float_as_int(c[4]), base = blink[k] * P1;
@@ -439,7 +447,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         // 2 and 3), at that chamber's pressure (rows 0 and 1)
                         const int ch = kind - kChamber0;
                         const bool on = ch < 0 || S.lk[(2 + ch) * L + blink[k]] > 0.f;
-                        float* out = S.dd + 3 * (blink[k] * D1 + t);
+                        float* vb = S.V + 3 * blink[k] * n_inc;
                         pend[k][0] = 0.f;
                         V3 im = mk(0.f, 0.f, 0.f);
                         if (on) {
@@ -453,7 +461,9 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                             pend[k][0] = dl;
                             im = (dl / len) * df;
                         }
-                        st3(out, im);
+                        // + on the first particle, - on the second
+                        st3(vb + 3 * __float_as_int(c[6]), im);
+                        st3(vb + 3 * __float_as_int(c[7]), -im);
                     } else if (bkind[k] == 2) {
                         const float* c = S.ar + kAR * t;
                         const int a = t;
@@ -481,7 +491,11 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         pend[k][0] = sc * sol.x;
                         pend[k][1] = sc * sol.y;
                         pend[k][2] = sc * sol.z;
-                        st3(S.da + 3 * (blink[k] * A1 + a), mk(pend[k][0], pend[k][1], pend[k][2]));
+                        const V3 inc_a = mk(pend[k][0], pend[k][1], pend[k][2]);
+                        float* dao = S.da + 6 * (blink[k] * A1 + a);                     // to the frame
+                        st3(dao, inc_a);
+                        st3(dao + 3, cross(u, inc_a));
+                        st3(S.V + 3 * (blink[k] * n_inc + __float_as_int(c[6])), -inc_a);   // to the particle
                     }
                 }
                 // the particle's ground contact: normal, then the slip since the
@@ -521,9 +535,8 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
 #pragma unroll
                 for (int k = 0; k < kSlots; ++k) {
                     if (bkind[k] == 0) {
-                        const float* qp = S.pt + kQR * (blink[k] * Tm + bidx[k]);
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) lam[k][q] += qp[q];
+                        for (int q = 0; q < 6; ++q) lam[k][q] += pend[k][q];
                     } else {
 #pragma unroll
                         for (int q = 0; q < 3; ++q) lam[k][q] += pend[k][q];
@@ -531,33 +544,20 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                 }
                 if (isp) {
                     V3 fsum = mk(0.f, 0.f, 0.f);
-                    const int kb = S.ikind[pk], incd = kb & 0xffff, inca = kb >> 16;
-                    // elements: U g of the particle's vertex slot, in list
-                    // order; the next entry is read while this one's data
-                    // arrive
-                    int ent = incd > inc0 ? S.inc[inc0] : 0;
-                    for (int e = inc0; e < incd; ++e) {
-                        const int blk = (ent >> 2) & 0x3ffffff, slot = ent & 3;
-                        const float* gm = S.tr + kTR * blk + 3 * slot;
-                        const float* up = S.U + kUR * (pl * Tm + blk);
-                        const float g0 = gm[0], g1 = gm[1], g2 = gm[2];
-                        float u[9];
-#pragma unroll
-                        for (int q = 0; q < 9; ++q) u[q] = up[q];
-                        if (e + 1 < incd) ent = S.inc[e + 1];
-                        fsum.x += u[0] * g0 + u[1] * g1 + u[2] * g2;
-                        fsum.y += u[3] * g0 + u[4] * g1 + u[5] * g2;
-                        fsum.z += u[6] * g0 + u[7] * g1 + u[8] * g2;
+                    // every block's share, in the particle's list order
+                    // (elements, distance rows, attachment), from its slots
+                    // (four read ahead of the sums)
+                    const float* vp = S.V + 3 * (pl * n_inc);
+                    int e = inc0;
+                    for (; e + 4 <= inc1; e += 4) {
+                        const V3 v0 = ld3(vp + 3 * e), v1 = ld3(vp + 3 * e + 3);
+                        const V3 v2 = ld3(vp + 3 * e + 6), v3 = ld3(vp + 3 * e + 9);
+                        fsum = fsum + v0;
+                        fsum = fsum + v1;
+                        fsum = fsum + v2;
+                        fsum = fsum + v3;
                     }
-                    // distance rows (+ on the first particle, - on the second)
-                    for (int e = incd; e < inca; ++e) {
-                        const int de = S.inc[e];
-                        const V3 im = ld3(S.dd + 3 * (pl * D1 + ((de >> 2) & 0x3ffffff)));
-                        fsum = (de & 3) == 0 ? fsum + im : fsum - im;
-                    }
-                    // attachment
-                    for (int e = inca; e < inc1; ++e)
-                        fsum = fsum - ld3(S.da + 3 * (pl * A1 + ((S.inc[e] >> 2) & 0x3ffffff)));
+                    for (; e < inc1; ++e) fsum = fsum + ld3(vp + 3 * e);
                     if (P.ground) {
                         lc = lc + dlc;
                         fsum = fsum + mk(dlc.y, dlc.z, dlc.x);
@@ -574,11 +574,21 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         const int l = tid - 1 + side;
                         if (l < 0 || l >= L) continue;
                         const int a0 = side == 0 ? A1 / 2 : 0, a1 = side == 0 ? A1 : A1 / 2;
-                        for (int a = a0; a < a1; ++a) {
-                            const V3 dl = ld3(S.da + 3 * (l * A1 + a));
-                            const V3 u = qrot(q, ld3(S.ar + kAR * a));
-                            F = F + dl;
-                            tq = tq + cross(u, dl);
+                        // the attachments' increments and torques, in order
+                        // (three read ahead of the sums)
+                        const float* da = S.da + 6 * (l * A1);
+                        int a = a0;
+                        for (; a + 3 <= a1; a += 3) {
+                            const V3 d0 = ld3(da + 6 * a), t0 = ld3(da + 6 * a + 3);
+                            const V3 d1 = ld3(da + 6 * a + 6), t1 = ld3(da + 6 * a + 9);
+                            const V3 d2 = ld3(da + 6 * a + 12), t2 = ld3(da + 6 * a + 15);
+                            F = F + d0, tq = tq + t0;
+                            F = F + d1, tq = tq + t1;
+                            F = F + d2, tq = tq + t2;
+                        }
+                        for (; a < a1; ++a) {
+                            F = F + ld3(da + 6 * a);
+                            tq = tq + ld3(da + 6 * a + 3);
                         }
                     }
                     const V3 th = frame_inv_inertia(P, q, tq);
