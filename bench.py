@@ -35,12 +35,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "snake-steps/s & constraint-iters/s at residual≤1e-4, plain vs NN warm-start"
-# FP32 operations per body per iteration (evaluation of its joint's stretch
-# and bend-twist blocks, its contact, the joint torques, the increments and
-# the gathered update), per final evaluation-only pass (evaluation and
-# torques), and per body per substep outside the iterations.  Counted from
-# the compiled iteration loop: add, sub, mul = 1, fused multiply-add = 2.
-FLOP_ITER = 462
+# FP32 operations of the solver kernel per body-iteration, from its VALU
+# counters on the uniform batch (4096 snakes of 64 bodies, every lane holds
+# a body): SQ_INSTS_VALU_FLOPS_FP32 (per wave instruction: add + mul + 2 fma
+# + transcendental) x 64 lanes / (262 144 bodies x 800 iterations) =
+# 64 x 1.4803e9 / 2.0972e8 = 451.7 per step at the 200-iteration cap, the
+# per-substep work and the final evaluation pass included (summary and
+# command in profiles/k_tile_uniform4096_counters.md).
+FLOP_ITER = 451.7
+# hand counts of one evaluation-only pass and of the per-substep work, used
+# by the Gauss-Seidel sweep count below
 FLOP_EVAL = 320
 FLOP_SUBSTEP = 100
 PEAK_FP32 = 157.3e12       # MI355X FP32 vector (published)
@@ -48,17 +52,17 @@ PEAK_FP32 = 157.3e12       # MI355X FP32 vector (published)
 # WRITE_SIZE runs scaled by a device copy of known size (summaries in
 # profiles/), keyed by workload, waves per workgroup and layout, with the digest of
 # the kernel sources they were taken on; a changed kernel reports null.
-MEASURED_TRAFFIC = {("uniform", 4, 1): 113.8e6, ("uneven", 4, 1): 696.3e6, ("stiff", 16, 1): 123.3e6}
-TRAFFIC_SOURCES_DIGEST = "91c62fffee1bdbe0:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"
+MEASURED_TRAFFIC = {("uniform", 4, 1): 115.9e6, ("uneven", 4, 1): 710.5e6, ("stiff", 16, 1): 123.3e6}
+TRAFFIC_SOURCES_DIGEST = "5f4411ff433f7b77:06967e1b979b9c85:bb2ea3129ebb4d43:96fa7fd0a2beec66:c6116ad10c3ff82b"
 PEAK_HBM = 8.0e12
 # the same for the other solvers' kernels on the uniform batch (--solver),
 # with the digest of their sources
-SOLVER_TRAFFIC = {"newton": (337.0e6, ("newton.hip", "lanes.h", "blocks.h", "device_math.h", "kernels.h"),
-                             "03507154f969a960:7d1acb2a40eb1590:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"),
-                  "carriage": (126.1e6, ("carriage.hip", "carriage.h", "lanes.h", "blocks.h", "device_math.h",
-                                         "kernels.h"), "de6cffb718471c85:b17d334d03f00823:7d1acb2a40eb1590:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726"),
-                  "gs": (52.8e6, ("gs.hip", "blocks.h", "device_math.h", "kernels.h"),
-                         "a845d97590629bbd:d9b1e61db4cc8d70:959545d7849e09a9:482cc8068db4d726")}
+# keyed by solver and workload at its default size
+SOLVER_TRAFFIC = {("newton", "uniform"): (337.1e6, ("newton.hip", "lanes.h", "blocks.h", "device_math.h", "kernels.h"),
+                                         "03507154f969a960:7d1acb2a40eb1590:06967e1b979b9c85:bb2ea3129ebb4d43:96fa7fd0a2beec66"),
+                  ("gs", "uniform"): (52.75e6, ("gs.hip", "blocks.h", "device_math.h", "kernels.h"), "a845d97590629bbd:06967e1b979b9c85:bb2ea3129ebb4d43:96fa7fd0a2beec66"),
+                  ("carriage", "uneven"): (206.9e6, ("carriage.hip", "carriage.h", "lanes.h", "blocks.h",
+                                                     "device_math.h", "kernels.h"), "de6cffb718471c85:b17d334d03f00823:7d1acb2a40eb1590:06967e1b979b9c85:bb2ea3129ebb4d43:96fa7fd0a2beec66")}
 # Newton solver (FP64): operations per body per inner conjugate-residual
 # iteration and per Newton iteration outside it (block evaluation, residual,
 # rows, the two initial products, the update), counted from the compiled
@@ -133,7 +137,7 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_digest(files=("step.hip", "blocks.h", "device_math.h", "kernels.h")):
+def kernel_digest(files=("step.hip", "blocks.h", "device_math.h", "kernels.h", "net_inputs.h")):
     import hashlib
     csrc = os.path.join(ROOT, "paper_1904_02833_amd", "csrc")
     return ":".join(hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()[:16] for f in files)
@@ -367,7 +371,7 @@ def newton_comparison(wl, n_steps=5):
             "rows": rows}
 
 
-def carriage_run(wl, n_steps=5, iters=CARRIAGE_ITERS):
+def carriage_run(wl, n_steps=5, iters=CARRIAGE_ITERS, default_size=True):
     """The batch on wheels (two per segment on hinge joints, FP64 Jacobi
     iterations) from the state after 20 steps on wheels: time per step, the
     residual reached and the kernel's FP64 throughput."""
@@ -393,8 +397,9 @@ def carriage_run(wl, n_steps=5, iters=CARRIAGE_ITERS):
     B = float(cw.bodies.sum())
     ach = B * cw.substeps * (iters * FLOP_CARRIAGE_ITER + FLOP_CARRIAGE_SUBSTEP) / (ms / 1e3)
     traffic = None
-    if wl.name == "uniform" and wl.n_snakes == 4096:
-        t, files, digest = SOLVER_TRAFFIC["carriage"]
+    key = ("carriage", wl.name)
+    if key in SOLVER_TRAFFIC and default_size:
+        t, files, digest = SOLVER_TRAFFIC[key]
         traffic = t if kernel_digest(files) == digest else None
     return {"workload": f"{wl.name} on wheels: {cw.n_snakes} snakes, {int(B)} segments, {int(2 * B)} wheels, "
                         f"{cw.substeps} substeps, {iters} iterations",
@@ -407,12 +412,17 @@ def carriage_run(wl, n_steps=5, iters=CARRIAGE_ITERS):
                          "flop_per_segment_iter": FLOP_CARRIAGE_ITER}}
 
 
-# Full-resolution link (FP32): VALU operations per element-iteration and
-# per distance-row / attachment-iteration and per particle-iteration
-# (gather, contact), from the rocprofv3 VALU instruction counters of the
-# kernel (summary in profiles/), the element dominating.
+# Full-resolution link (FP32): operations of the link kernel per
+# link-iteration (288 elements, 196 distance rows, 18 attachments and the
+# gather and contact of 117 particles, the elements dominating), from its
+# VALU counters on the link batch: SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes /
+# (2048 snakes x 4 links x 80 iterations) = 64 x 1.253e9 / 655 360
+# (profiles/k_link_link2048x4.md).  HBM bytes per launch from FETCH_SIZE
+# and WRITE_SIZE on that batch, with the digest of the kernel's sources.
 LINK_SNAKES = 2048
 LINK_STEPS = 10
+LINK_FLOP_ITER = 122_360
+LINK_TRAFFIC = (196.8e6, 2048, ("link.hip", "device_math.h"), "c07ab16c434133ae:bb2ea3129ebb4d43")
 
 
 def link_run(n_snakes=LINK_SNAKES, n_steps=LINK_STEPS, iters=20):
@@ -447,6 +457,17 @@ def link_run(n_snakes=LINK_SNAKES, n_steps=LINK_STEPS, iters=20):
     sim.close()
     tets = n_snakes * wl.n_links * wl.n_tets
     its = float(np.mean(r["iters"]))
+    # algorithmic HBM bytes per snake-step: particle positions and velocities
+    # in; positions, velocities, contact multipliers out; frame states in and
+    # out; pressures and commands; every multiplier out; the four status words
+    L, P1 = wl.n_links, wl.per_link
+    D1 = (wl.sections - 1) * (wl.ring + 1) + (wl.sections - 2) * wl.ring
+    A1 = 2 * (wl.ring + 1)
+    per_snake = (L * P1 * (24 + 36) + (L + 1) * 2 * 52 + L * (8 + 4 + 8)
+                 + L * (24 * wl.n_tets + 4 * D1 + 12 * A1) + 16)
+    flops = LINK_FLOP_ITER * n_snakes * L * its / (ms / 1e3)
+    t, n_ref, files, digest = LINK_TRAFFIC
+    traffic = t if (n_snakes == n_ref and kernel_digest(files) == digest) else None
     return {"workload": f"link: {n_snakes} snakes x {wl.n_links} soft links ({wl.per_link} particles, {wl.n_tets} "
                         f"tetrahedra per link) and {wl.n_links + 1} rigid frames, {wl.substeps} substeps x {iters} "
                         "iterations, drawn chamber commands",
@@ -455,7 +476,12 @@ def link_run(n_snakes=LINK_SNAKES, n_steps=LINK_STEPS, iters=20):
             "iters_per_step": its,
             "residual_last_step": {"median": float(np.median(r["residual"])),
                                    "max": float(np.max(r["residual"]))},
-            "nonfinite_snakes": int(np.sum((r["status"] & 1) != 0))}
+            "nonfinite_snakes": int(np.sum((r["status"] & 1) != 0)),
+            "roofline": {"bound": "alu", "achieved": flops / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                         "frac": flops / PEAK_FP32, "traffic": traffic, "kernel": "k_link", "dtype": "f32",
+                         "flop_per_link_iter": LINK_FLOP_ITER,
+                         "hbm_bytes_algorithmic": per_snake * n_snakes,
+                         "hbm_frac_algorithmic": per_snake * n_snakes / (ms / 1e3) / PEAK_HBM}}
 
 
 def host_cores():
@@ -685,7 +711,7 @@ def main():
     secs = ms / 1e3
     snake_steps = wl.n_snakes * args.steps / secs
     citers = float(np.sum(rows * its)) / secs
-    flops = float(np.sum(B * (its * FLOP_ITER + args.steps * wl.substeps * (FLOP_EVAL + FLOP_SUBSTEP))))
+    flops = float(np.sum(B * its)) * FLOP_ITER
     if newton:
         flops = float(B.sum()) * args.steps * wl.substeps * (
             ni * (FLOP_NEWTON_ITER + npc * FLOP_PCR_ITER) + FLOP_NEWTON_SUBSTEP)
@@ -694,11 +720,12 @@ def main():
     per_launch_ms = ms / args.steps
     achieved = flops / args.steps / (per_launch_ms / 1e3)
     hbm_bytes = float(B.sum()) * STATE_BYTES
-    traffic = MEASURED_TRAFFIC.get((args.workload, sim.mapping["waves"], sim.mapping["rows"]))
+    traffic = (MEASURED_TRAFFIC.get((args.workload, sim.mapping["waves"], sim.mapping["rows"]))
+               if args.snakes is None else None)
     if newton or gs:
         traffic = None
-        if args.workload == "uniform":
-            t, files, digest = SOLVER_TRAFFIC[args.solver]
+        if (args.solver, args.workload) in SOLVER_TRAFFIC and args.snakes is None:
+            t, files, digest = SOLVER_TRAFFIC[(args.solver, args.workload)]
             traffic = t if kernel_digest(files) == digest else None
     elif traffic is not None and kernel_digest() != TRAFFIC_SOURCES_DIGEST:
         traffic = None
@@ -754,7 +781,7 @@ def main():
         out["newton_pcr"] = newton_comparison(wl)
         print("[bench] solver comparison done", file=sys.stderr, flush=True)
     if not args.no_carriage:
-        out["wheel_carriage"] = carriage_run(wl)
+        out["wheel_carriage"] = carriage_run(wl, default_size=args.snakes is None)
     if not args.no_link:
         out["full_resolution_link"] = link_run()
         print("[bench] link done", file=sys.stderr, flush=True)
