@@ -53,6 +53,20 @@ def test_link_substep_parity(steps):
     assert_parity(f"link substep after {steps} steps", compare(o, g), wl.particles * wl.n_snakes)
 
 
+@pytest.mark.parametrize("sections,ring", [(5, 4), (7, 12)])
+def test_link_substep_parity_other_meshes(sections, ring):
+    """Other cross-section counts and ring sizes (four and twelve ring
+    particles: five and thirteen attachments per end section, so the frames'
+    sums run their read-ahead groups with and without a remainder; longer
+    and shorter incidence lists): one substep from the oracle's state after
+    four steps of drawn commands."""
+    wl = W.make_link(3, n_links=3, sections=sections, ring=ring)
+    st = state_after(wl, 4, seed=11)
+    o, g = advance_both(wl, st)
+    assert np.array_equal(np.asarray(g["iters"]), o.iters)
+    assert_parity(f"link mesh {sections}x{ring}", compare(o, g), wl.particles * wl.n_snakes)
+
+
 def test_link_whole_step_substep_by_substep():
     """A whole step (four substeps) in one launch equals four one-substep
     launches bit for bit; each of those is held to the per-substep gates
