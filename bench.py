@@ -553,6 +553,21 @@ def cpu_baseline(wl, n_snakes, n_steps, gpu_kw):
                                   f"residual<=1e-4 or at most {ow.iters} iterations" if ow.tol > 0 else
                                   f"first {nst} steps of {ow.n_snakes} snakes, {ow.iters} iterations"}
     out["other_batches"] = others
+    # the FP64 network's inference cost for the learned start (one thread):
+    # rows of 32 inputs through 32 -> 64 -> 64 -> 3 with exact-erf GELU
+    rng = np.random.default_rng(7)
+    n_rows = 1 << 16
+    params = rng.normal(scale=0.2, size=oracle.mlp_param_count())
+    xs = rng.normal(size=(n_rows, 32))
+    t0 = time.perf_counter()
+    oracle.mlp_forward(params, np.zeros(32), np.ones(32), xs)
+    t_net = time.perf_counter() - t0
+    rows_uneven = 2 * int(np.sum(wl.bodies - 1))
+    out["network_inference"] = {"rows_per_s": n_rows / t_net, "seconds": t_net, "cores": 1,
+                                "sample": f"{n_rows} rows of 32 inputs, random weights of the network's shape, "
+                                          "FP64 C oracle with exact-erf GELU",
+                                "per_substep_s_timed_batch": rows_uneven / (n_rows / t_net),
+                                "rows_per_substep_timed_batch": rows_uneven}
     o.commands()
     oo, g = advance_both(sub, rounded_state(o), threads=threads, **gpu_kw)
     err = compare(oo, g, np.asarray(sub.mu, np.float64))
