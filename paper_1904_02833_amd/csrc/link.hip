@@ -243,10 +243,13 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
     }
 
     const int64_t gp = (int64_t)s * NP + tid;     // particle
-    const int64_t gf = (int64_t)s * NF + tid;     // frame
+    // frames on the last wave's lanes, which hold no particle when the snake
+    // has at most 960: their update runs beside the particles' gathers
+    const int ft = tid - (kThreads - 64);
+    const int64_t gf = (int64_t)s * NF + ft;      // frame
     const int64_t gl = (int64_t)s * L + tid;      // link
-    const bool isp = tid < NP, isf = tid < NF, isl = tid < L;
-    const bool ffix = P.fixed0 && tid == 0;
+    const bool isp = tid < NP, isf = ft >= 0 && ft < NF, isl = tid < L;
+    const bool ffix = P.fixed0 && ft == 0;
 
     // particle state in registers
     V3 x = mk(0.f, 0.f, 0.f), v = x, lc = x, d = x, dlc = x;
@@ -266,7 +269,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
     const float mu = P.mu[s];
     // frame and link state in LDS
     if (isf) {
-        float* f = S.fr + kFr * tid;
+        float* f = S.fr + kFr * ft;
         f[0] = P.fx[gf], f[1] = P.fx[P.NF + gf], f[2] = P.fx[2 * P.NF + gf];
         f[6] = P.fq[gf], f[7] = P.fq[P.NF + gf], f[8] = P.fq[2 * P.NF + gf], f[9] = P.fq[3 * P.NF + gf];
         f[10] = P.fv[gf], f[11] = P.fv[P.NF + gf], f[12] = P.fv[2 * P.NF + gf];
@@ -323,7 +326,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                 st3(my + 3, d);
             }
             if (isf) {
-                float* f = S.fr + kFr * tid;
+                float* f = S.fr + kFr * ft;
                 Q4 q{f[6], f[7], f[8], f[9]};
                 f[16] = q.w, f[17] = q.x, f[18] = q.y, f[19] = q.z;
                 V3 fv = mk(f[10], f[11], f[12]), fw = mk(f[13], f[14], f[15]), fd = mk(0.f, 0.f, 0.f);
@@ -547,17 +550,16 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                     // every block's share, in the particle's list order
                     // (elements, distance rows, attachment), from its slots
                     // (four read ahead of the sums)
-                    const float* vp = S.V + 3 * (pl * n_inc);
-                    int e = inc0;
-                    for (; e + 4 <= inc1; e += 4) {
-                        const V3 v0 = ld3(vp + 3 * e), v1 = ld3(vp + 3 * e + 3);
-                        const V3 v2 = ld3(vp + 3 * e + 6), v3 = ld3(vp + 3 * e + 9);
+                    int o = 3 * (pl * n_inc + inc0), e = inc0;
+                    for (; e + 4 <= inc1; e += 4, o += 12) {
+                        const V3 v0 = ld3(S.V + o), v1 = ld3(S.V + o + 3);
+                        const V3 v2 = ld3(S.V + o + 6), v3 = ld3(S.V + o + 9);
                         fsum = fsum + v0;
                         fsum = fsum + v1;
                         fsum = fsum + v2;
                         fsum = fsum + v3;
                     }
-                    for (; e < inc1; ++e) fsum = fsum + ld3(vp + 3 * e);
+                    for (; e < inc1; ++e, o += 3) fsum = fsum + ld3(S.V + o);
                     if (P.ground) {
                         lc = lc + dlc;
                         fsum = fsum + mk(dlc.y, dlc.z, dlc.x);
@@ -566,29 +568,29 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                     st3(my + 3, d);
                 }
                 if (isf && !ffix) {
-                    float* f = S.fr + kFr * tid;
+                    float* f = S.fr + kFr * ft;
                     const Q4 q{f[6], f[7], f[8], f[9]};
                     V3 F = mk(0.f, 0.f, 0.f), tq = F;
                     // link f-1's last section, then link f's first
                     for (int side = 0; side < 2; ++side) {
-                        const int l = tid - 1 + side;
+                        const int l = ft - 1 + side;
                         if (l < 0 || l >= L) continue;
                         const int a0 = side == 0 ? A1 / 2 : 0, a1 = side == 0 ? A1 : A1 / 2;
                         // the attachments' increments and torques, in order
                         // (three read ahead of the sums)
-                        const float* da = S.da + 6 * (l * A1);
+                        int o = 6 * (l * A1 + a0);
                         int a = a0;
-                        for (; a + 3 <= a1; a += 3) {
-                            const V3 d0 = ld3(da + 6 * a), t0 = ld3(da + 6 * a + 3);
-                            const V3 d1 = ld3(da + 6 * a + 6), t1 = ld3(da + 6 * a + 9);
-                            const V3 d2 = ld3(da + 6 * a + 12), t2 = ld3(da + 6 * a + 15);
+                        for (; a + 3 <= a1; a += 3, o += 18) {
+                            const V3 d0 = ld3(S.da + o), t0 = ld3(S.da + o + 3);
+                            const V3 d1 = ld3(S.da + o + 6), t1 = ld3(S.da + o + 9);
+                            const V3 d2 = ld3(S.da + o + 12), t2 = ld3(S.da + o + 15);
                             F = F + d0, tq = tq + t0;
                             F = F + d1, tq = tq + t1;
                             F = F + d2, tq = tq + t2;
                         }
-                        for (; a < a1; ++a) {
-                            F = F + ld3(da + 6 * a);
-                            tq = tq + ld3(da + 6 * a + 3);
+                        for (; a < a1; ++a, o += 6) {
+                            F = F + ld3(S.da + o);
+                            tq = tq + ld3(S.da + o + 3);
                         }
                     }
                     const V3 th = frame_inv_inertia(P, q, tq);
@@ -607,7 +609,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                 v = P.inv_h * d;
             }
             if (isf && !ffix) {
-                float* f = S.fr + kFr * tid;
+                float* f = S.fr + kFr * ft;
                 const V3 fd = mk(f[3], f[4], f[5]);
                 f[0] += fd.x, f[1] += fd.y, f[2] += fd.z;
                 f[10] = P.inv_h * fd.x, f[11] = P.inv_h * fd.y, f[12] = P.inv_h * fd.z;
@@ -626,7 +628,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
         P.lam_c[gp] = lc.x, P.lam_c[P.NP + gp] = lc.y, P.lam_c[2 * P.NP + gp] = lc.z;
     }
     if (isf) {
-        const float* f = S.fr + kFr * tid;
+        const float* f = S.fr + kFr * ft;
         P.fx[gf] = f[0], P.fx[P.NF + gf] = f[1], P.fx[2 * P.NF + gf] = f[2];
         P.fq[gf] = f[6], P.fq[P.NF + gf] = f[7], P.fq[2 * P.NF + gf] = f[8], P.fq[3 * P.NF + gf] = f[9];
         P.fv[gf] = f[10], P.fv[P.NF + gf] = f[11], P.fv[2 * P.NF + gf] = f[12];
