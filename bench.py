@@ -422,7 +422,7 @@ def carriage_run(wl, n_steps=5, iters=CARRIAGE_ITERS, default_size=True):
 LINK_SNAKES = 2048
 LINK_STEPS = 10
 LINK_FLOP_ITER = 122_360
-LINK_TRAFFIC = (196.8e6, 2048, ("link.hip", "device_math.h"), "c07ab16c434133ae:bb2ea3129ebb4d43")
+LINK_TRAFFIC = (212.6e6, 2048, ("link.hip", "device_math.h"), "0cd65eec911c0c25:bb2ea3129ebb4d43")
 
 
 def link_run(n_snakes=LINK_SNAKES, n_steps=LINK_STEPS, iters=20):
