@@ -140,7 +140,9 @@ __device__ __forceinline__ V3 frame_inv_inertia(const Params& P, Q4 q, V3 t)
 // element record: g_0..g_3 (12), L (15), 1/D (6), E/h^2 (3), scale, vertices,
 // the gather slots of its four vertices (4), pad
 constexpr int kTR = 43;
-constexpr int kDR = 9;    // distance row: rest, w_i, w_j, scale, i | j << 16, kind, slots of i and j, pad
+// distance row: rest, w_i, w_j, scale, i | j << 16, kind, slots of i and j,
+// -scale / (w_i + w_j + rigid compliance)
+constexpr int kDR = 9;
 constexpr int kAR = 7;    // attachment: r (3), w_p, particle degree, particle, slot
 constexpr int kPR = 7;    // particle: start-of-substep position (3), displacement (3), pad
 constexpr int kFr = 20;   // frame: xp (3), d (3), q (4), v (3), w (3), q at the substep start (4)
@@ -220,7 +222,8 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
         const int e = i / kDR, f = i - e * kDR;
         if (f == 6 || f == 7) continue;
         S.dr[i] = f < 4 ? P.dist_c[f * D1 + e] : f == 4 ? __int_as_float(P.dist_ij[e])
-                                                : f == 5 ? __int_as_float(P.dist_kind[e]) : 0.f;
+                  : f == 5 ? __int_as_float(P.dist_kind[e])
+                           : -P.dist_c[3 * D1 + e] / (P.dist_c[D1 + e] + P.dist_c[2 * D1 + e] + P.a_rigid);
     }
     for (int i = tid; i < kAR * A1; i += kThreads) {
         const int e = i / kAR, f = i - e * kAR;
@@ -460,9 +463,9 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                             const float rest = c[0] * (1.f + press * P.young_inv_pmax);
                             const float rr = (len - rest) + P.a_rigid * lam[k][0];
                             res = fmaxf(res, fabsf(rr) * P.Lref_inv);
-                            const float dl = -c[3] * rr / (c[1] + c[2] + P.a_rigid);
+                            const float dl = c[8] * rr;
                             pend[k][0] = dl;
-                            im = (dl / len) * df;
+                            im = (dl * __builtin_amdgcn_rcpf(len)) * df;
                         }
                         // + on the first particle, - on the second
                         st3(vb + 3 * __float_as_int(c[6]), im);
