@@ -2,9 +2,11 @@
 // mesh per link, rigid frames between links, solved by block Jacobi in FP32.
 //
 // Mapping (gfx950): one workgroup of 1024 threads (16 wave64) per snake.
-// Thread i owns particle i, frame i (i < frames) and link i (i < links), and
-// the blocks b = i and b = i + 1024 of the snake's block list (tetrahedra,
-// distance rows, attachments).  A block keeps its multipliers, its pending
+// Thread i owns link i (i < links) and the blocks b = i and b = i + 1024 of
+// the snake's block list (tetrahedra, distance rows, attachments).  Each
+// particle has an aligned group of 1, 2, 4 or 8 lanes (a host-built plan,
+// more lanes for the particles with more incident blocks), whose first lane
+// holds the particle; each frame has a group of eight lanes in the last wave.  A block keeps its multipliers, its pending
 // increment and its start-of-substep geometry in registers for the whole
 // launch; the per-mesh constants (shared by every link of every snake) are
 // read through the caches.  One iteration: every block evaluates itself at
@@ -14,14 +16,16 @@
 // particle; an attachment its increment); the workgroup's residual maximum
 // decides the stop; then every particle gathers its blocks in the fixed
 // order of the mesh's incidence list (tetrahedra, distance rows,
-// attachment, its own contact) and every frame its attachments.  Two
-// barriers per iteration.  Positions are the start-of-substep position plus
+// attachment, its own contact) and every frame its attachments, each group
+// summing its members' ranges of the list and adding the partial sums
+// pairwise.  Two barriers per iteration.  Positions are the start-of-substep position plus
 // a displacement: edges and attachment gaps are formed from the
 // start-of-substep differences (computed once per substep) plus
 // displacement differences, so they keep FP32 precision far from the
 // origin.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -81,9 +85,16 @@ struct Params {
     const float* part_w;            // [P1] inverse masses
     const float* part_m;            // [P1] masses
     const int* part_deg;            // [P1] blocks touching the particle
-    const int* inc_off;             // [P1 + 1]
-    const int* inc;                 // incidence entries
+    const int* inc;                 // incidence entries, particle by particle
+    const int* gplan;               // [2][1024] per lane: particle | log2 group << 16 (-1: none),
+                                    // first | end << 16 of its range of the incidence entries
+    int gmax;                       // largest particle group
 };
+
+__device__ __forceinline__ V3 lane_xor(V3 v, int m)
+{
+    return mk(__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64), __shfl_xor(v.z, m, 64));
+}
 
 __device__ __forceinline__ float wave_max(float v)
 {
@@ -151,8 +162,6 @@ struct Lds {
     float* tr;    // [Tm][kTR]
     float* dr;    // [D1][kDR]
     float* ar;    // [A1][kAR]
-    int* ioff;    // [P1 + 1]
-    int* inc;     // incidence entries
     float* pr;    // [P][kPR]
     float* V;     // [L][n_inc][3] what each block sends each of its particles, in the
                   // particles' gather order (slot = incidence entry)
@@ -166,8 +175,7 @@ struct Lds {
 __host__ __device__ inline int lds_words(int L, int P1, int Tm, int D1, int A1, int n_inc)
 {
     const int P = L * P1, T = L * Tm, D = L * D1, A = L * A1;
-    return kTR * Tm + kDR * D1 + kAR * A1 + (P1 + 1) + n_inc + kPR * P + 3 * L * n_inc + 6 * A +
-           kFr * (L + 1) + 4 * L + kWaves;
+    return kTR * Tm + kDR * D1 + kAR * A1 + kPR * P + 3 * L * n_inc + 6 * A + kFr * (L + 1) + 4 * L + kWaves;
 }
 
 __device__ __forceinline__ V3 ld3(const float* a) { return mk(a[0], a[1], a[2]); }
@@ -192,8 +200,6 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
         S.tr = w, w += kTR * Tm;
         S.dr = w, w += kDR * D1;
         S.ar = w, w += kAR * A1;
-        S.ioff = reinterpret_cast<int*>(w), w += P1 + 1;
-        S.inc = reinterpret_cast<int*>(w), w += n_inc;
         S.pr = w, w += kPR * NP;
         S.V = w, w += 3 * L * n_inc;
         S.da = w, w += 6 * A;
@@ -230,12 +236,10 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
         if (f == 6) continue;
         S.ar[i] = f < 5 ? P.att_c[f * A1 + e] : __int_as_float(P.att_p[e]);
     }
-    for (int i = tid; i < P1 + 1; i += kThreads) S.ioff[i] = P.inc_off[i];
     // incidence entry i is gather slot i: each block records the slots of
     // its particles (one entry per block and particle)
     for (int i = tid; i < n_inc; i += kThreads) {
         const int ent = P.inc[i];
-        S.inc[i] = ent;
         const int type = ent >> 28, blk = (ent >> 2) & 0x3ffffff, slot = ent & 3;
         if (type == kIncTet)
             S.tr[kTR * blk + 38 + slot] = __int_as_float(i);
@@ -245,34 +249,41 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
             S.ar[kAR * blk + 6] = __int_as_float(i);
     }
 
-    const int64_t gp = (int64_t)s * NP + tid;     // particle
-    // frames on the last wave's lanes, which hold no particle when the snake
-    // has at most 960: their update runs beside the particles' gathers
-    const int ft = tid - (kThreads - 64);
-    const int64_t gf = (int64_t)s * NF + ft;      // frame
+    // this lane's particle group: the particle, the group's size, the
+    // lane's range of the particle's incidence entries; the group's first
+    // lane holds the particle
+    const int gw0 = P.gplan[tid], gw1 = P.gplan[kThreads + tid];
+    const bool isg = gw0 >= 0;
+    const int pidx = isg ? gw0 & 0xffff : 0, gsize = isg ? 1 << (gw0 >> 16) : 1;
+    const int e0 = gw1 & 0xffff, e1 = gw1 >> 16;
+    const bool isp = isg && (tid & (gsize - 1)) == 0;
+    const int64_t gp = (int64_t)s * NP + pidx;    // particle
+    // frame groups of eight lanes in the last wave, which holds no particle
+    // when the snake has at most 960: their sums run beside the particles'
+    const int fj = tid - (kThreads - 64), fi = fj >> 3, fsub = fj & 7;
+    const bool isfg = fj >= 0 && fi < NF, isf = isfg && fsub == 0;
+    const int64_t gf = (int64_t)s * NF + fi;      // frame
     const int64_t gl = (int64_t)s * L + tid;      // link
-    const bool isp = tid < NP, isf = ft >= 0 && ft < NF, isl = tid < L;
-    const bool ffix = P.fixed0 && ft == 0;
+    const bool isl = tid < L;
+    const bool ffix = P.fixed0 && fi == 0;
 
     // particle state in registers
     V3 x = mk(0.f, 0.f, 0.f), v = x, lc = x, d = x, dlc = x;
     float wp = 0.f, pmass = 0.f, cscale = 0.f;
-    int pl = 0, pk = 0;
+    const int pl = pidx / P1, pk = pidx - pl * P1;
     if (isp) {
         x = mk(P.x[gp], P.x[P.NP + gp], P.x[2 * P.NP + gp]);
         v = mk(P.v[gp], P.v[P.NP + gp], P.v[2 * P.NP + gp]);
         lc = mk(P.lam_c[gp], P.lam_c[P.NP + gp], P.lam_c[2 * P.NP + gp]);
-        pl = tid / P1;
-        pk = tid - pl * P1;
         wp = P.part_w[pk];
         pmass = P.part_m[pk];
         cscale = P.relax / (float)P.part_deg[pk];
     }
-    float* const my = S.pr + kPR * tid;   // this thread's particle record
+    float* const my = S.pr + kPR * pidx;   // this group's particle record
     const float mu = P.mu[s];
     // frame and link state in LDS
     if (isf) {
-        float* f = S.fr + kFr * ft;
+        float* f = S.fr + kFr * fi;
         f[0] = P.fx[gf], f[1] = P.fx[P.NF + gf], f[2] = P.fx[2 * P.NF + gf];
         f[6] = P.fq[gf], f[7] = P.fq[P.NF + gf], f[8] = P.fq[2 * P.NF + gf], f[9] = P.fq[3 * P.NF + gf];
         f[10] = P.fv[gf], f[11] = P.fv[P.NF + gf], f[12] = P.fv[2 * P.NF + gf];
@@ -299,7 +310,6 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
         for (int r = 0; r < 6; ++r) pend[k][r] = 0.f;
     }
     __syncthreads();
-    const int inc0 = isp ? S.ioff[pk] : 0, inc1 = isp ? S.ioff[pk + 1] : 0;
 
     float rstep = 0.f;
     int itstep = 0, status = 0, itsum = 0;
@@ -329,7 +339,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                 st3(my + 3, d);
             }
             if (isf) {
-                float* f = S.fr + kFr * ft;
+                float* f = S.fr + kFr * fi;
                 Q4 q{f[6], f[7], f[8], f[9]};
                 f[16] = q.w, f[17] = q.x, f[18] = q.y, f[19] = q.z;
                 V3 fv = mk(f[10], f[11], f[12]), fw = mk(f[13], f[14], f[15]), fd = mk(0.f, 0.f, 0.f);
@@ -548,21 +558,35 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         for (int q = 0; q < 3; ++q) lam[k][q] += pend[k][q];
                     }
                 }
-                if (isp) {
-                    V3 fsum = mk(0.f, 0.f, 0.f);
-                    // every block's share, in the particle's list order
-                    // (elements, distance rows, attachment), from its slots
-                    // (four read ahead of the sums)
-                    int o = 3 * (pl * n_inc + inc0), e = inc0;
-                    for (; e + 4 <= inc1; e += 4, o += 12) {
-                        const V3 v0 = ld3(S.V + o), v1 = ld3(S.V + o + 3);
-                        const V3 v2 = ld3(S.V + o + 6), v3 = ld3(S.V + o + 9);
+                // particles: every lane of a group sums its range of the
+                // particle's slots in list order (four read ahead), the group
+                // adds the partial sums pairwise, the first lane applies
+                V3 fsum = mk(0.f, 0.f, 0.f);
+                if (isg) {
+                    const float* vb = S.V + 3 * pl * n_inc;
+                    int e = e0;
+                    for (; e + 4 <= e1; e += 4) {
+                        const V3 v0 = ld3(vb + 3 * e), v1 = ld3(vb + 3 * e + 3);
+                        const V3 v2 = ld3(vb + 3 * e + 6), v3 = ld3(vb + 3 * e + 9);
                         fsum = fsum + v0;
                         fsum = fsum + v1;
                         fsum = fsum + v2;
                         fsum = fsum + v3;
                     }
-                    for (; e < inc1; ++e, o += 3) fsum = fsum + ld3(S.V + o);
+                    if (e < e1) {
+                        // the last one to three entries, read together
+                        const V3 v0 = ld3(vb + 3 * e);
+                        const V3 v1 = ld3(vb + 3 * min(e + 1, e1 - 1)), v2 = ld3(vb + 3 * min(e + 2, e1 - 1));
+                        fsum = fsum + v0;
+                        if (e + 1 < e1) fsum = fsum + v1;
+                        if (e + 2 < e1) fsum = fsum + v2;
+                    }
+                }
+                for (int off = 1; off < P.gmax; off <<= 1) {
+                    const V3 o = lane_xor(fsum, off);
+                    if (off < gsize) fsum = fsum + o;
+                }
+                if (isp) {
                     if (P.ground) {
                         lc = lc + dlc;
                         fsum = fsum + mk(dlc.y, dlc.z, dlc.x);
@@ -570,20 +594,19 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                     d = d + wp * fsum;
                     st3(my + 3, d);
                 }
-                if (isf && !ffix) {
-                    float* f = S.fr + kFr * ft;
-                    const Q4 q{f[6], f[7], f[8], f[9]};
+                // frames (the last wave): lanes 0-3 of a frame's group sum
+                // quarters of link f-1's last section's attachments, lanes
+                // 4-7 quarters of link f's first section's, in list order
+                if (fj >= 0) {
                     V3 F = mk(0.f, 0.f, 0.f), tq = F;
-                    // link f-1's last section, then link f's first
-                    for (int side = 0; side < 2; ++side) {
-                        const int l = ft - 1 + side;
-                        if (l < 0 || l >= L) continue;
-                        const int a0 = side == 0 ? A1 / 2 : 0, a1 = side == 0 ? A1 : A1 / 2;
-                        // the attachments' increments and torques, in order
-                        // (three read ahead of the sums)
-                        int o = 6 * (l * A1 + a0);
-                        int a = a0;
-                        for (; a + 3 <= a1; a += 3, o += 18) {
+                    const int l = fi - 1 + (fsub >> 2);
+                    if (isfg && !ffix && l >= 0 && l < L) {
+                        const int a0 = fsub < 4 ? A1 / 2 : 0, a1 = fsub < 4 ? A1 : A1 / 2;
+                        const int ch = (a1 - a0 + 3) >> 2;
+                        const int lo = min(a1, a0 + (fsub & 3) * ch), hi = min(a1, lo + ch);
+                        int o = 6 * (l * A1 + lo);
+                        int a = lo;
+                        for (; a + 3 <= hi; a += 3, o += 18) {
                             const V3 d0 = ld3(S.da + o), t0 = ld3(S.da + o + 3);
                             const V3 d1 = ld3(S.da + o + 6), t1 = ld3(S.da + o + 9);
                             const V3 d2 = ld3(S.da + o + 12), t2 = ld3(S.da + o + 15);
@@ -591,15 +614,24 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                             F = F + d1, tq = tq + t1;
                             F = F + d2, tq = tq + t2;
                         }
-                        for (; a < a1; ++a, o += 6) {
+                        for (; a < hi; ++a, o += 6) {
                             F = F + ld3(S.da + o);
                             tq = tq + ld3(S.da + o + 3);
                         }
                     }
-                    const V3 th = frame_inv_inertia(P, q, tq);
-                    const Q4 qn = qturn(q, th);
-                    f[3] += P.frame_w * F.x, f[4] += P.frame_w * F.y, f[5] += P.frame_w * F.z;
-                    f[6] = qn.w, f[7] = qn.x, f[8] = qn.y, f[9] = qn.z;
+#pragma unroll
+                    for (int off = 1; off < 8; off <<= 1) {
+                        F = F + lane_xor(F, off);
+                        tq = tq + lane_xor(tq, off);
+                    }
+                    if (isf && !ffix) {
+                        float* f = S.fr + kFr * fi;
+                        const Q4 q{f[6], f[7], f[8], f[9]};
+                        const V3 th = frame_inv_inertia(P, q, tq);
+                        const Q4 qn = qturn(q, th);
+                        f[3] += P.frame_w * F.x, f[4] += P.frame_w * F.y, f[5] += P.frame_w * F.z;
+                        f[6] = qn.w, f[7] = qn.x, f[8] = qn.y, f[9] = qn.z;
+                    }
                 }
                 __syncthreads();
                 ++k_it;
@@ -612,7 +644,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                 v = P.inv_h * d;
             }
             if (isf && !ffix) {
-                float* f = S.fr + kFr * ft;
+                float* f = S.fr + kFr * fi;
                 const V3 fd = mk(f[3], f[4], f[5]);
                 f[0] += fd.x, f[1] += fd.y, f[2] += fd.z;
                 f[10] = P.inv_h * fd.x, f[11] = P.inv_h * fd.y, f[12] = P.inv_h * fd.z;
@@ -631,7 +663,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
         P.lam_c[gp] = lc.x, P.lam_c[P.NP + gp] = lc.y, P.lam_c[2 * P.NP + gp] = lc.z;
     }
     if (isf) {
-        const float* f = S.fr + kFr * ft;
+        const float* f = S.fr + kFr * fi;
         P.fx[gf] = f[0], P.fx[P.NF + gf] = f[1], P.fx[2 * P.NF + gf] = f[2];
         P.fq[gf] = f[6], P.fq[P.NF + gf] = f[7], P.fq[2 * P.NF + gf] = f[8], P.fq[3 * P.NF + gf] = f[9];
         P.fv[gf] = f[10], P.fv[P.NF + gf] = f[11], P.fv[2 * P.NF + gf] = f[12];
@@ -847,6 +879,8 @@ struct Topo {
     int P1 = 0, Tm = 0, D1 = 0, A1 = 0;
     std::vector<int> dist_ij, dist_kind, dist_i, dist_j, att_p, deg_p, deg_f, inc_off, inc, tet_v, tets;
     std::vector<float> dist_c, att_c;
+    std::vector<int> gplan;   // [2][1024] the kernel's per-lane particle groups
+    int gmax = 1;
 };
 
 int axial_kind(int ring, int slot)
@@ -916,6 +950,50 @@ int validate(const link_desc_t* d, Sz* z)
 }
 
 // constraint lists of one link, degrees and the particles' incidence lists
+// The particles' lane groups of the link kernel.  Particle p's incidence
+// list of c entries is cut into g equal ranges, one per lane of an aligned
+// group of g lanes (g a power of two up to 8, so a group lies in one wave),
+// g the least that keeps every range within K entries, K the least for
+// which the groups fit below the frames' wave (when the particles need
+// more lanes, one lane each over the whole workgroup).
+void gather_plan(int L, Topo* t)
+{
+    const int P = L * t->P1, avail = P <= lk::kThreads - 64 ? lk::kThreads - 64 : lk::kThreads;
+    auto count = [&](int p) { return t->inc_off[p % t->P1 + 1] - t->inc_off[p % t->P1]; };
+    auto group = [](int c, int K) {
+        int g = 1;
+        while (g < 8 && g * K < c) g <<= 1;
+        return g;
+    };
+    auto lanes = [&](int K) {
+        int cur = 0;
+        for (int p = 0; p < P; ++p) {
+            const int g = group(count(p), K);
+            cur = ((cur + g - 1) & ~(g - 1)) + g;
+        }
+        return cur;
+    };
+    int cmax = 1;
+    for (int p = 0; p < t->P1; ++p) cmax = std::max(cmax, count(p));
+    int K = 1;
+    while (K < cmax && lanes(K) > avail) ++K;
+    t->gplan.assign(2 * lk::kThreads, 0);
+    for (int i = 0; i < lk::kThreads; ++i) t->gplan[i] = -1;
+    t->gmax = 1;
+    int cur = 0;
+    for (int p = 0; p < P; ++p) {
+        const int c = count(p), g = group(c, K), ch = (c + g - 1) / g, first = t->inc_off[p % t->P1];
+        const int lg = g == 1 ? 0 : g == 2 ? 1 : g == 4 ? 2 : 3;
+        cur = (cur + g - 1) & ~(g - 1);
+        for (int j = 0; j < g; ++j) {
+            t->gplan[cur + j] = p | lg << 16;
+            t->gplan[lk::kThreads + cur + j] = (first + std::min(c, j * ch)) | (first + std::min(c, (j + 1) * ch)) << 16;
+        }
+        cur += g;
+        t->gmax = std::max(t->gmax, g);
+    }
+}
+
 void topology(const link_desc_t* d, const Sz& z, Topo* t)
 {
     const int n = d->ring + 1, S = d->sections;
@@ -964,6 +1042,7 @@ void topology(const link_desc_t* d, const Sz& z, Topo* t)
         t->tet_v.push_back(v[0] | v[1] << 8 | v[2] << 16 | v[3] << 24);
     }
     for (int e = 0; e < t->D1; ++e) t->dist_ij.push_back(t->dist_i[e] | t->dist_j[e] << 16);
+    gather_plan(L, t);
 }
 
 struct Carve {
@@ -985,7 +1064,7 @@ struct Arrays {
     int *iters, *status, *iters_total;
     // constants and setup data
     float* mu;
-    int *tet_v, *dist_ij, *dist_kind, *att_p, *part_deg, *inc_off, *inc, *tets;
+    int *tet_v, *dist_ij, *dist_kind, *att_p, *part_deg, *gplan, *inc, *tets;
     float *tet_g, *tet_ldl, *tet_alpha, *tet_scale, *dist_c, *att_c, *part_w, *part_m;
     double *X, *mass;
 };
@@ -1015,7 +1094,7 @@ size_t carve(const Sz& z, int64_t n_inc, char* base, Arrays* a)
     a->dist_kind = c.take<int>(z.D1);
     a->att_p = c.take<int>(z.A1);
     a->part_deg = c.take<int>(z.P1);
-    a->inc_off = c.take<int>(z.P1 + 1);
+    a->gplan = c.take<int>(2 * lk::kThreads);
     a->inc = c.take<int>(n_inc);
     a->tets = c.take<int>(4 * z.Tm);
     a->tet_g = c.take<float>(12 * z.Tm);
@@ -1094,7 +1173,7 @@ int link_create(const link_desc_t* d, void* workspace, size_t bytes, void* hip_s
     up(A.dist_ij, t.dist_ij.data(), sizeof(int) * t.D1);
     up(A.dist_kind, t.dist_kind.data(), sizeof(int) * t.D1);
     up(A.att_p, t.att_p.data(), sizeof(int) * t.A1);
-    up(A.inc_off, t.inc_off.data(), sizeof(int) * t.inc_off.size());
+    up(A.gplan, t.gplan.data(), sizeof(int) * t.gplan.size());
     up(A.inc, t.inc.data(), sizeof(int) * t.inc.size());
     lk::Setup su{};
     su.P1 = t.P1, su.Tm = t.Tm;
@@ -1189,7 +1268,8 @@ int link_create(const link_desc_t* d, void* workspace, size_t bytes, void* hip_s
     P.NP = z.NP, P.NF = z.NF, P.NL = z.NL, P.NT = z.NT, P.ND = z.ND, P.NA = z.NA;
     P.tet_v = A.tet_v, P.tet_g = A.tet_g, P.tet_ldl = A.tet_ldl, P.tet_alpha = A.tet_alpha, P.tet_scale = A.tet_scale;
     P.dist_ij = A.dist_ij, P.dist_kind = A.dist_kind, P.dist_c = A.dist_c, P.att_p = A.att_p, P.att_c = A.att_c;
-    P.part_w = A.part_w, P.part_m = A.part_m, P.part_deg = A.part_deg, P.inc_off = A.inc_off, P.inc = A.inc;
+    P.part_w = A.part_w, P.part_m = A.part_m, P.part_deg = A.part_deg, P.inc = A.inc;
+    P.gplan = A.gplan, P.gmax = t.gmax;
     *out = s;
     return LINK_OK;
 }
