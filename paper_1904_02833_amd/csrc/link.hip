@@ -108,36 +108,49 @@ __device__ __forceinline__ float wave_max(float v)
 // Convergence is quadratic: with the iterate R (I + E), E symmetric, one
 // step leaves about E^2 / 2 and moves the iterate by about |E|, so a step
 // that moved no entry by more than 1e-4 (|E| below 3e-4 in norm) leaves an
-// error below 5e-8, under FP32 rounding, and ends the iteration.
+// error below 5e-8, under FP32 rounding, and ends the iteration; the first
+// step (from F) is not tested.  The iterate is kept as Z_k = 2^k R_k, so
+// that Z_{k+1} = Z_k + 4^k cof(Z_k) / det Z_k takes one fused multiply-add
+// per entry (R^-T = cof R / det R; the powers of two are exact).
+__device__ __forceinline__ bool polar_step(float* Z, float sc, float& diff, bool test)
+{
+    const float c00 = Z[4] * Z[8] - Z[5] * Z[7], c01 = Z[5] * Z[6] - Z[3] * Z[8], c02 = Z[3] * Z[7] - Z[4] * Z[6];
+    const float c10 = Z[2] * Z[7] - Z[1] * Z[8], c11 = Z[0] * Z[8] - Z[2] * Z[6], c12 = Z[1] * Z[6] - Z[0] * Z[7];
+    const float c20 = Z[1] * Z[5] - Z[2] * Z[4], c21 = Z[2] * Z[3] - Z[0] * Z[5], c22 = Z[0] * Z[4] - Z[1] * Z[3];
+    const float det = Z[0] * c00 + Z[1] * c01 + Z[2] * c02;
+    // hardware reciprocal (1 ulp): the iteration's fixed point is the
+    // rotation either way, within the convergence test
+    const float id = sc * __builtin_amdgcn_rcpf(det);
+    const float c[9] = {c00, c01, c02, c10, c11, c12, c20, c21, c22};
+    diff = 0.f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const float n = fmaf(c[k], id, Z[k]);
+        if (test) diff = fmaxf(diff, fabsf(fmaf(-2.f, Z[k], n)));
+        Z[k] = n;
+    }
+    return det > 0.f;
+}
+
 __device__ __forceinline__ bool polar(const float* F, float* R)
 {
+    float Z[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) R[k] = F[k];
-    bool ok = true;
+    for (int k = 0; k < 9; ++k) Z[k] = F[k];
+    float diff;
+    bool ok = polar_step(Z, 1.f, diff, false);
+    // after step k + 1: 4^(k+1), 2^-(k+1), and the bound on |Z_{k+1} - 2 Z_k|
+    float sc = 4.f, inv = 0.5f, lim = 4e-4f;
 #pragma unroll 2
-    for (int it = 0; it < 12; ++it) {
-        const float c00 = R[4] * R[8] - R[5] * R[7], c01 = R[5] * R[6] - R[3] * R[8], c02 = R[3] * R[7] - R[4] * R[6];
-        const float c10 = R[2] * R[7] - R[1] * R[8], c11 = R[0] * R[8] - R[2] * R[6], c12 = R[1] * R[6] - R[0] * R[7];
-        const float c20 = R[1] * R[5] - R[2] * R[4], c21 = R[2] * R[3] - R[0] * R[5], c22 = R[0] * R[4] - R[1] * R[3];
-        const float det = R[0] * c00 + R[1] * c01 + R[2] * c02;
-        if (!(det > 0.f)) {
-            ok = false;
-            break;
-        }
-        // hardware reciprocal (1 ulp): the iteration's fixed point is the
-        // rotation either way, within the convergence test
-        const float id = __builtin_amdgcn_rcpf(det);
-        // R^-T = cofactor matrix / det
-        const float c[9] = {c00, c01, c02, c10, c11, c12, c20, c21, c22};
-        float diff = 0.f;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const float n = 0.5f * (R[k] + c[k] * id);
-            diff = fmaxf(diff, fabsf(n - R[k]));
-            R[k] = n;
-        }
-        if (diff <= 1e-4f) break;
+    for (int it = 1; ok && it < 12; ++it) {
+        ok = polar_step(Z, sc, diff, true);
+        sc *= 4.f;
+        inv *= 0.5f;
+        if (diff <= lim) break;
+        lim *= 2.f;
     }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) R[k] = Z[k] * inv;
     return ok;
 }
 
@@ -152,9 +165,9 @@ __device__ __forceinline__ V3 frame_inv_inertia(const Params& P, Q4 q, V3 t)
 // records (array of structures with odd strides, free of bank conflicts for
 // consecutive blocks), so one address per record serves all its fields
 // through the instructions' immediate offsets.
-// element record: g_0..g_3 (12), L (15), 1/D (6), E/h^2 (3), scale, vertices,
+// element record: g_1..g_3 (9), L (15), -scale / D (6), E/h^2 (3), vertices,
 // the gather slots of its four vertices (4), pad
-constexpr int kTR = 43;
+constexpr int kTR = 39;
 // distance row: rest, w_i, w_j, scale, i | j << 16, kind, slots of i and j,
 // -scale / (w_i + w_j + rigid compliance)
 constexpr int kDR = 9;
@@ -214,17 +227,17 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
     // per-mesh constants into records (the slot fields are filled below)
     for (int i = tid; i < kTR * Tm; i += kThreads) {
         const int t = i / kTR, f = i - t * kTR;
-        if (f >= 38 && f < 42) continue;
+        if (f >= 34 && f < 38) continue;
         float val = 0.f;
-        if (f < 12)
-            val = P.tet_g[f * Tm + t];
+        if (f < 9)
+            val = P.tet_g[(f + 3) * Tm + t];
+        else if (f < 24)
+            val = P.tet_ldl[(f - 9) * Tm + t];
+        else if (f < 30)
+            val = -P.tet_scale[t] * P.tet_ldl[(f - 9) * Tm + t];
         else if (f < 33)
-            val = P.tet_ldl[(f - 12) * Tm + t];
-        else if (f < 36)
-            val = P.tet_alpha[(f - 33) * Tm + t];
-        else if (f == 36)
-            val = P.tet_scale[t];
-        else if (f == 37)
+            val = P.tet_alpha[(f - 30) * Tm + t];
+        else if (f == 33)
             val = __int_as_float(P.tet_v[t]);
         S.tr[i] = val;
     }
@@ -246,7 +259,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
         const int ent = P.inc[i];
         const int type = ent >> 28, blk = (ent >> 2) & 0x3ffffff, slot = ent & 3;
         if (type == kIncTet)
-            S.tr[kTR * blk + 38 + slot] = __int_as_float(i);
+            S.tr[kTR * blk + 34 + slot] = __int_as_float(i);
         else if (type == kIncDist)
             S.dr[kDR * blk + 6 + slot] = __int_as_float(i);
         else
@@ -379,7 +392,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                     const int t = bidx[k];
                     if (bkind[k] == 0) {
                         const float* c = S.tr + kTR * t;
-                        const int vv = __float_as_int(c[37]), base = blink[k] * P1;
+                        const int vv = __float_as_int(c[33]), base = blink[k] * P1;
                         const float* p0 = S.pr + kPR * (base + (vv & 255));
                         float F[9];
                         {
@@ -395,51 +408,50 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                             for (int j = 0; j < 3; ++j)
 #pragma unroll
                                 for (int i = 0; i < 3; ++i)
-                                    F[3 * i + j] = E[i][0] * c[3 + j] + E[i][1] * c[6 + j] + E[i][2] * c[9 + j];
+                                    F[3 * i + j] = E[i][0] * c[j] + E[i][1] * c[3 + j] + E[i][2] * c[6 + j];
                         }
                         float R[9];
                         const bool ok = polar(F, R);
-                        // S = R^T F; strain sym(S) - I in Voigt order (xx yy zz yz xz xy)
+                        // strain sym(R^T F) - I in Voigt order (xx yy zz yz xz xy);
+                        // R^T F is symmetric at the polar factor, so one of each
+                        // off-diagonal pair serves
                         float y[6];
                         {
-                            float Sm[9];
-#pragma unroll
-                            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                                for (int b = 0; b < 3; ++b)
-                                    Sm[3 * a + b] = R[a] * F[b] + R[3 + a] * F[3 + b] + R[6 + a] * F[6 + b];
-                            const float ad = c[33], ao = c[34], as = c[35];
+                            const float s00 = R[0] * F[0] + R[3] * F[3] + R[6] * F[6];
+                            const float s11 = R[1] * F[1] + R[4] * F[4] + R[7] * F[7];
+                            const float s22 = R[2] * F[2] + R[5] * F[5] + R[8] * F[8];
+                            const float s12 = R[1] * F[2] + R[4] * F[5] + R[7] * F[8];
+                            const float s02 = R[0] * F[2] + R[3] * F[5] + R[6] * F[8];
+                            const float s01 = R[0] * F[1] + R[3] * F[4] + R[6] * F[7];
+                            const float ad = c[30], ao = c[31], as = c[32];
                             const float* l = lam[k];
-                            y[0] = (Sm[0] - 1.f) + ad * l[0] + ao * (l[1] + l[2]);
-                            y[1] = (Sm[4] - 1.f) + ad * l[1] + ao * (l[0] + l[2]);
-                            y[2] = (Sm[8] - 1.f) + ad * l[2] + ao * (l[0] + l[1]);
-                            y[3] = 0.5f * (Sm[5] + Sm[7]) + as * l[3];
-                            y[4] = 0.5f * (Sm[2] + Sm[6]) + as * l[4];
-                            y[5] = 0.5f * (Sm[1] + Sm[3]) + as * l[5];
+                            y[0] = (s00 - 1.f) + ad * l[0] + ao * (l[1] + l[2]);
+                            y[1] = (s11 - 1.f) + ad * l[1] + ao * (l[0] + l[2]);
+                            y[2] = (s22 - 1.f) + ad * l[2] + ao * (l[0] + l[1]);
+                            y[3] = s12 + as * l[3];
+                            y[4] = s02 + as * l[4];
+                            y[5] = s01 + as * l[5];
                         }
                         float rm = 0.f;
 #pragma unroll
                         for (int q = 0; q < 6; ++q) rm = fmaxf(rm, fabsf(y[q]));
                         res = fmaxf(res, ok ? rm : INFINITY);
-                        // (L D L^T)^-1 y: forward, diagonal, backward
+                        // -scale (L D L^T)^-1 y: forward, diagonal (with -scale), backward
 #pragma unroll
                         for (int q = 1; q < 6; ++q)
 #pragma unroll
-                            for (int cc = 0; cc < q; ++cc) y[q] -= c[12 + q * (q - 1) / 2 + cc] * y[cc];
+                            for (int cc = 0; cc < q; ++cc) y[q] -= c[9 + q * (q - 1) / 2 + cc] * y[cc];
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) y[q] *= c[27 + q];
+                        for (int q = 0; q < 6; ++q) y[q] *= c[24 + q];
 #pragma unroll
                         for (int q = 4; q >= 0; --q)
 #pragma unroll
-                            for (int cc = q + 1; cc < 6; ++cc) y[q] -= c[12 + cc * (cc - 1) / 2 + q] * y[cc];
-                        const float sc = -c[36];
+                            for (int cc = q + 1; cc < 6; ++cc) y[q] -= c[9 + cc * (cc - 1) / 2 + q] * y[cc];
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) {
-                            y[q] *= sc;
-                            pend[k][q] = y[q];
-                        }
+                        for (int q = 0; q < 6; ++q) pend[k][q] = y[q];
                         // U = R T, T the increment as a symmetric tensor; vertex m
-                        // receives U g_m, written to its gather slot
+                        // receives U g_m, written to its gather slot (g_0 = -(g_1 +
+                        // g_2 + g_3), so vertex 0 the negated sum of the others)
                         const float Tn[9] = {y[0], 0.5f * y[5], 0.5f * y[4], 0.5f * y[5], y[1], 0.5f * y[3],
                                              0.5f * y[4], 0.5f * y[3], y[2]};
                         float u[9];
@@ -449,14 +461,16 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                             for (int j = 0; j < 3; ++j)
                                 u[3 * i + j] = R[3 * i] * Tn[j] + R[3 * i + 1] * Tn[3 + j] + R[3 * i + 2] * Tn[6 + j];
                         float* vb = S.V + 3 * blink[k] * n_inc;
+                        V3 sum = mk(0.f, 0.f, 0.f);
 #pragma unroll
-                        for (int m = 0; m < 4; ++m) {
-                            const float g0 = c[3 * m], g1 = c[3 * m + 1], g2 = c[3 * m + 2];
-                            float* o = vb + 3 * __float_as_int(c[38 + m]);
-                            o[0] = u[0] * g0 + u[1] * g1 + u[2] * g2;
-                            o[1] = u[3] * g0 + u[4] * g1 + u[5] * g2;
-                            o[2] = u[6] * g0 + u[7] * g1 + u[8] * g2;
+                        for (int m = 1; m < 4; ++m) {
+                            const float g0 = c[3 * m - 3], g1 = c[3 * m - 2], g2 = c[3 * m - 1];
+                            const V3 o = mk(u[0] * g0 + u[1] * g1 + u[2] * g2, u[3] * g0 + u[4] * g1 + u[5] * g2,
+                                            u[6] * g0 + u[7] * g1 + u[8] * g2);
+                            st3(vb + 3 * __float_as_int(c[34 + m]), o);
+                            sum = m == 1 ? o : sum + o;
                         }
+                        st3(vb + 3 * __float_as_int(c[34]), -sum);
                     } else if (bkind[k] == 1) {
                         const float* c = S.dr + kDR * t;
                         const int ij = __float_as_int(c[4]), base = blink[k] * P1;
