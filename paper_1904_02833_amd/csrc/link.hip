@@ -171,7 +171,9 @@ constexpr int kTR = 39;
 // distance row: rest, w_i, w_j, scale, i | j << 16, kind, slots of i and j,
 // -scale / (w_i + w_j + rigid compliance)
 constexpr int kDR = 9;
-constexpr int kAR = 7;    // attachment: r (3), w_p, particle degree, particle, slot
+// attachment: r (3), w_p, -relax / max(particle degree, frame degree) at an
+// end frame and at an inner frame, particle, slot, pad
+constexpr int kAR = 9;
 constexpr int kPR = 7;    // particle: start-of-substep position (3), displacement (3), pad
 constexpr int kFr = 20;   // frame: xp (3), d (3), q (4), v (3), w (3), q at the substep start (4)
 
@@ -250,8 +252,11 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
     }
     for (int i = tid; i < kAR * A1; i += kThreads) {
         const int e = i / kAR, f = i - e * kAR;
-        if (f == 6) continue;
-        S.ar[i] = f < 5 ? P.att_c[f * A1 + e] : __int_as_float(P.att_p[e]);
+        if (f == 7) continue;
+        const int dpart = (int)P.att_c[4 * A1 + e], dend = A1 / 2 > dpart ? A1 / 2 : dpart,
+                  dmid = A1 > dpart ? A1 : dpart;
+        S.ar[i] = f < 4 ? P.att_c[f * A1 + e] : f == 4 ? -P.relax / (float)dend : f == 5 ? -P.relax / (float)dmid
+                : f == 6 ? __int_as_float(P.att_p[e]) : 0.f;
     }
     // incidence entry i is gather slot i: each block records the slots of
     // its particles (one entry per block and particle)
@@ -263,7 +268,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
         else if (type == kIncDist)
             S.dr[kDR * blk + 6 + slot] = __int_as_float(i);
         else
-            S.ar[kAR * blk + 6] = __int_as_float(i);
+            S.ar[kAR * blk + 7] = __int_as_float(i);
     }
 
     // this lane's particle group: the particle, the group's size, the
@@ -487,13 +492,14 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         if (on) {
                             const float press = ch < 0 ? 0.f : S.lk[ch * L + blink[k]];
                             const V3 df = (ld3(pi) - ld3(pj)) + (ld3(pi + 3) - ld3(pj + 3));
-                            const float len = sqrtf(dot(df, df));
+                            // hardware reciprocal square root (1 ulp)
+                            const float dd = dot(df, df), il = __builtin_amdgcn_rsqf(dd), len = dd * il;
                             const float rest = c[0] * (1.f + press * P.young_inv_pmax);
                             const float rr = (len - rest) + P.a_rigid * lam[k][0];
                             res = fmaxf(res, fabsf(rr) * P.Lref_inv);
                             const float dl = c[8] * rr;
                             pend[k][0] = dl;
-                            im = (dl * __builtin_amdgcn_rcpf(len)) * df;
+                            im = (dl * il) * df;
                         }
                         // + on the first particle, - on the second
                         st3(vb + 3 * __float_as_int(c[6]), im);
@@ -501,7 +507,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                     } else if (bkind[k] == 2) {
                         const float* c = S.ar + kAR * t;
                         const int a = t;
-                        const float* pi = S.pr + kPR * (blink[k] * P1 + __float_as_int(c[5]));
+                        const float* pi = S.pr + kPR * (blink[k] * P1 + __float_as_int(c[6]));
                         const int f = blink[k] + (a < A1 / 2 ? 0 : 1);
                         const float* fr = S.fr + kFr * f;
                         const Q4 q{fr[6], fr[7], fr[8], fr[9]};
@@ -519,9 +525,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         const V3 iz = fixedf ? z0 : frame_inv_inertia(P, q, cz);
                         const V3 sol = snake::sym3_solve(wdiag + dot(cx, ix), dot(cx, iy), dot(cx, iz), wdiag + dot(cy, iy),
                                                          dot(cy, iz), wdiag + dot(cz, iz), rr);
-                        const int dfr = (f == 0 || f == L) ? A1 / 2 : A1;
-                        const int dpart = (int)c[4];
-                        const float sc = -P.relax / (float)(dpart > dfr ? dpart : dfr);
+                        const float sc = (f == 0 || f == L) ? c[4] : c[5];
                         pend[k][0] = sc * sol.x;
                         pend[k][1] = sc * sol.y;
                         pend[k][2] = sc * sol.z;
@@ -529,7 +533,7 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                         float* dao = S.da + 6 * (blink[k] * A1 + a);                     // to the frame
                         st3(dao, inc_a);
                         st3(dao + 3, cross(u, inc_a));
-                        st3(S.V + 3 * (blink[k] * n_inc + __float_as_int(c[6])), -inc_a);   // to the particle
+                        st3(S.V + 3 * (blink[k] * n_inc + __float_as_int(c[7])), -inc_a);   // to the particle
                     }
                 }
                 // the particle's ground contact: normal, then the slip since the
@@ -539,11 +543,12 @@ __global__ void __launch_bounds__(kThreads) k_link(Params P, int n_steps)
                     res = fmaxf(res, (lc.x > 0.f ? fabsf(z) : fmaxf(-z, 0.f)) * P.Lref_inv);
                     const float ln = fmaxf(0.f, lc.x + cscale * (-pmass * z));
                     float tx = lc.y + cscale * (-pmass * d.x), ty = lc.z + cscale * (-pmass * d.y);
-                    const float cap = mu * ln, nt = sqrtf(tx * tx + ty * ty);
+                    const float cap = mu * ln, n2 = tx * tx + ty * ty;
                     if (!(ln > 0.f)) {
                         tx = ty = 0.f;
-                    } else if (nt > cap) {
-                        const float f = cap / nt;
+                    } else if (n2 > cap * cap) {
+                        // hardware reciprocal square root (1 ulp)
+                        const float f = cap * __builtin_amdgcn_rsqf(n2);
                         tx *= f;
                         ty *= f;
                     }
