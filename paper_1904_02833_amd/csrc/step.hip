@@ -237,7 +237,10 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
         // blocks on body i and body i+1; a joint block is scaled by the larger
         const int dA = gnd + (i > 0 ? 2 : 0) + (i + 1 < B ? 2 : 0);
         const int dB = gnd + 2 + (i + 2 < B ? 2 : 0);
-        const float sj = P.relax / (float)max(dA, dB);
+        // zero on a lane without a joint, whose increments are then zero and
+        // its multiplier updates need no mask (its joint with whatever lies
+        // in the next lane is evaluated and discarded)
+        const float sj = hasj ? P.relax / (float)max(dA, dB) : 0.f;
         const float sc = P.relax / (float)max(dA, 1);
         const float wA = fixed ? 0.f : P.inv_m, c1A = fixed ? 0.f : P.c1, c2A = fixed ? 0.f : P.c2;
         const float wB = P.inv_m, c1B = P.c1, c2B = P.c2;
@@ -516,15 +519,14 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                         const bool recv = hasb && i > 0;
                         const V3 fsum = sel(recv, inf, zero) + sel(hasj, dls, zero);
                         const V3 tsum = sel(recv, intq, zero) + sel(hasj, tA, zero);
-                        if (hasj) {
-                            ls = ls + dls;
-                            lb = lb + dlb;
-                        }
-                        if (hasb && gnd) lc = lc + dlc;
-                        if (hasb && !fixed) {
-                            d = fma3(wA, fsum + mk(dlc.y, dlc.z, dlc.x), d);
-                            q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
-                        }
+                        // unmasked: zero increments without a joint, the
+                        // fixed root's zero inverse mass, and an empty lane's
+                        // state, read only by the joints that are discarded
+                        ls = ls + dls;
+                        lb = lb + dlb;
+                        if (gnd) lc = lc + dlc;
+                        d = fma3(wA, fsum + mk(dlc.y, dlc.z, dlc.x), d);
+                        if (!fixed) q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
                     }
                 }
                             return rdone;
@@ -621,15 +623,14 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                         const bool recv = hasb && i > 0;
                         const V3 fsum = sel(recv, inf, zero) + sel(hasj, dls, zero);
                         const V3 tsum = sel(recv, intq, zero) + sel(hasj, tA, zero);
-                        if (hasj) {
-                            ls = ls + dls;
-                            lb = lb + dlb;
-                        }
-                        if (hasb && gnd) lc = lc + dlc;
-                        if (hasb && !fixed) {
-                            d = fma3(wA, fsum + mk(dlc.y, dlc.z, dlc.x), d);
-                            q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
-                        }
+                        // unmasked: zero increments without a joint, the
+                        // fixed root's zero inverse mass, and an empty lane's
+                        // state, read only by the joints that are discarded
+                        ls = ls + dls;
+                        lb = lb + dlb;
+                        if (gnd) lc = lc + dlc;
+                        d = fma3(wA, fsum + mk(dlc.y, dlc.z, dlc.x), d);
+                        if (!fixed) q = qturn(q, inv_inertia(tsum, aA, c1A, c2A));
                     }
                 }
                 if (live) kdone += extra;
