@@ -241,6 +241,16 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
         // its multiplier updates need no mask (its joint with whatever lies
         // in the next lane is evaluated and discarded)
         const float sj = hasj ? P.relax / (float)max(dA, dB) : 0.f;
+        // lane masks (all ones / zero) for the joint's and the received
+        // increments: a bitwise and (a full-rate VALU operation) zeroes what a
+        // lane does not own, NaN included; the empty asm keeps the compiler
+        // from turning the and back into a select
+        int mj = hasj ? -1 : 0, mr = (hasb && i > 0) ? -1 : 0;
+        asm volatile("" : "+v"(mj), "+v"(mr));
+        auto andz = [](int m, V3 a) {
+            return mk(__int_as_float(__float_as_int(a.x) & m), __int_as_float(__float_as_int(a.y) & m),
+                      __int_as_float(__float_as_int(a.z) & m));
+        };
         const float sc = P.relax / (float)max(dA, 1);
         const float wA = fixed ? 0.f : P.inv_m, c1A = fixed ? 0.f : P.c1, c2A = fixed ? 0.f : P.c2;
         const float wB = P.inv_m, c1B = P.c1, c2B = P.c2;
@@ -501,7 +511,7 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                     V3 tA, tB;
                     joint_torques(g, dls, dlb, hl, tA, tB);
                     V3 inf, intq;
-                    const float r = fetch_prev(sel(hasj, -dls, zero), sel(hasj, tB, zero), rl, inf, intq);
+                    const float r = fetch_prev(andz(mj, -dls), andz(mj, tB), rl, inf, intq);
 
                     if (!done) {
                         const bool bad = !(r < INFINITY);
@@ -516,9 +526,8 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                         // gather in a fixed order: forces of joint i-1 (received),
                         // joint i and the contact through the inverse mass; torques
                         // of the two joints through the inverse inertia
-                        const bool recv = hasb && i > 0;
-                        const V3 fsum = sel(recv, inf, zero) + sel(hasj, dls, zero);
-                        const V3 tsum = sel(recv, intq, zero) + sel(hasj, tA, zero);
+                        const V3 fsum = andz(mr, inf) + andz(mj, dls);
+                        const V3 tsum = andz(mr, intq) + andz(mj, tA);
                         // unmasked: zero increments without a joint, the
                         // fixed root's zero inverse mass, and an empty lane's
                         // state, read only by the joints that are discarded
@@ -598,7 +607,7 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                     V3 tA, tB;
                     joint_torques(g, dls, dlb, hl, tA, tB);
                     V3 inf, intq;
-                    const float r = fetch_prev(sel(hasj, -dls, zero), sel(hasj, tB, zero), rl, inf, intq);
+                    const float r = fetch_prev(andz(mj, -dls), andz(mj, tB), rl, inf, intq);
 
                     if (!done) {
                         const int kl = k + koff;
@@ -620,9 +629,8 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                         // gather in a fixed order: forces of joint i-1 (received),
                         // joint i and the contact through the inverse mass; torques
                         // of the two joints through the inverse inertia
-                        const bool recv = hasb && i > 0;
-                        const V3 fsum = sel(recv, inf, zero) + sel(hasj, dls, zero);
-                        const V3 tsum = sel(recv, intq, zero) + sel(hasj, tA, zero);
+                        const V3 fsum = andz(mr, inf) + andz(mj, dls);
+                        const V3 tsum = andz(mr, intq) + andz(mj, tA);
                         // unmasked: zero increments without a joint, the
                         // fixed root's zero inverse mass, and an empty lane's
                         // state, read only by the joints that are discarded
