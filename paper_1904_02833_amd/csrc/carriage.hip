@@ -46,6 +46,31 @@ __device__ __forceinline__ D3 qcol2(DQ f)
 struct S3 {
     double a00, a01, a02, a11, a12, a22;
 };
+
+// 1/x and 1/sqrt(x) in FP64 from the hardware estimates refined by two
+// Newton-Raphson steps each (every step squares the relative error, so two
+// take the estimate to the last bits of FP64); in place of the IEEE
+// division and square-root sequences, for finite positive x
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ double rsqrt64(double x)
+{
+    // Goldschmidt form: g -> sqrt(x), h -> 1 / (2 sqrt(x))
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    e = fma(-g, h, 0.5);
+    h = fma(h, e, h);
+    return 2.0 * h;
+}
 __device__ __forceinline__ D3 solve_sym3(const S3& K, D3 b)
 {
     const double c00 = K.a11 * K.a22 - K.a12 * K.a12;
@@ -54,7 +79,7 @@ __device__ __forceinline__ D3 solve_sym3(const S3& K, D3 b)
     const double c11 = K.a00 * K.a22 - K.a02 * K.a02;
     const double c12 = K.a01 * K.a02 - K.a00 * K.a12;
     const double c22 = K.a00 * K.a11 - K.a01 * K.a01;
-    const double id = 1.0 / (K.a00 * c00 + K.a01 * c01 + K.a02 * c02);
+    const double id = rcp64(K.a00 * c00 + K.a01 * c01 + K.a02 * c02);
     return D3{(c00 * b.x + c01 * b.y + c02 * b.z) * id, (c01 * b.x + c11 * b.y + c12 * b.z) * id,
               (c02 * b.x + c12 * b.y + c22 * b.z) * id};
 }
@@ -64,12 +89,12 @@ __device__ __forceinline__ D3 solve_sym3(const S3& K, D3 b)
 // u = (b - U z) / alpha, U = [u0 u1], D = diag(d0, d1).
 __device__ __forceinline__ D3 solve_rank2(double alpha, D3 u0, double d0, D3 u1, double d1, D3 b)
 {
-    const double ia = 1.0 / alpha;
+    const double ia = rcp64(alpha);
     const double g00 = dot(u0, u0), g01 = dot(u0, u1), g11 = dot(u1, u1);
     const double y0 = d0 * dot(u0, b) * ia, y1 = d1 * dot(u1, b) * ia;
     const double m00 = 1.0 + d0 * g00 * ia, m01 = d0 * g01 * ia;
     const double m10 = d1 * g01 * ia, m11 = 1.0 + d1 * g11 * ia;
-    const double idet = 1.0 / (m00 * m11 - m01 * m10);
+    const double idet = rcp64(m00 * m11 - m01 * m10);
     const double z0 = (m11 * y0 - m01 * y1) * idet, z1 = (m00 * y1 - m10 * y0) * idet;
     return ia * (b - (z0 * u0 + z1 * u1));
 }
@@ -85,7 +110,7 @@ __device__ __forceinline__ DQ qturn1(DQ q, D3 dth)
 {
     const DQ t = qmul(DQ{0.0, dth.x, dth.y, dth.z}, q);
     const DQ r{q.w + 0.5 * t.w, q.x + 0.5 * t.x, q.y + 0.5 * t.y, q.z + 0.5 * t.z};
-    const double in = 1.0 / sqrt(r.w * r.w + r.x * r.x + r.y * r.y + r.z * r.z);
+    const double in = rsqrt64(r.w * r.w + r.x * r.x + r.y * r.y + r.z * r.z);
     return DQ{r.w * in, r.x * in, r.y * in, r.z * in};
 }
 
@@ -97,8 +122,8 @@ __device__ __forceinline__ double rmax(double a, double b) { return (b > a || b 
 __device__ __forceinline__ D3 low_point(D3 a, double rw)
 {
     const D3 u{-a.z * a.x, -a.z * a.y, 1.0 - a.z * a.z};
-    const double n = sqrt(dot(u, u));
-    return n > 0.0 ? (-rw / n) * u : D3{0.0, 0.0, 0.0};
+    const double n2 = dot(u, u);
+    return n2 > 0.0 ? (-rw * rsqrt64(n2)) * u : D3{0.0, 0.0, 0.0};
 }
 
 template <int SEG>
@@ -322,7 +347,7 @@ k_carriage(KParams P, NParams Q, WParams Wp, const int* __restrict__ list, int c
                         const double k22 = iform(H2[k], H2[k], aA, c1A, c2A) + iform(H2[k], H2[k], aW, c1W, c2W);
                         const double r0 = 2.0 * e.x, r2 = 2.0 * e.z;
                         rl = rmax(rl, rmax(fabs(r0), fabs(r2)));
-                        const double id = 1.0 / (k00 * k22 - k02 * k02);
+                        const double id = rcp64(k00 * k22 - k02 * k02);
                         dla[k] = d3(-sch * (k22 * r0 - k02 * r2) * id, 0.0, -sch * (k00 * r2 - k02 * r0) * id);
                     }
                     // contact: lowest rim point; friction on the anchored material point
@@ -341,19 +366,20 @@ k_carriage(KParams P, NParams Q, WParams Wp, const int* __restrict__ list, int c
                         const double k11 = wW + iform(j0, j0, aW, c1W, c2W);
                         const double k12 = iform(j0, j1, aW, c1W, c2W);
                         const double k22 = wW + iform(j1, j1, aW, c1W, c2W);
-                        double ln = lc[k].x + scc * (-cn / knn);
+                        double ln = lc[k].x + scc * (-cn * rcp64(knn));
                         if (ln < 0.0) ln = 0.0;
-                        const double idet = 1.0 / (k11 * k22 - k12 * k12);
+                        const double idet = rcp64(k11 * k22 - k12 * k12);
                         const double y0 = (k22 * c0 - k12 * c1t) * idet;
                         const double y1 = (k11 * c1t - k12 * c0) * idet;
                         double lt0 = lc[k].y - scc * y0, lt1 = lc[k].z - scc * y1;
                         const double cap = mu * ln;
-                        const double nt = sqrt(lt0 * lt0 + lt1 * lt1);
+                        const double nt2 = lt0 * lt0 + lt1 * lt1;
                         if (ln <= 0.0) {
                             lt0 = lt1 = 0.0;
-                        } else if (nt > cap) {
-                            lt0 *= cap / nt;
-                            lt1 *= cap / nt;
+                        } else if (nt2 > cap * cap) {
+                            const double f = cap * rsqrt64(nt2);
+                            lt0 *= f;
+                            lt1 *= f;
                         }
                         dlc[k] = d3(ln - lc[k].x, lt0 - lc[k].y, lt1 - lc[k].z);
                     }
