@@ -21,6 +21,7 @@
 #include <math.h>
 
 #include "blocks.h"
+#include "fp64_recip.h"
 #include "kernels.h"
 #include "lanes.h"
 
@@ -379,7 +380,7 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
                 }
                 // the preconditioner as reciprocals, once per Newton iteration
 #pragma unroll
-                for (int k2 = 0; k2 < 9; ++k2) dg[k2] = dg[k2] > 0.0 ? 1.0 / dg[k2] : 1.0;
+                for (int k2 = 0; k2 < 9; ++k2) dg[k2] = dg[k2] > 0.0 ? rcp64(dg[k2]) : 1.0;
                 auto project = [&](double (&u)[9]) {
 #pragma unroll
                     for (int k2 = 0; k2 < 6; ++k2) u[k2] *= pj;
@@ -425,7 +426,7 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
                     precondition(Ap, Mq);
                     const double den = sdot(Ap, Mq);
                     if (!(den > 0.0)) break;
-                    const double alpha = rho / den;
+                    const double alpha = rho * rcp64(den);
 #pragma unroll
                     for (int k2 = 0; k2 < 9; ++k2) {
                         xs[k2] += alpha * pv[k2];
@@ -435,7 +436,7 @@ k_newton(KParams P, NParams Q, const int* __restrict__ list, int count, int n_st
                     apply(z, Az);
                     project(Az);
                     const double rho1 = sdot(z, Az);
-                    const double beta = rho1 / rho;
+                    const double beta = rho1 * rcp64(rho);
                     rho = rho1;
 #pragma unroll
                     for (int k2 = 0; k2 < 9; ++k2) {
