@@ -108,8 +108,10 @@ __device__ __forceinline__ float wave_max(float v)
 // Convergence is quadratic: with the iterate R (I + E), E symmetric, one
 // step leaves about E^2 / 2 and moves the iterate by about |E|, so a step
 // that moved no entry by more than 1e-4 (|E| below 3e-4 in norm) leaves an
-// error below 5e-8, under FP32 rounding, and ends the iteration; the first
-// step (from F) is not tested.  The iterate is kept as Z_k = 2^k R_k, so
+// error below 5e-8, under FP32 rounding, and ends the iteration.  The first
+// two steps are not tested: from F at the strains of a link's elements one
+// step never suffices and two rarely do, so a wave (whose lanes run until
+// the last one stops) would pay for the test without ending sooner.  The iterate is kept as Z_k = 2^k R_k, so
 // that Z_{k+1} = Z_k + 4^k cof(Z_k) / det Z_k takes one fused multiply-add
 // per entry (R^-T = cof R / det R; the powers of two are exact).
 __device__ __forceinline__ bool polar_step(float* Z, float sc, float& diff, bool test)
@@ -139,10 +141,11 @@ __device__ __forceinline__ bool polar(const float* F, float* R)
     for (int k = 0; k < 9; ++k) Z[k] = F[k];
     float diff;
     bool ok = polar_step(Z, 1.f, diff, false);
+    ok = ok && polar_step(Z, 4.f, diff, false);
     // after step k + 1: 4^(k+1), 2^-(k+1), and the bound on |Z_{k+1} - 2 Z_k|
-    float sc = 4.f, inv = 0.5f, lim = 4e-4f;
+    float sc = 16.f, inv = 0.25f, lim = 8e-4f;
 #pragma unroll 2
-    for (int it = 1; ok && it < 12; ++it) {
+    for (int it = 2; ok && it < 12; ++it) {
         ok = polar_step(Z, sc, diff, true);
         sc *= 4.f;
         inv *= 0.5f;
