@@ -417,13 +417,13 @@ def carriage_run(wl, n_steps=5, iters=CARRIAGE_ITERS, default_size=True):
 # gather and contact of 117 particles, the elements dominating), from its
 # VALU counters on the link batch (k_link dispatches only):
 # SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes / (2048 snakes x 4 links x 80
-# iterations) = 64 x 1.92916e9 / 655 360 (profiles/k_link_link2048x4.md).
+# iterations) = 64 x 1.86413e9 / 655 360 (profiles/k_link_link2048x4.md).
 # HBM bytes per launch from FETCH_SIZE and WRITE_SIZE on that batch, with
 # the digest of the kernel's sources.
 LINK_SNAKES = 2048
 LINK_STEPS = 10
-LINK_FLOP_ITER = 188_390
-LINK_TRAFFIC = (440.8e6, 2048, ("link.hip", "device_math.h"), "1012d2fb1f70203b:bb2ea3129ebb4d43")
+LINK_FLOP_ITER = 182_040
+LINK_TRAFFIC = (436.2e6, 2048, ("link.hip", "device_math.h"), "155a46f077ff79dc:bb2ea3129ebb4d43")
 
 
 def link_run(n_snakes=LINK_SNAKES, n_steps=LINK_STEPS, iters=20):
