@@ -1,5 +1,6 @@
 /*
- * FP64 oracle of the full-resolution soft link (survey row "FEM link").
+ * FP64 oracle of the full-resolution soft link (sections "Particles",
+ * "Tetrahedral Finite-Elements" and "Soft robotic snake model").
  * TEST INFRASTRUCTURE ONLY, like the rest of this folder; shares nothing
  * with the GPU library.
  *
