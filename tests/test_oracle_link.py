@@ -1,6 +1,7 @@
 """Pins of the oracle's full-resolution link solve (the soft link of
-section "Soft robotic snake model": particles with lumped masses, corotational tetrahedra with the element
-compliance of section "Tetrahedral Finite-Elements", distance constraints
+section "Soft robotic snake model": particles with lumped masses,
+corotational tetrahedra with the element compliance of section
+"Tetrahedral Finite-Elements", distance constraints
 with the actuation rest length of eq. expansion, attachments of
 eq. rigid_to_particle, ground contact), on the procedural link mesh.
 
