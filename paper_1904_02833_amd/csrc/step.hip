@@ -158,12 +158,15 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
                 // the segment's piece in wave wa holds that wave's lane 63, the
                 // pieces in the following waves hold their lane 0 (all NW
                 // entries are read at once, so the reads overlap)
+                // (non-negative values and +inf: the integer order of the bit
+                // patterns is the float order, with no NaN canonicalisation)
                 float fv[NW];
                 lds_row<NW>(xfirst, fv);
-                r = xlast[wa];
+                int ri = __float_as_int(xlast[wa]);
 #pragma unroll
                 for (int w = 1; w < NW; ++w)
-                    if (w > wa && w <= wb) r = fmaxf(r, fv[w]);
+                    if (w > wa && w <= wb) ri = max(ri, __float_as_int(fv[w]));
+                r = __int_as_float(ri);
             }
             return r;
         };
