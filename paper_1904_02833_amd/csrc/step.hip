@@ -122,11 +122,14 @@ k_tile(KParams P, const int4* __restrict__ hdr, const int2* __restrict__ slots, 
             }
             __syncthreads();
             // all flags in vector reads, so the latencies overlap
+            // (each flag is 1.0f or +0.0f, so the and of the bit patterns is
+            // nonzero exactly when every flag is set)
             float fl[NW];
             lds_row<NW>(xdone[buf], fl);
-            bool all = true;
+            int fa = -1;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) all &= fl[w] != 0.f;
+            for (int w = 0; w < NW; ++w) fa &= __float_as_int(fl[w]);
+            const bool all = fa != 0;
             if (lane == 63 && wv + 1 < NW) {
                 const float* e = xnext[buf][wv + 1];
                 un = mk(e[0], e[1], e[2]);
