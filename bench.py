@@ -423,7 +423,7 @@ def carriage_run(wl, n_steps=5, iters=CARRIAGE_ITERS, default_size=True):
 LINK_SNAKES = 2048
 LINK_STEPS = 10
 LINK_FLOP_ITER = 182_040
-LINK_TRAFFIC = (436.2e6, 2048, ("link.hip", "device_math.h"), "155a46f077ff79dc:bb2ea3129ebb4d43")
+LINK_TRAFFIC = (436.2e6, 2048, ("link.hip", "device_math.h"), "1b641d59d387afe6:bb2ea3129ebb4d43")
 
 
 def link_run(n_snakes=LINK_SNAKES, n_steps=LINK_STEPS, iters=20):

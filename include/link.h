@@ -187,6 +187,20 @@ int link_write_state(link_t* s, uint32_t fields, const void* const* src, int mem
  * Synchronous. */
 int link_read_index(link_t* s, int32_t which, int32_t* dst, int64_t count);
 
+/* The solver kernel's lane plan of the particles' gathers for a
+ * descriptor, on the host (no device, no state), as link_create builds it.
+ * A snake's workgroup has 1024 lanes; each particle of the snake owns an
+ * aligned group of 1, 2, 4 or 8 lanes of one wave, whose lanes sum
+ * consecutive ranges of the particle's incidence list (its blocks of
+ * section "Soft robotic snake model" in the gather order: elements,
+ * distance rows, attachment; a link's lists follow one another particle by
+ * particle, 4 T1 + 2 D1 + A1 entries per link).  Caller host memory:
+ *   out[lane] = particle | log2(group size) << 16, or -1 for no particle
+ *   out[1024 + lane] = first | end << 16, the lane's range of entries
+ *   (in its link's list)
+ * and *gmax the largest group.  LINK_EINVAL for an invalid descriptor. */
+int link_plan_gathers(const link_desc_t* d, int32_t* out2048, int32_t* gmax);
+
 /* Sizes of the batch: n_snakes, P, F, T, D, A (totals) and L = links,
  * per snake P1, D1, A1 (host int64 out[10]). */
 int link_sizes(const link_t* s, int64_t* out10);

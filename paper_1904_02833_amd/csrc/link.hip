@@ -1396,6 +1396,18 @@ int link_read_index(link_t* s, int32_t which, int32_t* dst, int64_t count)
     return LINK_OK;
 }
 
+int link_plan_gathers(const link_desc_t* d, int32_t* out2048, int32_t* gmax)
+{
+    Sz z;
+    if (int rc = validate(d, &z)) return rc;
+    if (!out2048 || !gmax) return lfail(LINK_EINVAL, "out2048 or gmax is NULL");
+    Topo t;
+    topology(d, z, &t);
+    std::memcpy(out2048, t.gplan.data(), sizeof(int32_t) * t.gplan.size());
+    *gmax = t.gmax;
+    return LINK_OK;
+}
+
 int link_sizes(const link_t* s, int64_t* out10)
 {
     if (!s || !out10) return lfail(LINK_EINVAL, "link or out is NULL");

@@ -16,7 +16,8 @@ MEM_HOST, MEM_DEVICE = 0, 1
 FLAG_FIXED_FRAME0, FLAG_NO_GROUND = 1, 2
 STATUS_NONFINITE, STATUS_NOT_CONVERGED = 1, 2
 EXPORTS = ["link_workspace_bytes", "link_create", "link_set_commands", "link_step", "link_read_state",
-           "link_write_state", "link_read_index", "link_sizes", "link_destroy", "link_last_error"]
+           "link_write_state", "link_read_index", "link_plan_gathers", "link_sizes", "link_destroy",
+           "link_last_error"]
 # state fields: bit -> (name, dtype, rows, length key)
 FIELDS = [
     ("pos", np.float32, 3, "P"), ("vel", np.float32, 3, "P"),
@@ -59,6 +60,7 @@ def lib():
         L.link_read_state.argtypes = [_P, C.c_uint32, C.POINTER(_P), C.c_int]
         L.link_write_state.argtypes = [_P, C.c_uint32, C.POINTER(_P), C.c_int]
         L.link_read_index.argtypes = [_P, C.c_int32, _P, C.c_int64]
+        L.link_plan_gathers.argtypes = [dp, _P, C.POINTER(C.c_int32)]
         L.link_sizes.argtypes = [_P, C.POINTER(C.c_int64)]
         L.link_destroy.argtypes = [_P]
         L.link_destroy.restype = None
@@ -106,6 +108,20 @@ def workspace_bytes(wl, **over) -> int:
     n = C.c_size_t(0)
     _check(lib().link_workspace_bytes(C.byref(d), C.byref(n)))
     return int(n.value)
+
+
+def plan_gathers(wl, **over):
+    """The kernel's lane plan of the particles' gathers (host only):
+    per lane (particle, group size, first, end) with particle -1 for an
+    idle lane, and the largest group."""
+    d, keep = make_desc(wl, **over)
+    out = np.zeros(2048, np.int32)
+    gmax = C.c_int32(0)
+    _check(lib().link_plan_gathers(C.byref(d), out.ctypes.data_as(_P), C.byref(gmax)))
+    w0, w1 = out[:1024], out[1024:]
+    part = np.where(w0 >= 0, w0 & 0xffff, -1)
+    size = np.where(w0 >= 0, 1 << (w0 >> 16), 0)
+    return part, size, w1 & 0xffff, w1 >> 16, int(gmax.value)
 
 
 class LinkSim:

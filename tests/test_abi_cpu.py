@@ -379,3 +379,51 @@ def test_link_validation_and_workspace(L):
     big = W.make_link(1, n_links=4, sections=30)
     with pytest.raises(LK.LinkError):
         LK.workspace_bytes(big)
+
+
+def _link_incidence_counts(sections, ring, tets):
+    """Blocks touching each particle of a link, counted from the mesh: its
+    tetrahedra, the axial rows to the same slot of the neighbouring
+    sections, the radial rows between an inner section's centre and its
+    ring, and the end sections' attachments."""
+    n = ring + 1
+    cnt = np.bincount(np.asarray(tets).ravel(), minlength=sections * n).astype(np.int64)
+    for g in range(sections):
+        for s in range(n):
+            p = g * n + s
+            cnt[p] += (g > 0) + (g < sections - 1)
+            if 0 < g < sections - 1:
+                cnt[p] += ring if s == 0 else 1
+            if g == 0 or g == sections - 1:
+                cnt[p] += 1
+    return cnt
+
+
+@pytest.mark.parametrize("sections,ring,n_links", [(13, 8, 4), (5, 4, 4), (7, 12, 2), (13, 8, 1)])
+def test_link_gather_plan_covers_every_incidence_entry_once(L, sections, ring, n_links):
+    """The kernel's lane plan (host only): every particle owns one aligned
+    group of 1-8 lanes within a wave, below the frames' wave; the group's
+    ranges follow one another and cover the particle's incidence list
+    exactly, the lists of a link particle by particle, each range within
+    the group's even share."""
+    from paper_1904_02833_amd import link as LK
+
+    wl = W.make_link(1, n_links=n_links, sections=sections, ring=ring)
+    part, size, first, end, gmax = LK.plan_gathers(wl)
+    P1 = sections * (ring + 1)
+    cnt = _link_incidence_counts(sections, ring, wl.tets)
+    off = np.concatenate([[0], np.cumsum(cnt)])
+    n_inc = 4 * len(wl.tets) + 2 * ((sections - 1) * (ring + 1) + (sections - 2) * ring) + 2 * (ring + 1)
+    assert off[-1] == n_inc
+    assert np.all(part[960:] == -1)
+    assert gmax == size.max() and gmax in (1, 2, 4, 8)
+    for p in range(n_links * P1):
+        lanes = np.flatnonzero(part == p)
+        g = len(lanes)
+        assert g >= 1 and np.all(size[lanes] == g), p
+        assert lanes[0] % g == 0 and np.array_equal(lanes, lanes[0] + np.arange(g)), p
+        pk = p % P1
+        assert first[lanes[0]] == off[pk] and end[lanes[-1]] == off[pk + 1], p
+        assert np.array_equal(first[lanes[1:]], end[lanes[:-1]]), p
+        assert np.all(end[lanes] - first[lanes] <= -(-cnt[pk] // g)), p
+    assert np.sum(part >= 0) == np.sum(size[part >= 0] > 0)
