@@ -287,6 +287,10 @@ def learned_converging(n_steps=6):
                          "not_converged_last_step": int(np.sum((r["status"] & 2) != 0)),
                          "fell_back_last_step": int(np.sum((r["status"] & 4) != 0))}
             sim.close()
+        res["gain"] = {"fewer_iterations": res["learned"]["mean_iters_per_substep"]
+                       < res["plain"]["mean_iters_per_substep"],
+                       "more_snake_steps_per_s": res["learned"]["snake_steps_per_s"]
+                       > res["plain"]["snake_steps_per_s"]}
         return res
 
     out.update(compare(ev, state, CONVERGING_FALLBACK_K, n_steps))
