@@ -62,7 +62,9 @@ SOLVER_TRAFFIC = {("newton", "uniform"): (337.3e6, ("newton.hip", "lanes.h", "bl
                                          "ffd5e28127f1372a:7d1acb2a40eb1590:06967e1b979b9c85:bb2ea3129ebb4d43:96fa7fd0a2beec66:631740f795bf42f6"),
                   ("gs", "uniform"): (52.75e6, ("gs.hip", "blocks.h", "device_math.h", "kernels.h"), "a845d97590629bbd:06967e1b979b9c85:bb2ea3129ebb4d43:96fa7fd0a2beec66"),
                   ("carriage", "uneven"): (851.5e6, ("carriage.hip", "carriage.h", "lanes.h", "blocks.h", "device_math.h", "kernels.h", "fp64_recip.h"),
-                                           "e51011eec61ec901:b17d334d03f00823:7d1acb2a40eb1590:06967e1b979b9c85:bb2ea3129ebb4d43:96fa7fd0a2beec66:631740f795bf42f6")}
+                                           "e51011eec61ec901:b17d334d03f00823:7d1acb2a40eb1590:06967e1b979b9c85:bb2ea3129ebb4d43:96fa7fd0a2beec66:631740f795bf42f6"),
+                  ("carriage", "uniform"): (121.5e6, ("carriage.hip", "carriage.h", "lanes.h", "blocks.h", "device_math.h", "kernels.h", "fp64_recip.h"),
+                                            "e51011eec61ec901:b17d334d03f00823:7d1acb2a40eb1590:06967e1b979b9c85:bb2ea3129ebb4d43:96fa7fd0a2beec66:631740f795bf42f6")}
 # Newton solver (FP64): operations per body per inner conjugate-residual
 # iteration and per Newton iteration outside it (block evaluation, residual,
 # rows, the two initial products, the update), counted from the compiled
