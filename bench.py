@@ -194,8 +194,7 @@ def learned_comparison(n_steps):
         sim.close()
     out["workload"] = (f"learned: the uneven batch's shape and draws, evaluation seed, {ev.n_snakes} snakes, "
                        f"residual<=1e-4 or at most {ev.iters} iterations per substep")
-    out["gain"] = {"fewer_iterations": out["learned"]["mean_iters_per_substep"] < out["plain"]["mean_iters_per_substep"],
-                   "more_snake_steps_per_s": out["learned"]["snake_steps_per_s"] > out["plain"]["snake_steps_per_s"]}
+    out["gain"] = learned_gain(out["plain"], out["learned"])
     return out
 
 
@@ -232,6 +231,16 @@ def training_step_rate(net, ds, batch=4096, n=50):
             "roofline": {"bound": "mfma", "achieved": flop / (us * 1e-6) / 1e12, "peak": PEAK_BF16 / 1e12,
                          "unit": "TFLOP/s", "frac": flop / (us * 1e-6) / PEAK_BF16,
                          "flop_per_sample": NET_FWD_FLOP + NET_BWD_FLOP}}
+
+
+def learned_gain(plain, learned, margin=0.02):
+    """Whether the learned start takes fewer iterations and gives more
+    snake-steps/s than the plain one; a rate counts as higher only beyond
+    the run-to-run spread of a step time on one GPU (about 2 %)."""
+    ratio = learned["snake_steps_per_s"] / plain["snake_steps_per_s"]
+    return {"fewer_iterations": learned["mean_iters_per_substep"] < plain["mean_iters_per_substep"],
+            "snake_steps_per_s_ratio": ratio,
+            "more_snake_steps_per_s": ratio > 1.0 + margin}
 
 
 def learned_converging(n_steps=6):
@@ -289,10 +298,7 @@ def learned_converging(n_steps=6):
                          "not_converged_last_step": int(np.sum((r["status"] & 2) != 0)),
                          "fell_back_last_step": int(np.sum((r["status"] & 4) != 0))}
             sim.close()
-        res["gain"] = {"fewer_iterations": res["learned"]["mean_iters_per_substep"]
-                       < res["plain"]["mean_iters_per_substep"],
-                       "more_snake_steps_per_s": res["learned"]["snake_steps_per_s"]
-                       > res["plain"]["snake_steps_per_s"]}
+        res["gain"] = learned_gain(res["plain"], res["learned"])
         return res
 
     out.update(compare(ev, state, CONVERGING_FALLBACK_K, n_steps))
